@@ -1,0 +1,21 @@
+"""Plain FP64 CPU oracle for the steady and transient temperature solve.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or run anything in this package.  The GPU
+library never calls it and shares no code with it; the two meet only in the seeded inputs
+of the ``workloads`` package.
+
+Modules
+-------
+kernel     cell-averaged Green's function of the die (Sec. II-B, Appendix Theorem I), the
+           method of images for the die edges (Sec. IV-F)
+steady     direct spatial summation and the leakage / conductivity fixed point
+           (Eqs. Pt, Pleak, condsi, fspvsk; the iterate-to-convergence ground truth of Sec. V-C)
+transient  single-pole transient Green's function (Eq. tranGreen) and full-history
+           superposition of step responses (Eq. tranapprox)
+fd         brute-force finite-volume solve of the heat equation (Eq. fourier), used to pin
+           the kernel to the physics
+surrogate  FP64 reference layers of the convolutional warm-start network
+
+Parity status of each function is stated in its module header.
+"""

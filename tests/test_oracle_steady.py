@@ -1,0 +1,246 @@
+"""Pins of the oracle's steady solve: the images-folded direct sum and the leakage /
+conductivity fixed point (Eqs. Green, Pt, Pleak, condsi, fspvsk, detsol; Sec. IV-F; Sec. V-C).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.fft as sfft
+from scipy import integrate, optimize, special
+
+import workloads as W
+from oracle import fd
+from oracle import kernel as K
+from oracle import steady as S
+
+T = 0.5e-3
+KC = 150.0
+
+
+def _geom(n=16, lx=10e-3, ly=10e-3, eta=0.0, ny=None):
+    return S.Geometry(lx, ly, n, ny or n, T, KC, eta, 318.0)
+
+
+# ----------------------------------------------------------------------------- direct sum
+@pytest.mark.parametrize("nx,ny", [(4, 4), (5, 3), (2, 6)])
+def test_blocked_sum_equals_literal_loops(nx, ny):
+    g = S.Geometry(1.5e-3, 2.5e-3, nx, ny, T, KC, 0.0, 318.0)
+    op = S.DirectSum(g)
+    p = np.random.default_rng(nx * 10 + ny).random((ny, nx))
+    assert np.allclose(op.apply(p), S.direct_sum_literal(op.table, p), rtol=1e-13, atol=0)
+
+
+def test_apply_at_matches_full():
+    op = S.DirectSum(_geom(16))
+    p = np.random.default_rng(3).random((16, 16))
+    full = op.apply(p)
+    rows = np.array([0, 15, 7, 3])
+    cols = np.array([0, 15, 8, 12])
+    assert np.allclose(op.apply_at(p, rows, cols), full[rows, cols], rtol=1e-13)
+
+
+@pytest.mark.parametrize("n,lx", [(16, 10e-3), (32, 10e-3), (8, 1e-3)])
+def test_uniform_power_gives_q_t_over_k(n, lx):
+    # uniform flux into an adiabatic-walled slab over an isothermal bottom: 1-D conduction
+    g = _geom(n, lx, lx)
+    op = S.DirectSum(g)
+    q = 1.0e6
+    theta = op.apply(np.full((n, n), q * g.hx * g.hy))
+    assert np.allclose(theta, q * T / KC, rtol=1e-12, atol=0)
+
+
+def test_linearity_delta_response_and_symmetries():
+    n = 16
+    g = _geom(n)
+    op = S.DirectSum(g)
+    rng = np.random.default_rng(7)
+    p1, p2 = rng.random((n, n)), rng.random((n, n))
+    assert np.allclose(op.apply(2.0 * p1 - 3.0 * p2), 2.0 * op.apply(p1) - 3.0 * op.apply(p2), rtol=1e-12, atol=1e-14)
+    # a unit source in cell (k, l) produces the kernel plus its three mirror images
+    delta = np.zeros((n, n))
+    delta[3, 5] = 1.0
+    resp = op.apply(delta)
+    i, j = 10, 2
+    exp = sum(float(K.cell_kernel(a, b, g.hx, g.hy, T, KC)[0])
+              for a in (j - 5, j + 5 + 1, j - 5 + 2 * n, j + 5 + 1 - 2 * n)
+              for b in (i - 3, i + 3 + 1, i - 3 - 2 * n, i + 3 + 1 - 2 * n))
+    assert resp[i, j] == pytest.approx(exp, rel=1e-12)
+    # D4 equivariance on a square die
+    base = op.apply(p1)
+    assert np.allclose(op.apply(p1[::-1, :]), base[::-1, :], rtol=1e-12)
+    assert np.allclose(op.apply(p1[:, ::-1]), base[:, ::-1], rtol=1e-12)
+    assert np.allclose(op.apply(p1.T), base.T, rtol=1e-12)
+
+
+def test_alternate_points_patterns_sum_to_uniform():
+    # the alternate-points test case: four shifted every-other-point patterns tile the grid,
+    # so their responses add up to the uniform-power answer
+    n = 64
+    total = np.zeros((n, n))
+    for off in ((0, 0), (0, 1), (1, 0), (1, 1)):
+        inp = W.alternate_points_problem(n, 0.05, offset=off)
+        prob, opts = S.problem_from_inputs(inp)
+        g = prob.geom
+        total += prob.op.apply(prob.power(np.zeros((n, n)), opts))
+    q_uniform = 0.05 / (g.hx * g.hy)
+    assert np.allclose(total, q_uniform * T / KC, rtol=1e-12)
+    assert 0.05 * (n // 2) ** 2 == pytest.approx(51.2)  # total power of one pattern (paper: 51.2 W)
+
+
+# ----------------------------------------------------------------------------- fixed point
+def test_uniform_linear_leakage_closed_form():
+    n = 16
+    qd, ql, beta = 1.0e6, 0.2e6, 0.017
+    inp = W.uniform_problem(n, 1.0, 0.2, beta=beta, leak="linear")
+    prob, opts = S.problem_from_inputs(inp)
+    opts.tol, opts.max_iter = 1e-13, 200
+    dT, st = S.solve_steady(prob, opts)
+    r = T / KC
+    assert st.status == S.Status.OK
+    assert np.allclose(dT, r * (qd + ql) / (1.0 - beta * r * ql), rtol=1e-12)
+
+
+@pytest.mark.parametrize("qd,ql", [(1.0, 0.2), (2.0, 1.0), (0.5, 3.0)])
+def test_uniform_exp_leakage_lambert_w(qd, ql):
+    n = 16
+    beta = 0.017
+    inp = W.uniform_problem(n, qd, ql, beta=beta)
+    prob, opts = S.problem_from_inputs(inp)
+    opts.tol, opts.max_iter = 1e-13, 500
+    dT, st = S.solve_steady(prob, opts)
+    r = T / KC
+    a, b = r * qd * 1e6, r * ql * 1e6
+    z = -beta * b * math.exp(beta * a)
+    assert z > -1.0 / math.e
+    exact = a - special.lambertw(z, 0).real / beta
+    assert st.status == S.Status.OK
+    assert np.allclose(dT, exact, rtol=1e-12)
+    if (qd, ql) == (1.0, 0.2):
+        assert exact == pytest.approx(4.04749, abs=5e-6)
+
+
+def test_runaway_beyond_lambert_branch_point():
+    # beta b exp(beta a) > 1/e: no fixed point, the iteration must report RUNAWAY
+    n = 8
+    beta = 0.017
+    r = T / KC
+    ql = 1.2 / (math.e * beta * r) / 1e6  # W/mm^2, just past the branch point at a = 0
+    inp = W.uniform_problem(n, 1e-9, ql, beta=beta)
+    prob, opts = S.problem_from_inputs(inp)
+    opts.max_iter = 10000
+    _, st = S.solve_steady(prob, opts)
+    assert st.status == S.Status.RUNAWAY
+
+
+def test_not_converged_and_kirchhoff_domain():
+    inp = W.config1(0, n=16)
+    prob, opts = S.problem_from_inputs(inp)
+    opts.max_iter, opts.tol = 1, 1e-6
+    _, st = S.solve_steady(prob, opts)
+    assert st.status == S.Status.NOT_CONVERGED and st.iterations == 1
+    g = _geom(8, eta=1.3)
+    prob = S.SteadyProblem(g, np.full((8, 8), 5e8))  # theta ~ 1.7e4 K, far past T_amb / (eta - 1)
+    _, st = S.solve_steady(prob, S.Options(leak="none"))
+    assert st.status == S.Status.RUNAWAY
+
+
+def test_kirchhoff_roundtrip_and_quadrature():
+    t_amb, eta = 318.0, 1.3
+    theta = np.array([0.0, 0.5, 3.0, 25.0, 120.0])
+    dT, ok = S.kirchhoff_inverse(theta, t_amb, eta)
+    assert np.all(ok)
+    for th, d in zip(theta, dT):
+        quad, _ = integrate.quad(lambda tt: (tt / t_amb) ** (-eta), t_amb, t_amb + d, epsabs=1e-14, epsrel=1e-14)
+        assert quad == pytest.approx(th, rel=1e-12, abs=1e-13)
+    # second-order expansion: dT = theta + eta theta^2 / (2 T_amb) + O(theta^3)
+    small = 1e-2
+    d = float(S.kirchhoff_inverse(np.array([small]), t_amb, eta)[0][0])
+    assert d == pytest.approx(small + eta * small ** 2 / (2 * t_amb), rel=1e-9)
+    assert np.allclose(S.kirchhoff(dT, t_amb, eta), theta, rtol=1e-13, atol=1e-13)
+
+
+def test_uniform_with_k_of_t_against_ode():
+    # uniform flux through a slab with k = k0 (T/300)^-eta: integrate dT/dz = q / k(T) upward
+    # from the isothermal bottom (independent of the closed-form Kirchhoff inverse), and find
+    # the leakage fixed point on the scalar top temperature
+    n, eta, t_amb, beta = 8, 1.3, 318.0, 0.017
+    qd, ql = 1.5e6, 0.4e6
+    g = _geom(n, eta=eta)
+    prob = S.SteadyProblem(g, np.full((n, n), qd), np.full((n, n), ql))
+    opts = S.Options(leak="exp", beta=beta, tol=1e-12, max_iter=200)
+    dT, st = S.solve_steady(prob, opts)
+
+    def top_rise(q):
+        sol = integrate.solve_ivp(lambda z, y: [q / (KC * ((t_amb + y[0]) / 300.0) ** (-eta))], (0.0, T), [0.0],
+                                  rtol=1e-12, atol=1e-14, method="DOP853")
+        return sol.y[0, -1]
+
+    root = optimize.brentq(lambda d: top_rise(qd + ql * math.exp(beta * d)) - d, 0.0, 50.0, xtol=1e-14)
+    assert st.status == S.Status.OK
+    assert np.allclose(dT, root, rtol=1e-9)
+
+
+def test_uniform_conductivity_multiplier_is_exact():
+    # m = c uniform is a homogeneous slab with conductivity c k: dT = q t / (c k)
+    n = 8
+    g = _geom(n)
+    prob = S.SteadyProblem(g, np.full((n, n), 1e6), cond_map=np.full((n, n), 1.04))
+    dT, st = S.solve_steady(prob, S.Options(leak="none"))
+    assert np.allclose(dT, 1e6 * T / (1.04 * KC), rtol=1e-12)
+
+
+def test_leakage_aware_green_function_alpha_zero():
+    # Eq. detsol with alpha = 0 (linear leakage, uniform baseline leakage mu, no k(T), m = 1):
+    # the converged map satisfies DCT(dT) = lambda DCT(g) / (1 - beta mu hx hy lambda),
+    # g = hx hy (q_dyn + mu), lambda the cosine transform of the periodised kernel.
+    n = 16
+    inp = W.config1(0, n=n)
+    g = _geom(n)
+    mu = 0.3e6
+    prob = S.SteadyProblem(g, inp.q_dyn, np.full((n, n), mu))
+    opts = S.Options(leak="linear", beta=0.017, tol=1e-14, max_iter=300)
+    dT, st = S.solve_steady(prob, opts)
+    assert st.status == S.Status.OK
+    lam = sfft.dct(sfft.dct(prob.op.table, type=1, axis=0), type=1, axis=1)[:n, :n]
+    gmap = g.hx * g.hy * (inp.q_dyn + mu)
+    ghat = sfft.dctn(gmap, type=2)
+    expect = sfft.idctn(lam * ghat / (1.0 - opts.beta * mu * g.hx * g.hy * lam), type=2)
+    assert np.allclose(dT, expect, rtol=1e-11, atol=1e-11 * np.max(dT))
+
+
+# ----------------------------------------------------------------------------- physics
+def test_direct_sum_against_finite_volume_heat_equation():
+    # small die (4 t across) so the side-wall images matter; 8 x 8 random cell powers
+    n, lx = 8, 2e-3
+    g = _geom(n, lx, lx)
+    op = S.DirectSum(g)
+    q = np.random.default_rng(11).uniform(0.1e6, 2e6, (n, n))
+    theta = op.apply(q * g.hx * g.hy)
+    ref = fd.richardson(q, lx, lx, T, KC, r0=9, nz0=18, levels=2)
+    assert np.max(np.abs(theta - ref)) / np.max(ref) < 1e-8
+
+
+def test_fixed_point_against_finite_volume_with_leakage():
+    n, lx, beta = 8, 2e-3, 0.017
+    g = _geom(n, lx, lx)
+    rng = np.random.default_rng(12)
+    qd = rng.uniform(0.1e6, 2e6, (n, n))
+    ql = 0.3 * qd * np.exp(-0.7 * rng.standard_normal((n, n)))
+    prob = S.SteadyProblem(g, qd, ql)
+    dT, st = S.solve_steady(prob, S.Options(leak="exp", beta=beta, tol=1e-12, max_iter=100))
+    fd_dT = np.zeros((n, n))
+    for _ in range(100):
+        new = fd.richardson(qd + ql * np.exp(beta * fd_dT), lx, lx, T, KC, r0=3, nz0=6, levels=2)
+        if np.max(np.abs(new - fd_dT)) < 1e-12:
+            fd_dT = new
+            break
+        fd_dT = new
+    assert st.status == S.Status.OK
+    assert np.max(np.abs(dT - fd_dT)) / np.max(fd_dT) < 1e-6
+
+
+def test_finite_volume_solvers_agree():
+    q = np.random.default_rng(5).uniform(0.0, 1e6, (3, 4))
+    a = fd.solve_modes(q, 1e-3, 0.8e-3, T, KC, 3, 5)
+    b = fd.solve_sparse(q, 1e-3, 0.8e-3, T, KC, 3, 5)
+    assert np.allclose(a, b, rtol=1e-12)
