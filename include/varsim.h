@@ -1,0 +1,232 @@
+/*
+ * varsim.h -- C ABI of the MI355X (gfx950) steady and transient chip-temperature solve.
+ *
+ * The solve follows VarSim (Sultan & Sarangi, arXiv 2307.12119):
+ *   - the temperature rise is the power map convolved with the die's Green's function
+ *     (Sec. II-B, Eq. Green), the die edges handled by mirror-image sources (Sec. IV-F);
+ *   - total power is dynamic plus leakage, leakage grows with temperature and is scaled by
+ *     the process-variation map (Sec. II-D, Eqs. Ileakmod, Pleak, Pt);
+ *   - conductivity follows k = k0 (T/300)^-eta (Sec. II-E, Eq. condsi) and a spatial
+ *     conductivity-variation map scales the Green's function as 1/k (Eq. fspvsk);
+ *   - leakage and conductivity are iterated against temperature until convergence, the
+ *     ground truth of Sec. V-C;
+ *   - transients use the single-pole transient Green's function (Eq. tranGreen) superposed
+ *     over a piecewise-constant power history (Eq. tranapprox).
+ *
+ * Conventions shared by every entry point
+ *   - SI units throughout: metres, watts, kelvin, seconds; power maps are densities in W/m^2.
+ *   - Maps are DEVICE pointers, row-major [ny][nx], contiguous, element type given by
+ *     varsim_options.precision (float for VARSIM_F32, double for VARSIM_F64).
+ *   - Outputs are the temperature RISE dT above the ambient temperature, never absolute T.
+ *   - The caller owns every map and the workspace; the library never frees caller memory.
+ *     The context owns only its caches (Green's-function tables, twiddle tables, timing).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Work is
+ *     stream-ordered; calls that return statistics synchronise that stream before returning.
+ *   - A context is not thread-safe: use one context per host thread.
+ *   - Supported grids: nx == ny, a power of two in [16, 1024]; one silicon layer with an
+ *     isothermal bottom at the ambient temperature.  Anything else is VARSIM_ERR_UNSUPPORTED.
+ *
+ * Errors: every entry point returns a varsim_status; on failure varsim_last_error() holds a
+ * message.  Device failures (launch or runtime errors) return VARSIM_ERR_DEVICE.
+ */
+#ifndef VARSIM_H
+#define VARSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define VARSIM_API __attribute__((visibility("default")))
+#else
+#define VARSIM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum varsim_status {
+  VARSIM_OK = 0,
+  VARSIM_ERR_INVALID = 1,        /* NULL required pointer, non-positive size, m <= 0, tol <= 0, ... */
+  VARSIM_ERR_UNSUPPORTED = 2,    /* grid, layer stack or boundary outside the supported set */
+  VARSIM_ERR_NOT_CONVERGED = 3,  /* max_iter reached; dT_out holds the last iterate, stats valid */
+  VARSIM_ERR_RUNAWAY = 4,        /* non-finite iterate, dT above dT_cap_K, or the conductivity law
+                                    left its domain: no stable fixed point (thermal runaway) */
+  VARSIM_ERR_DEVICE = 5,         /* HIP runtime or launch failure */
+  VARSIM_ERR_NO_MEMORY = 6       /* workspace too small, or a context cache allocation failed */
+} varsim_status;
+
+enum { VARSIM_LEAK_NONE = 0, VARSIM_LEAK_EXP = 1, VARSIM_LEAK_LINEAR = 2 };
+enum { VARSIM_F32 = 0, VARSIM_F64 = 1 };
+enum { VARSIM_TAU_MOMENT = 0, VARSIM_TAU_LUMPED = 1 };
+
+typedef struct varsim_ctx varsim_ctx;
+
+/* One material layer (Table param gives the paper's stack; one silicon layer is supported). */
+typedef struct varsim_layer {
+  double thickness_m;   /* t, > 0 */
+  double k0_W_mK;       /* conductivity at 300 K, > 0 (Eq. condsi) */
+  double eta;           /* exponent of k = k0 (T/300)^-eta, >= 0 */
+  double rho_c_J_m3K;   /* volumetric heat capacity, > 0 (transient only) */
+} varsim_layer;
+
+/* Die geometry and boundary (Sec. V-A: a die of lx x ly discretised on an nx x ny grid). */
+typedef struct varsim_geometry {
+  double lx_m, ly_m;            /* die size, > 0 */
+  int32_t nx, ny;               /* grid; nx == ny, power of two in [16, 1024] */
+  int32_t n_layers;             /* must be 1 */
+  const varsim_layer* layers;   /* host pointer, n_layers entries */
+  int32_t bottom_bc;            /* 0 = bottom face isothermal at t_amb_K (only value supported) */
+  double h_bottom_W_m2K;        /* reserved for a convective bottom; ignored */
+  double t_amb_K;               /* ambient temperature, > 0 */
+} varsim_geometry;
+
+/* Solver options.  Zero-initialised fields are invalid: fill every field. */
+typedef struct varsim_options {
+  int32_t leak;                 /* VARSIM_LEAK_EXP: L = exp(beta dT); LINEAR: 1 + beta dT (Eq. Pleak) */
+  double beta_per_K;            /* leakage temperature coefficient */
+  int32_t sv_radius;            /* shift-variant stencil radius; only 0 (pointwise 1/m) supported */
+  int32_t precision;            /* VARSIM_F32 or VARSIM_F64: element type of every map */
+  int32_t max_iter;             /* >= 1, <= 1000 */
+  double tol_K;                 /* stop at the first iterate with max |dT_k - dT_{k-1}| <= tol, > 0 */
+  double dT_cap_K;              /* RUNAWAY when any dT exceeds it, > 0 (1000 K is a sane value) */
+  int32_t final_f64_residual;   /* 1: report max |G64(dT) - dT| from one FP64 application */
+} varsim_options;
+
+/* One steady problem (all maps device pointers [ny][nx]; see conventions above). */
+typedef struct varsim_problem {
+  const varsim_geometry* geom;  /* host pointer */
+  const void* q_dyn;            /* dynamic power density, W/m^2, required */
+  const void* q_leak0;          /* leakage density at T_amb, W/m^2; NULL = no leakage */
+  const void* leak_var;         /* variation multiplier v of leakage; NULL = 1 */
+  const void* cond_map;         /* conductivity multiplier m (> 0); NULL = 1 */
+  const void* dT_init;          /* starting iterate; NULL = 0; a non-finite entry falls back to 0 */
+  void* dT_out;                 /* result dT (may alias dT_init) */
+} varsim_problem;
+
+/* Per-problem result statistics. */
+typedef struct varsim_stats {
+  int32_t status;               /* varsim_status of this problem */
+  int32_t iterations;           /* applications of the fixed-point map performed */
+  double last_increment_K;      /* max |dT_k - dT_{k-1}| of the last iteration */
+  double residual_f64_K;        /* max |G64(dT) - dT| in FP64 (NaN when not requested) */
+  double dT_max_K;              /* max of dT */
+  double dT_mean_K;             /* mean of dT (FP64 accumulation) */
+  int64_t hotspot_index;        /* row-major index of the max (lowest index on ties) */
+  int32_t warm_start_rejected;  /* 1 when dT_init held a non-finite value and 0 was used */
+  int32_t reserved;
+} varsim_stats;
+
+/* Transient description (Sec. IV-E, Eq. tranapprox): power held constant over each step. */
+typedef struct varsim_transient {
+  double dt_s;                  /* step length, > 0 */
+  int32_t n_steps;              /* >= 1 */
+  int32_t out_every;            /* write dT every out_every steps (>= 1) */
+  int32_t n_blocks;             /* >= 1 */
+  const int32_t* block_rects;   /* DEVICE [n_blocks][4] = x0, y0, w, h in cells; later blocks
+                                   overwrite earlier ones where they overlap */
+  const void* trace;            /* DEVICE [n_steps][n_blocks] dynamic power density of each block
+                                   held over step n, W/m^2, element type = precision */
+  int32_t tau_model;            /* VARSIM_TAU_MOMENT or VARSIM_TAU_LUMPED */
+} varsim_transient;
+
+/* ----------------------------------------------------------------------------------------
+ * Context.  varsim_create makes `device` current, allocates nothing large, and returns a
+ * context; varsim_destroy frees the context's caches.  Errors: INVALID (NULL out), DEVICE.
+ */
+VARSIM_API varsim_status varsim_create(int device, varsim_ctx** out);
+VARSIM_API void varsim_destroy(varsim_ctx* ctx);
+VARSIM_API const char* varsim_status_string(varsim_status s);
+VARSIM_API const char* varsim_last_error(const varsim_ctx* ctx);
+
+/* ----------------------------------------------------------------------------------------
+ * Green's-function table (Sec. II-B Eq. Green; Appendix Theorem I; Sec. IV-F images).
+ *
+ * Tabulates in FP64 on the device the cell-averaged slab kernel K_per(a, b) of the die
+ * (rise at the centre of cell (a, b) per watt spread over the cell at the origin, summed over
+ * the mirror images of the side walls), a in [0, nx], b in [0, ny], and its cosine transform
+ *     lambda[p][q] = sum_{a, b in (-n, n]} K_per(a, b) cos(pi p b / ny) cos(pi q a / nx)
+ * which diagonalises the mirrored convolution.  The conductivity used is k(T_amb).
+ *   kernel_out : DEVICE double [ny + 1][nx + 1], or NULL
+ *   lambda_out : DEVICE double [ny][nx], or NULL
+ * The table is also cached in the context for the solves.  Synchronises `stream`.
+ * Errors: INVALID, UNSUPPORTED, DEVICE, NO_MEMORY.
+ */
+VARSIM_API varsim_status varsim_green_table(varsim_ctx* ctx, const varsim_geometry* geom, void* kernel_out,
+                                 void* lambda_out, void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Shift-invariant convolution (Eq. Green with the images of Sec. IV-F): for each of n_maps
+ * power maps P (W per cell, DEVICE [n_maps][ny][nx], element type `precision`) writes
+ * theta = K_per (*) P with images, computed as DCT-III(lambda . DCT-II(P)).
+ * theta_out may alias power.  Synchronises `stream` before returning.
+ * Errors: INVALID, UNSUPPORTED, DEVICE, NO_MEMORY.
+ */
+VARSIM_API varsim_status varsim_conv(varsim_ctx* ctx, const varsim_geometry* geom, int32_t precision,
+                          const void* power, void* theta_out, int32_t n_maps, void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Workspace size in bytes for solving `n` problems with `opts` (steady or batch).  The
+ * caller allocates at least that much device memory (alignment 256 B) and passes it in.
+ * Errors: INVALID, UNSUPPORTED.
+ */
+VARSIM_API varsim_status varsim_workspace_size(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
+                                    const varsim_options* opts, size_t* bytes);
+
+/* ----------------------------------------------------------------------------------------
+ * Steady solve of one problem: the fixed point dT = G(dT) of
+ *   P     = hx hy [q_dyn + q_leak0 v L(dT)]                  (Eqs. Pt, Pleak)
+ *   theta = (K_per (*) P) / m                                (Eqs. Green, fspvsk)
+ *   G(dT) = Phi^-1(theta), Phi the Kirchhoff transform of k(T) (Eq. condsi)
+ * by Picard iteration from dT_init (or 0) to the first increment <= tol_K.
+ * Writes dT_out and *stats (host pointer).  Synchronises `stream`; returns stats->status.
+ * Errors: INVALID, UNSUPPORTED, NOT_CONVERGED, RUNAWAY, DEVICE, NO_MEMORY.
+ */
+VARSIM_API varsim_status varsim_solve_steady(varsim_ctx* ctx, const varsim_problem* problem,
+                                  const varsim_options* opts, void* workspace, size_t ws_bytes,
+                                  varsim_stats* stats, void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Batched steady solve (Monte Carlo over variation samples, Sec. I): n problems, possibly of
+ * different grid sizes and possibly sharing input pointers, solved together; each problem
+ * stops at its own convergence.  stats: host array of n entries.  Returns the worst status.
+ * Synchronises `stream`.
+ */
+VARSIM_API varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
+                                 const varsim_options* opts, void* workspace, size_t ws_bytes,
+                                 varsim_stats* stats, void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Transient solve (Eqs. Ttran, tranGreen, tranapprox).  Starting from dT = 0 at t = 0, step n
+ * holds the block powers trace[n] over (t_{n-1}, t_n]; each spatial cosine mode responds with
+ * a single pole, the leakage and conductivity of step n use dT_{n-1}.  Writes dT every
+ * out_every steps into dT_steps_out (DEVICE [n_steps / out_every][ny][nx]) and the final
+ * step's stats.  problem->q_dyn is ignored (the trace replaces it); problem->dT_out receives
+ * the final dT.  Synchronises `stream`.
+ * Errors: INVALID, UNSUPPORTED, RUNAWAY, DEVICE, NO_MEMORY.
+ */
+VARSIM_API varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* problem,
+                                     const varsim_transient* tr, const varsim_options* opts,
+                                     void* dT_steps_out, void* workspace, size_t ws_bytes,
+                                     varsim_stats* stats, void* stream);
+
+VARSIM_API varsim_status varsim_transient_workspace_size(varsim_ctx* ctx, const varsim_problem* problem,
+                                              const varsim_transient* tr,
+                                              const varsim_options* opts, size_t* bytes);
+
+/* ----------------------------------------------------------------------------------------
+ * Kernel timing.  When enabled, every kernel launch of the solves is bracketed by HIP events
+ * on the launch stream; varsim_kernel_times reports, per kernel class, the launch count and
+ * the summed durations (ms) since the last reset.  Class names are returned in names[i]
+ * (static strings).  n_io: in = capacity, out = number of classes written.
+ */
+VARSIM_API varsim_status varsim_set_timing(varsim_ctx* ctx, int32_t enable);
+VARSIM_API varsim_status varsim_kernel_times(varsim_ctx* ctx, const char** names, int64_t* counts,
+                                  double* total_ms, int32_t* n_io);
+VARSIM_API varsim_status varsim_reset_timing(varsim_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VARSIM_H */

@@ -1,0 +1,685 @@
+// C ABI of the varsim library: context, caches, validation, workspace layout and the
+// host-side sequencing of the device passes.  No arithmetic of the method runs here: every
+// step of the solve is a kernel launch; the host only orders them and reads back per-map
+// convergence counts and statistics.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace vs;
+
+namespace {
+
+struct TableEntry {
+  double* kper = nullptr;
+  double* lam64T = nullptr;
+  float* lam32T = nullptr;
+};
+
+struct TwEntry {
+  Cx<double>* tw64 = nullptr;
+  Cx<float>* tw32 = nullptr;
+  Cx<double>* qw64 = nullptr;
+  Cx<float>* qw32 = nullptr;
+};
+
+using TableKey = std::tuple<int, int, double, double, double, double>;
+
+struct TimedEvent {
+  const char* cls;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct varsim_ctx {
+  int device = 0;
+  std::string err;
+  std::map<TableKey, TableEntry> tables;
+  std::map<int, TwEntry> twiddles;
+  bool timing = false;
+  std::vector<TimedEvent> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<long long, double>> times;
+  std::vector<const char*> class_names;
+  int* active_dev = nullptr;
+  int* active_host = nullptr;
+  // host staging of per-call descriptor arrays (kept alive until the call returns)
+  std::vector<MapPtrs> h_maps;
+  std::vector<PrepArgs> h_prep;
+  std::vector<varsim_stats> h_stats;
+  MapPtrs* conv_maps = nullptr;
+  size_t conv_maps_cap = 0;
+};
+
+namespace {
+
+varsim_status fail(varsim_ctx* c, varsim_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                            \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return fail(ctx, VARSIM_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+hipEvent_t take_event(varsim_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+template <class F>
+hipError_t timed(varsim_ctx* c, const char* cls, hipStream_t s, F&& f) {
+  if (!c->timing) return f();
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return hipErrorOutOfMemory;
+  (void)hipEventRecord(a, s);
+  const hipError_t e = f();
+  (void)hipEventRecord(b, s);
+  c->pending.push_back({cls, a, b});
+  return e;
+}
+
+void flush_timing(varsim_ctx* c) {
+  for (auto& p : c->pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    auto& slot = c->times[p.cls];
+    if (slot.first == 0 &&
+        std::find_if(c->class_names.begin(), c->class_names.end(), [&](const char* n) { return !strcmp(n, p.cls); }) ==
+            c->class_names.end())
+      c->class_names.push_back(p.cls);
+    slot.first += 1;
+    slot.second += ms;
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+bool is_pow2_in_range(int n) { return n >= kMinN && n <= kMaxN && (n & (n - 1)) == 0; }
+
+varsim_status check_geometry(varsim_ctx* ctx, const varsim_geometry* g) {
+  if (!g) return fail(ctx, VARSIM_ERR_INVALID, "geometry is NULL");
+  if (!(g->lx_m > 0) || !(g->ly_m > 0) || !(g->t_amb_K > 0))
+    return fail(ctx, VARSIM_ERR_INVALID, "die size and ambient temperature must be positive");
+  if (g->nx <= 0 || g->ny <= 0) return fail(ctx, VARSIM_ERR_INVALID, "grid size must be positive");
+  if (g->nx != g->ny || !is_pow2_in_range(g->nx))
+    return fail(ctx, VARSIM_ERR_UNSUPPORTED, "grid %dx%d: need nx == ny, a power of two in [16, 1024]", g->nx, g->ny);
+  if (g->n_layers != 1 || !g->layers)
+    return fail(ctx, g->n_layers < 1 || !g->layers ? VARSIM_ERR_INVALID : VARSIM_ERR_UNSUPPORTED,
+                "exactly one layer is supported");
+  if (g->bottom_bc != 0) return fail(ctx, VARSIM_ERR_UNSUPPORTED, "only an isothermal bottom is supported");
+  const varsim_layer& L = g->layers[0];
+  if (!(L.thickness_m > 0) || !(L.k0_W_mK > 0) || !(L.eta >= 0))
+    return fail(ctx, VARSIM_ERR_INVALID, "layer thickness, k0 must be positive and eta >= 0");
+  return VARSIM_OK;
+}
+
+varsim_status check_options(varsim_ctx* ctx, const varsim_options* o) {
+  if (!o) return fail(ctx, VARSIM_ERR_INVALID, "options is NULL");
+  if (o->leak < VARSIM_LEAK_NONE || o->leak > VARSIM_LEAK_LINEAR) return fail(ctx, VARSIM_ERR_INVALID, "bad leak law");
+  if (o->precision != VARSIM_F32 && o->precision != VARSIM_F64) return fail(ctx, VARSIM_ERR_INVALID, "bad precision");
+  if (o->max_iter < 1 || o->max_iter > kMaxIter) return fail(ctx, VARSIM_ERR_INVALID, "max_iter must be in [1, 1000]");
+  if (!(o->tol_K > 0)) return fail(ctx, VARSIM_ERR_INVALID, "tol_K must be positive");
+  if (!(o->dT_cap_K > 0)) return fail(ctx, VARSIM_ERR_INVALID, "dT_cap_K must be positive");
+  if (!std::isfinite(o->beta_per_K)) return fail(ctx, VARSIM_ERR_INVALID, "beta must be finite");
+  if (o->sv_radius != 0) return fail(ctx, VARSIM_ERR_UNSUPPORTED, "only sv_radius = 0 is supported");
+  return VARSIM_OK;
+}
+
+double k_ref_of(const varsim_geometry* g) {
+  const varsim_layer& L = g->layers[0];
+  return L.k0_W_mK * std::pow(g->t_amb_K / 300.0, -L.eta);
+}
+
+TableKey key_of(const varsim_geometry* g) {
+  return TableKey(g->nx, g->ny, g->lx_m, g->ly_m, g->layers[0].thickness_m, k_ref_of(g));
+}
+
+varsim_status get_twiddles(varsim_ctx* ctx, int n, hipStream_t s, TwEntry* out) {
+  auto it = ctx->twiddles.find(n);
+  if (it != ctx->twiddles.end()) {
+    *out = it->second;
+    return VARSIM_OK;
+  }
+  TwEntry e;
+  if (hipMalloc(&e.tw64, n * sizeof(Cx<double>)) != hipSuccess || hipMalloc(&e.tw32, n * sizeof(Cx<float>)) != hipSuccess ||
+      hipMalloc(&e.qw64, n * sizeof(Cx<double>)) != hipSuccess || hipMalloc(&e.qw32, n * sizeof(Cx<float>)) != hipSuccess)
+    return fail(ctx, VARSIM_ERR_NO_MEMORY, "twiddle table allocation failed");
+  HIP_TRY(launch_twiddles(n, e.tw64, e.tw32, e.qw64, e.qw32, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  ctx->twiddles[n] = e;
+  *out = e;
+  return VARSIM_OK;
+}
+
+varsim_status get_table(varsim_ctx* ctx, const varsim_geometry* g, hipStream_t s, TableEntry* out,
+                        double* lam_rowmajor = nullptr) {
+  const TableKey key = key_of(g);
+  auto it = ctx->tables.find(key);
+  if (it != ctx->tables.end() && !lam_rowmajor) {
+    *out = it->second;
+    return VARSIM_OK;
+  }
+  TableSpec sp{g->nx, g->ny, g->lx_m, g->ly_m, g->layers[0].thickness_m, k_ref_of(g)};
+  TableEntry e = it != ctx->tables.end() ? it->second : TableEntry{};
+  const bool fresh = it == ctx->tables.end();
+  if (fresh) {
+    if (hipMalloc(&e.kper, (size_t)(sp.nx + 1) * (sp.ny + 1) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&e.lam64T, (size_t)sp.nx * sp.ny * sizeof(double)) != hipSuccess ||
+        hipMalloc(&e.lam32T, (size_t)sp.nx * sp.ny * sizeof(float)) != hipSuccess)
+      return fail(ctx, VARSIM_ERR_NO_MEMORY, "table allocation failed");
+  }
+  double* scratch = nullptr;
+  if (hipMalloc(&scratch, green_table_scratch_doubles(sp.nx, sp.ny) * sizeof(double)) != hipSuccess)
+    return fail(ctx, VARSIM_ERR_NO_MEMORY, "table scratch allocation failed");
+  hipError_t err = timed(ctx, "green_table", s,
+                         [&] { return launch_green_table(sp, e.kper, e.lam64T, e.lam32T, lam_rowmajor, scratch, s); });
+  hipError_t err2 = hipStreamSynchronize(s);
+  (void)hipFree(scratch);
+  if (err != hipSuccess || err2 != hipSuccess)
+    return fail(ctx, VARSIM_ERR_DEVICE, "green table: %s", hipGetErrorString(err != hipSuccess ? err : err2));
+  ctx->tables[key] = e;
+  *out = e;
+  return VARSIM_OK;
+}
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// Workspace layout of a batch (problems in group-sorted order).
+struct Layout {
+  int stride = 0;
+  size_t resid = 0, sum = 0, maxpack = 0, flags = 0, resid64 = 0, state_end = 0;
+  size_t stats = 0, maps = 0, prep = 0;
+  std::vector<size_t> S, QL, MINV, S64;
+  size_t total = 0;
+};
+
+size_t esize(int precision) { return precision == VARSIM_F64 ? 8 : 4; }
+
+Layout make_layout(const std::vector<const varsim_problem*>& probs, const varsim_options* o) {
+  Layout L;
+  const size_t n = probs.size();
+  L.stride = o->max_iter + 2;
+  size_t off = 0;
+  L.resid = off;
+  off = align_up(off + n * L.stride * 8);
+  L.sum = off;
+  off = align_up(off + n * L.stride * 8);
+  L.maxpack = off;
+  off = align_up(off + n * L.stride * 8);
+  L.flags = off;
+  off = align_up(off + n * 4);
+  L.resid64 = off;
+  off = align_up(off + n * 8);
+  L.state_end = off;
+  L.stats = off;
+  off = align_up(off + n * sizeof(varsim_stats));
+  L.maps = off;
+  off = align_up(off + n * sizeof(MapPtrs));
+  L.prep = off;
+  off = align_up(off + n * sizeof(PrepArgs));
+  const size_t es = esize(o->precision);
+  for (const varsim_problem* p : probs) {
+    const size_t cells = (size_t)p->geom->nx * p->geom->ny;
+    L.S.push_back(off);
+    off = align_up(off + cells * es);
+    if (p->q_leak0 && o->leak != VARSIM_LEAK_NONE && p->leak_var) {
+      L.QL.push_back(off);
+      off = align_up(off + cells * es);
+    } else {
+      L.QL.push_back((size_t)-1);
+    }
+    if (p->cond_map) {
+      L.MINV.push_back(off);
+      off = align_up(off + cells * es);
+    } else {
+      L.MINV.push_back((size_t)-1);
+    }
+    if (o->final_f64_residual && o->precision == VARSIM_F32) {
+      L.S64.push_back(off);
+      off = align_up(off + cells * 8);
+    } else {
+      L.S64.push_back((size_t)-1);
+    }
+  }
+  L.total = off;
+  return L;
+}
+
+PointParams point_params(const varsim_geometry* g, const varsim_options* o) {
+  PointParams pp{};
+  pp.hxhy = (g->lx_m / g->nx) * (g->ly_m / g->ny);
+  pp.beta = o->beta_per_K;
+  pp.t_amb = g->t_amb_K;
+  const double eta = g->layers[0].eta;
+  pp.eta_mode = eta == 0.0 ? 0 : (eta == 1.0 ? 1 : 2);
+  pp.inv_1m_eta = eta == 1.0 ? 0.0 : 1.0 / (1.0 - eta);
+  pp.c_1m_eta = (1.0 - eta) / g->t_amb_K;
+  pp.cap = o->dT_cap_K;
+  pp.tol = o->tol_K;
+  pp.leak = o->leak;
+  return pp;
+}
+
+struct Group {
+  int first, count;  // range in sorted order
+  const varsim_geometry* geom;
+  TableEntry table;
+  TwEntry tw;
+};
+
+varsim_status validate_problem(varsim_ctx* ctx, const varsim_problem* p) {
+  if (!p) return fail(ctx, VARSIM_ERR_INVALID, "problem is NULL");
+  varsim_status s = check_geometry(ctx, p->geom);
+  if (s != VARSIM_OK) return s;
+  if (!p->q_dyn || !p->dT_out) return fail(ctx, VARSIM_ERR_INVALID, "q_dyn and dT_out are required");
+  return VARSIM_OK;
+}
+
+varsim_status sort_into_groups(varsim_ctx* ctx, const varsim_problem* problems, int n,
+                               std::vector<int>& order, std::vector<Group>& groups) {
+  order.resize(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const varsim_geometry* ga = problems[a].geom;
+    const varsim_geometry* gb = problems[b].geom;
+    const auto ka = std::make_tuple(key_of(ga), ga->t_amb_K, ga->layers[0].eta);
+    const auto kb = std::make_tuple(key_of(gb), gb->t_amb_K, gb->layers[0].eta);
+    return ka < kb;
+  });
+  groups.clear();
+  for (int i = 0; i < n; ++i) {
+    const varsim_geometry* g = problems[order[i]].geom;
+    const auto k = std::make_tuple(key_of(g), g->t_amb_K, g->layers[0].eta);
+    if (!groups.empty()) {
+      const varsim_geometry* h = groups.back().geom;
+      if (std::make_tuple(key_of(h), h->t_amb_K, h->layers[0].eta) == k) {
+        groups.back().count++;
+        continue;
+      }
+    }
+    groups.push_back(Group{i, 1, g, {}, {}});
+  }
+  return VARSIM_OK;
+}
+
+}  // namespace
+
+// =========================================================================================
+extern "C" {
+
+varsim_status varsim_create(int device, varsim_ctx** out) {
+  if (!out) return VARSIM_ERR_INVALID;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return VARSIM_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return VARSIM_ERR_DEVICE;
+  varsim_ctx* c = new varsim_ctx();
+  c->device = device;
+  if (hipMalloc(&c->active_dev, sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&c->active_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return VARSIM_ERR_NO_MEMORY;
+  }
+  *out = c;
+  return VARSIM_OK;
+}
+
+void varsim_destroy(varsim_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->tables) {
+    (void)hipFree(kv.second.kper);
+    (void)hipFree(kv.second.lam64T);
+    (void)hipFree(kv.second.lam32T);
+  }
+  for (auto& kv : c->twiddles) {
+    (void)hipFree(kv.second.tw64);
+    (void)hipFree(kv.second.tw32);
+    (void)hipFree(kv.second.qw64);
+    (void)hipFree(kv.second.qw32);
+  }
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  (void)hipFree(c->active_dev);
+  (void)hipHostFree(c->active_host);
+  (void)hipFree(c->conv_maps);
+  delete c;
+}
+
+const char* varsim_status_string(varsim_status s) {
+  switch (s) {
+    case VARSIM_OK: return "ok";
+    case VARSIM_ERR_INVALID: return "invalid argument";
+    case VARSIM_ERR_UNSUPPORTED: return "unsupported configuration";
+    case VARSIM_ERR_NOT_CONVERGED: return "not converged";
+    case VARSIM_ERR_RUNAWAY: return "thermal runaway";
+    case VARSIM_ERR_DEVICE: return "device error";
+    case VARSIM_ERR_NO_MEMORY: return "out of memory";
+  }
+  return "unknown status";
+}
+
+const char* varsim_last_error(const varsim_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+varsim_status varsim_green_table(varsim_ctx* ctx, const varsim_geometry* geom, void* kernel_out, void* lambda_out,
+                                 void* stream) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  varsim_status st = check_geometry(ctx, geom);
+  if (st != VARSIM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  TableEntry e;
+  st = get_table(ctx, geom, s, &e, (double*)lambda_out);
+  if (st != VARSIM_OK) return st;
+  if (kernel_out)
+    HIP_TRY(hipMemcpyAsync(kernel_out, e.kper, (size_t)(geom->nx + 1) * (geom->ny + 1) * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  flush_timing(ctx);
+  return VARSIM_OK;
+}
+
+varsim_status varsim_conv(varsim_ctx* ctx, const varsim_geometry* geom, int32_t precision, const void* power,
+                          void* theta_out, int32_t n_maps, void* stream) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  varsim_status st = check_geometry(ctx, geom);
+  if (st != VARSIM_OK) return st;
+  if (!power || !theta_out || n_maps < 1) return fail(ctx, VARSIM_ERR_INVALID, "power/theta NULL or n_maps < 1");
+  if (precision != VARSIM_F32 && precision != VARSIM_F64) return fail(ctx, VARSIM_ERR_INVALID, "bad precision");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  TableEntry tab;
+  TwEntry tw;
+  if ((st = get_table(ctx, geom, s, &tab)) != VARSIM_OK) return st;
+  if ((st = get_twiddles(ctx, geom->nx, s, &tw)) != VARSIM_OK) return st;
+  const size_t cells = (size_t)geom->nx * geom->ny, es = esize(precision);
+  if (ctx->conv_maps_cap < (size_t)n_maps) {
+    (void)hipFree(ctx->conv_maps);
+    ctx->conv_maps = nullptr;
+    ctx->conv_maps_cap = 0;
+    if (hipMalloc(&ctx->conv_maps, n_maps * sizeof(MapPtrs)) != hipSuccess)
+      return fail(ctx, VARSIM_ERR_NO_MEMORY, "descriptor allocation failed");
+    ctx->conv_maps_cap = n_maps;
+  }
+  ctx->h_maps.assign(n_maps, MapPtrs{});
+  for (int i = 0; i < n_maps; ++i) {
+    ctx->h_maps[i].qd = (const char*)power + i * cells * es;
+    ctx->h_maps[i].dT = (char*)theta_out + i * cells * es;
+    ctx->h_maps[i].S = ctx->h_maps[i].dT;
+  }
+  HIP_TRY(hipMemcpyAsync(ctx->conv_maps, ctx->h_maps.data(), n_maps * sizeof(MapPtrs), hipMemcpyHostToDevice, s));
+  PassArgs a{};
+  a.maps = ctx->conv_maps;
+  a.n_maps = n_maps;
+  a.n = geom->nx;
+  a.tw = Twiddles{tw.tw64, tw.tw32, tw.qw64, tw.qw32};
+  a.iter = -1;
+  HIP_TRY(timed(ctx, "row_conv_head", s, [&] { return launch_row_pass(ROW_CONV_HEAD, precision, precision, a, s); }));
+  HIP_TRY(timed(ctx, "col", s, [&] {
+    return launch_col_pass(precision, a, precision == VARSIM_F32 ? (const void*)tab.lam32T : (const void*)tab.lam64T, s);
+  }));
+  HIP_TRY(timed(ctx, "row_conv_tail", s, [&] { return launch_row_pass(ROW_CONV_TAIL, precision, precision, a, s); }));
+  HIP_TRY(hipStreamSynchronize(s));
+  flush_timing(ctx);
+  return VARSIM_OK;
+}
+
+varsim_status varsim_workspace_size(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
+                                    const varsim_options* opts, size_t* bytes) {
+  if (!ctx || !problems || n < 1 || !bytes) return fail(ctx, VARSIM_ERR_INVALID, "bad workspace query");
+  varsim_status st = check_options(ctx, opts);
+  if (st != VARSIM_OK) return st;
+  std::vector<const varsim_problem*> ps;
+  for (int i = 0; i < n; ++i) {
+    if ((st = validate_problem(ctx, &problems[i])) != VARSIM_OK) return st;
+    ps.push_back(&problems[i]);
+  }
+  *bytes = make_layout(ps, opts).total;
+  return VARSIM_OK;
+}
+
+varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
+                                 const varsim_options* opts, void* workspace, size_t ws_bytes, varsim_stats* stats,
+                                 void* stream) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  if (!problems || n < 1 || !stats || !workspace) return fail(ctx, VARSIM_ERR_INVALID, "NULL argument or n < 1");
+  varsim_status st = check_options(ctx, opts);
+  if (st != VARSIM_OK) return st;
+  for (int i = 0; i < n; ++i)
+    if ((st = validate_problem(ctx, &problems[i])) != VARSIM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+
+  std::vector<int> order;
+  std::vector<Group> groups;
+  sort_into_groups(ctx, problems, n, order, groups);
+  std::vector<const varsim_problem*> sorted(n);
+  for (int i = 0; i < n; ++i) sorted[i] = &problems[order[i]];
+  const Layout L = make_layout(sorted, opts);
+  if (ws_bytes < L.total)
+    return fail(ctx, VARSIM_ERR_NO_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  for (Group& g : groups) {
+    if ((st = get_table(ctx, g.geom, s, &g.table)) != VARSIM_OK) return st;
+    if ((st = get_twiddles(ctx, g.geom->nx, s, &g.tw)) != VARSIM_OK) return st;
+  }
+
+  char* ws = (char*)workspace;
+  IterState base{};
+  base.resid = (unsigned long long*)(ws + L.resid);
+  base.sum = (double*)(ws + L.sum);
+  base.maxpack = (unsigned long long*)(ws + L.maxpack);
+  base.flags = (unsigned*)(ws + L.flags);
+  base.resid64 = (unsigned long long*)(ws + L.resid64);
+  base.stride = L.stride;
+  MapPtrs* d_maps = (MapPtrs*)(ws + L.maps);
+  PrepArgs* d_prep = (PrepArgs*)(ws + L.prep);
+  varsim_stats* d_stats = (varsim_stats*)(ws + L.stats);
+  const int io = opts->precision;
+  const bool want_res = opts->final_f64_residual != 0;
+
+  ctx->h_maps.assign(n, MapPtrs{});
+  ctx->h_prep.assign(n, PrepArgs{});
+  bool any_init = false;
+  for (int i = 0; i < n; ++i) {
+    const varsim_problem* p = sorted[i];
+    MapPtrs& m = ctx->h_maps[i];
+    PrepArgs& q = ctx->h_prep[i];
+    m.qd = p->q_dyn;
+    m.dT = p->dT_out;
+    m.S = ws + L.S[i];
+    m.S64 = L.S64[i] != (size_t)-1 ? ws + L.S64[i] : nullptr;
+    m.init = p->dT_init;
+    const bool leak = p->q_leak0 && opts->leak != VARSIM_LEAK_NONE;
+    m.ql = leak ? (L.QL[i] != (size_t)-1 ? (const void*)(ws + L.QL[i]) : p->q_leak0) : nullptr;
+    m.minv = L.MINV[i] != (size_t)-1 ? ws + L.MINV[i] : nullptr;
+    q.q_leak0 = p->q_leak0;
+    q.leak_var = p->leak_var;
+    q.cond_map = p->cond_map;
+    q.init = p->dT_init;
+    q.ql_out = (leak && L.QL[i] != (size_t)-1) ? ws + L.QL[i] : nullptr;
+    q.minv_out = (void*)m.minv;
+    q.dT = p->dT_out;
+    q.flags = base.flags + i;
+    any_init = any_init || p->dT_init;
+  }
+
+  HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(ws, L.state_end, s); }));
+  HIP_TRY(hipMemcpyAsync(d_maps, ctx->h_maps.data(), n * sizeof(MapPtrs), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_prep, ctx->h_prep.data(), n * sizeof(PrepArgs), hipMemcpyHostToDevice, s));
+
+  auto group_args = [&](const Group& g, int iter) {
+    PassArgs a{};
+    a.maps = d_maps + g.first;
+    a.n_maps = g.count;
+    a.n = g.geom->nx;
+    a.st = base;
+    a.st.resid += (size_t)g.first * L.stride;
+    a.st.sum += (size_t)g.first * L.stride;
+    a.st.maxpack += (size_t)g.first * L.stride;
+    a.st.flags += g.first;
+    a.st.resid64 += g.first;
+    a.pp = point_params(g.geom, opts);
+    a.tw = Twiddles{g.tw.tw64, g.tw.tw32, g.tw.qw64, g.tw.qw32};
+    a.iter = iter;
+    a.zero_start = 0;
+    return a;
+  };
+
+  for (const Group& g : groups) {
+    const long cells = (long)g.geom->nx * g.geom->ny;
+    HIP_TRY(timed(ctx, "prep", s, [&] { return launch_prep(io, d_prep + g.first, g.count, cells, s); }));
+    if (any_init) HIP_TRY(timed(ctx, "prep", s, [&] { return launch_init_copy(io, d_prep + g.first, g.count, cells, s); }));
+  }
+  // iteration 1 head: P(dT_0) -> row spectrum.  Maps without a warm start use zero_start.
+  for (const Group& g : groups) {
+    PassArgs a = group_args(g, 1);
+    // a map without dT_init starts from 0; with one, from dT_out (which holds the copy)
+    bool all_zero = true;
+    for (int i = g.first; i < g.first + g.count; ++i) all_zero = all_zero && !sorted[i]->dT_init;
+    a.zero_start = all_zero ? 1 : 0;
+    if (!all_zero) {
+      // mixed warm / cold starts inside a group: cold maps get dT_out zeroed first
+      for (int i = g.first; i < g.first + g.count; ++i)
+        if (!sorted[i]->dT_init)
+          HIP_TRY(launch_zero_words(sorted[i]->dT_out, (size_t)g.geom->nx * g.geom->ny * esize(io), s));
+    }
+    HIP_TRY(timed(ctx, "row_head", s, [&] { return launch_row_pass(ROW_HEAD, io, io, a, s); }));
+  }
+
+  int iters_run = 0;
+  for (int k = 1; k <= opts->max_iter; ++k) {
+    for (const Group& g : groups) {
+      PassArgs a = group_args(g, k);
+      bool all_zero = true;
+      for (int i = g.first; i < g.first + g.count; ++i) all_zero = all_zero && !sorted[i]->dT_init;
+      a.zero_start = all_zero ? 1 : 0;
+      const void* lam = io == VARSIM_F32 ? (const void*)g.table.lam32T : (const void*)g.table.lam64T;
+      HIP_TRY(timed(ctx, "col", s, [&] { return launch_col_pass(io, a, lam, s); }));
+      const int mode = k < opts->max_iter ? ROW_MERGED : ROW_LAST;
+      HIP_TRY(timed(ctx, mode == ROW_MERGED ? "row_merged" : "row_last", s,
+                    [&] { return launch_row_pass(mode, io, io, a, s); }));
+    }
+    iters_run = k;
+    if (k >= 2 || k == opts->max_iter) {
+      HIP_TRY(launch_zero_words(ctx->active_dev, sizeof(int), s));
+      HIP_TRY(launch_count_active(base, n, k, opts->tol_K, ctx->active_dev, s));
+      HIP_TRY(hipMemcpyAsync(ctx->active_host, ctx->active_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (*ctx->active_host == 0) break;
+    }
+  }
+
+  if (want_res) {
+    for (const Group& g : groups) {
+      PassArgs a = group_args(g, 0);
+      a.resid_pass = 1;
+      a.use_s64 = io == VARSIM_F32 ? 1 : 0;
+      HIP_TRY(timed(ctx, "resid_head", s, [&] { return launch_row_pass(ROW_HEAD, io, VARSIM_F64, a, s); }));
+      HIP_TRY(timed(ctx, "resid_col", s, [&] { return launch_col_pass(VARSIM_F64, a, g.table.lam64T, s); }));
+      HIP_TRY(timed(ctx, "resid_tail", s, [&] { return launch_row_pass(ROW_RESID, io, VARSIM_F64, a, s); }));
+    }
+  }
+  for (const Group& g : groups) {
+    PassArgs a = group_args(g, 0);
+    HIP_TRY(launch_finalize(a.st, d_maps + g.first, g.count, io, (long)g.geom->nx * g.geom->ny, opts->max_iter,
+                            iters_run, opts->tol_K, want_res ? 1 : 0, d_stats + g.first, s));
+  }
+  ctx->h_stats.resize(n);
+  HIP_TRY(hipMemcpyAsync(ctx->h_stats.data(), d_stats, n * sizeof(varsim_stats), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  flush_timing(ctx);
+  int worst = VARSIM_OK;
+  for (int i = 0; i < n; ++i) {
+    stats[order[i]] = ctx->h_stats[i];
+    const int si = ctx->h_stats[i].status;
+    worst = std::max(worst, si);
+  }
+  if (worst != VARSIM_OK) {
+    for (int i = 0; i < n; ++i)
+      if (stats[i].status == worst) {
+        fail(ctx, (varsim_status)worst, "problem %d: %s", i, varsim_status_string((varsim_status)worst));
+        break;
+      }
+  }
+  return (varsim_status)worst;
+}
+
+varsim_status varsim_solve_steady(varsim_ctx* ctx, const varsim_problem* problem, const varsim_options* opts,
+                                  void* workspace, size_t ws_bytes, varsim_stats* stats, void* stream) {
+  return varsim_solve_batch(ctx, problem, 1, opts, workspace, ws_bytes, stats, stream);
+}
+
+varsim_status varsim_transient_workspace_size(varsim_ctx* ctx, const varsim_problem*, const varsim_transient*,
+                                              const varsim_options*, size_t* bytes) {
+  if (bytes) *bytes = 0;
+  return fail(ctx, VARSIM_ERR_UNSUPPORTED, "transient solve not built");
+}
+
+varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem*, const varsim_transient*,
+                                     const varsim_options*, void*, void*, size_t, varsim_stats*, void*) {
+  return fail(ctx, VARSIM_ERR_UNSUPPORTED, "transient solve not built");
+}
+
+varsim_status varsim_set_timing(varsim_ctx* ctx, int32_t enable) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  ctx->timing = enable != 0;
+  return VARSIM_OK;
+}
+
+varsim_status varsim_reset_timing(varsim_ctx* ctx) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  ctx->times.clear();
+  ctx->class_names.clear();
+  return VARSIM_OK;
+}
+
+varsim_status varsim_kernel_times(varsim_ctx* ctx, const char** names, int64_t* counts, double* total_ms,
+                                  int32_t* n_io) {
+  if (!ctx || !n_io) return VARSIM_ERR_INVALID;
+  const int cap = *n_io;
+  int k = 0;
+  for (const char* nm : ctx->class_names) {
+    if (k >= cap) break;
+    const auto& v = ctx->times[nm];
+    if (names) names[k] = nm;
+    if (counts) counts[k] = v.first;
+    if (total_ms) total_ms[k] = v.second;
+    ++k;
+  }
+  *n_io = k;
+  return VARSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Shared definitions of the varsim HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "varsim.h"
+
+namespace vs {
+
+template <typename T>
+struct Cx {
+  T r, i;
+};
+
+constexpr int kMinN = 16;
+constexpr int kMaxN = 1024;
+constexpr int kMaxIter = 1000;
+
+// per-map flag bits (IterState::flags)
+constexpr unsigned kFlagRunaway = 1u;       // non-finite / above cap / Kirchhoff domain left
+constexpr unsigned kFlagWarmRejected = 2u;  // dT_init had a non-finite entry: start from 0
+constexpr unsigned kFlagInvalid = 4u;       // conductivity map not strictly positive
+constexpr unsigned kFlagSkip = kFlagRunaway | kFlagInvalid;
+
+// Device pointers of one map (all [n][n] row-major).
+struct MapPtrs {
+  const void* qd;    // dynamic power density (io type)
+  const void* ql;    // leakage density at ambient times variation (io type), or null
+  const void* minv;  // 1 / conductivity multiplier (io type), or null
+  void* dT;          // temperature rise, in/out (io type)
+  void* S;           // transform work array (compute type of the main loop)
+  void* S64;         // FP64 work array for the residual pass, or null
+  const void* init;  // warm start (io type), or null
+  void* aux;         // spare per-map pointer (transient state)
+};
+
+// Pointwise physics constants of one geometry.
+struct PointParams {
+  double hxhy;        // cell area, m^2
+  double beta;        // leakage temperature coefficient, 1/K
+  double t_amb;       // K
+  double inv_1m_eta;  // 1 / (1 - eta)
+  double c_1m_eta;    // (1 - eta) / T_amb
+  double cap;         // runaway cap, K
+  double tol;         // convergence tolerance, K
+  int leak;           // VARSIM_LEAK_*
+  int eta_mode;       // 0: eta == 0, 1: eta == 1, 2: general
+};
+
+// Per-map iteration state in the workspace.
+struct IterState {
+  unsigned long long* resid;    // [maps][stride] double bits of max |dT_k - dT_{k-1}|
+  double* sum;                  // [maps][stride] sum of dT_k
+  unsigned long long* maxpack;  // [maps][stride] (orderable bits of dT_k << 32) | ~index
+  unsigned* flags;              // [maps]
+  unsigned long long* resid64;  // [maps] double bits of the FP64 residual
+  int stride;
+};
+
+__host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
+
+}  // namespace vs

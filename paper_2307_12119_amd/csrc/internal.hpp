@@ -1,0 +1,80 @@
+// Host-side declarations shared by the translation units of the varsim library.
+#pragma once
+
+#include "common.hpp"
+
+namespace vs {
+
+struct TableSpec {
+  int nx, ny;
+  double lx, ly, t, k_ref;
+};
+
+// Green's-function table: K_per [ny+1][nx+1], lambda transposed and scaled (FP64, FP32), and
+// optionally lambda row-major unscaled.  scratch: green_table_scratch_doubles(nx, ny) doubles.
+hipError_t launch_green_table(const TableSpec& sp, double* kper, double* lam64T, float* lam32T, double* lam_rowmajor,
+                              double* scratch, hipStream_t stream);
+size_t green_table_scratch_doubles(int nx, int ny);
+
+hipError_t launch_twiddles(int n, Cx<double>* tw64, Cx<float>* tw32, Cx<double>* qw64, Cx<float>* qw32,
+                           hipStream_t stream);
+
+// Row-pass variants.
+enum RowMode : int {
+  ROW_HEAD = 0,       // dT (or 0) -> P -> row DCT-II -> S
+  ROW_MERGED = 1,     // S -> row DCT-III -> theta -> dT' (+residual, stats) -> P -> row DCT-II -> S
+  ROW_LAST = 2,       // as MERGED without the forward transform
+  ROW_RESID = 3,      // S -> theta -> dT'' ; residual max |dT'' - dT| only (no write)
+  ROW_CONV_HEAD = 4,  // power map (W per cell) -> row DCT-II -> S
+  ROW_CONV_TAIL = 5,  // S -> row DCT-III -> theta written to the output map
+};
+
+struct Twiddles {
+  const Cx<double>* tw64;
+  const Cx<float>* tw32;
+  const Cx<double>* qw64;
+  const Cx<float>* qw32;
+};
+
+struct PassArgs {
+  const MapPtrs* maps;  // device array, one entry per map of the group
+  int n_maps;
+  int n;  // grid size (nx == ny)
+  IterState st;
+  PointParams pp;
+  Twiddles tw;
+  int iter;        // 1-based iteration index of the pass
+  int zero_start;  // iteration 1 starts from dT = 0 (no warm start)
+  int use_s64;     // operate on MapPtrs::S64 instead of S
+  int resid_pass;  // FP64 residual pass: skip only maps flagged invalid / runaway
+};
+
+// io: element type of the maps (VARSIM_F32 / VARSIM_F64); compute: type of the transforms.
+hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hipStream_t stream);
+hipError_t launch_col_pass(int compute, const PassArgs& a, const void* lamT, hipStream_t stream);
+
+// Static inputs: QL = q_leak0 * v, MINV = 1 / m (per map), warm-start screening and copy.
+struct PrepArgs {
+  const void* q_leak0;
+  const void* leak_var;
+  const void* cond_map;
+  const void* init;
+  void* ql_out;    // or null
+  void* minv_out;  // or null
+  void* dT;
+  unsigned* flags;  // this map's flag word
+};
+// args: device array of n_maps entries; count = cells per map
+hipError_t launch_prep(int io, const PrepArgs* args, int n_maps, long count, hipStream_t stream);
+hipError_t launch_init_copy(int io, const PrepArgs* args, int n_maps, long count, hipStream_t stream);
+
+hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t stream);
+
+// Convergence count: number of maps not yet finished after iteration `iter`.
+hipError_t launch_count_active(const IterState& st, int n_maps, int iter, double tol, int* out, hipStream_t stream);
+
+// Final statistics of every map into a device varsim_stats array.
+hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, long cells, int max_iter,
+                           int iters_run, double tol, int residual_done, varsim_stats* out, hipStream_t stream);
+
+}  // namespace vs

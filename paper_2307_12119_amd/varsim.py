@@ -1,0 +1,264 @@
+"""ctypes binding of libvarsim.so (argument marshalling only).
+
+Every step of the solve runs in the HIP library; this module only builds the C structs of
+``include/varsim.h`` from torch tensors (device memory) and plain numbers, passes device
+pointers and the current HIP stream, and turns status codes into exceptions.  It fails
+loudly when the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvarsim.so")
+
+OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_NOT_CONVERGED, ERR_RUNAWAY, ERR_DEVICE, ERR_NO_MEMORY = range(7)
+LEAK_NONE, LEAK_EXP, LEAK_LINEAR = 0, 1, 2
+F32, F64 = 0, 1
+TAU_MOMENT, TAU_LUMPED = 0, 1
+
+
+class VarsimError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"varsim status {status}: {message}")
+        self.status = status
+
+
+class Layer(Structure):
+    _fields_ = [("thickness_m", c_double), ("k0_W_mK", c_double), ("eta", c_double), ("rho_c_J_m3K", c_double)]
+
+
+class Geometry(Structure):
+    _fields_ = [("lx_m", c_double), ("ly_m", c_double), ("nx", c_int32), ("ny", c_int32), ("n_layers", c_int32),
+                ("layers", POINTER(Layer)), ("bottom_bc", c_int32), ("h_bottom_W_m2K", c_double),
+                ("t_amb_K", c_double)]
+
+
+class Options(Structure):
+    _fields_ = [("leak", c_int32), ("beta_per_K", c_double), ("sv_radius", c_int32), ("precision", c_int32),
+                ("max_iter", c_int32), ("tol_K", c_double), ("dT_cap_K", c_double), ("final_f64_residual", c_int32)]
+
+
+class Problem(Structure):
+    _fields_ = [("geom", POINTER(Geometry)), ("q_dyn", c_void_p), ("q_leak0", c_void_p), ("leak_var", c_void_p),
+                ("cond_map", c_void_p), ("dT_init", c_void_p), ("dT_out", c_void_p)]
+
+
+class Stats(Structure):
+    _fields_ = [("status", c_int32), ("iterations", c_int32), ("last_increment_K", c_double),
+                ("residual_f64_K", c_double), ("dT_max_K", c_double), ("dT_mean_K", c_double),
+                ("hotspot_index", c_int64), ("warm_start_rejected", c_int32), ("reserved", c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class Transient(Structure):
+    _fields_ = [("dt_s", c_double), ("n_steps", c_int32), ("out_every", c_int32), ("n_blocks", c_int32),
+                ("block_rects", c_void_p), ("trace", c_void_p), ("tau_model", c_int32)]
+
+
+EXPORTS = {
+    "varsim_create": (c_int, [c_int, POINTER(c_void_p)]),
+    "varsim_destroy": (None, [c_void_p]),
+    "varsim_status_string": (c_char_p, [c_int]),
+    "varsim_last_error": (c_char_p, [c_void_p]),
+    "varsim_green_table": (c_int, [c_void_p, POINTER(Geometry), c_void_p, c_void_p, c_void_p]),
+    "varsim_conv": (c_int, [c_void_p, POINTER(Geometry), c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
+    "varsim_workspace_size": (c_int, [c_void_p, POINTER(Problem), c_int32, POINTER(Options), POINTER(c_size_t)]),
+    "varsim_solve_steady": (c_int, [c_void_p, POINTER(Problem), POINTER(Options), c_void_p, c_size_t,
+                                    POINTER(Stats), c_void_p]),
+    "varsim_solve_batch": (c_int, [c_void_p, POINTER(Problem), c_int32, POINTER(Options), c_void_p, c_size_t,
+                                   POINTER(Stats), c_void_p]),
+    "varsim_solve_transient": (c_int, [c_void_p, POINTER(Problem), POINTER(Transient), POINTER(Options), c_void_p,
+                                       c_void_p, c_size_t, POINTER(Stats), c_void_p]),
+    "varsim_transient_workspace_size": (c_int, [c_void_p, POINTER(Problem), POINTER(Transient), POINTER(Options),
+                                                POINTER(c_size_t)]),
+    "varsim_set_timing": (c_int, [c_void_p, c_int32]),
+    "varsim_kernel_times": (c_int, [c_void_p, POINTER(c_char_p), POINTER(c_int64), POINTER(c_double),
+                                    POINTER(c_int32)]),
+    "varsim_reset_timing": (c_int, [c_void_p]),
+}
+
+
+class Library:
+    """The loaded shared library with typed entry points."""
+
+    _instance = None
+
+    def __init__(self, path: str = LIB_PATH):
+        if not os.path.exists(path):
+            raise FileNotFoundError(f"{path} is not built; run paper_2307_12119_amd.build.build() first")
+        self.path = path
+        self.cdll = ctypes.CDLL(path)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(self.cdll, name)
+            fn.restype = res
+            fn.argtypes = args
+            setattr(self, name, fn)
+
+    @classmethod
+    def load(cls) -> "Library":
+        if cls._instance is None:
+            cls._instance = cls()
+        return cls._instance
+
+
+# ----------------------------------------------------------------------------------------- helpers
+def _ptr(t) -> int | None:
+    """Device address of a contiguous torch tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to varsim must be contiguous")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    import torch
+
+    return torch.cuda.current_stream().cuda_stream
+
+
+@dataclass
+class Die:
+    """Geometry and material of a single-layer die (SI units)."""
+
+    lx_m: float
+    ly_m: float
+    t_m: float
+    k0: float
+    eta: float
+    t_amb: float
+    rho_c: float = 1.66e6
+
+
+def make_geometry(die: Die, n: int) -> tuple[Geometry, Layer]:
+    layer = Layer(die.t_m, die.k0, die.eta, die.rho_c)
+    geom = Geometry(die.lx_m, die.ly_m, n, n, 1, None, 0, 0.0, die.t_amb)
+    return geom, layer
+
+
+def make_options(precision: int = F32, leak: int = LEAK_EXP, beta: float = 0.017, max_iter: int = 50,
+                 tol: float = 1e-3, cap: float = 1000.0, f64_residual: bool = False) -> Options:
+    return Options(leak, beta, 0, precision, max_iter, tol, cap, 1 if f64_residual else 0)
+
+
+class Context:
+    """A library context on one device (owns the Green's-function and twiddle caches)."""
+
+    def __init__(self, device: int = 0, lib: Library | None = None):
+        self.lib = lib or Library.load()
+        h = c_void_p()
+        st = self.lib.varsim_create(device, ctypes.byref(h))
+        if st != OK:
+            raise VarsimError(st, "varsim_create failed")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            self.lib.varsim_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, allow=(OK,)):
+        if st not in allow:
+            msg = self.lib.varsim_last_error(self.handle)
+            raise VarsimError(st, msg.decode() if msg else "")
+        return st
+
+    # -------------------------------------------------------------------------------- table
+    def green_table(self, die: Die, n: int):
+        """(K_per [n+1][n+1], lambda [n][n]) as FP64 device tensors."""
+        import torch
+
+        geom, layer = make_geometry(die, n)
+        geom.layers = ctypes.pointer(layer)
+        dev = torch.device("cuda", self.device)
+        kper = torch.empty((n + 1, n + 1), dtype=torch.float64, device=dev)
+        lam = torch.empty((n, n), dtype=torch.float64, device=dev)
+        self._check(self.lib.varsim_green_table(self.handle, ctypes.byref(geom), _ptr(kper), _ptr(lam), _stream()))
+        return kper, lam
+
+    def conv(self, die: Die, power, out=None):
+        """theta = mirrored Green's convolution of power maps [..., n, n] (W per cell)."""
+        import torch
+
+        n = power.shape[-1]
+        geom, layer = make_geometry(die, n)
+        geom.layers = ctypes.pointer(layer)
+        prec = F64 if power.dtype == torch.float64 else F32
+        out = torch.empty_like(power) if out is None else out
+        n_maps = power.numel() // (n * n)
+        self._check(self.lib.varsim_conv(self.handle, ctypes.byref(geom), prec, _ptr(power), _ptr(out), n_maps,
+                                         _stream()))
+        return out
+
+    # -------------------------------------------------------------------------------- solves
+    def _problems(self, items: list[dict]):
+        geoms, layers, probs = [], [], (Problem * len(items))()
+        for i, it in enumerate(items):
+            geom, layer = make_geometry(it["die"], it["q_dyn"].shape[-1])
+            layers.append(layer)
+            geoms.append(geom)
+            geom.layers = ctypes.pointer(layer)
+            probs[i] = Problem(ctypes.pointer(geom), _ptr(it["q_dyn"]), _ptr(it.get("q_leak0")),
+                               _ptr(it.get("leak_var")), _ptr(it.get("cond_map")), _ptr(it.get("dT_init")),
+                               _ptr(it["dT_out"]))
+        return probs, (geoms, layers)
+
+    def workspace_bytes(self, items: list[dict], opts: Options) -> int:
+        probs, keep = self._problems(items)
+        nbytes = c_size_t()
+        self._check(self.lib.varsim_workspace_size(self.handle, probs, len(items), ctypes.byref(opts),
+                                                   ctypes.byref(nbytes)))
+        return nbytes.value
+
+    def solve_batch(self, items: list[dict], opts: Options, workspace=None, raise_on=(ERR_INVALID,
+                    ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY)) -> list[dict]:
+        """Solve every problem (dicts of device tensors: die, q_dyn, dT_out, optional q_leak0,
+        leak_var, cond_map, dT_init); returns per-problem stats dicts."""
+        import torch
+
+        probs, keep = self._problems(items)
+        need = self.workspace_bytes(items, opts)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=torch.device("cuda", self.device))
+        stats = (Stats * len(items))()
+        for i in range(len(items)):
+            stats[i].status = -1
+        st = self.lib.varsim_solve_batch(self.handle, probs, len(items), ctypes.byref(opts), _ptr(workspace),
+                                         workspace.numel(), stats, _stream())
+        filled = all(stats[i].status >= 0 for i in range(len(items)))
+        # argument / device errors leave the stats unfilled; per-problem statuses are returned
+        if st in raise_on and not (filled and st == ERR_INVALID):
+            self._check(st, allow=())
+        return [stats[i].as_dict() for i in range(len(items))]
+
+    def solve_steady(self, item: dict, opts: Options, workspace=None) -> dict:
+        return self.solve_batch([item], opts, workspace)[0]
+
+    # -------------------------------------------------------------------------------- timing
+    def set_timing(self, enable: bool):
+        self._check(self.lib.varsim_set_timing(self.handle, 1 if enable else 0))
+
+    def reset_timing(self):
+        self._check(self.lib.varsim_reset_timing(self.handle))
+
+    def kernel_times(self) -> dict:
+        cap = 64
+        names = (c_char_p * cap)()
+        counts = (c_int64 * cap)()
+        tot = (c_double * cap)()
+        n = c_int32(cap)
+        self._check(self.lib.varsim_kernel_times(self.handle, names, counts, tot, ctypes.byref(n)))
+        return {names[i].decode(): {"count": counts[i], "total_ms": tot[i]} for i in range(n.value)}

@@ -30,13 +30,17 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field, replace
+from functools import lru_cache
 
 import numpy as np
+import scipy.fft as sfft
 from scipy.special import ndtr
 
 SEED_ROOT = 230712119
 LATTICE = 1024
 W_PER_MM2 = 1.0e6  # W/m^2 in one W/mm^2
+
+FFT_WORKERS = -1  # scipy.fft worker threads for the random fields (-1: all cores)
 
 K_BOLTZMANN = 1.380649e-23
 Q_ELECTRON = 1.602176634e-19
@@ -164,7 +168,7 @@ def gaussian_field(n: int, cell_m: float, ell_m: float, rng: np.random.Generator
     kk = k[:, None] ** 2 + k[None, :] ** 2
     amp = np.exp(-0.25 * ell_m * ell_m * kk)
     amp /= math.sqrt(float(np.mean(amp * amp)))
-    z = np.fft.ifft2(np.fft.fft2(noise) * amp).real
+    z = sfft.ifft2(sfft.fft2(noise, workers=FFT_WORKERS) * amp, workers=FFT_WORKERS).real
     return np.ascontiguousarray(z[:n, :n])
 
 
@@ -175,6 +179,21 @@ def vth_leak_scale(t_amb: float, vth0: float = 0.30, rel_sigma: float = 0.1, n_s
 
 
 # ----------------------------------------------------------------------------- workloads
+@lru_cache(maxsize=64)
+def _floorplan_density(config: int, floorplan: int, n_blocks: int, n: int) -> np.ndarray:
+    frng = make_rng(config, floorplan, 0, 0)
+    blocks = random_blocks(n_blocks, frng)
+    q = frng.uniform(0.1, 2.0, size=n_blocks) * W_PER_MM2
+    out = area_average(paint(blocks, q), n)
+    out.setflags(write=False)
+    return out
+
+
+def floorplan_density(config: int, floorplan: int, n_blocks: int, n: int) -> np.ndarray:
+    """Dynamic power density of a seeded block floorplan rasterised on an n x n grid [W/m^2]."""
+    return _floorplan_density(config, floorplan, n_blocks, n).copy()
+
+
 def steady_problem(config: int, n: int, n_blocks: int, floorplan: int = 0, sample: int = 0,
                    variation: bool = True, eta: float = 1.3, die: Die | None = None,
                    beta: float = 0.017, leak_fraction: float = 0.2) -> SteadyInputs:
@@ -185,10 +204,7 @@ def steady_problem(config: int, n: int, n_blocks: int, floorplan: int = 0, sampl
     """
     die = die or Die()
     die = replace(die, eta=eta if variation else 0.0)
-    frng = make_rng(config, floorplan, 0, 0)
-    blocks = random_blocks(n_blocks, frng)
-    q = frng.uniform(0.1, 2.0, size=n_blocks) * W_PER_MM2
-    q_dyn = area_average(paint(blocks, q), n)
+    q_dyn = floorplan_density(config, floorplan, n_blocks, n)
     q_leak0 = leak_fraction * q_dyn
     if variation:
         cell = die.lx_m / n
