@@ -51,8 +51,9 @@ struct varsim_ctx {
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<long long, double>> times;
   std::vector<const char*> class_names;
-  int* active_dev = nullptr;
-  int* active_host = nullptr;
+  int* active_dev = nullptr;   // [2] device counters of maps still iterating
+  int* active_host = nullptr;  // [2] pinned host copies
+  hipEvent_t active_ev[2] = {nullptr, nullptr};
   // host staging of per-call descriptor arrays (kept alive until the call returns)
   std::vector<MapPtrs> h_maps;
   std::vector<PrepArgs> h_prep;
@@ -285,6 +286,20 @@ PointParams point_params(const varsim_geometry* g, const varsim_options* o) {
   pp.cap = o->dT_cap_K;
   pp.tol = o->tol_K;
   pp.leak = o->leak;
+  // Taylor series of the Kirchhoff inverse in u = u_scale theta:
+  //   (1 + u)^a - 1 = sum_k C(a, k) u^k, a = 1/(1 - eta);  exp(u) - 1 = sum_k u^k / k! (eta = 1).
+  // The FP32 path uses it where the first dropped term is below 1e-9 of the leading one.
+  pp.u_scale = eta == 1.0 ? 1.0 / g->t_amb_K : (1.0 - eta) / g->t_amb_K;
+  double c[kPoly + 1];
+  double ck = 1.0;
+  for (int k = 1; k <= kPoly + 1; ++k) {
+    ck = eta == 1.0 ? ck / k : ck * (pp.inv_1m_eta - (k - 1)) / k;
+    c[k - 1] = ck;
+  }
+  for (int k = 0; k < kPoly; ++k) pp.polyf[k] = (float)c[k];
+  const double lead = std::fabs(c[0]), drop = std::fabs(c[kPoly]);
+  pp.poly_umax = drop > 0.0 ? std::min(0.1, std::pow(1e-9 * lead / drop, 1.0 / kPoly)) : 0.1;
+  if (eta == 0.0) pp.poly_umax = 0.0;
   return pp;
 }
 
@@ -343,8 +358,10 @@ varsim_status varsim_create(int device, varsim_ctx** out) {
   if (hipSetDevice(device) != hipSuccess) return VARSIM_ERR_DEVICE;
   varsim_ctx* c = new varsim_ctx();
   c->device = device;
-  if (hipMalloc(&c->active_dev, sizeof(int)) != hipSuccess ||
-      hipHostMalloc(&c->active_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+  if (hipMalloc(&c->active_dev, 2 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&c->active_host, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->active_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->active_ev[1], hipEventDisableTiming) != hipSuccess) {
     delete c;
     return VARSIM_ERR_NO_MEMORY;
   }
@@ -374,6 +391,8 @@ void varsim_destroy(varsim_ctx* c) {
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   (void)hipFree(c->active_dev);
   (void)hipHostFree(c->active_host);
+  for (hipEvent_t e : c->active_ev)
+    if (e) (void)hipEventDestroy(e);
   (void)hipFree(c->conv_maps);
   delete c;
 }
@@ -592,12 +611,21 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
                     [&] { return launch_row_pass(mode, io, io, a, s); }));
     }
     iters_run = k;
-    if (k >= 2 || k == opts->max_iter) {
-      HIP_TRY(launch_zero_words(ctx->active_dev, sizeof(int), s));
-      HIP_TRY(launch_count_active(base, n, k, opts->tol_K, ctx->active_dev, s));
-      HIP_TRY(hipMemcpyAsync(ctx->active_host, ctx->active_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      if (*ctx->active_host == 0) break;
+    // Convergence is read one iteration late so that the device never idles: the count of
+    // maps still iterating after iteration k is copied to pinned memory behind iteration k,
+    // and the host waits for iteration k-1's count only after launching iteration k.
+    // Launches past a map's convergence return at once (the map is marked finished).
+    if (k >= 1) {
+      const int slot = k & 1;
+      HIP_TRY(launch_zero_words(ctx->active_dev + slot, sizeof(int), s));
+      HIP_TRY(launch_count_active(base, n, k, opts->tol_K, ctx->active_dev + slot, s));
+      HIP_TRY(hipMemcpyAsync(ctx->active_host + slot, ctx->active_dev + slot, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(ctx->active_ev[slot], s));
+    }
+    if (k >= 2) {
+      const int prev = (k - 1) & 1;
+      HIP_TRY(hipEventSynchronize(ctx->active_ev[prev]));
+      if (ctx->active_host[prev] == 0) break;
     }
   }
 

@@ -48,7 +48,13 @@ struct PointParams {
   double tol;         // convergence tolerance, K
   int leak;           // VARSIM_LEAK_*
   int eta_mode;       // 0: eta == 0, 1: eta == 1, 2: general
+  // Taylor coefficients of (1 + u)^(1/(1-eta)) - 1 = sum_k poly[k-1] u^k (k = 1..kPoly), used
+  // by the FP32 path for |u| <= poly_umax, u = (1 - eta) theta / T_amb; 0 disables it.
+  double u_scale;     // u = u_scale * theta: (1 - eta) / T_amb, or 1 / T_amb when eta == 1
+  double poly_umax;
+  float polyf[10];
 };
+constexpr int kPoly = 10;
 
 // Per-map iteration state in the workspace.
 struct IterState {

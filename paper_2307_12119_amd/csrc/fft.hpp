@@ -1,16 +1,21 @@
 // Device building blocks for the real 2-D cosine transforms of the convolution.
 //
-// A length-N complex DFT runs on N/8 threads, each owning 8 elements, as a sequence of
-// Stockham autosort stages of radix 8 (a final radix 4 or 2 when log2 N is not a multiple of
-// 3) through LDS.  LDS holds real and imaginary parts in separate arrays with one pad word
-// every 8 entries so that the strided butterfly stores do not collide in the LDS banks.
+// A length-N complex DFT belongs to one group of TPF = N / E lanes of a single wavefront
+// (E = 8 elements per lane, 16 for N = 1024), so only wavefront-level ordering is needed.
+// Lane t of the group holds element t + TPF m in register slot m.  The transform is a
+// Stockham autosort sequence: the first stage is a radix-E DFT of the lane's own slots (in
+// registers), the middle stages are radix 8 (a final radix 4 or 2 when needed) through an LDS
+// buffer, and the last stage leaves element t + TPF m in slot m again -- the layout the next
+// transform starts from.  LDS keeps real and imaginary parts in separate arrays with one pad
+// word every 8 entries so that the strided butterfly stores spread over the banks.
 //
 // Two real sequences share one complex DFT (one as the real part, one as the imaginary
-// part).  The cosine transforms use the N-point reordering of the sequence (even samples
-// ascending, odd samples descending), after which
-//     DCT-II:  X[p] = Re( e^{-i pi p / 2N} V[p] ),  V = DFT(v)
-//     inverse: V[p] = e^{+i pi p / 2N} (X[p] - i X[N-p]),  v = unnormalised inverse DFT(V)
-// The pair split / merge formulas below combine both identities for the two packed rows.
+// part).  The cosine transforms use the N-point reordering of a sequence (even samples
+// ascending, odd samples descending); with V = DFT(v),
+//     DCT-II:  X[p] = Re( e^{-i pi p / 2N} V[p] )
+//     inverse: V[p] = e^{+i pi p / 2N} (X[p] - i X[N-p]),  v = unnormalised inverse DFT of V.
+// Splitting the two packed spectra needs Z[N-p] next to Z[p]; that partner sits in lane
+// (TPF - t) mod TPF of the group and is fetched with a lane permute.
 #pragma once
 
 #include "common.hpp"
@@ -18,15 +23,57 @@
 namespace vs {
 
 template <int N>
-struct Lds {
-  static constexpr int STRIDE = N + N / 8 + 1;  // odd: consecutive buffers start in other banks
-  __device__ __forceinline__ static int at(int i) { return i + (i >> 3); }
+struct Shape {
+  static constexpr int E = N >= 1024 ? 16 : 8;  // elements per lane
+  static constexpr int TPF = N / E;             // lanes per transform (<= 64)
+  static constexpr int STRIDE = N + N / 8 + 1;  // LDS buffer pitch (odd)
 };
 
-// position of sample i in the reordered sequence
+__device__ __forceinline__ int lds_at(int i) { return i + (i >> 3); }
+
+// sample position of slot k of the reordered sequence (and of its spectrum slot)
+template <int N>
+__device__ __forceinline__ int unperm(int k) {
+  return k < N / 2 ? 2 * k : 2 * N - 1 - 2 * k;
+}
 template <int N>
 __device__ __forceinline__ int perm(int i) {
   return (i & 1) ? (N - 1 - (i >> 1)) : (i >> 1);
+}
+
+// Ordering point for LDS traffic inside one wavefront: no instruction is moved across it and
+// the wavefront's LDS operations before it are visible to its lanes after it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// value of `v` held by lane `src` of the wavefront
+__device__ __forceinline__ float lane_get(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_get(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// out[m] = element N - (t + TPF m) of the group's sequence held in own[] (lane-reversed).
+// PERIODIC: index N means 0 (a DFT); otherwise element N is taken as 0 (a cosine spectrum).
+template <typename T, int N, bool PERIODIC>
+__device__ __forceinline__ void partner(const T* own, T* out, int t) {
+  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
+  const int lane = __lane_id();
+  const int src = (lane & ~(TPF - 1)) + ((TPF - t) & (TPF - 1));
+  const bool head = t == 0;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const T send = head ? own[(E - r) & (E - 1)] : own[E - 1 - r];
+    out[r] = lane_get(send, src);
+  }
+  if (!PERIODIC && head) out[0] = (T)0;
 }
 
 // multiply by DIR * i
@@ -68,6 +115,18 @@ __device__ __forceinline__ void dft4(T* r, T* i) {
   i[3] = d0i - d1i;
 }
 
+// strided radix-4 on elements base, base+s, base+2s, base+3s
+template <typename T, int DIR>
+__device__ __forceinline__ void dft4s(T* r, T* i, int b, int s) {
+  T xr[4] = {r[b], r[b + s], r[b + 2 * s], r[b + 3 * s]}, xi[4] = {i[b], i[b + s], i[b + 2 * s], i[b + 3 * s]};
+  dft4<T, DIR>(xr, xi);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r[b + k * s] = xr[k];
+    i[b + k * s] = xi[k];
+  }
+}
+
 template <typename T, int DIR>
 __device__ __forceinline__ void dft8(T* r, T* i) {
   T er[4] = {r[0], r[2], r[4], r[6]}, ei[4] = {i[0], i[2], i[4], i[6]};
@@ -95,70 +154,126 @@ __device__ __forceinline__ void dft8(T* r, T* i) {
   }
 }
 
-// One Stockham stage of radix R and span NS on the buffer (re, im); thread t of N/8.
-// tw[k] = exp(-2 pi i k / N); the inverse direction uses the conjugates.
-template <typename T, int N, int R, int NS, int DIR>
-__device__ __forceinline__ void stockham_stage(T* re, T* im, const Cx<T>* __restrict__ tw, int t) {
-  constexpr int NB = N / R;
-  constexpr int PER = 8 / R;
-  constexpr int TPF = N / 8;
-  T xr[8], xi[8];
+// radix 16 as 4 x 4: inner DFT-4 over n1 of x[4 n1 + n2], twiddle W16^(n2 k1), outer DFT-4 over n2
+template <typename T, int DIR>
+__device__ __forceinline__ void dft16(T* r, T* i) {
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int b = t + u * TPF;
+  for (int n2 = 0; n2 < 4; ++n2) dft4s<T, DIR>(r, i, n2, 4);  // a[n2 + 4 k1]
+  const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, h = (T)0.70710678118654752440;
+  const T cs[10] = {(T)1, c1, h, s1, (T)0, -s1, -h, -c1, (T)-1, -c1};  // cos(2 pi j / 16), j = 0..9
+  const T sn[10] = {(T)0, s1, h, c1, (T)1, c1, h, s1, (T)0, -s1};      // sin(2 pi j / 16)
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int s = Lds<N>::at(b + r * NB);
-      xr[u * R + r] = re[s];
-      xi[u * R + r] = im[s];
+  for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) {
+      const int j = n2 * k1;
+      const T wr = cs[j], wi = (T)DIR * sn[j];
+      const int e = n2 + 4 * k1;
+      const T a = r[e], b = i[e];
+      r[e] = a * wr - b * wi;
+      i[e] = a * wi + b * wr;
+    }
+  T yr[16], yi[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    T xr[4] = {r[4 * k1], r[4 * k1 + 1], r[4 * k1 + 2], r[4 * k1 + 3]};
+    T xi[4] = {i[4 * k1], i[4 * k1 + 1], i[4 * k1 + 2], i[4 * k1 + 3]};
+    dft4<T, DIR>(xr, xi);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      yr[k1 + 4 * k2] = xr[k2];
+      yi[k1 + 4 * k2] = xi[k2];
     }
   }
-  __syncthreads();
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int b = t + u * TPF;
-    const int j = b & (NS - 1);
-    if constexpr (NS > 1) {
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const Cx<T> w = tw[j * r * (N / (NS * R))];
-        const T wi = DIR < 0 ? w.i : -w.i;
-        const T a = xr[u * R + r], c = xi[u * R + r];
-        xr[u * R + r] = a * w.r - c * wi;
-        xi[u * R + r] = a * wi + c * w.r;
-      }
-    }
-    if constexpr (R == 8) {
-      dft8<T, DIR>(xr + u * R, xi + u * R);
-    } else if constexpr (R == 4) {
-      dft4<T, DIR>(xr + u * R, xi + u * R);
-    } else {
-      dft2<T, DIR>(xr + u * R, xi + u * R);
-    }
-    const int base = (b / NS) * NS * R + j;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int s = Lds<N>::at(base + r * NS);
-      re[s] = xr[u * R + r];
-      im[s] = xi[u * R + r];
-    }
+  for (int k = 0; k < 16; ++k) {
+    r[k] = yr[k];
+    i[k] = yi[k];
   }
-  __syncthreads();
 }
 
-// Full unnormalised DFT (DIR = -1) or inverse DFT (DIR = +1), natural order in and out.
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dft_r(T* r, T* i) {
+  if constexpr (R == 16) dft16<T, DIR>(r, i);
+  else if constexpr (R == 8) dft8<T, DIR>(r, i);
+  else if constexpr (R == 4) dft4<T, DIR>(r, i);
+  else dft2<T, DIR>(r, i);
+}
+
+// Stockham stages of span NS onwards: LDS in, LDS out (middle) or registers out (last).
 template <typename T, int N, int NS, int DIR>
-__device__ __forceinline__ void fft_stages(T* re, T* im, const Cx<T>* __restrict__ tw, int t) {
-  if constexpr (NS < N) {
-    constexpr int R = (N / NS >= 8) ? 8 : (N / NS);
-    stockham_stage<T, N, R, NS, DIR>(re, im, tw, t);
-    fft_stages<T, N, NS * R, DIR>(re, im, tw, t);
+__device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx<T>* __restrict__ tw, int t) {
+  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
+  constexpr int R = (N / NS >= 8) ? 8 : (N / NS);
+  constexpr int NB = N / R, PER = E / R;
+  constexpr bool LAST = NS * R == N;
+  T yr[E], yi[E];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int b = t + TPF * u;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int s = lds_at(b + r * NB);
+      yr[u * R + r] = re[s];
+      yi[u * R + r] = im[s];
+    }
   }
+  wave_sync();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int b = t + TPF * u;
+    const int j = b & (NS - 1);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      const Cx<T> w = tw[j * r * (N / (NS * R))];
+      const T wi = DIR < 0 ? w.i : -w.i;
+      const T a = yr[u * R + r], c = yi[u * R + r];
+      yr[u * R + r] = a * w.r - c * wi;
+      yi[u * R + r] = a * wi + c * w.r;
+    }
+    dft_r<T, R, DIR>(yr + u * R, yi + u * R);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        xr[u + r * PER] = yr[u * R + r];
+        xi[u + r * PER] = yi[u * R + r];
+      }
+    } else {
+      const int base = (b / NS) * NS * R + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int s = lds_at(base + r * NS);
+        re[s] = yr[u * R + r];
+        im[s] = yi[u * R + r];
+      }
+    }
+  }
+  if constexpr (!LAST) {
+    wave_sync();
+    stages_from<T, N, NS * R, DIR>(xr, xi, re, im, tw, t);
+  }
+}
+
+// Unnormalised DFT (DIR = -1) or inverse DFT (DIR = +1) of the group's sequence, slot m of lane
+// t holding element t + TPF m on entry and on exit.  (re, im): this group's LDS buffer; the
+// caller must have finished its own reads of that buffer (wave_sync) before the call.
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void fft_reg(T* xr, T* xi, T* re, T* im, const Cx<T>* __restrict__ tw, int t) {
+  constexpr int E = Shape<N>::E;
+  dft_r<T, E, DIR>(xr, xi);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int s = lds_at(t * E + r);
+    re[s] = xr[r];
+    im[s] = xi[r];
+  }
+  wave_sync();
+  stages_from<T, N, E, DIR>(xr, xi, re, im, tw, t);
 }
 
 // ---------------------------------------------------------------------------------------
-// Pair split after the forward DFT: from Z[p] = (A, B) and Z[N-p] = (C, D) produce the
-// DCT-II values of the two packed sequences at p and N-p.  (c, s) = (cos, sin)(pi p / 2N).
+// Split after the forward DFT: Z[p] = (A, B), Z[N-p] = (C, D) give the DCT-II values of the
+// two packed sequences at p (and at N - p).  (c, s) = (cos, sin)(pi p / 2N).
 template <typename T>
 __device__ __forceinline__ void split_pair(T A, T B, T C, T D, T c, T s, T& xa, T& xb, T& xa2, T& xb2) {
   xa = (T)0.5 * (c * (A + C) + s * (B - D));
@@ -167,14 +282,12 @@ __device__ __forceinline__ void split_pair(T A, T B, T C, T D, T c, T s, T& xa, 
   xb2 = (T)0.5 * (s * (D + B) + c * (A - C));
 }
 
-// Pair merge before the inverse DFT: from the cosine coefficients of two sequences at p
-// and N-p produce Z[p] and Z[N-p] of the packed inverse.
+// Merge before the inverse DFT: cosine coefficients of the two sequences at p and N - p give
+// Z[p] of the packed inverse.
 template <typename T>
-__device__ __forceinline__ void merge_pair(T ya, T yb, T ya2, T yb2, T c, T s, T& zr, T& zi, T& z2r, T& z2i) {
+__device__ __forceinline__ void merge_pair(T ya, T yb, T ya2, T yb2, T c, T s, T& zr, T& zi) {
   zr = c * ya + s * ya2 - (s * yb - c * yb2);
   zi = s * ya - c * ya2 + c * yb + s * yb2;
-  z2r = s * ya2 + c * ya - (c * yb2 - s * yb);
-  z2i = c * ya2 - s * ya + s * yb2 + c * yb;
 }
 
 }  // namespace vs

@@ -21,28 +21,77 @@ namespace {
 
 template <int N>
 struct RowCfg {
-  static constexpr int TPF = N / 8;
+  static constexpr int TPF = Shape<N>::TPF;
   static constexpr int FFTS = (256 / TPF) < (N / 2) ? (256 / TPF) : (N / 2);
   static constexpr int THREADS = FFTS * TPF;
   static constexpr int WAVE = THREADS < 64 ? THREADS : 64;
+  static constexpr int WAVES = THREADS / WAVE;
 };
 
-constexpr int col_count(int n, int esz) {
-  int c = 32;
-  while (c > 2 && (long)c * 2 * (n + n / 8 + 1) * esz > 78000) c /= 2;
+// columns per column-pass workgroup: at most 16, LDS <= 40 KB (two workgroups per CU),
+// <= 512 threads
+constexpr int col_count(int n, int esz, int tpf) {
+  int c = 16;
+  while (c > 2 && ((long)c * (n + n / 8 + 4) * esz > 40000 || (c / 2) * tpf > 512)) c /= 2;
   return c < n ? c : n;
+}
+
+// Workgroups are handed to the 8 XCDs round-robin in launch order; renumber them so that
+// consecutive tiles (neighbouring column strips of one map, which share L2 lines) run on the
+// same XCD.  Identity when the grid is not a multiple of 8.
+__device__ __forceinline__ void xcd_tile(int& strip, int& map) {
+  const int gx = gridDim.x, g = gx * gridDim.y;
+  const int w = blockIdx.x + gx * blockIdx.y;
+  const int l = (g & 7) ? w : (w & 7) * (g >> 3) + (w >> 3);
+  strip = l % gx;
+  map = l / gx;
 }
 
 template <typename Tc, int N>
 struct ColCfg {
-  static constexpr int TPF = N / 8;
-  static constexpr int COLS = col_count(N, (int)sizeof(Tc));
+  static constexpr int TPF = Shape<N>::TPF;
+  static constexpr int COLS = col_count(N, (int)sizeof(Tc), TPF);
   static constexpr int FFTS = COLS / 2;
-  static constexpr int GROUPS = (256 / TPF) < FFTS ? (256 / TPF) : FFTS;
-  static constexpr int THREADS = GROUPS * TPF;
-  static constexpr int ROUNDS = FFTS / GROUPS;
+  static constexpr int THREADS = FFTS * TPF;
   static constexpr int VEC = (int)(16 / sizeof(Tc)) < COLS ? (int)(16 / sizeof(Tc)) : COLS;
+  // staging tile [N][PITCH] in natural row order; the pitch keeps both the row-segment stores
+  // and the strided column reads of a half-wavefront on distinct LDS banks
+  static constexpr int PITCH = sizeof(Tc) == 4 ? COLS + 3 : COLS + 1;
+  static constexpr int TILE = N * PITCH;
+  static constexpr int SCRATCH = FFTS * 2 * Shape<N>::STRIDE;
+  static constexpr int LDS = TILE > SCRATCH ? TILE : SCRATCH;
 };
+
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Vec {
+  T v[V];
+};
+
+// Row values at the sample positions of this lane's slots (slot m <-> reordered index
+// t + TPF m).  Each lane loads the adjacent pair (2k, 2k+1) of its even slot k = t + TPF m;
+// the odd sample 2k+1 belongs to slot E-1-m of the mirror lane TPF-1-t and is swapped over.
+template <typename Tio, typename Tc, int N>
+__device__ __forceinline__ void load_slots(const Tio* __restrict__ row, Tc* out, int t, int mirror) {
+  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
+#pragma unroll
+  for (int m = 0; m < E / 2; ++m) {
+    const Vec<Tio, 2> v = *reinterpret_cast<const Vec<Tio, 2>*>(row + 2 * (t + TPF * m));
+    out[m] = (Tc)v.v[0];
+    out[E - 1 - m] = (Tc)lane_get(v.v[1], mirror);
+  }
+}
+
+template <typename Tio, typename Tc, int N>
+__device__ __forceinline__ void store_slots(Tio* __restrict__ row, const Tc* val, int t, int mirror) {
+  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
+#pragma unroll
+  for (int m = 0; m < E / 2; ++m) {
+    Vec<Tio, 2> v;
+    v.v[0] = (Tio)val[m];
+    v.v[1] = lane_get((Tio)val[E - 1 - m], mirror);
+    *reinterpret_cast<Vec<Tio, 2>*>(row + 2 * (t + TPF * m)) = v;
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ T ldm(const void* p, long i) {
@@ -58,24 +107,34 @@ __device__ __forceinline__ unsigned long long pack_max(float v, long idx) {
   return ((unsigned long long)order_key(v) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)idx);
 }
 
+__device__ __forceinline__ float exp_leak(float x) { return __expf(x); }
+__device__ __forceinline__ double exp_leak(double x) { return exp(x); }
+
 template <typename Tc>
 __device__ __forceinline__ Tc leak_factor(Tc dT, const PointParams& pp) {
-  if (pp.leak == VARSIM_LEAK_EXP) return exp((Tc)pp.beta * dT);
+  if (pp.leak == VARSIM_LEAK_EXP) return exp_leak((Tc)pp.beta * dT);
   if (pp.leak == VARSIM_LEAK_LINEAR) return (Tc)1 + (Tc)pp.beta * dT;
   return (Tc)0;
 }
 
-// dT = Phi^-1(theta) for k = k_ref (T / T_amb)^-eta
+// dT = Phi^-1(theta) for k = k_ref (T / T_amb)^-eta (Kirchhoff inverse).  NaN outside the
+// law's domain (1 + (1 - eta) theta / T_amb <= 0), which the caller reports as runaway.
 template <typename Tc>
-__device__ __forceinline__ Tc kirchhoff_inv(Tc theta, const PointParams& pp, bool& bad) {
+__device__ __forceinline__ Tc kirchhoff_inv(Tc theta, const PointParams& pp) {
   if (pp.eta_mode == 0) return theta;
-  if (pp.eta_mode == 1) return (Tc)pp.t_amb * expm1(theta / (Tc)pp.t_amb);
-  const Tc x = (Tc)pp.c_1m_eta * theta;
-  if (!(x > (Tc)-1)) {
-    bad = true;
-    return (Tc)0;
+  const Tc u = (Tc)pp.u_scale * theta;
+  if constexpr (sizeof(Tc) == 4) {
+    // FP32: Horner form of the Taylor series of (1 + u)^a - 1 (exp(u) - 1 for eta = 1)
+    if (fabsf(u) <= (float)pp.poly_umax) {
+      float acc = pp.polyf[kPoly - 1];
+#pragma unroll
+      for (int k = kPoly - 2; k >= 0; --k) acc = fmaf(acc, u, pp.polyf[k]);
+      return (float)pp.t_amb * u * acc;
+    }
   }
-  return (Tc)pp.t_amb * expm1((Tc)pp.inv_1m_eta * log1p(x));
+  if (pp.eta_mode == 1) return (Tc)pp.t_amb * expm1(u);
+  if (!(u > (Tc)-1)) return (Tc)NAN;
+  return (Tc)pp.t_amb * expm1((Tc)pp.inv_1m_eta * log1p(u));
 }
 
 template <int W>
@@ -106,14 +165,94 @@ __device__ __forceinline__ bool finished_before(const IterState& st, int map, in
   return prev <= tol;
 }
 
+// Per-lane running statistics of the new iterate.
+template <typename Tc>
+struct LaneStats {
+  Tc inc = (Tc)0;       // max |dT_new - dT_old|
+  Tc sum = (Tc)0;       // sum of dT_new (NaN / inf propagate: runaway detection)
+  Tc xmax = (Tc)-INFINITY;
+  int imax = 0x7fffffff;
+  __device__ __forceinline__ void add(Tc x, Tc old, int idx) {
+    inc = fmax(inc, fabs(x - old));
+    sum += x;
+    if (x > xmax || (x == xmax && idx < imax)) {
+      xmax = x;
+      imax = idx;
+    }
+  }
+};
+
+// one map's pointwise update of one row: theta slots -> dT (stored) -> total power slots
+template <typename Tio, typename Tc, int N, int MODE>
+__device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off, int t, int mirror, bool zero_old,
+                                              const PointParams& pp, LaneStats<Tc>& ls) {
+  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
+  Tc x[E];
+  if constexpr (MODE == ROW_HEAD) {
+    if (zero_old) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) x[m] = (Tc)0;
+    } else {
+      load_slots<Tio, Tc, N>((const Tio*)mp.dT + off, x, t, mirror);
+    }
+  } else {
+    Tc old[E];
+    if (mp.minv) {
+      Tc mv[E];
+      load_slots<Tio, Tc, N>((const Tio*)mp.minv + off, mv, t, mirror);
+#pragma unroll
+      for (int m = 0; m < E; ++m) z[m] *= mv[m];
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) x[m] = kirchhoff_inv<Tc>(z[m], pp);
+    if (zero_old) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) old[m] = (Tc)0;
+    } else {
+      load_slots<Tio, Tc, N>((const Tio*)mp.dT + off, old, t, mirror);
+    }
+    if constexpr (MODE == ROW_RESID) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        ls.inc = fmax(ls.inc, fabs(x[m] - old[m]));
+        ls.sum += x[m];
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        x[m] = (Tc)(Tio)x[m];  // the iterate as stored
+        ls.add(x[m], old[m], (int)off + unperm<N>(t + TPF * m));
+      }
+      store_slots<Tio, Tc, N>((Tio*)mp.dT + off, x, t, mirror);
+    }
+  }
+  if constexpr (MODE == ROW_HEAD || MODE == ROW_MERGED) {
+    Tc q[E];
+    load_slots<Tio, Tc, N>((const Tio*)mp.qd + off, q, t, mirror);
+    if (mp.ql) {
+      Tc ql[E];
+      load_slots<Tio, Tc, N>((const Tio*)mp.ql + off, ql, t, mirror);
+#pragma unroll
+      for (int m = 0; m < E; ++m) q[m] += ql[m] * leak_factor<Tc>(x[m], pp);
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) z[m] = (Tc)pp.hxhy * q[m];
+  }
+}
+
 template <typename Tio, typename Tc, int N, int MODE>
 __global__ void __launch_bounds__(RowCfg<N>::THREADS)
     row_pass_kernel(PassArgs a, const Cx<Tc>* __restrict__ tw, const Cx<Tc>* __restrict__ qw) {
   using Cfg = RowCfg<N>;
   constexpr int TPF = Cfg::TPF;
-  constexpr int ST = Lds<N>::STRIDE;
+  constexpr int E = Shape<N>::E;
+  constexpr int ST = Shape<N>::STRIDE;
+  constexpr bool INV = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_CONV_TAIL;
+  constexpr bool FWD = MODE == ROW_HEAD || MODE == ROW_MERGED || MODE == ROW_CONV_HEAD;
+  constexpr bool STATS = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID;
   __shared__ Tc s_re[Cfg::FFTS * ST];
   __shared__ Tc s_im[Cfg::FFTS * ST];
+  __shared__ double s_red[3][Cfg::WAVES];
 
   const int map = blockIdx.y;
   unsigned flags = 0u;
@@ -123,144 +262,110 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
     if ((MODE == ROW_MERGED || MODE == ROW_LAST) && finished_before(a.st, map, a.iter, a.pp.tol)) return;
   }
   const MapPtrs mp = a.maps[map];
-  const int f = threadIdx.x / TPF, t = threadIdx.x % TPF;
+  int f = threadIdx.x / TPF;
+  if constexpr (TPF == 64) f = __builtin_amdgcn_readfirstlane(f);
+  const int t = threadIdx.x % TPF;
+  const int mirror = (__lane_id() & ~(TPF - 1)) + (TPF - 1 - t);
   const int row = (blockIdx.x * Cfg::FFTS + f) * 2;
   Tc* re = s_re + f * ST;
   Tc* im = s_im + f * ST;
-  Tc* S = (Tc*)(a.use_s64 ? mp.S64 : mp.S);
+  Tc* const Sa = (Tc*)(a.use_s64 ? mp.S64 : mp.S) + (long)row * N;
+  Tc* const Sb = Sa + N;
   const long oa = (long)row * N, ob = oa + N;
   const PointParams& pp = a.pp;
-  const Tc sqrt2 = (Tc)1.4142135623730950488016887242097;
-  const Tc half_sqrt2 = (Tc)0.70710678118654752440084436210485;
+
+  // slot m of this lane holds spectrum index / reordered sample t + TPF m
+  Tc zr[E], zi[E];
 
   // ---- inverse half: spectrum rows -> theta (row DCT-III of the packed pair)
-  if constexpr (MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_CONV_TAIL) {
+  if constexpr (INV) {
+    Tc xa[E], xb[E], xa2[E], xb2[E];
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int p = t + s4 * TPF;
-      if (p == 0) {
-        re[Lds<N>::at(0)] = S[oa];
-        im[Lds<N>::at(0)] = S[ob];
-        re[Lds<N>::at(N / 2)] = sqrt2 * S[oa + N / 2];
-        im[Lds<N>::at(N / 2)] = sqrt2 * S[ob + N / 2];
-      } else {
-        const Cx<Tc> q = qw[p];
-        Tc zr, zi, z2r, z2i;
-        merge_pair<Tc>(S[oa + p], S[ob + p], S[oa + N - p], S[ob + N - p], q.r, q.i, zr, zi, z2r, z2i);
-        re[Lds<N>::at(p)] = zr;
-        im[Lds<N>::at(p)] = zi;
-        re[Lds<N>::at(N - p)] = z2r;
-        im[Lds<N>::at(N - p)] = z2i;
-      }
+    for (int m = 0; m < E; ++m) {
+      xa[m] = Sa[t + TPF * m];
+      xb[m] = Sb[t + TPF * m];
     }
-    __syncthreads();
-    fft_stages<Tc, N, 1, +1>(re, im, tw, t);
+    partner<Tc, N, false>(xa, xa2, t);
+    partner<Tc, N, false>(xb, xb2, t);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const Cx<Tc> q = qw[t + TPF * m];
+      merge_pair<Tc>(xa[m], xb[m], xa2[m], xb2[m], q.r, q.i, zr[m], zi[m]);
+    }
+    fft_reg<Tc, N, +1>(zr, zi, re, im, tw, t);
   }
 
   // ---- pointwise: conductivity factor, Kirchhoff inverse, increment, stats, new power
-  double inc = 0.0, sum = 0.0;
-  unsigned long long best = 0ull;
-  bool bad = false;
+  LaneStats<Tc> ls;
   const bool zero_old = (a.iter == 1) && (a.zero_start || (flags & kFlagWarmRejected));
-#pragma unroll
-  for (int s8 = 0; s8 < 8; ++s8) {
-    const int i = t + s8 * TPF;
-    const int li = Lds<N>::at(perm<N>(i));
-    if constexpr (MODE == ROW_CONV_TAIL) {
-      ((Tio*)mp.dT)[oa + i] = (Tio)re[li];
-      ((Tio*)mp.dT)[ob + i] = (Tio)im[li];
-      continue;
-    } else if constexpr (MODE == ROW_CONV_HEAD) {
-      re[li] = (Tc)ldm<Tio>(mp.qd, oa + i);
-      im[li] = (Tc)ldm<Tio>(mp.qd, ob + i);
-      continue;
-    } else {
-      Tc xa, xb;
-      if constexpr (MODE == ROW_HEAD) {
-        if (zero_old) {
-          xa = (Tc)0;
-          xb = (Tc)0;
-        } else {
-          xa = (Tc)ldm<Tio>(mp.dT, oa + i);
-          xb = (Tc)ldm<Tio>(mp.dT, ob + i);
-        }
-      } else {
-        Tc ta = re[li], tb = im[li];
-        if (mp.minv) {
-          ta *= (Tc)ldm<Tio>(mp.minv, oa + i);
-          tb *= (Tc)ldm<Tio>(mp.minv, ob + i);
-        }
-        xa = kirchhoff_inv<Tc>(ta, pp, bad);
-        xb = kirchhoff_inv<Tc>(tb, pp, bad);
-        const Tc olda = zero_old ? (Tc)0 : (Tc)ldm<Tio>(mp.dT, oa + i);
-        const Tc oldb = zero_old ? (Tc)0 : (Tc)ldm<Tio>(mp.dT, ob + i);
-        const Tc da = xa - olda, db = xb - oldb;
-        inc = fmax(inc, (double)fmax(fabs(da), fabs(db)));
-        if (!isfinite(xa) || !isfinite(xb) || xa > (Tc)pp.cap || xb > (Tc)pp.cap) bad = true;
-        if constexpr (MODE != ROW_RESID) {
-          const Tio sa = (Tio)xa, sb = (Tio)xb;
-          ((Tio*)mp.dT)[oa + i] = sa;
-          ((Tio*)mp.dT)[ob + i] = sb;
-          sum += (double)sa + (double)sb;
-          const unsigned long long ka = pack_max((float)sa, oa + i), kb = pack_max((float)sb, ob + i);
-          best = ka > best ? ka : best;
-          best = kb > best ? kb : best;
-        }
-      }
-      if constexpr (MODE == ROW_HEAD || MODE == ROW_MERGED) {
-        Tc qa = (Tc)ldm<Tio>(mp.qd, oa + i), qb = (Tc)ldm<Tio>(mp.qd, ob + i);
-        if (mp.ql) {
-          qa += (Tc)ldm<Tio>(mp.ql, oa + i) * leak_factor<Tc>(xa, pp);
-          qb += (Tc)ldm<Tio>(mp.ql, ob + i) * leak_factor<Tc>(xb, pp);
-        }
-        re[li] = (Tc)pp.hxhy * qa;
-        im[li] = (Tc)pp.hxhy * qb;
-      }
-    }
+  if constexpr (MODE == ROW_CONV_TAIL) {
+    store_slots<Tio, Tc, N>((Tio*)mp.dT + oa, zr, t, mirror);
+    store_slots<Tio, Tc, N>((Tio*)mp.dT + ob, zi, t, mirror);
+  } else if constexpr (MODE == ROW_CONV_HEAD) {
+    load_slots<Tio, Tc, N>((const Tio*)mp.qd + oa, zr, t, mirror);
+    load_slots<Tio, Tc, N>((const Tio*)mp.qd + ob, zi, t, mirror);
+  } else {
+    row_pointwise<Tio, Tc, N, MODE>(zr, mp, oa, t, mirror, zero_old, pp, ls);
+    row_pointwise<Tio, Tc, N, MODE>(zi, mp, ob, t, mirror, zero_old, pp, ls);
   }
 
-  if constexpr (MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID) {
+  if constexpr (STATS) {
     constexpr int W = Cfg::WAVE;
-    inc = wave_max<W>(inc);
-    const bool lane0 = (threadIdx.x % W) == 0;
+    const int wave = threadIdx.x / W;
+    const bool bad = !(ls.xmax <= (Tc)pp.cap) || !isfinite(ls.sum);
+    double inc = wave_max<W>((double)ls.inc);
     const unsigned bad_any = __any(bad);
-    if (MODE == ROW_RESID) {
-      if (lane0) atomicMax(&a.st.resid64[map], (unsigned long long)__double_as_longlong(inc));
-    } else {
-      sum = wave_sum<W>(sum);
+    double sum = 0.0;
+    unsigned long long best = 0ull;
+    if (MODE != ROW_RESID) {
+      sum = wave_sum<W>((double)ls.sum);
+      best = ls.imax == 0x7fffffff ? 0ull : pack_max((float)ls.xmax, ls.imax);
       best = wave_max_u64<W>(best);
-      if (lane0) {
+    }
+    if ((threadIdx.x % W) == 0) {
+      s_red[0][wave] = bad_any ? (double)NAN : inc;
+      s_red[1][wave] = sum;
+      s_red[2][wave] = __longlong_as_double((long long)best);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double i0 = s_red[0][0], s0 = s_red[1][0];
+      unsigned long long b0 = (unsigned long long)__double_as_longlong(s_red[2][0]);
+      bool any_bad = isnan(i0);
+      for (int w = 1; w < Cfg::WAVES; ++w) {
+        any_bad = any_bad || isnan(s_red[0][w]);
+        i0 = fmax(i0, s_red[0][w]);
+        s0 += s_red[1][w];
+        const unsigned long long bw = (unsigned long long)__double_as_longlong(s_red[2][w]);
+        b0 = bw > b0 ? bw : b0;
+      }
+      if (MODE == ROW_RESID) {
+        atomicMax(&a.st.resid64[map], (unsigned long long)__double_as_longlong(any_bad ? (double)INFINITY : i0));
+      } else {
         const long slot = (long)map * a.st.stride + a.iter;
-        atomicMax(&a.st.resid[slot], (unsigned long long)__double_as_longlong(inc));
-        atomicAdd(&a.st.sum[slot], sum);
-        atomicMax(&a.st.maxpack[slot], best);
+        atomicMax(&a.st.resid[slot], (unsigned long long)__double_as_longlong(any_bad ? (double)INFINITY : i0));
+        atomicAdd(&a.st.sum[slot], s0);
+        atomicMax(&a.st.maxpack[slot], b0);
+        if (any_bad) atomicOr(&a.st.flags[map], kFlagRunaway);
       }
     }
-    if (lane0 && bad_any) atomicOr(&a.st.flags[map], kFlagRunaway);
   }
 
   // ---- forward half: P rows -> row DCT-II spectrum
-  if constexpr (MODE == ROW_HEAD || MODE == ROW_MERGED || MODE == ROW_CONV_HEAD) {
-    __syncthreads();
-    fft_stages<Tc, N, 1, -1>(re, im, tw, t);
+  if constexpr (FWD) {
+    wave_sync();
+    fft_reg<Tc, N, -1>(zr, zi, re, im, tw, t);
+    Tc pr[E], pim[E];
+    partner<Tc, N, true>(zr, pr, t);
+    partner<Tc, N, true>(zi, pim, t);
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int p = t + s4 * TPF;
-      if (p == 0) {
-        S[oa] = re[Lds<N>::at(0)];
-        S[ob] = im[Lds<N>::at(0)];
-        S[oa + N / 2] = half_sqrt2 * re[Lds<N>::at(N / 2)];
-        S[ob + N / 2] = half_sqrt2 * im[Lds<N>::at(N / 2)];
-      } else {
-        const Cx<Tc> q = qw[p];
-        Tc xa, xb, xa2, xb2;
-        split_pair<Tc>(re[Lds<N>::at(p)], im[Lds<N>::at(p)], re[Lds<N>::at(N - p)], im[Lds<N>::at(N - p)], q.r, q.i,
-                       xa, xb, xa2, xb2);
-        S[oa + p] = xa;
-        S[ob + p] = xb;
-        S[oa + N - p] = xa2;
-        S[ob + N - p] = xb2;
-      }
+    for (int m = 0; m < E; ++m) {
+      const int p = t + TPF * m;
+      const Cx<Tc> q = qw[p];
+      Tc xa, xb, xa2, xb2;
+      split_pair<Tc>(zr[m], zi[m], pr[m], pim[m], q.r, q.i, xa, xb, xa2, xb2);
+      Sa[p] = xa;
+      Sb[p] = xb;
     }
   }
 }
@@ -271,82 +376,79 @@ __global__ void __launch_bounds__((ColCfg<Tc, N>::THREADS))
                     const Cx<Tc>* __restrict__ qw) {
   using Cfg = ColCfg<Tc, N>;
   constexpr int TPF = Cfg::TPF;
-  constexpr int ST = Lds<N>::STRIDE;
+  constexpr int E = Shape<N>::E;
+  constexpr int ST = Shape<N>::STRIDE;
   constexpr int VEC = Cfg::VEC;
   constexpr int VPR = Cfg::COLS / VEC;
-  __shared__ Tc s_re[Cfg::FFTS * ST];
-  __shared__ Tc s_im[Cfg::FFTS * ST];
+  constexpr int P = Cfg::PITCH;
+  // one LDS block: first the staging tile, then (after a barrier) the transform scratch
+  __shared__ Tc lds[Cfg::LDS];
 
-  const int map = blockIdx.y;
+  int strip, map;
+  xcd_tile(strip, map);
   if (a.iter >= 0) {  // iter < 0: plain convolution, no solver state
     if (a.st.flags[map] & kFlagSkip) return;
     if (!a.resid_pass && finished_before(a.st, map, a.iter, a.pp.tol)) return;
   }
   const MapPtrs mp = a.maps[map];
   Tc* S = (Tc*)(a.use_s64 ? mp.S64 : mp.S);
-  const int c0 = blockIdx.x * Cfg::COLS;
+  const int c0 = strip * Cfg::COLS;
 
   for (int it = threadIdx.x; it < N * VPR; it += Cfg::THREADS) {
     const int y = it / VPR, j = it % VPR;
-    const Tc* src = S + (long)y * N + c0 + j * VEC;
-    Tc v[VEC];
+    const Vec<Tc, VEC> v = *reinterpret_cast<const Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC);
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) v[e] = src[e];
-    const int li = Lds<N>::at(perm<N>(y));
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      const int col = j * VEC + e;
-      ((col & 1) ? s_im : s_re)[(col >> 1) * ST + li] = v[e];
-    }
+    for (int e = 0; e < VEC; ++e) lds[y * P + j * VEC + e] = v.v[e];
   }
   __syncthreads();
 
-  const int g = threadIdx.x / TPF, t = threadIdx.x % TPF;
-  for (int rd = 0; rd < Cfg::ROUNDS; ++rd) {
-    const int fi = rd * Cfg::GROUPS + g;
-    Tc* re = s_re + fi * ST;
-    Tc* im = s_im + fi * ST;
-    fft_stages<Tc, N, 1, -1>(re, im, tw, t);
-    const Tc* la = lamT + (long)(c0 + 2 * fi) * N;
-    const Tc* lb = la + N;
+  // column pair (2f, 2f+1) -> one complex sequence in reordered slots
+  int f = threadIdx.x / TPF;
+  if constexpr (TPF == 64) f = __builtin_amdgcn_readfirstlane(f);
+  const int t = threadIdx.x % TPF;
+  Tc zr[E], zi[E];
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int p = t + s4 * TPF;
-      if (p == 0) {
-        re[Lds<N>::at(0)] *= la[0];
-        im[Lds<N>::at(0)] *= lb[0];
-        re[Lds<N>::at(N / 2)] *= la[N / 2];
-        im[Lds<N>::at(N / 2)] *= lb[N / 2];
-      } else {
-        const Cx<Tc> q = qw[p];
-        const int lp = Lds<N>::at(p), lq = Lds<N>::at(N - p);
-        Tc xa, xb, xa2, xb2;
-        split_pair<Tc>(re[lp], im[lp], re[lq], im[lq], q.r, q.i, xa, xb, xa2, xb2);
-        xa *= la[p];
-        xb *= lb[p];
-        xa2 *= la[N - p];
-        xb2 *= lb[N - p];
-        Tc zr, zi, z2r, z2i;
-        merge_pair<Tc>(xa, xb, xa2, xb2, q.r, q.i, zr, zi, z2r, z2i);
-        re[lp] = zr;
-        im[lp] = zi;
-        re[lq] = z2r;
-        im[lq] = z2i;
-      }
-    }
-    __syncthreads();
-    fft_stages<Tc, N, 1, +1>(re, im, tw, t);
+  for (int m = 0; m < E; ++m) {
+    const int y = unperm<N>(t + TPF * m);
+    zr[m] = lds[y * P + 2 * f];
+    zi[m] = lds[y * P + 2 * f + 1];
   }
+  __syncthreads();
+
+  Tc* re = lds + f * 2 * ST;
+  Tc* im = re + ST;
+  fft_reg<Tc, N, -1>(zr, zi, re, im, tw, t);
+  Tc pr[E], pim[E];
+  partner<Tc, N, true>(zr, pr, t);
+  partner<Tc, N, true>(zi, pim, t);
+  const Tc* la = lamT + (long)(c0 + 2 * f) * N;
+  const Tc* lb = la + N;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int p = t + TPF * m, p2 = (N - p) & (N - 1);
+    const Cx<Tc> q = qw[p];
+    Tc xa, xb, xa2, xb2;
+    split_pair<Tc>(zr[m], zi[m], pr[m], pim[m], q.r, q.i, xa, xb, xa2, xb2);
+    merge_pair<Tc>(xa * la[p], xb * lb[p], xa2 * la[p2], xb2 * lb[p2], q.r, q.i, zr[m], zi[m]);
+  }
+  wave_sync();
+  fft_reg<Tc, N, +1>(zr, zi, re, im, tw, t);
+  __syncthreads();
+
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int y = unperm<N>(t + TPF * m);
+    lds[y * P + 2 * f] = zr[m];
+    lds[y * P + 2 * f + 1] = zi[m];
+  }
+  __syncthreads();
 
   for (int it = threadIdx.x; it < N * VPR; it += Cfg::THREADS) {
     const int y = it / VPR, j = it % VPR;
-    Tc* dst = S + (long)y * N + c0 + j * VEC;
-    const int li = Lds<N>::at(perm<N>(y));
+    Vec<Tc, VEC> v;
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      const int col = j * VEC + e;
-      dst[e] = ((col & 1) ? s_im : s_re)[(col >> 1) * ST + li];
-    }
+    for (int e = 0; e < VEC; ++e) v.v[e] = lds[y * P + j * VEC + e];
+    *reinterpret_cast<Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC) = v;
   }
 }
 

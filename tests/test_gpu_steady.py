@@ -72,6 +72,49 @@ def test_conv_matches_direct_sum(ctx, n):
     assert np.max(np.abs(buf.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("n", [512, 1024])
+def test_conv_large_sampled_cells(ctx, n):
+    """Full-size convolution checked against the direct image sum at sampled cells."""
+    import torch
+
+    rng = np.random.default_rng(n + 1)
+    die = W.Die()
+    g = S.Geometry(die.lx_m, die.ly_m, n, n, die.t_m, die.k0, 0.0, die.t_amb)
+    op = S.DirectSum(g)
+    p = rng.uniform(0.0, 1.0, (n, n)) * g.hx * g.hy * 1e6
+    rows = np.concatenate([[0, 0, n - 1, n - 1, n // 2], rng.integers(0, n, 40)])
+    cols = np.concatenate([[0, n - 1, 0, n - 1, n // 2], rng.integers(0, n, 40)])
+    ref = op.apply_at(p, rows, cols)
+    vdie = die_of(W.uniform_problem(n, 1.0))
+    got64 = ctx.conv(vdie, to_dev(p, torch.float64)).cpu().numpy()[rows, cols]
+    assert np.max(np.abs(got64 - ref)) <= 1e-12 * np.max(np.abs(ref))
+    got32 = ctx.conv(vdie, to_dev(p, torch.float32)).cpu().numpy()[rows, cols]
+    assert np.max(np.abs(got32 - ref)) <= 2e-6 * np.max(np.abs(ref))
+
+
+def test_full_size_1024_fixed_point_sampled(ctx):
+    """1024 x 1024 FP32 solve: the oracle's fixed-point map, evaluated at sampled cells on the
+    GPU result, reproduces it (contraction: error to the fixed point <= residual / (1 - rho))."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    inp = W.config3(3, 0)
+    item = gpu_item(inp, torch.float32)
+    st = ctx.solve_steady(item, _opts(V.F32, inp, 50, 1e-4, res=True))
+    assert st["status"] == V.OK
+    got = item["dT_out"].cpu().numpy().astype(np.float64)
+    prob, opts = S.problem_from_inputs(inp)
+    rng = np.random.default_rng(5)
+    hot = np.unravel_index(int(np.argmax(got)), got.shape)
+    rows = np.concatenate([[0, 1023, hot[0]], rng.integers(0, 1024, 30)])
+    cols = np.concatenate([[0, 1023, hot[1]], rng.integers(0, 1024, 30)])
+    theta = prob.op.apply_at(prob.power(got, opts), rows, cols) / prob.m[rows, cols]
+    again, ok = S.kirchhoff_inverse(theta, prob.geom.t_amb, prob.geom.eta)
+    assert np.all(ok)
+    assert np.max(np.abs(again - got[rows, cols])) <= 2e-3
+    assert st["residual_f64_K"] <= 2e-3
+
+
 # ----------------------------------------------------------------------------- steady FP64
 @pytest.mark.parametrize("iters", [1, 2, 3])
 def test_fp64_iterates_match_oracle(ctx, iters):
