@@ -71,6 +71,23 @@ def algorithmic_bytes(n: int) -> dict:
     }
 
 
+def measured_traffic(kernel: str, n: int, batch: int):
+    """HBM bytes per map-pass of `kernel` from the committed rocprofv3 counter record, if the
+    record's kernel sources are still the current ones (else None)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"steady_{n}x{n}_batch{batch}_{kernel}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_map_pass"]
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +190,8 @@ def main() -> int:
                          "total_ms": v["total_ms"], "GB/s": b / (v["total_ms"] * 1e-3) / 1e9 if v["total_ms"] else None}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dom_bytes_per_launch = per_map[dom] * passes[dom] / kernels[dom]["launches"]
+    per_pass = measured_traffic(dom, args.n, args.batch)
+    traffic = None if per_pass is None else int(per_pass * passes[dom] / kernels[dom]["launches"])
     achieved = kernels[dom]["GB/s"]
     total_alg = sum(per_map[k] * passes[k] for k in kernels)
     resid = [s["residual_f64_K"] for s in stats]
@@ -194,7 +213,7 @@ def main() -> int:
                                "Monte Carlo samples, tol 1e-3 K, FP64 residual per map",
                    "n": args.n, "batch": args.batch, "tol_K": 1e-3, "precision": "f32"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": int(dom_bytes_per_launch), "avg_launch_ms": kernels[dom]["avg_ms"]},
         "solve": {"iterations_mean": float(it.mean()), "iterations_max": int(it.max()), "statuses": statuses,
                   "residual_f64_max_K": float(np.max(resid)),

@@ -23,6 +23,8 @@ struct TableEntry {
   double* kper = nullptr;
   double* lam64T = nullptr;
   float* lam32T = nullptr;
+  double* coef64 = nullptr;
+  float* coef32 = nullptr;
 };
 
 struct TwEntry {
@@ -194,14 +196,19 @@ varsim_status get_table(varsim_ctx* ctx, const varsim_geometry* g, hipStream_t s
   if (fresh) {
     if (hipMalloc(&e.kper, (size_t)(sp.nx + 1) * (sp.ny + 1) * sizeof(double)) != hipSuccess ||
         hipMalloc(&e.lam64T, (size_t)sp.nx * sp.ny * sizeof(double)) != hipSuccess ||
-        hipMalloc(&e.lam32T, (size_t)sp.nx * sp.ny * sizeof(float)) != hipSuccess)
+        hipMalloc(&e.lam32T, (size_t)sp.nx * sp.ny * sizeof(float)) != hipSuccess ||
+        hipMalloc(&e.coef64, coef_entries(sp.nx, sp.ny) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&e.coef32, coef_entries(sp.nx, sp.ny) * sizeof(float)) != hipSuccess)
       return fail(ctx, VARSIM_ERR_NO_MEMORY, "table allocation failed");
   }
   double* scratch = nullptr;
   if (hipMalloc(&scratch, green_table_scratch_doubles(sp.nx, sp.ny) * sizeof(double)) != hipSuccess)
     return fail(ctx, VARSIM_ERR_NO_MEMORY, "table scratch allocation failed");
   hipError_t err = timed(ctx, "green_table", s,
-                         [&] { return launch_green_table(sp, e.kper, e.lam64T, e.lam32T, lam_rowmajor, scratch, s); });
+                         [&] {
+                           return launch_green_table(sp, e.kper, e.lam64T, e.lam32T, e.coef64, e.coef32, lam_rowmajor,
+                                                     scratch, s);
+                         });
   hipError_t err2 = hipStreamSynchronize(s);
   (void)hipFree(scratch);
   if (err != hipSuccess || err2 != hipSuccess)
@@ -377,6 +384,8 @@ void varsim_destroy(varsim_ctx* c) {
     (void)hipFree(kv.second.kper);
     (void)hipFree(kv.second.lam64T);
     (void)hipFree(kv.second.lam32T);
+    (void)hipFree(kv.second.coef64);
+    (void)hipFree(kv.second.coef32);
   }
   for (auto& kv : c->twiddles) {
     (void)hipFree(kv.second.tw64);
@@ -467,7 +476,7 @@ varsim_status varsim_conv(varsim_ctx* ctx, const varsim_geometry* geom, int32_t 
   a.iter = -1;
   HIP_TRY(timed(ctx, "row_conv_head", s, [&] { return launch_row_pass(ROW_CONV_HEAD, precision, precision, a, s); }));
   HIP_TRY(timed(ctx, "col", s, [&] {
-    return launch_col_pass(precision, a, precision == VARSIM_F32 ? (const void*)tab.lam32T : (const void*)tab.lam64T, s);
+    return launch_col_pass(precision, a, precision == VARSIM_F32 ? (const void*)tab.coef32 : (const void*)tab.coef64, s);
   }));
   HIP_TRY(timed(ctx, "row_conv_tail", s, [&] { return launch_row_pass(ROW_CONV_TAIL, precision, precision, a, s); }));
   HIP_TRY(hipStreamSynchronize(s));
@@ -604,7 +613,7 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
       bool all_zero = true;
       for (int i = g.first; i < g.first + g.count; ++i) all_zero = all_zero && !sorted[i]->dT_init;
       a.zero_start = all_zero ? 1 : 0;
-      const void* lam = io == VARSIM_F32 ? (const void*)g.table.lam32T : (const void*)g.table.lam64T;
+      const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
       HIP_TRY(timed(ctx, "col", s, [&] { return launch_col_pass(io, a, lam, s); }));
       const int mode = k < opts->max_iter ? ROW_MERGED : ROW_LAST;
       HIP_TRY(timed(ctx, mode == ROW_MERGED ? "row_merged" : "row_last", s,
@@ -635,7 +644,7 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
       a.resid_pass = 1;
       a.use_s64 = io == VARSIM_F32 ? 1 : 0;
       HIP_TRY(timed(ctx, "resid_head", s, [&] { return launch_row_pass(ROW_HEAD, io, VARSIM_F64, a, s); }));
-      HIP_TRY(timed(ctx, "resid_col", s, [&] { return launch_col_pass(VARSIM_F64, a, g.table.lam64T, s); }));
+      HIP_TRY(timed(ctx, "resid_col", s, [&] { return launch_col_pass(VARSIM_F64, a, g.table.coef64, s); }));
       HIP_TRY(timed(ctx, "resid_tail", s, [&] { return launch_row_pass(ROW_RESID, io, VARSIM_F64, a, s); }));
     }
   }

@@ -10,10 +10,12 @@ struct TableSpec {
   double lx, ly, t, k_ref;
 };
 
-// Green's-function table: K_per [ny+1][nx+1], lambda transposed and scaled (FP64, FP32), and
-// optionally lambda row-major unscaled.  scratch: green_table_scratch_doubles(nx, ny) doubles.
-hipError_t launch_green_table(const TableSpec& sp, double* kper, double* lam64T, float* lam32T, double* lam_rowmajor,
-                              double* scratch, hipStream_t stream);
+// Green's-function table: K_per [ny+1][nx+1], lambda transposed and scaled (FP64, FP32), the
+// column-pass coefficients [nx][ny/2+1][4] (FP64, FP32), and optionally lambda row-major
+// unscaled.  scratch: green_table_scratch_doubles(nx, ny) doubles.
+hipError_t launch_green_table(const TableSpec& sp, double* kper, double* lam64T, float* lam32T, double* coef64,
+                              float* coef32, double* lam_rowmajor, double* scratch, hipStream_t stream);
+inline size_t coef_entries(int nx, int ny) { return (size_t)nx * (ny / 2 + 1) * 4; }
 size_t green_table_scratch_doubles(int nx, int ny);
 
 hipError_t launch_twiddles(int n, Cx<double>* tw64, Cx<float>* tw32, Cx<double>* qw64, Cx<float>* qw32,
@@ -51,7 +53,8 @@ struct PassArgs {
 
 // io: element type of the maps (VARSIM_F32 / VARSIM_F64); compute: type of the transforms.
 hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hipStream_t stream);
-hipError_t launch_col_pass(int compute, const PassArgs& a, const void* lamT, hipStream_t stream);
+// coef: the column-pass coefficient table of the compute type
+hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream);
 
 // Static inputs: QL = q_leak0 * v, MINV = 1 / m (per map), warm-start screening and copy.
 struct PrepArgs {

@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
 
 template <typename Tc, int N>
 __global__ void __launch_bounds__((ColCfg<Tc, N>::THREADS))
-    col_pass_kernel(PassArgs a, const Tc* __restrict__ lamT, const Cx<Tc>* __restrict__ tw,
+    col_pass_kernel(PassArgs a, const Tc* __restrict__ coef, const Cx<Tc>* __restrict__ tw,
                     const Cx<Tc>* __restrict__ qw) {
   using Cfg = ColCfg<Tc, N>;
   constexpr int TPF = Cfg::TPF;
@@ -421,15 +421,19 @@ __global__ void __launch_bounds__((ColCfg<Tc, N>::THREADS))
   Tc pr[E], pim[E];
   partner<Tc, N, true>(zr, pr, t);
   partner<Tc, N, true>(zi, pim, t);
-  const Tc* la = lamT + (long)(c0 + 2 * f) * N;
-  const Tc* lb = la + N;
+  // split, multiply by lambda and merge in one step (coefficients alpha, beta, gamma per column)
+  const Vec<Tc, 4>* ca = reinterpret_cast<const Vec<Tc, 4>*>(coef) + (long)(c0 + 2 * f) * (N / 2 + 1);
+  const Vec<Tc, 4>* cb = ca + (N / 2 + 1);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    const int p = t + TPF * m, p2 = (N - p) & (N - 1);
-    const Cx<Tc> q = qw[p];
-    Tc xa, xb, xa2, xb2;
-    split_pair<Tc>(zr[m], zi[m], pr[m], pim[m], q.r, q.i, xa, xb, xa2, xb2);
-    merge_pair<Tc>(xa * la[p], xb * lb[p], xa2 * la[p2], xb2 * lb[p2], q.r, q.i, zr[m], zi[m]);
+    const int p = t + TPF * m;
+    const bool hi = m >= E / 2;  // p >= N/2: stored at N - p with beta negated
+    const int pi = hi ? N - p : p;
+    const Vec<Tc, 4> ka = ca[pi], kb = cb[pi];
+    const Tc ba = hi ? -ka.v[1] : ka.v[1], bb = hi ? -kb.v[1] : kb.v[1];
+    const Tc u = zr[m] + pr[m], v = zi[m] - pim[m], w = zi[m] + pim[m], x = pr[m] - zr[m];
+    zr[m] = ka.v[0] * u + ba * v - bb * w - kb.v[2] * x;
+    zi[m] = ba * u + ka.v[2] * v + kb.v[0] * w + bb * x;
   }
   wave_sync();
   fft_reg<Tc, N, +1>(zr, zi, re, im, tw, t);
@@ -582,23 +586,23 @@ hipError_t row_dispatch_n(int mode, const PassArgs& a, const Cx<Tc>* tw, const C
 }
 
 template <typename Tc, int N>
-hipError_t col_launch(const PassArgs& a, const Tc* lamT, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+hipError_t col_launch(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   using Cfg = ColCfg<Tc, N>;
-  hipLaunchKernelGGL((col_pass_kernel<Tc, N>), dim3(N / Cfg::COLS, a.n_maps), dim3(Cfg::THREADS), 0, s, a, lamT, tw,
+  hipLaunchKernelGGL((col_pass_kernel<Tc, N>), dim3(N / Cfg::COLS, a.n_maps), dim3(Cfg::THREADS), 0, s, a, coef, tw,
                      qw);
   return hipGetLastError();
 }
 
 template <typename Tc>
-hipError_t col_dispatch_n(const PassArgs& a, const Tc* lamT, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+hipError_t col_dispatch_n(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   switch (a.n) {
-    case 16: return col_launch<Tc, 16>(a, lamT, tw, qw, s);
-    case 32: return col_launch<Tc, 32>(a, lamT, tw, qw, s);
-    case 64: return col_launch<Tc, 64>(a, lamT, tw, qw, s);
-    case 128: return col_launch<Tc, 128>(a, lamT, tw, qw, s);
-    case 256: return col_launch<Tc, 256>(a, lamT, tw, qw, s);
-    case 512: return col_launch<Tc, 512>(a, lamT, tw, qw, s);
-    case 1024: return col_launch<Tc, 1024>(a, lamT, tw, qw, s);
+    case 16: return col_launch<Tc, 16>(a, coef, tw, qw, s);
+    case 32: return col_launch<Tc, 32>(a, coef, tw, qw, s);
+    case 64: return col_launch<Tc, 64>(a, coef, tw, qw, s);
+    case 128: return col_launch<Tc, 128>(a, coef, tw, qw, s);
+    case 256: return col_launch<Tc, 256>(a, coef, tw, qw, s);
+    case 512: return col_launch<Tc, 512>(a, coef, tw, qw, s);
+    case 1024: return col_launch<Tc, 1024>(a, coef, tw, qw, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -614,9 +618,9 @@ hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hip
   return row_dispatch_n<double, double>(mode, a, a.tw.tw64, a.tw.qw64, stream);
 }
 
-hipError_t launch_col_pass(int compute, const PassArgs& a, const void* lamT, hipStream_t stream) {
-  if (compute == VARSIM_F32) return col_dispatch_n<float>(a, (const float*)lamT, a.tw.tw32, a.tw.qw32, stream);
-  return col_dispatch_n<double>(a, (const double*)lamT, a.tw.tw64, a.tw.qw64, stream);
+hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream) {
+  if (compute == VARSIM_F32) return col_dispatch_n<float>(a, (const float*)coef, a.tw.tw32, a.tw.qw32, stream);
+  return col_dispatch_n<double>(a, (const double*)coef, a.tw.tw64, a.tw.qw64, stream);
 }
 
 hipError_t launch_prep(int io, const PrepArgs* args, int n_maps, long count, hipStream_t stream) {

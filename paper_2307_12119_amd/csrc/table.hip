@@ -260,6 +260,43 @@ __global__ void __launch_bounds__(256) dct1_y_kernel(const double* __restrict__ 
   if (lam_rowmajor) lam_rowmajor[(size_t)p * nx + q] = acc;
 }
 
+// Column-pass coefficients.  For the packed column pair the split of the forward transform,
+// the multiplication by lambda and the merge of the inverse combine, at spectral index p with
+// (c, s) = (cos, sin)(pi p / 2n), into
+//     alpha = (c^2 l[p] + s^2 l[n-p]) / 2,  beta = c s (l[p] - l[n-p]) / 2,  gamma = (s^2 l[p] + c^2 l[n-p]) / 2
+// per column (alpha, gamma even and beta odd under p -> n - p, so p in [0, n/2] is stored).
+// out[q][p] = (alpha, beta, gamma, 0) for column q; l = lamT[q][.] (already scaled).
+__global__ void __launch_bounds__(256) coef_kernel(const double* __restrict__ lamT, double* __restrict__ c64,
+                                                   float* __restrict__ c32, int nx, int ny) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  const int half = ny / 2;
+  if (p > half) return;
+  const double* l = lamT + (size_t)q * ny;
+  double a, b, g;
+  if (p == 0) {
+    a = 0.5 * l[0];
+    b = 0.0;
+    g = 0.0;
+  } else {
+    double sn, cs;
+    sincospi(0.5 * p / ny, &sn, &cs);
+    const double lp = l[p], lq = l[ny - p];
+    a = 0.5 * (cs * cs * lp + sn * sn * lq);
+    b = 0.5 * cs * sn * (lp - lq);
+    g = 0.5 * (sn * sn * lp + cs * cs * lq);
+  }
+  const size_t o = ((size_t)q * (half + 1) + p) * 4;
+  c64[o] = a;
+  c64[o + 1] = b;
+  c64[o + 2] = g;
+  c64[o + 3] = 0.0;
+  c32[o] = (float)a;
+  c32[o + 1] = (float)b;
+  c32[o + 2] = (float)g;
+  c32[o + 3] = 0.0f;
+}
+
 // DFT twiddles exp(-2 pi i k / n) and quarter-wave pairs (cos, sin)(pi p / 2n)
 __global__ void twiddle_kernel(Cx<double>* tw64, Cx<float>* tw32, Cx<double>* qw64, Cx<float>* qw32, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,8 +320,8 @@ static int periods_needed(double lx, double ly, double t) {
   return m;
 }
 
-hipError_t launch_green_table(const TableSpec& sp, double* kper, double* lam64T, float* lam32T, double* lam_rowmajor,
-                              double* scratch, hipStream_t stream) {
+hipError_t launch_green_table(const TableSpec& sp, double* kper, double* lam64T, float* lam32T, double* coef64,
+                              float* coef32, double* lam_rowmajor, double* scratch, hipStream_t stream) {
   // scratch: Gauss-Legendre rules, kCheb + 2 nx + 2 ny + (ny + 1) nx doubles
   double* gl = scratch;
   double* coef = gl + 2 * kGLTotal;
@@ -306,6 +343,8 @@ hipError_t launch_green_table(const TableSpec& sp, double* kper, double* lam64T,
                      sp.ny);
   hipLaunchKernelGGL(dct1_y_kernel, dim3((sp.ny + 255) / 256, sp.nx), dim3(256), 0, stream, A, lam64T, lam32T,
                      lam_rowmajor, cosy, sp.nx, sp.ny, 1.0 / ((double)sp.nx * sp.ny));
+  hipLaunchKernelGGL(coef_kernel, dim3((sp.ny / 2 + 1 + 255) / 256, sp.nx), dim3(256), 0, stream, lam64T, coef64, coef32,
+                     sp.nx, sp.ny);
   return hipGetLastError();
 }
 
