@@ -1,0 +1,117 @@
+"""Transient temperature solve -- oracle (test infrastructure only).
+
+Definition followed:
+  * Eq. Ttran: T = f_sp (*) P - C f_sp (*) dT/dt makes every spatial Fourier (here: cosine)
+    mode of the die a single pole: with P constant from t = 0 the mode's rise is
+    F(T_ss) (1 - exp(-t / tau))  (Eq. tranGreen with the alpha C g term dropped as the paper
+    does).  In the discrete, mirrored setting the steady response of mode (p, q) is the
+    eigenvalue lambda[p, q] of the Green's operator, so the step response of that mode is
+        S_hat[p, q](t) = lambda[p, q] (1 - exp(-t / tau[p, q])).
+  * tau: the paper leaves C undetermined.  Default ("moment"): tau(s) is the exact first moment
+    of the slab's multi-exponential response to a heat-flux step at lateral wavenumber s,
+        tau(s) = (1 - x / sinh x) / (2 alpha s^2),  x = 2 s t_d,  alpha = k_ref / (rho c),
+    with tau(0) = t_d^2 / (3 alpha).  Option "lumped": the paper's tau = C F(f_sp0) with
+    C = rho c t_d / 3 per unit area, i.e. tau = (rho c t_d / 3) hx hy lambda[p, q] (it equals the
+    moment value for the uniform mode).  s for mode (p, q) is pi sqrt((p/Lx)^2 + (q/Ly)^2).
+  * Eq. tranapprox: a power map held over (t_{n-1}, t_n] enters through the step kernels,
+        theta_n = sum_{j=1..n} S_j (*) (P_{n-j+1} - P_{n-j}),   P_0 = 0,
+    with S_j the real-space kernel whose cosine eigenvalues are S_hat(j dt) and (*) the same
+    mirror-image direct sum as the steady oracle.  Here the whole history is kept (the paper
+    truncates it after 5 ms).
+  * Leakage and k(T) (Sec. IV-E: "substitute the leakage-aware Green's function"): step n uses
+    the previous step's rise, P_n = hx hy [q_dyn(t_n) + q_leak0 v L(dT_{n-1})], and
+    dT_n = Phi^-1(theta_n / m) pointwise.
+
+The step kernels come from lambda (an (N+1)-point cosine transform of the periodised steady
+kernel) by the inverse transform; the superposition itself is a plain direct sum.
+
+Parity: pinned -- the superposition against an independent single-pole recursion, the long-time
+limit against the steady operator, uniform power against q t / k (1 - exp(-t / tau(0))), and
+tau(s) against a numerically summed modal first moment.  The single-pole model itself (how well
+one pole per mode approximates the slab) is the paper's reading: parity unpinned against the
+full heat equation.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.fft as sfft
+
+from . import steady as S
+
+
+def tau_moment(s: np.ndarray, t: float, alpha: float) -> np.ndarray:
+    """First moment of the slab's step response at lateral wavenumber s (closed form)."""
+    s = np.asarray(s, dtype=np.float64)
+    x = 2.0 * s * t
+    out = np.empty_like(s)
+    small = x < 1e-3
+    xs = x[small]
+    # 1 - x / sinh x = x^2/6 - 7 x^4/360 + 31 x^6/15120 - ...
+    out[small] = t * t / (3.0 * alpha) * (1.0 - 7.0 * xs * xs / 60.0 + 31.0 * xs ** 4 / 2520.0)
+    xl = x[~small]
+    sl = s[~small]
+    out[~small] = (1.0 - xl / np.sinh(xl)) / (2.0 * alpha * sl * sl)
+    return out
+
+
+class TransientModel:
+    """Single-pole-per-mode transient model of one die (Eqs. Ttran, tranGreen)."""
+
+    def __init__(self, geom: S.Geometry, rho_c: float, tau_model: str = "moment",
+                 operator: S.DirectSum | None = None):
+        self.geom = geom
+        self.op = operator or S.DirectSum(geom)
+        g = geom
+        # lambda over p, q in [0, N] from the periodised kernel (cosine transform, type I)
+        self.lam_full = sfft.dct(sfft.dct(self.op.table, type=1, axis=0), type=1, axis=1)
+        self.alpha = g.k_ref / rho_c
+        pp = np.arange(g.ny + 1)[:, None]
+        qq = np.arange(g.nx + 1)[None, :]
+        s = math.pi * np.sqrt((pp / g.ly) ** 2 + (qq / g.lx) ** 2)
+        if tau_model == "moment":
+            self.tau = tau_moment(s, g.t, self.alpha)
+        elif tau_model == "lumped":
+            self.tau = rho_c * g.t / 3.0 * g.hx * g.hy * self.lam_full
+        else:
+            raise ValueError(tau_model)
+        self.rho_c = rho_c
+
+    def step_kernel(self, time: float) -> np.ndarray:
+        """Real-space periodised kernel whose cosine eigenvalues are lambda (1 - exp(-time/tau))."""
+        shat = self.lam_full * (-np.expm1(-time / self.tau))
+        return sfft.idct(sfft.idct(shat, type=1, axis=0), type=1, axis=1)
+
+
+def solve_transient(model: TransientModel, q_dyn_steps: np.ndarray, dt: float, q_leak: np.ndarray | None = None,
+                    cond_map: np.ndarray | None = None, leak: str = "exp", beta: float = 0.017,
+                    record_every: int = 1):
+    """Full-history superposition (Eq. tranapprox) with the one-step-lagged leakage loop.
+
+    q_dyn_steps: [n_steps][ny][nx] dynamic power density held over each step.  Returns the rises
+    dT_n for n = record_every, 2 record_every, ... (array [n_rec][ny][nx]) and the final rise.
+    """
+    g = model.geom
+    n_steps = q_dyn_steps.shape[0]
+    kernels = [S.DirectSum(g, table=model.step_kernel((j + 1) * dt)) for j in range(n_steps)]
+    dT = np.zeros((g.ny, g.nx))
+    p_hist = []  # P_1 .. P_n in W per cell
+    out = []
+    for n in range(1, n_steps + 1):
+        q = q_dyn_steps[n - 1]
+        if q_leak is not None and leak != "none":
+            lf = np.exp(beta * dT) if leak == "exp" else 1.0 + beta * dT
+            q = q + q_leak * lf
+        p_hist.append(g.hx * g.hy * q)
+        theta = np.zeros((g.ny, g.nx))
+        for j in range(1, n + 1):  # S_j applied to P_{n-j+1} - P_{n-j}
+            newer = p_hist[n - j]
+            older = p_hist[n - j - 1] if n - j - 1 >= 0 else 0.0
+            theta += kernels[j - 1].apply(newer - older)
+        if cond_map is not None:
+            theta = theta / cond_map
+        dT, ok = S.kirchhoff_inverse(theta, g.t_amb, g.eta)
+        if n % record_every == 0:
+            out.append(dT.copy())
+    return np.array(out), dT

@@ -1,0 +1,86 @@
+"""Pins of the transient oracle (Eqs. Ttran, tranGreen, tranapprox)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.fft as sfft
+
+import workloads as W
+from oracle import steady as S
+from oracle import transient as T
+
+TD, KC, RHOC = 0.5e-3, 150.0, 1.66e6
+
+
+def _geom(n=16, l=10e-3, eta=0.0):
+    return S.Geometry(l, l, n, n, TD, KC, eta, 318.0, RHOC)
+
+
+@pytest.mark.parametrize("s", [0.0, 10.0, 1e3, 3e3, 1e4, 1e5])
+def test_tau_is_first_moment_of_slab_modes(s):
+    # slab modes cos(mu_m z), mu_m = (m + 1/2) pi / t: steady gain per mode (2/t) / (k (mu^2 + s^2)),
+    # decay time 1 / (alpha (mu^2 + s^2)); the response's first moment is sum A tau / sum A
+    alpha = KC / RHOC
+    m = np.arange(200000)
+    mu2 = ((m + 0.5) * math.pi / TD) ** 2 + s * s
+    a = (2.0 / TD) / (KC * mu2)
+    tau_m = 1.0 / (alpha * mu2)
+    gain = a.sum()
+    steady = TD / KC if s == 0 else math.tanh(s * TD) / (KC * s)
+    assert gain == pytest.approx(steady, rel=1e-4)  # truncated sum, tail ~ 2 t s / (pi^2 M)
+    # numerator terms fall off like m^-4 (truncation ~1e-16); divide by the exact steady gain
+    moment = (a * tau_m).sum() / steady
+    assert float(T.tau_moment(np.array([s]), TD, alpha)[0]) == pytest.approx(moment, rel=1e-9)
+
+
+def test_long_time_kernel_is_steady_kernel():
+    model = T.TransientModel(_geom(16), RHOC)
+    k_inf = model.step_kernel(1.0)  # 1 s >> every tau
+    assert np.allclose(k_inf, model.op.table, rtol=1e-12, atol=1e-15 * np.max(model.op.table))
+
+
+def test_uniform_power_single_pole():
+    g = _geom(16)
+    model = T.TransientModel(g, RHOC)
+    q = 1.0e6
+    dt = 50e-6
+    steps = np.full((12, 16, 16), q)
+    rec, _ = T.solve_transient(model, steps, dt, leak="none")
+    tau0 = TD * TD * RHOC / (3.0 * KC)
+    for n in range(12):
+        expect = q * TD / KC * (1.0 - math.exp(-(n + 1) * dt / tau0))
+        assert np.allclose(rec[n], expect, rtol=1e-11)
+
+
+def test_lumped_tau_matches_moment_at_dc():
+    g = _geom(16)
+    a = T.TransientModel(g, RHOC, "moment")
+    b = T.TransientModel(g, RHOC, "lumped")
+    assert b.tau[0, 0] == pytest.approx(a.tau[0, 0], rel=1e-12)
+    assert np.all(b.tau[1:, 1:] < a.tau[1:, 1:] * 10)
+
+
+def test_superposition_equals_single_pole_recursion():
+    """Eq. tranapprox (full history, real-space step kernels, direct sums) against an independent
+    per-mode recursion theta_hat_n = a theta_hat_{n-1} + b P_hat_n, with the lagged leakage, the
+    conductivity map and k(T)."""
+    n, steps, dt = 16, 25, 20e-6
+    g = _geom(n, eta=1.3)
+    model = T.TransientModel(g, RHOC)
+    tr = W.transient_problem(n=n, n_steps=steps, dt_s=dt, n_blocks=6, hold_s=5 * dt)
+    qd = np.stack([W.raster_trace_step(tr.block_rects, tr.trace[i], n) for i in range(steps)])
+    ql = tr.q_leak0 * tr.leak_var
+    rec, last = T.solve_transient(model, qd, dt, q_leak=ql, cond_map=tr.cond_map)
+    lam = model.lam_full[:n, :n]
+    tau = model.tau[:n, :n]
+    a = np.exp(-dt / tau)
+    b = -np.expm1(-dt / tau) * lam
+    th_hat = np.zeros((n, n))
+    dT = np.zeros((n, n))
+    for i in range(steps):
+        p = g.hx * g.hy * (qd[i] + ql * np.exp(0.017 * dT))
+        th_hat = a * th_hat + b * sfft.dctn(p, type=2)
+        theta = sfft.idctn(th_hat, type=2) / tr.cond_map
+        dT, ok = S.kirchhoff_inverse(theta, g.t_amb, g.eta)
+        assert np.allclose(rec[i], dT, rtol=1e-11, atol=1e-12 * np.max(np.abs(dT)))
+    assert np.max(last) > 0.5
