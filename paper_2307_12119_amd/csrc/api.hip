@@ -352,6 +352,61 @@ varsim_status sort_into_groups(varsim_ctx* ctx, const varsim_problem* problems, 
   return VARSIM_OK;
 }
 
+varsim_status check_transient(varsim_ctx* ctx, const varsim_problem* p, const varsim_transient* tr,
+                              const varsim_options* o) {
+  if (!p || !tr) return fail(ctx, VARSIM_ERR_INVALID, "problem or transient is NULL");
+  varsim_status s = check_geometry(ctx, p->geom);
+  if (s != VARSIM_OK) return s;
+  if ((s = check_options(ctx, o)) != VARSIM_OK) return s;
+  if (!p->dT_out) return fail(ctx, VARSIM_ERR_INVALID, "dT_out is required");
+  if (!(p->geom->layers[0].rho_c_J_m3K > 0) || !std::isfinite(p->geom->layers[0].rho_c_J_m3K))
+    return fail(ctx, VARSIM_ERR_INVALID, "rho_c must be positive");
+  if (!(tr->dt_s > 0) || !std::isfinite(tr->dt_s)) return fail(ctx, VARSIM_ERR_INVALID, "dt_s must be positive");
+  if (tr->n_steps < 1 || tr->out_every < 1 || tr->n_blocks < 1)
+    return fail(ctx, VARSIM_ERR_INVALID, "n_steps, out_every and n_blocks must be >= 1");
+  if (!tr->block_rects || !tr->trace) return fail(ctx, VARSIM_ERR_INVALID, "block_rects and trace are required");
+  if (tr->tau_model != VARSIM_TAU_MOMENT && tr->tau_model != VARSIM_TAU_LUMPED)
+    return fail(ctx, VARSIM_ERR_INVALID, "bad tau_model");
+  return VARSIM_OK;
+}
+
+// Workspace of one transient solve.
+struct TransLayout {
+  size_t flags = 0, state_end = 0, stats = 0, prep = 0, S = 0, state = 0, ab = 0, ids = 0;
+  size_t QL = (size_t)-1, MINV = (size_t)-1, total = 0;
+};
+
+TransLayout make_transient_layout(const varsim_problem* p, const varsim_options* o) {
+  TransLayout L;
+  const size_t cells = (size_t)p->geom->nx * p->geom->ny, es = esize(o->precision);
+  size_t off = 0;
+  L.flags = off;
+  off = align_up(off + 4);
+  L.state_end = off;
+  L.stats = off;
+  off = align_up(off + sizeof(varsim_stats));
+  L.prep = off;
+  off = align_up(off + sizeof(PrepArgs));
+  L.S = off;
+  off = align_up(off + cells * es);
+  L.state = off;
+  off = align_up(off + cells * es);
+  L.ab = off;
+  off = align_up(off + 2 * cells * es);
+  L.ids = off;
+  off = align_up(off + cells * 4);
+  if (p->q_leak0 && o->leak != VARSIM_LEAK_NONE && p->leak_var) {
+    L.QL = off;
+    off = align_up(off + cells * es);
+  }
+  if (p->cond_map) {
+    L.MINV = off;
+    off = align_up(off + cells * es);
+  }
+  L.total = off;
+  return L;
+}
+
 }  // namespace
 
 // =========================================================================================
@@ -678,15 +733,111 @@ varsim_status varsim_solve_steady(varsim_ctx* ctx, const varsim_problem* problem
   return varsim_solve_batch(ctx, problem, 1, opts, workspace, ws_bytes, stats, stream);
 }
 
-varsim_status varsim_transient_workspace_size(varsim_ctx* ctx, const varsim_problem*, const varsim_transient*,
-                                              const varsim_options*, size_t* bytes) {
-  if (bytes) *bytes = 0;
-  return fail(ctx, VARSIM_ERR_UNSUPPORTED, "transient solve not built");
+varsim_status varsim_transient_workspace_size(varsim_ctx* ctx, const varsim_problem* problem,
+                                              const varsim_transient* tr, const varsim_options* opts, size_t* bytes) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  if (!bytes) return fail(ctx, VARSIM_ERR_INVALID, "bytes is NULL");
+  varsim_status st = check_transient(ctx, problem, tr, opts);
+  if (st != VARSIM_OK) return st;
+  *bytes = make_transient_layout(problem, opts).total;
+  return VARSIM_OK;
 }
 
-varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem*, const varsim_transient*,
-                                     const varsim_options*, void*, void*, size_t, varsim_stats*, void*) {
-  return fail(ctx, VARSIM_ERR_UNSUPPORTED, "transient solve not built");
+varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* problem, const varsim_transient* tr,
+                                     const varsim_options* opts, void* dT_steps_out, void* workspace, size_t ws_bytes,
+                                     varsim_stats* stats, void* stream) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  if (!stats || !workspace) return fail(ctx, VARSIM_ERR_INVALID, "NULL stats or workspace");
+  varsim_status st = check_transient(ctx, problem, tr, opts);
+  if (st != VARSIM_OK) return st;
+  const TransLayout L = make_transient_layout(problem, opts);
+  if (ws_bytes < L.total)
+    return fail(ctx, VARSIM_ERR_NO_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const varsim_geometry* g = problem->geom;
+  TableEntry tab;
+  TwEntry tw;
+  if ((st = get_table(ctx, g, s, &tab)) != VARSIM_OK) return st;
+  if ((st = get_twiddles(ctx, g->nx, s, &tw)) != VARSIM_OK) return st;
+
+  const int io = opts->precision;
+  const long cells = (long)g->nx * g->ny;
+  char* ws = (char*)workspace;
+  unsigned* d_flags = (unsigned*)(ws + L.flags);
+  varsim_stats* d_stats = (varsim_stats*)(ws + L.stats);
+  PrepArgs* d_prep = (PrepArgs*)(ws + L.prep);
+  const bool leak = problem->q_leak0 && opts->leak != VARSIM_LEAK_NONE;
+
+  TransArgs a{};
+  a.n = g->nx;
+  a.S = ws + L.S;
+  a.state = ws + L.state;
+  a.ab = ws + L.ab;
+  a.ids = (const int*)(ws + L.ids);
+  a.trace = tr->trace;
+  a.n_blocks = tr->n_blocks;
+  a.ql = leak ? (L.QL != (size_t)-1 ? (const void*)(ws + L.QL) : problem->q_leak0) : nullptr;
+  a.minv = L.MINV != (size_t)-1 ? ws + L.MINV : nullptr;
+  a.dT = problem->dT_out;
+  a.snaps = dT_steps_out;
+  a.out_every = tr->out_every;
+  a.flags = d_flags;
+  a.pp = point_params(g, opts);
+  a.tw = Twiddles{tw.tw64, tw.tw32, tw.qw64, tw.qw32};
+
+  ctx->h_prep.assign(1, PrepArgs{});
+  PrepArgs& q = ctx->h_prep[0];
+  q.q_leak0 = problem->q_leak0;
+  q.leak_var = problem->leak_var;
+  q.cond_map = problem->cond_map;
+  q.ql_out = (leak && L.QL != (size_t)-1) ? ws + L.QL : nullptr;
+  q.minv_out = (void*)a.minv;
+  q.dT = problem->dT_out;
+  q.flags = d_flags;
+
+  // static inputs: flags, spectral state, QL, 1/m, block ids, per-mode (a, b)
+  const TableSpec sp{g->nx, g->ny, g->lx_m, g->ly_m, g->layers[0].thickness_m, k_ref_of(g)};
+  const double alpha = sp.k_ref / g->layers[0].rho_c_J_m3K;
+  HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(ws, L.state_end, s); }));
+  HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(a.state, (size_t)cells * esize(io), s); }));
+  HIP_TRY(hipMemcpyAsync(d_prep, ctx->h_prep.data(), sizeof(PrepArgs), hipMemcpyHostToDevice, s));
+  HIP_TRY(timed(ctx, "prep", s, [&] { return launch_prep(io, d_prep, 1, cells, s); }));
+  HIP_TRY(timed(ctx, "setup", s, [&] {
+    return launch_block_ids(tr->block_rects, tr->n_blocks, (int*)a.ids, g->nx, g->ny, s);
+  }));
+  HIP_TRY(timed(ctx, "setup", s, [&] {
+    return launch_transient_coef(sp, tab.lam64T, io, (void*)a.ab, alpha, tr->dt_s, tr->tau_model,
+                                 g->layers[0].rho_c_J_m3K, s);
+  }));
+  unsigned h_flags = 0;
+  HIP_TRY(hipMemcpyAsync(&h_flags, d_flags, sizeof h_flags, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  flush_timing(ctx);
+  if (h_flags & kFlagInvalid) {
+    varsim_stats bad{};
+    bad.status = VARSIM_ERR_INVALID;
+    bad.last_increment_K = bad.residual_f64_K = bad.dT_max_K = bad.dT_mean_K = NAN;
+    bad.hotspot_index = -1;
+    *stats = bad;
+    return fail(ctx, VARSIM_ERR_INVALID, "conductivity map must be positive and finite");
+  }
+
+  // step n: column pass (mode update with P_n) then row pass (dT_n, and P_{n+1} unless last)
+  HIP_TRY(timed(ctx, "tr_row_head", s, [&] { return launch_transient_row(TR_HEAD, io, a, 0, s); }));
+  for (int n = 1; n <= tr->n_steps; ++n) {
+    HIP_TRY(timed(ctx, "tr_col", s, [&] { return launch_transient_col(io, a, s); }));
+    const bool last = n == tr->n_steps;
+    HIP_TRY(timed(ctx, last ? "tr_row_last" : "tr_row", s,
+                  [&] { return launch_transient_row(last ? TR_LAST : TR_MERGED, io, a, n, s); }));
+  }
+  HIP_TRY(launch_map_stats(io, problem->dT_out, cells, d_flags, tr->n_steps, d_stats, s));
+  HIP_TRY(hipMemcpyAsync(stats, d_stats, sizeof(varsim_stats), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  flush_timing(ctx);
+  if (stats->status != VARSIM_OK)
+    return fail(ctx, (varsim_status)stats->status, "transient: %s", varsim_status_string((varsim_status)stats->status));
+  return VARSIM_OK;
 }
 
 varsim_status varsim_set_timing(varsim_ctx* ctx, int32_t enable) {

@@ -80,4 +80,35 @@ hipError_t launch_count_active(const IterState& st, int n_maps, int iter, double
 hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, long cells, int max_iter,
                            int iters_run, double tol, int residual_done, varsim_stats* out, hipStream_t stream);
 
+// Transient solve of one map (element type T = io = compute type).
+struct TransArgs {
+  int n;
+  void* S;            // [n][n] transform work array
+  void* state;        // [n][n] spectral state theta_hat, layout [q][p] (q: row-transform index)
+  const void* ab;     // [n][n][2] per-mode (a, b), layout [q][p]
+  const int* ids;     // [n][n] block id of each cell, -1 where no block
+  const void* trace;  // [n_steps][n_blocks] block power densities
+  int n_blocks;
+  const void* ql;     // leakage density at ambient times variation, or null
+  const void* minv;   // 1 / conductivity multiplier, or null
+  void* dT;           // final rise
+  void* snaps;        // [n_steps / out_every][n][n], or null
+  int out_every;
+  unsigned* flags;    // runaway flag word
+  PointParams pp;
+  Twiddles tw;
+};
+enum TransMode : int { TR_HEAD = 0, TR_MERGED = 1, TR_LAST = 2 };
+
+// (a, b) per mode from lambda (lam64T, scaled as the column pass uses it), dt and tau_model
+hipError_t launch_transient_coef(const TableSpec& sp, const double* lam64T, int io, void* ab, double alpha, double dt,
+                                 int tau_model, double rho_c, hipStream_t stream);
+hipError_t launch_block_ids(const int* rects, int n_blocks, int* ids, int nx, int ny, hipStream_t stream);
+// TR_HEAD: P_1 -> row spectrum; TR_MERGED (step n): row synthesis -> dT_n -> P_{n+1} -> row
+// spectrum; TR_LAST: row synthesis -> dT_n (final)
+hipError_t launch_transient_row(int mode, int io, const TransArgs& a, int step, hipStream_t stream);
+hipError_t launch_transient_col(int io, const TransArgs& a, hipStream_t stream);
+hipError_t launch_map_stats(int io, const void* dT, long cells, const unsigned* flags, int steps, varsim_stats* out,
+                            hipStream_t stream);
+
 }  // namespace vs

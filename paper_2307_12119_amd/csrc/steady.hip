@@ -14,156 +14,11 @@
 #include "common.hpp"
 #include "fft.hpp"
 #include "internal.hpp"
+#include "passes.hpp"
 
 namespace vs {
 
 namespace {
-
-template <int N>
-struct RowCfg {
-  static constexpr int TPF = Shape<N>::TPF;
-  static constexpr int FFTS = (256 / TPF) < (N / 2) ? (256 / TPF) : (N / 2);
-  static constexpr int THREADS = FFTS * TPF;
-  static constexpr int WAVE = THREADS < 64 ? THREADS : 64;
-  static constexpr int WAVES = THREADS / WAVE;
-};
-
-// columns per column-pass workgroup: at most 16, LDS <= 40 KB (two workgroups per CU),
-// <= 512 threads
-constexpr int col_count(int n, int esz, int tpf) {
-  int c = 16;
-  while (c > 2 && ((long)c * (n + n / 8 + 4) * esz > 40000 || (c / 2) * tpf > 512)) c /= 2;
-  return c < n ? c : n;
-}
-
-// Workgroups are handed to the 8 XCDs round-robin in launch order; renumber them so that
-// consecutive tiles (neighbouring column strips of one map, which share L2 lines) run on the
-// same XCD.  Identity when the grid is not a multiple of 8.
-__device__ __forceinline__ void xcd_tile(int& strip, int& map) {
-  const int gx = gridDim.x, g = gx * gridDim.y;
-  const int w = blockIdx.x + gx * blockIdx.y;
-  const int l = (g & 7) ? w : (w & 7) * (g >> 3) + (w >> 3);
-  strip = l % gx;
-  map = l / gx;
-}
-
-template <typename Tc, int N>
-struct ColCfg {
-  static constexpr int TPF = Shape<N>::TPF;
-  static constexpr int COLS = col_count(N, (int)sizeof(Tc), TPF);
-  static constexpr int FFTS = COLS / 2;
-  static constexpr int THREADS = FFTS * TPF;
-  static constexpr int VEC = (int)(16 / sizeof(Tc)) < COLS ? (int)(16 / sizeof(Tc)) : COLS;
-  // staging tile [N][PITCH] in natural row order; the pitch keeps both the row-segment stores
-  // and the strided column reads of a half-wavefront on distinct LDS banks
-  static constexpr int PITCH = sizeof(Tc) == 4 ? COLS + 3 : COLS + 1;
-  static constexpr int TILE = N * PITCH;
-  static constexpr int SCRATCH = FFTS * 2 * Shape<N>::STRIDE;
-  static constexpr int LDS = TILE > SCRATCH ? TILE : SCRATCH;
-};
-
-template <typename T, int V>
-struct alignas(sizeof(T) * V) Vec {
-  T v[V];
-};
-
-// Row values at the sample positions of this lane's slots (slot m <-> reordered index
-// t + TPF m).  Each lane loads the adjacent pair (2k, 2k+1) of its even slot k = t + TPF m;
-// the odd sample 2k+1 belongs to slot E-1-m of the mirror lane TPF-1-t and is swapped over.
-template <typename Tio, typename Tc, int N>
-__device__ __forceinline__ void load_slots(const Tio* __restrict__ row, Tc* out, int t, int mirror) {
-  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
-#pragma unroll
-  for (int m = 0; m < E / 2; ++m) {
-    const Vec<Tio, 2> v = *reinterpret_cast<const Vec<Tio, 2>*>(row + 2 * (t + TPF * m));
-    out[m] = (Tc)v.v[0];
-    out[E - 1 - m] = (Tc)lane_get(v.v[1], mirror);
-  }
-}
-
-template <typename Tio, typename Tc, int N>
-__device__ __forceinline__ void store_slots(Tio* __restrict__ row, const Tc* val, int t, int mirror) {
-  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
-#pragma unroll
-  for (int m = 0; m < E / 2; ++m) {
-    Vec<Tio, 2> v;
-    v.v[0] = (Tio)val[m];
-    v.v[1] = lane_get((Tio)val[E - 1 - m], mirror);
-    *reinterpret_cast<Vec<Tio, 2>*>(row + 2 * (t + TPF * m)) = v;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ T ldm(const void* p, long i) {
-  return ((const T*)p)[i];
-}
-
-// order-preserving key of a float for packed max / argmax
-__device__ __forceinline__ unsigned order_key(float v) {
-  const unsigned u = __float_as_uint(v);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ unsigned long long pack_max(float v, long idx) {
-  return ((unsigned long long)order_key(v) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)idx);
-}
-
-__device__ __forceinline__ float exp_leak(float x) { return __expf(x); }
-__device__ __forceinline__ double exp_leak(double x) { return exp(x); }
-
-template <typename Tc>
-__device__ __forceinline__ Tc leak_factor(Tc dT, const PointParams& pp) {
-  if (pp.leak == VARSIM_LEAK_EXP) return exp_leak((Tc)pp.beta * dT);
-  if (pp.leak == VARSIM_LEAK_LINEAR) return (Tc)1 + (Tc)pp.beta * dT;
-  return (Tc)0;
-}
-
-// dT = Phi^-1(theta) for k = k_ref (T / T_amb)^-eta (Kirchhoff inverse).  NaN outside the
-// law's domain (1 + (1 - eta) theta / T_amb <= 0), which the caller reports as runaway.
-template <typename Tc>
-__device__ __forceinline__ Tc kirchhoff_inv(Tc theta, const PointParams& pp) {
-  if (pp.eta_mode == 0) return theta;
-  const Tc u = (Tc)pp.u_scale * theta;
-  if constexpr (sizeof(Tc) == 4) {
-    // FP32: Horner form of the Taylor series of (1 + u)^a - 1 (exp(u) - 1 for eta = 1)
-    if (fabsf(u) <= (float)pp.poly_umax) {
-      float acc = pp.polyf[kPoly - 1];
-#pragma unroll
-      for (int k = kPoly - 2; k >= 0; --k) acc = fmaf(acc, u, pp.polyf[k]);
-      return (float)pp.t_amb * u * acc;
-    }
-  }
-  if (pp.eta_mode == 1) return (Tc)pp.t_amb * expm1(u);
-  if (!(u > (Tc)-1)) return (Tc)NAN;
-  return (Tc)pp.t_amb * expm1((Tc)pp.inv_1m_eta * log1p(u));
-}
-
-template <int W>
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, W));
-  return v;
-}
-template <int W>
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
-  return v;
-}
-template <int W>
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) {
-    const unsigned long long w = __shfl_xor(v, o, W);
-    v = w > v ? w : v;
-  }
-  return v;
-}
-
-__device__ __forceinline__ bool finished_before(const IterState& st, int map, int iter, double tol) {
-  if (iter < 2) return false;
-  const double prev = __longlong_as_double((long long)st.resid[(long)map * st.stride + iter - 1]);
-  return prev <= tol;
-}
 
 // Per-lane running statistics of the new iterate.
 template <typename Tc>

@@ -207,11 +207,11 @@ class Context:
     def _problems(self, items: list[dict]):
         geoms, layers, probs = [], [], (Problem * len(items))()
         for i, it in enumerate(items):
-            geom, layer = make_geometry(it["die"], it["q_dyn"].shape[-1])
+            geom, layer = make_geometry(it["die"], it["dT_out"].shape[-1])
             layers.append(layer)
             geoms.append(geom)
             geom.layers = ctypes.pointer(layer)
-            probs[i] = Problem(ctypes.pointer(geom), _ptr(it["q_dyn"]), _ptr(it.get("q_leak0")),
+            probs[i] = Problem(ctypes.pointer(geom), _ptr(it.get("q_dyn")), _ptr(it.get("q_leak0")),
                                _ptr(it.get("leak_var")), _ptr(it.get("cond_map")), _ptr(it.get("dT_init")),
                                _ptr(it["dT_out"]))
         return probs, (geoms, layers)
@@ -246,6 +246,41 @@ class Context:
 
     def solve_steady(self, item: dict, opts: Options, workspace=None) -> dict:
         return self.solve_batch([item], opts, workspace)[0]
+
+    # ----------------------------------------------------------------------------- transient
+    def _transient(self, block_rects, trace, dt_s: float, out_every: int, tau_model: int) -> Transient:
+        return Transient(dt_s, trace.shape[0], out_every, trace.shape[1], _ptr(block_rects), _ptr(trace), tau_model)
+
+    def transient_workspace_bytes(self, item: dict, block_rects, trace, dt_s: float, opts: Options,
+                                  out_every: int = 1, tau_model: int = TAU_MOMENT) -> int:
+        probs, keep = self._problems([item])
+        tr = self._transient(block_rects, trace, dt_s, out_every, tau_model)
+        n = ctypes.c_size_t(0)
+        self._check(self.lib.varsim_transient_workspace_size(self.handle, probs, ctypes.byref(tr),
+                                                             ctypes.byref(opts), ctypes.byref(n)))
+        return n.value
+
+    def solve_transient(self, item: dict, block_rects, trace, dt_s: float, opts: Options, snapshots=None,
+                        out_every: int = 1, tau_model: int = TAU_MOMENT, workspace=None,
+                        raise_on=(ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY)) -> dict:
+        """Transient solve from dT = 0 (item: die, dT_out, optional q_leak0, leak_var, cond_map as
+        device tensors).  block_rects: int32 [n_blocks][4] device tensor; trace: [n_steps][n_blocks]
+        device tensor of the map dtype; snapshots: optional [n_steps // out_every][n][n] output."""
+        import torch
+
+        probs, keep = self._problems([item])
+        tr = self._transient(block_rects, trace, dt_s, out_every, tau_model)
+        need = self.transient_workspace_bytes(item, block_rects, trace, dt_s, opts, out_every, tau_model)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=torch.device("cuda", self.device))
+        stats = Stats()
+        stats.status = -1
+        st = self.lib.varsim_solve_transient(self.handle, probs, ctypes.byref(tr), ctypes.byref(opts),
+                                             _ptr(snapshots), _ptr(workspace), workspace.numel(),
+                                             ctypes.byref(stats), _stream())
+        if st in raise_on and not (stats.status >= 0 and st == ERR_INVALID):
+            self._check(st, allow=())
+        return stats.as_dict()
 
     # -------------------------------------------------------------------------------- timing
     def set_timing(self, enable: bool):

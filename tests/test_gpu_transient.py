@@ -1,0 +1,232 @@
+"""GPU parity of the transient solve against the FP64 CPU oracle (through the C ABI).
+
+Tolerances: FP64 max |dT_gpu - dT_oracle| <= 1e-9 * max dT_oracle over every recorded step;
+FP32 max |dT_gpu - dT_oracle| <= 0.05 K.  At the full 1024 x 1024 size: the uniform-power
+closed form, and the oracle's superposition evaluated at sampled cells with the power history
+rebuilt from the recorded rises.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import steady as S
+from oracle import transient as T
+from tests._util import die_of, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FP32_GATE_K = 0.05
+FP64_GATE_REL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    from paper_2307_12119_amd import varsim as V
+
+    c = V.Context(0, gpu_lib)
+    yield c
+    c.close()
+
+
+def _tau_code(name):
+    from paper_2307_12119_amd import varsim as V
+
+    return {"moment": V.TAU_MOMENT, "lumped": V.TAU_LUMPED}[name]
+
+
+def _leak_code(name):
+    from paper_2307_12119_amd import varsim as V
+
+    return {"exp": V.LEAK_EXP, "linear": V.LEAK_LINEAR, "none": V.LEAK_NONE}[name]
+
+
+def _run_gpu(ctx, inp, dtype, out_every=1, tau="moment", leak="exp", cap=1000.0, snapshots=True):
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    n = inp.n
+    prec = V.F64 if dtype == torch.float64 else V.F32
+    item = {
+        "die": die_of(inp),
+        "q_leak0": to_dev(inp.q_leak0, dtype) if leak != "none" else None,
+        "leak_var": to_dev(inp.leak_var, dtype),
+        "cond_map": to_dev(inp.cond_map, dtype),
+        "dT_out": torch.full((n, n), float("nan"), dtype=dtype, device="cuda"),
+    }
+    rects = to_dev(inp.block_rects, torch.int32)
+    trace = to_dev(inp.trace, dtype)
+    snaps = None
+    if snapshots and inp.n_steps // out_every > 0:
+        snaps = torch.full((inp.n_steps // out_every, n, n), float("nan"), dtype=dtype, device="cuda")
+    opts = V.make_options(prec, _leak_code(leak), inp.beta, 1, 1e-3, cap=cap)
+    st = ctx.solve_transient(item, rects, trace, inp.dt_s, opts, snapshots=snaps, out_every=out_every,
+                             tau_model=_tau_code(tau), raise_on=(V.ERR_INVALID, V.ERR_UNSUPPORTED, V.ERR_DEVICE,
+                                                                  V.ERR_NO_MEMORY))
+    torch.cuda.synchronize()
+    rec = None if snaps is None else snaps.cpu().numpy().astype(np.float64)
+    return st, rec, item["dT_out"].cpu().numpy().astype(np.float64)
+
+
+def _oracle(inp, out_every=1, tau="moment", leak="exp"):
+    g = S.geometry_from_die(inp.die, inp.n)
+    model = T.TransientModel(g, inp.die.rho_c, tau)
+    steps = np.stack([W.raster_trace_step(inp.block_rects, inp.trace[k], inp.n) for k in range(inp.n_steps)])
+    q_leak = None
+    if leak != "none" and inp.q_leak0 is not None:
+        q_leak = inp.q_leak0 * (inp.leak_var if inp.leak_var is not None else 1.0)
+    return T.solve_transient(model, steps, inp.dt_s, q_leak=q_leak, cond_map=inp.cond_map, leak=leak,
+                             beta=inp.beta, record_every=out_every)
+
+
+CASES = [
+    # n, steps, dt, variation, leak, tau, out_every
+    (16, 30, 50e-6, False, "exp", "moment", 1),
+    (16, 24, 100e-6, True, "exp", "lumped", 1),
+    (32, 20, 50e-6, True, "exp", "moment", 3),
+    (32, 16, 200e-6, True, "linear", "moment", 4),
+    (64, 12, 100e-6, True, "exp", "moment", 1),
+    (64, 10, 100e-6, False, "none", "lumped", 5),
+    (128, 6, 100e-6, True, "exp", "moment", 2),
+]
+
+
+def _case_input(n, steps, dt, variation, seed=0):
+    return W.transient_problem(n=n, n_steps=steps, dt_s=dt, n_blocks=8 if n <= 32 else 24, hold_s=3 * dt,
+                               seed=seed, variation=variation)
+
+
+@pytest.mark.parametrize("n,steps,dt,variation,leak,tau,every", CASES)
+def test_transient_fp64_matches_oracle(ctx, n, steps, dt, variation, leak, tau, every):
+    import torch
+
+    inp = _case_input(n, steps, dt, variation)
+    ref, ref_last = _oracle(inp, every, tau, leak)
+    st, rec, last = _run_gpu(ctx, inp, torch.float64, every, tau, leak)
+    assert st["status"] == 0 and st["iterations"] == steps
+    scale = max(np.max(np.abs(ref)), np.max(np.abs(ref_last)))
+    assert scale > 0.1  # a meaningful rise
+    assert rec.shape == ref.shape
+    assert np.max(np.abs(rec - ref)) <= FP64_GATE_REL * scale
+    assert np.max(np.abs(last - ref_last)) <= FP64_GATE_REL * scale
+    assert st["dT_max_K"] == pytest.approx(float(np.max(ref_last)), rel=1e-9)
+    assert st["hotspot_index"] == int(np.argmax(ref_last))
+    assert st["dT_mean_K"] == pytest.approx(float(np.mean(ref_last)), rel=1e-9)
+
+
+@pytest.mark.parametrize("n,steps,dt,variation,leak,tau,every", [CASES[0], CASES[2], CASES[4], CASES[6]])
+def test_transient_fp32_matches_oracle(ctx, n, steps, dt, variation, leak, tau, every):
+    import torch
+
+    inp = _case_input(n, steps, dt, variation, seed=1)
+    ref, ref_last = _oracle(inp, every, tau, leak)
+    st, rec, last = _run_gpu(ctx, inp, torch.float32, every, tau, leak)
+    assert st["status"] == 0
+    assert np.max(np.abs(rec - ref)) <= FP32_GATE_K
+    assert np.max(np.abs(last - ref_last)) <= FP32_GATE_K
+
+
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+@pytest.mark.parametrize("eta", [0.0, 1.3])
+def test_transient_uniform_power_closed_form_1024(ctx, dtype_name, eta):
+    """Uniform power excites only the uniform mode: theta_n = q t / k_ref (1 - exp(-n dt / tau(0))),
+    tau(0) = t^2 rho c / (3 k_ref), and dT_n = Phi^-1(theta_n) in every cell."""
+    import torch
+
+    dtype = getattr(torch, dtype_name)
+    n, steps, dt, q = 1024, 40, 100e-6, 2.0e6
+    die = W.Die(eta=eta)
+    inp = W.TransientInputs(die, n, dt, steps, np.array([[0, 0, n, n]], np.int32), np.full((steps, 1), q), None,
+                            None, None)
+    st, rec, last = _run_gpu(ctx, inp, dtype, out_every=1, leak="none")
+    assert st["status"] == 0
+    k_ref = die.k0 * (die.t_amb / 300.0) ** (-eta)
+    tau0 = die.t_m ** 2 * die.rho_c / (3.0 * k_ref)
+    theta = q * die.t_m / k_ref * -np.expm1(-(np.arange(steps) + 1) * dt / tau0)
+    expect, ok = S.kirchhoff_inverse(theta, die.t_amb, eta)
+    assert np.all(ok)
+    tol = 1e-9 * expect[-1] if dtype == torch.float64 else 2e-3
+    assert np.max(np.abs(rec - expect[:, None, None])) <= tol
+    assert np.max(np.abs(last - expect[-1])) <= tol
+
+
+def test_transient_long_time_reaches_steady_fixed_point(ctx):
+    """Constant block powers held for many time constants: the lagged-leakage transient settles on
+    the steady leakage + variation fixed point."""
+    import torch
+
+    n, steps, dt = 64, 150, 2e-3
+    inp = W.transient_problem(n=n, n_steps=steps, dt_s=dt, n_blocks=16, hold_s=1.0, seed=3)
+    inp.trace[:] = inp.trace[0]
+    _, _, last = _run_gpu(ctx, inp, torch.float64, out_every=steps, snapshots=False)
+    g = S.geometry_from_die(inp.die, n)
+    q_dyn = W.raster_trace_step(inp.block_rects, inp.trace[0], n)
+    prob = S.SteadyProblem(g, q_dyn, inp.q_leak0, inp.leak_var, inp.cond_map)
+    opts = S.Options(leak="exp", beta=inp.beta, max_iter=200, tol=1e-12)
+    ref, stat = S.solve_steady(prob, opts)
+    assert stat.status == S.Status.OK
+    assert np.max(np.abs(last - ref)) <= 1e-9 * np.max(ref)
+
+
+def test_transient_full_size_sampled(ctx):
+    """1024 x 1024, FP32, leakage + variation: at sampled cells the recorded rise of the last step
+    equals the oracle's superposition of the power history rebuilt from the recorded rises."""
+    import torch
+
+    n, steps, dt = 1024, 10, 50e-6
+    inp = W.transient_problem(n=n, n_steps=steps, dt_s=dt, n_blocks=64, hold_s=2 * dt, seed=2)
+    st, rec, last = _run_gpu(ctx, inp, torch.float32, out_every=1)
+    assert st["status"] == 0
+    assert np.array_equal(rec[-1], last)
+    g = S.geometry_from_die(inp.die, n)
+    model = T.TransientModel(g, inp.die.rho_c)
+    ql = inp.q_leak0 * inp.leak_var
+    hist = [np.zeros((n, n))]
+    prev = np.zeros((n, n))
+    for k in range(steps):
+        q = W.raster_trace_step(inp.block_rects, inp.trace[k], n) + ql * np.exp(inp.beta * prev)
+        hist.append(g.hx * g.hy * q)
+        prev = rec[k]
+    rng = np.random.default_rng(11)
+    hot = np.unravel_index(int(np.argmax(last)), last.shape)
+    rows = np.concatenate([[0, n - 1, hot[0]], rng.integers(0, n, 12)])
+    cols = np.concatenate([[0, n - 1, hot[1]], rng.integers(0, n, 12)])
+    theta = np.zeros(len(rows))
+    for j in range(1, steps + 1):
+        op = S.DirectSum(g, table=model.step_kernel(j * dt))
+        theta += op.apply_at(hist[steps - j + 1] - hist[steps - j], rows, cols)
+    expect, ok = S.kirchhoff_inverse(theta / inp.cond_map[rows, cols], g.t_amb, g.eta)
+    assert np.all(ok)
+    assert np.max(np.abs(last[rows, cols] - expect)) <= FP32_GATE_K
+    assert np.max(expect) > 1.0
+
+
+def test_transient_statuses_and_edges(ctx):
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    # one step, no snapshots (out_every > n_steps)
+    inp = _case_input(16, 1, 50e-6, True)
+    ref, ref_last = _oracle(inp, 1)
+    st, rec, last = _run_gpu(ctx, inp, torch.float64, out_every=5)
+    assert st["status"] == V.OK and rec is None
+    assert np.max(np.abs(last - ref_last)) <= FP64_GATE_REL * np.max(ref_last)
+    # non-positive conductivity: INVALID
+    bad = _case_input(16, 3, 50e-6, True)
+    bad.cond_map[3, 4] = 0.0
+    st, _, _ = _run_gpu(ctx, bad, torch.float64)
+    assert st["status"] == V.ERR_INVALID
+    # runaway: enormous leakage with a steep exponential law
+    hot = _case_input(16, 40, 1e-3, True)
+    hot.q_leak0 = hot.q_leak0 * 400.0
+    st, _, _ = _run_gpu(ctx, hot, torch.float32, cap=500.0)
+    assert st["status"] == V.ERR_RUNAWAY
+    assert st["hotspot_index"] == -1
+    # argument errors raise
+    good = _case_input(16, 3, 50e-6, False)
+    with pytest.raises(V.VarsimError):
+        bad_dt = W.TransientInputs(good.die, 16, -1.0, 3, good.block_rects, good.trace, None, None, None)
+        _run_gpu(ctx, bad_dt, torch.float64)
+    with pytest.raises(V.VarsimError):
+        _run_gpu(ctx, _case_input(24, 3, 50e-6, False), torch.float64)  # not a power of two
