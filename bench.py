@@ -103,6 +103,8 @@ def main() -> int:
                     help="npy file to reuse the generated inputs from (written when missing)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (counter calibration)")
+    ap.add_argument("--no-transient", action="store_true", help="skip the 1024^2 x 1000-step transient run")
+    ap.add_argument("--transient-runs", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sample sharding is described in "
@@ -221,10 +223,82 @@ def main() -> int:
         "surrogate": None,
     }
 
+    if not args.no_transient:
+        del ws
+        result["transient"] = transient_bench(ctx, args.transient_runs)
     if not args.no_cpu_baseline:
         result["cpu_baseline"], result["max_err_K"] = cpu_baseline(args.n, out[0].cpu().numpy())
     print(json.dumps(result))
     return 0
+
+
+TRANSIENT_BYTES_PER_CELL = {"tr_row": 20, "tr_col": 24}  # FP32: see transient_bench
+
+
+def transient_bench(ctx, runs: int) -> dict:
+    """One 1000-step transient of a 64-block, 1024 x 1024 die (10 us steps, block powers redrawn
+    every 1 ms, leakage + variation, k(T) with eta = 1.3), FP32, snapshots every 100 steps; the
+    same run in FP64 (untimed) gives the FP32 error at every snapshot."""
+    import numpy as np
+    import torch
+
+    import workloads.gen as W
+    from paper_2307_12119_amd import varsim as V
+
+    n, steps, every = 1024, 1000, 100
+    inp = W.transient_problem(n=n, n_steps=steps, dt_s=10e-6, n_blocks=64, hold_s=1e-3, seed=0)
+    dev = torch.device("cuda", 0)
+    d = inp.die
+    die = V.Die(d.lx_m, d.ly_m, d.t_m, d.k0, d.eta, d.t_amb, d.rho_c)
+
+    def setup(dtype):
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dtype)
+        item = {"die": die, "q_leak0": t(inp.q_leak0), "leak_var": t(inp.leak_var), "cond_map": t(inp.cond_map),
+                "dT_out": torch.zeros((n, n), dtype=dtype, device=dev)}
+        snaps = torch.zeros((steps // every, n, n), dtype=dtype, device=dev)
+        return item, t(inp.block_rects).to(torch.int32), t(inp.trace), snaps
+
+    item, rects, trace, snaps = setup(torch.float32)
+    opts = V.make_options(V.F32, V.LEAK_EXP, inp.beta, 1, 1e-3)
+    ws = torch.empty(ctx.transient_workspace_bytes(item, rects, trace, inp.dt_s, opts, every), dtype=torch.uint8,
+                     device=dev)
+    st = ctx.solve_transient(item, rects, trace, inp.dt_s, opts, snaps, every, workspace=ws)  # warm-up, table
+    torch.cuda.synchronize()
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        st = ctx.solve_transient(item, rects, trace, inp.dt_s, opts, snaps, every, workspace=ws)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / runs
+    ctx.set_timing(False)
+    kt = ctx.kernel_times()
+    ctx.set_timing(False)
+    # untimed: no per-kernel events
+    t0 = time.perf_counter()
+    ctx.solve_transient(item, rects, trace, inp.dt_s, opts, snaps, every, workspace=ws)
+    torch.cuda.synchronize()
+    wall_untimed = time.perf_counter() - t0
+    got = snaps.cpu().numpy().astype(np.float64)
+    item64, rects64, trace64, snaps64 = setup(torch.float64)
+    opts64 = V.make_options(V.F64, V.LEAK_EXP, inp.beta, 1, 1e-3)
+    ctx.solve_transient(item64, rects64, trace64, inp.dt_s, opts64, snaps64, every)
+    torch.cuda.synchronize()
+    ref = snaps64.cpu().numpy()
+    kernels = {}
+    for name in ("tr_row", "tr_col"):
+        v = kt.get(name)
+        if not v:
+            continue
+        avg = v["total_ms"] / v["count"]
+        kernels[name] = {"launches": v["count"], "avg_ms": avg,
+                         "GB/s": TRANSIENT_BYTES_PER_CELL[name] * n * n / (avg * 1e-3) / 1e9}
+    return {"workload": "transient 1024x1024 FP32, 1000 steps of 10 us, 64 blocks redrawn every 1 ms, "
+                        "leakage + variation, eta 1.3, snapshots every 100 steps",
+            "ms_per_run": round(wall_untimed * 1e3, 3), "ms_per_run_with_kernel_events": round(wall * 1e3, 3),
+            "steps_per_s": round(steps / wall_untimed, 1), "status": st["status"],
+            "dT_max_K": st["dT_max_K"], "fp64_shadow_max_diff_K": float(np.max(np.abs(got - ref))),
+            "kernels": kernels}
 
 
 def cpu_baseline(n: int, gpu_map0):
