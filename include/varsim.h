@@ -215,6 +215,84 @@ VARSIM_API varsim_status varsim_transient_workspace_size(varsim_ctx* ctx, const 
                                               const varsim_options* opts, size_t* bytes);
 
 /* ----------------------------------------------------------------------------------------
+ * Learned warm start.  The paper has no learned part (it argues against relying on learned
+ * thermal models); this network only proposes a starting iterate.  It maps the steady
+ * solve's own inputs -- dynamic power q, leakage variation v, conductivity map m and the die
+ * conductivity k0 -- to a predicted converged rise, which is passed as varsim_problem.dT_init;
+ * the fixed-point solve then decides the result, so a poor prediction costs iterations, not
+ * accuracy.  The network: the 4 x 4 patches of the standardized features
+ *     f = ((q / 1e6 - shift0) scale0, (ln v - shift1) scale1, (k0 m / 150 - shift2) scale2)
+ * enter a 1x1 "stem" convolution on the n/4 grid, then a five-level encoder-decoder of 3x3
+ * 'same' convolutions with ReLU (two per encoder level, 2x2 average pooling between levels;
+ * one per decoder level on [nearest-2x-upsampled coarser output, encoder skip]), and a 1x1
+ * head gives the 16 fine values of each coarse pixel, times out_scale.
+ * Parameters (FP32, this order and layout; convolution weights [cout][ky][kx][cin]):
+ *   stem.w [w0][48] (input index (py*4 + px)*3 + c), stem.b [w0];
+ *   enc<l>a.w [wl][3][3][w(l-1) | w0 for l = 0], enc<l>a.b, enc<l>b.w [wl][3][3][wl], enc<l>b.b,
+ *     l = 0..4;
+ *   dec<l>.w [wl][3][3][w(l+1) + wl] (upsampled channels first), dec<l>.b, l = 3, 2, 1, 0;
+ *   head.w [16][w0] (output (py*4 + px) of a coarse pixel), head.b [16].
+ * Arithmetic: BF16 activations and weights on the matrix cores, FP32 accumulation, FP32 master
+ * weights and Adam state.
+ */
+typedef struct varsim_net varsim_net;
+
+typedef struct varsim_net_config {
+  int32_t n;          /* input grid: a multiple of 64 in [64, 1024] */
+  int32_t width[5];   /* channels of the five levels: multiples of 16 in [16, 256] */
+  float shift[3];     /* feature standardisation (see above) */
+  float scale[3];
+  float out_scale;    /* predicted dT = out_scale * network output, K */
+  float k0_W_mK;      /* die conductivity at 300 K */
+} varsim_net_config;
+
+/* Creates a network with all parameters zero (set them with varsim_net_set_params). */
+VARSIM_API varsim_status varsim_net_create(varsim_ctx* ctx, const varsim_net_config* cfg, varsim_net** out);
+VARSIM_API void varsim_net_destroy(varsim_net* net);
+VARSIM_API varsim_status varsim_net_param_count(const varsim_net* net, int64_t* count);
+/* params: DEVICE float[param_count].  set also resets the Adam state. */
+VARSIM_API varsim_status varsim_net_set_params(varsim_net* net, const float* params, void* stream);
+VARSIM_API varsim_status varsim_net_get_params(varsim_net* net, float* params, void* stream);
+/* Workspace for a batch (training = 1: also the buffers of varsim_net_gradient). */
+VARSIM_API varsim_status varsim_net_workspace_size(varsim_net* net, int32_t batch, int32_t training,
+                                        size_t* bytes);
+/* Predicted rise of `batch` problems.  q_dyn, leak_var, cond_map: DEVICE float [*][n][n]
+ * (leak_var / cond_map NULL = 1); problem b reads map index sample_idx[b] (DEVICE int32, NULL =
+ * b).  dT_out: DEVICE float [batch][n][n].  Stream-ordered, does not synchronise. */
+VARSIM_API varsim_status varsim_net_forward(varsim_net* net, int32_t batch, const float* q_dyn,
+                                 const float* leak_var, const float* cond_map,
+                                 const int32_t* sample_idx, float* dT_out, void* workspace,
+                                 size_t ws_bytes, void* stream);
+/* Mean-squared error against target (DEVICE float [*][n][n], indexed like the inputs) and its
+ * gradient with respect to every parameter: grad DEVICE float[param_count], loss DEVICE
+ * float[1].  Stream-ordered. */
+VARSIM_API varsim_status varsim_net_gradient(varsim_net* net, int32_t batch, const float* q_dyn,
+                                  const float* leak_var, const float* cond_map,
+                                  const int32_t* sample_idx, const float* target, float* grad,
+                                  float* loss, void* workspace, size_t ws_bytes, void* stream);
+/* One Adam step (bias-corrected) on the FP32 master parameters with gradient grad. */
+VARSIM_API varsim_status varsim_net_adam(varsim_net* net, const float* grad, float lr, float beta1,
+                              float beta2, float eps, void* stream);
+
+/* One convolution layer on the matrix cores, for testing the kernels the network uses.
+ * Tensors are [batch][h][w][c] BF16 bit patterns (channels last); weights [cout][k][k][cin]
+ * BF16; cin, cout multiples of 16; k = 1 or 3 ('same' zero padding).
+ *   VARSIM_NN_FWD:   a = x, b = weights, bias (FP32 [cout] or NULL), relu -> out BF16 [..][cout]
+ *   VARSIM_NN_DGRAD: a = dz [..][cout], b = weights -> out FP32 [..][cin], the gradient of
+ *                    sum(dz * conv(x)) with respect to x
+ *   VARSIM_NN_WGRAD: a = x, b = dz -> out FP32 [cout][k][k][cin], its gradient with respect to
+ *                    the weights
+ * The workspace (varsim_nn_conv_workspace) holds transposed weights or partial sums.
+ * Synchronises `stream`. */
+enum { VARSIM_NN_FWD = 0, VARSIM_NN_DGRAD = 1, VARSIM_NN_WGRAD = 2 };
+VARSIM_API varsim_status varsim_nn_conv_workspace(int32_t op, int32_t k, int32_t batch, int32_t h,
+                                       int32_t w, int32_t cin, int32_t cout, size_t* bytes);
+VARSIM_API varsim_status varsim_nn_conv(varsim_ctx* ctx, int32_t op, int32_t k, int32_t batch,
+                             int32_t h, int32_t w, int32_t cin, int32_t cout, const uint16_t* a,
+                             const uint16_t* b, const float* bias, int32_t relu, void* out,
+                             void* workspace, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------
  * Kernel timing.  When enabled, every kernel launch of the solves is bracketed by HIP events
  * on the launch stream; varsim_kernel_times reports, per kernel class, the launch count and
  * the summed durations (ms) since the last reset.  Class names are returned in names[i]

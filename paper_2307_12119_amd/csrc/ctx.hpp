@@ -1,0 +1,130 @@
+// The library context and the helpers every entry point shares: error reporting and
+// optional per-kernel-class event timing.
+#pragma once
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace vs {
+
+struct TableEntry {
+  double* kper = nullptr;
+  double* lam64T = nullptr;
+  float* lam32T = nullptr;
+  double* coef64 = nullptr;
+  float* coef32 = nullptr;
+};
+
+struct TwEntry {
+  Cx<double>* tw64 = nullptr;
+  Cx<float>* tw32 = nullptr;
+  Cx<double>* qw64 = nullptr;
+  Cx<float>* qw32 = nullptr;
+};
+
+using TableKey = std::tuple<int, int, double, double, double, double>;
+
+struct TimedEvent {
+  const char* cls;
+  hipEvent_t a, b;
+};
+
+}  // namespace vs
+
+struct varsim_ctx {
+  using TableKey = vs::TableKey;
+  using TableEntry = vs::TableEntry;
+  using TwEntry = vs::TwEntry;
+  using TimedEvent = vs::TimedEvent;
+  using MapPtrs = vs::MapPtrs;
+  using PrepArgs = vs::PrepArgs;
+  int device = 0;
+  std::string err;
+  std::map<TableKey, TableEntry> tables;
+  std::map<int, TwEntry> twiddles;
+  bool timing = false;
+  std::vector<TimedEvent> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<long long, double>> times;
+  std::vector<const char*> class_names;
+  int* active_dev = nullptr;   // [2] device counters of maps still iterating
+  int* active_host = nullptr;  // [2] pinned host copies
+  hipEvent_t active_ev[2] = {nullptr, nullptr};
+  // host staging of per-call descriptor arrays (kept alive until the call returns)
+  std::vector<MapPtrs> h_maps;
+  std::vector<PrepArgs> h_prep;
+  std::vector<varsim_stats> h_stats;
+  MapPtrs* conv_maps = nullptr;
+  size_t conv_maps_cap = 0;
+};
+
+namespace {
+
+inline varsim_status fail(varsim_ctx* c, varsim_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                            \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return fail(ctx, VARSIM_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+inline hipEvent_t take_event(varsim_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+template <class F>
+hipError_t timed(varsim_ctx* c, const char* cls, hipStream_t s, F&& f) {
+  if (!c->timing) return f();
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return hipErrorOutOfMemory;
+  (void)hipEventRecord(a, s);
+  const hipError_t e = f();
+  (void)hipEventRecord(b, s);
+  c->pending.push_back({cls, a, b});
+  return e;
+}
+
+inline void flush_timing(varsim_ctx* c) {
+  for (auto& p : c->pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    auto& slot = c->times[p.cls];
+    if (slot.first == 0 &&
+        std::find_if(c->class_names.begin(), c->class_names.end(), [&](const char* n) { return !strcmp(n, p.cls); }) ==
+            c->class_names.end())
+      c->class_names.push_back(p.cls);
+    slot.first += 1;
+    slot.second += ms;
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+}  // namespace

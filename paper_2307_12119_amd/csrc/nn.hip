@@ -1,0 +1,564 @@
+// Device kernels of the convolutional warm-start surrogate (gfx950, BF16 MFMA, FP32 accumulate).
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16: M = output channels, N = pixels,
+// K = taps x input channels.  A lane supplies row (lane % 16) of A and column (lane % 16) of B,
+// each with the same 8 consecutive K values (group lane / 16); with channels last and the input
+// channel count a multiple of 16, those 8 values are one 16-byte load from one pixel and one tap.
+// The output tile comes back as D[4 (lane / 16) + r][lane % 16], r = 0..3: four consecutive
+// output channels of one pixel, one vector store.  The same kernel computes the input gradient
+// with tap-reversed, channel-transposed weights.  The weight gradient contracts over pixels: its
+// operand tiles are staged through LDS transposed so that K (pixels) is contiguous, and chunks
+// of pixels write partial sums that a second kernel adds in a fixed order.
+#include <cmath>
+
+#include "nn.hpp"
+
+namespace vs {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 ld16(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ __forceinline__ bf16x8 as_bf(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((unsigned)h << 16); }
+__device__ __forceinline__ unsigned pack2(float a, float b) { return (unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16); }
+
+// ------------------------------------------------------------------------------ convolution
+template <int KS, int MW, int NW, int EPI, bool RELU>
+__global__ void __launch_bounds__(256) conv_kernel(NnConv a) {
+  constexpr int TAPS = KS * KS, R = KS / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int H = a.H, W = a.W, cu = a.cu, cx = a.cx, cin = cu + cx;
+  const long HW = (long)H * W;
+  const long P = (long)a.B * HW;
+  const long p0 = ((long)blockIdx.x * 4 + wave) * (16 * NW);
+  const int co0 = blockIdx.y * (16 * MW);
+  int pb[NW], py[NW], px[NW];
+  bool pv[NW];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const long p = p0 + j * 16 + lr;
+    pv[j] = p < P;
+    const long q = pv[j] ? p : 0;
+    pb[j] = (int)(q / HW);
+    const int rem = (int)(q - (long)pb[j] * HW);
+    py[j] = rem / W;
+    px[j] = rem - py[j] * W;
+  }
+  f32x4 acc[MW][NW];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+
+  for (int tap = 0; tap < TAPS; ++tap) {
+    const int dy = tap / KS - R, dx = tap % KS - R;
+    for (int c0 = 0; c0 < cin; c0 += 32) {
+      const int ci = c0 + 8 * lg;
+      const bool kv = ci < cin;
+      const bool up = ci < cu;
+      uint4 av[MW], bv[NW];
+#pragma unroll
+      for (int i = 0; i < MW; ++i) {
+        const int co = co0 + i * 16 + lr;
+        av[i] = kv ? ld16(a.w + ((long)co * TAPS + tap) * cin + ci) : z4;
+      }
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const int yy = py[j] + dy, xx = px[j] + dx;
+        const bool in = kv && pv[j] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const uint16_t* src = up ? a.xu + (((long)pb[j] * (H >> 1) + (yy >> 1)) * (W >> 1) + (xx >> 1)) * cu + ci
+                                 : a.x + (((long)pb[j] * H + yy) * W + xx) * cx + (ci - cu);
+        bv[j] = in ? ld16(src) : z4;
+      }
+#pragma unroll
+      for (int i = 0; i < MW; ++i)
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av[i]), as_bf(bv[j]), acc[i][j], 0, 0, 0);
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < MW; ++i) {
+    const int co = co0 + i * 16 + 4 * lg;
+    float bias[4] = {0.f, 0.f, 0.f, 0.f};
+    if (a.bias)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bias[r] = a.bias[co + r];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      if (!pv[j]) continue;
+      const long p = p0 + j * 16 + lr;
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = acc[i][j][r] + bias[r];
+        if (RELU) v[r] = fmaxf(v[r], 0.f);
+      }
+      if constexpr (EPI == NN_EPI_BF16) {
+        *reinterpret_cast<uint2*>((uint16_t*)a.y + p * a.cout + co) = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+      } else if constexpr (EPI == NN_EPI_F32) {
+        *reinterpret_cast<float4*>((float*)a.y + p * a.cout + co) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        // cout = 16: output channel co + r = 4 lg + r is sub-pixel (lg, r) of the 4x4 patch
+        float* out = (float*)a.y + ((long)pb[j] * (4 * H) + 4 * py[j] + lg) * (4L * W) + 4 * px[j];
+        const float s = a.out_scale;
+        *reinterpret_cast<float4*>(out) = make_float4(s * v[0], s * v[1], s * v[2], s * v[3]);
+      }
+    }
+  }
+}
+
+template <int KS, int MW, int NW, int EPI, bool RELU>
+hipError_t conv_launch(const NnConv& a, hipStream_t s) {
+  const long P = (long)a.B * a.H * a.W;
+  const dim3 grid((unsigned)((P + 64 * NW - 1) / (64 * NW)), a.cout / (16 * MW));
+  hipLaunchKernelGGL((conv_kernel<KS, MW, NW, EPI, RELU>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int KS, int EPI, bool RELU>
+hipError_t conv_tile(const NnConv& a, hipStream_t s) {
+  if (a.cout % 64 == 0) return conv_launch<KS, 4, 2, EPI, RELU>(a, s);
+  if (a.cout % 32 == 0) return conv_launch<KS, 2, 4, EPI, RELU>(a, s);
+  return conv_launch<KS, 1, 8, EPI, RELU>(a, s);
+}
+
+template <int KS>
+hipError_t conv_ks(int epi, bool relu, const NnConv& a, hipStream_t s) {
+  switch (epi) {
+    case NN_EPI_BF16: return relu ? conv_tile<KS, NN_EPI_BF16, true>(a, s) : conv_tile<KS, NN_EPI_BF16, false>(a, s);
+    case NN_EPI_F32: return conv_tile<KS, NN_EPI_F32, false>(a, s);
+    case NN_EPI_SHUFFLE:
+      if (a.cout != 16) return hipErrorInvalidValue;
+      return conv_launch<KS, 1, 8, NN_EPI_SHUFFLE, false>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ------------------------------------------------------------------------------ weight gradient
+constexpr int kWgPitch = 40;  // LDS row pitch (elements): 32 pixels + pad, rows 16-byte aligned
+
+template <int KS>
+__global__ void __launch_bounds__(256) wgrad_kernel(NnConv a, const uint16_t* __restrict__ dz, float* __restrict__ part,
+                                                    long chunk) {
+  constexpr int TAPS = KS * KS, R = KS / 2;
+  __shared__ __attribute__((aligned(16))) uint16_t sz[64 * kWgPitch];
+  __shared__ __attribute__((aligned(16))) uint16_t sx[64 * kWgPitch];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lg = lane >> 4;
+  const int H = a.H, W = a.W, cu = a.cu, cx = a.cx, cin = cu + cx, cout = a.cout;
+  const long HW = (long)H * W, P = (long)a.B * HW;
+  const int tap = blockIdx.y, dy = tap / KS - R, dx = tap % KS - R;
+  const int nco = (cout + 63) / 64;
+  const int cob = (int)(blockIdx.z % nco) * 64, cib = (int)(blockIdx.z / nco) * 64;
+  const int wco = (wave >> 1) * 32, wci = (wave & 1) * 32;
+  const long pbeg = (long)blockIdx.x * chunk;
+  const long pend = P < pbeg + chunk ? P : pbeg + chunk;
+  const int sp = t >> 3, c8 = (t & 7) * 8;  // staging: pixel sp of the step, channels c8..c8+7
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (long p = pbeg; p < pend; p += 32) {
+    const long q = p + sp;
+    const bool pv = q < pend;
+    const int co = cob + c8, ci = cib + c8;
+    const uint4 vz = (pv && co < cout) ? ld16(dz + q * cout + co) : z4;
+    uint4 vx = z4;
+    if (pv && ci < cin) {
+      const int b = (int)(q / HW);
+      const int rem = (int)(q - (long)b * HW);
+      const int yy = rem / W + dy, xx = rem % W + dx;
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+        vx = ci < cu ? ld16(a.xu + (((long)b * (H >> 1) + (yy >> 1)) * (W >> 1) + (xx >> 1)) * cu + ci)
+                     : ld16(a.x + (((long)b * H + yy) * W + xx) * cx + (ci - cu));
+    }
+    __syncthreads();  // the previous step's operand reads are done
+    const uint16_t* ez = reinterpret_cast<const uint16_t*>(&vz);
+    const uint16_t* ex = reinterpret_cast<const uint16_t*>(&vx);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      sz[(c8 + e) * kWgPitch + sp] = ez[e];
+      sx[(c8 + e) * kWgPitch + sp] = ex[e];
+    }
+    __syncthreads();
+    uint4 av[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) av[i] = *reinterpret_cast<const uint4*>(sz + (wco + i * 16 + lr) * kWgPitch + 8 * lg);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const uint4*>(sx + (wci + j * 16 + lr) * kWgPitch + 8 * lg);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av[i]), as_bf(bv[j]), acc[i][j], 0, 0, 0);
+  }
+
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = cob + wco + i * 16 + 4 * lg + r, ci = cib + wci + j * 16 + lr;
+        if (co < cout && ci < cin) part[(((long)blockIdx.x * cout + co) * TAPS + tap) * cin + ci] = acc[i][j][r];
+      }
+}
+
+__global__ void __launch_bounds__(256) reduce_parts_kernel(const float* __restrict__ part, int ns, int cout, int taps,
+                                                           int cin_src, int cin_dst, float* __restrict__ out) {
+  const long n = (long)cout * taps * cin_dst, len = (long)cout * taps * cin_src;
+  for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
+    const long rt = j / cin_dst;
+    const long src = rt * cin_src + (j - rt * cin_dst);
+    float s = 0.f;
+    for (int k = 0; k < ns; ++k) s += part[k * len + src];
+    out[j] = s;
+  }
+}
+
+// ------------------------------------------------------------------------------ elementwise
+__global__ void __launch_bounds__(256) relu_bwd_kernel(const float* __restrict__ da, const float* __restrict__ dpool,
+                                                       const uint16_t* __restrict__ act, uint16_t* __restrict__ dz,
+                                                       int B, int H, int W, int C, float* __restrict__ part) {
+  __shared__ float s[256];
+  for (int i = threadIdx.x; i < C; i += 256) s[i] = 0.f;
+  __syncthreads();
+  const long n = (long)B * H * W * C;
+  for (long e = ((long)blockIdx.x * 256 + threadIdx.x) * 8; e < n; e += (long)gridDim.x * 256 * 8) {
+    const long p = e / C;
+    const int c = (int)(e - p * C);
+    float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (da) {
+      const float4 lo = *reinterpret_cast<const float4*>(da + e), hi = *reinterpret_cast<const float4*>(da + e + 4);
+      g[0] = lo.x, g[1] = lo.y, g[2] = lo.z, g[3] = lo.w, g[4] = hi.x, g[5] = hi.y, g[6] = hi.z, g[7] = hi.w;
+    }
+    if (dpool) {
+      const long HW = (long)H * W;
+      const int b = (int)(p / HW);
+      const int rem = (int)(p - (long)b * HW);
+      const int y = rem / W, x = rem % W;
+      const float* d = dpool + (((long)b * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1)) * C + c;
+      const float4 lo = *reinterpret_cast<const float4*>(d), hi = *reinterpret_cast<const float4*>(d + 4);
+      g[0] += 0.25f * lo.x, g[1] += 0.25f * lo.y, g[2] += 0.25f * lo.z, g[3] += 0.25f * lo.w;
+      g[4] += 0.25f * hi.x, g[5] += 0.25f * hi.y, g[6] += 0.25f * hi.z, g[7] += 0.25f * hi.w;
+    }
+    if (act) {
+      const uint4 u = ld16(act + e);
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(&u);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (!(bf2f(h[k]) > 0.f)) g[k] = 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) atomicAdd(&s[c + k], g[k]);
+    if (dz)
+      *reinterpret_cast<uint4*>(dz + e) = make_uint4(pack2(g[0], g[1]), pack2(g[2], g[3]), pack2(g[4], g[5]),
+                                                     pack2(g[6], g[7]));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < C; i += 256) part[(long)blockIdx.x * C + i] = s[i];
+}
+
+__global__ void colsum_kernel(const float* __restrict__ part, int nb, int stride, int C, float scale,
+                              float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  float s = 0.f;
+  for (int b = 0; b < nb; ++b) s += part[(long)b * stride + c];
+  out[c] = scale * s;
+}
+
+// y = 2x2 mean of x; one thread per (coarse pixel, 8 channels)
+__global__ void __launch_bounds__(256) avgpool_kernel(const uint16_t* __restrict__ x, uint16_t* __restrict__ y, int B,
+                                                      int Hc, int Wc, int C) {
+  const int g8 = C / 8;
+  const long n = (long)B * Hc * Wc * g8;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long pc = i / g8;
+    const int c = (int)(i - pc * g8) * 8;
+    const int b = (int)(pc / ((long)Hc * Wc));
+    const int rem = (int)(pc - (long)b * Hc * Wc);
+    const int Y = rem / Wc, X = rem % Wc;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const long pf = ((long)b * 2 * Hc + 2 * Y + (d >> 1)) * (2L * Wc) + 2 * X + (d & 1);
+      const uint4 u = ld16(x + pf * C + c);
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(&u);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[k] += bf2f(h[k]);
+    }
+    *reinterpret_cast<uint4*>(y + pc * C + c) =
+        make_uint4(pack2(0.25f * acc[0], 0.25f * acc[1]), pack2(0.25f * acc[2], 0.25f * acc[3]),
+                   pack2(0.25f * acc[4], 0.25f * acc[5]), pack2(0.25f * acc[6], 0.25f * acc[7]));
+  }
+}
+
+// dcoarse[pc][c] = sum of the 2x2 fine dcat[.][c], c < cu
+__global__ void __launch_bounds__(256) upsample_grad_kernel(const float* __restrict__ dcat, int C, int cu,
+                                                            float* __restrict__ dcoarse, int B, int Hc, int Wc) {
+  const int g4 = cu / 4;
+  const long n = (long)B * Hc * Wc * g4;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long pc = i / g4;
+    const int c = (int)(i - pc * g4) * 4;
+    const int b = (int)(pc / ((long)Hc * Wc));
+    const int rem = (int)(pc - (long)b * Hc * Wc);
+    const int Y = rem / Wc, X = rem % Wc;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const long pf = ((long)b * 2 * Hc + 2 * Y + (d >> 1)) * (2L * Wc) + 2 * X + (d & 1);
+      const float4 v = *reinterpret_cast<const float4*>(dcat + pf * C + c);
+      s.x += v.x, s.y += v.y, s.z += v.z, s.w += v.w;
+    }
+    *reinterpret_cast<float4*>(dcoarse + pc * cu + c) = s;
+  }
+}
+
+__global__ void __launch_bounds__(256) slice_kernel(const float* __restrict__ dcat, int C, int cu, int cx,
+                                                    float* __restrict__ dskip, long P) {
+  const int g4 = cx / 4;
+  const long n = P * g4;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long p = i / g4;
+    const int c = (int)(i - p * g4) * 4;
+    *reinterpret_cast<float4*>(dskip + p * cx + c) = *reinterpret_cast<const float4*>(dcat + p * C + cu + c);
+  }
+}
+
+// one thread per coarse pixel: the 48 standardized patch features, padded to 64
+__global__ void __launch_bounds__(256) features_kernel(const float* __restrict__ q, const float* __restrict__ v,
+                                                       const float* __restrict__ m, const int* __restrict__ idx, int n,
+                                                       int B, NnFeat f, uint16_t* __restrict__ out) {
+  const int mc = n / 4;
+  const long total = (long)B * mc * mc;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(i / ((long)mc * mc));
+    const int rem = (int)(i - (long)b * mc * mc);
+    const int Y = rem / mc, X = rem % mc;
+    const long s = idx ? idx[b] : b;
+    float feat[64];
+#pragma unroll
+    for (int py = 0; py < 4; ++py) {
+      const long o = s * n * n + (long)(4 * Y + py) * n + 4 * X;
+      const float4 qq = *reinterpret_cast<const float4*>(q + o);
+      const float4 vv = v ? *reinterpret_cast<const float4*>(v + o) : make_float4(1.f, 1.f, 1.f, 1.f);
+      const float4 mm = m ? *reinterpret_cast<const float4*>(m + o) : make_float4(1.f, 1.f, 1.f, 1.f);
+      const float qa[4] = {qq.x, qq.y, qq.z, qq.w}, va[4] = {vv.x, vv.y, vv.z, vv.w}, ma[4] = {mm.x, mm.y, mm.z, mm.w};
+#pragma unroll
+      for (int px = 0; px < 4; ++px) {
+        const int k = (py * 4 + px) * 3;
+        feat[k] = (qa[px] * 1e-6f - f.shift[0]) * f.scale[0];
+        feat[k + 1] = (logf(va[px]) - f.shift[1]) * f.scale[1];
+        feat[k + 2] = (f.k0 * ma[px] * (1.f / 150.f) - f.shift[2]) * f.scale[2];
+      }
+    }
+#pragma unroll
+    for (int k = 48; k < 64; ++k) feat[k] = 0.f;
+    uint4* o = reinterpret_cast<uint4*>(out + i * 64);
+#pragma unroll
+    for (int w = 0; w < 8; ++w)
+      o[w] = make_uint4(pack2(feat[8 * w], feat[8 * w + 1]), pack2(feat[8 * w + 2], feat[8 * w + 3]),
+                        pack2(feat[8 * w + 4], feat[8 * w + 5]), pack2(feat[8 * w + 6], feat[8 * w + 7]));
+  }
+}
+
+__global__ void __launch_bounds__(256) mse_grad_kernel(const float* __restrict__ y, const float* __restrict__ t,
+                                                       const int* __restrict__ idx, int n, int B, float out_scale,
+                                                       uint16_t* __restrict__ dh, float* __restrict__ part) {
+  __shared__ float s[17];
+  if (threadIdx.x < 17) s[threadIdx.x] = 0.f;
+  __syncthreads();
+  const int mc = n / 4;
+  const long total = (long)B * mc * mc;
+  const float k = 2.f / ((float)B * (float)n * (float)n);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(i / ((long)mc * mc));
+    const int rem = (int)(i - (long)b * mc * mc);
+    const int Y = rem / mc, X = rem % mc;
+    const long st = idx ? idx[b] : b;
+    float g[16];
+    float sq = 0.f;
+#pragma unroll
+    for (int py = 0; py < 4; ++py) {
+      const float4 yy = *reinterpret_cast<const float4*>(y + ((long)b * n + 4 * Y + py) * n + 4 * X);
+      const float4 tt = *reinterpret_cast<const float4*>(t + (st * n + 4 * Y + py) * n + 4 * X);
+      const float d[4] = {yy.x - tt.x, yy.y - tt.y, yy.z - tt.z, yy.w - tt.w};
+#pragma unroll
+      for (int px = 0; px < 4; ++px) {
+        sq += d[px] * d[px];
+        g[py * 4 + px] = out_scale * k * d[px];
+      }
+    }
+    uint4* o = reinterpret_cast<uint4*>(dh + i * 16);
+    o[0] = make_uint4(pack2(g[0], g[1]), pack2(g[2], g[3]), pack2(g[4], g[5]), pack2(g[6], g[7]));
+    o[1] = make_uint4(pack2(g[8], g[9]), pack2(g[10], g[11]), pack2(g[12], g[13]), pack2(g[14], g[15]));
+#pragma unroll
+    for (int j = 0; j < 16; ++j) atomicAdd(&s[j], g[j]);
+    atomicAdd(&s[16], sq);
+  }
+  __syncthreads();
+  if (threadIdx.x < 17) part[(long)blockIdx.x * 17 + threadIdx.x] = s[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                                   const float* __restrict__ g, long n, float lr, float b1, float b2,
+                                                   float eps, float bc1, float bc2) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+}
+
+__device__ __forceinline__ uint16_t to_bf(float x) { return f2bf(x); }
+__device__ __forceinline__ uint16_t to_bf(uint16_t x) { return x; }
+
+template <typename S>
+__global__ void __launch_bounds__(256) weight_cast_kernel(const S* __restrict__ src, int cout, int taps, int cin_src,
+                                                          int cin_pad, uint16_t* __restrict__ dst,
+                                                          uint16_t* __restrict__ dstT) {
+  const long n = (long)cout * taps * cin_pad;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int ci = (int)(i % cin_pad);
+    const long rt = i / cin_pad;
+    const int tap = (int)(rt % taps), co = (int)(rt / taps);
+    const uint16_t h = ci < cin_src ? to_bf(src[rt * cin_src + ci]) : (uint16_t)0;
+    if (dst) dst[i] = h;
+    if (dstT) dstT[((long)ci * taps + (taps - 1 - tap)) * cout + co] = h;
+  }
+}
+
+unsigned blocks_for(long n, int per_thread = 1, unsigned cap = 4096) {
+  const long b = (n / per_thread + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+hipError_t nn_conv(int ks, int epi, bool relu, const NnConv& a, hipStream_t s) {
+  if ((a.cu % 16) || (a.cx % 16) || a.cu + a.cx <= 0 || (a.cout % 16) || a.cout <= 0 || a.B <= 0 || a.H <= 0 ||
+      a.W <= 0 || (a.cu && ((a.H | a.W) & 1)))
+    return hipErrorInvalidValue;
+  if (ks == 1) return conv_ks<1>(epi, relu, a, s);
+  if (ks == 3) return conv_ks<3>(epi, relu, a, s);
+  return hipErrorInvalidValue;
+}
+
+int nn_wgrad_splits(long pixels) {
+  const long s = (pixels + 2047) / 2048;
+  return (int)(s < 1 ? 1 : (s > kNnMaxSplit ? kNnMaxSplit : s));
+}
+
+hipError_t nn_wgrad(int ks, const NnConv& a, const uint16_t* dz, float* part, int n_split, hipStream_t s) {
+  if ((a.cu % 16) || (a.cx % 16) || (a.cout % 16) || n_split < 1 || n_split > kNnMaxSplit) return hipErrorInvalidValue;
+  const long P = (long)a.B * a.H * a.W;
+  long chunk = (P + n_split - 1) / n_split;
+  chunk = (chunk + 31) / 32 * 32;
+  const int cin = a.cu + a.cx;
+  const dim3 grid(n_split, ks * ks, ((a.cout + 63) / 64) * ((cin + 63) / 64));
+  if (ks == 1)
+    hipLaunchKernelGGL(wgrad_kernel<1>, grid, dim3(256), 0, s, a, dz, part, chunk);
+  else if (ks == 3)
+    hipLaunchKernelGGL(wgrad_kernel<3>, grid, dim3(256), 0, s, a, dz, part, chunk);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t nn_reduce_parts(const float* part, int n_split, int cout, int taps, int cin_src, int cin_dst, float* out,
+                           hipStream_t s) {
+  const long n = (long)cout * taps * cin_dst;
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(n)), dim3(256), 0, s, part, n_split, cout, taps, cin_src,
+                     cin_dst, out);
+  return hipGetLastError();
+}
+
+hipError_t nn_relu_bwd(const float* da, const float* dpool, const uint16_t* act, uint16_t* dz, int B, int H, int W,
+                       int C, float* part, hipStream_t s) {
+  if (C % 8 || C > 256 || (dpool && ((H | W) & 1))) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(relu_bwd_kernel, dim3(kNnReluBlocks), dim3(256), 0, s, da, dpool, act, dz, B, H, W, C, part);
+  return hipGetLastError();
+}
+
+hipError_t nn_colsum(const float* part, int nb, int stride, int C, float scale, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_kernel, dim3((C + 63) / 64), dim3(64), 0, s, part, nb, stride, C, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t nn_avgpool(const uint16_t* x, uint16_t* y, int B, int Hc, int Wc, int C, hipStream_t s) {
+  if (C % 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(avgpool_kernel, dim3(blocks_for((long)B * Hc * Wc * (C / 8))), dim3(256), 0, s, x, y, B, Hc, Wc,
+                     C);
+  return hipGetLastError();
+}
+
+hipError_t nn_split_cat_grad(const float* dcat, int cu, int cx, float* dcoarse, float* dskip, int B, int H, int W,
+                             hipStream_t s) {
+  if ((cu % 4) || (cx % 4) || ((H | W) & 1)) return hipErrorInvalidValue;
+  const int C = cu + cx;
+  if (dcoarse && cu) {
+    hipLaunchKernelGGL(upsample_grad_kernel, dim3(blocks_for((long)B * (H / 2) * (W / 2) * (cu / 4))), dim3(256), 0, s,
+                       dcat, C, cu, dcoarse, B, H / 2, W / 2);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (dskip && cx) {
+    const long P = (long)B * H * W;
+    hipLaunchKernelGGL(slice_kernel, dim3(blocks_for(P * (cx / 4))), dim3(256), 0, s, dcat, C, cu, cx, dskip, P);
+  }
+  return hipGetLastError();
+}
+
+hipError_t nn_features(const float* q, const float* v, const float* m, const int* idx, int n, int B, NnFeat f,
+                       uint16_t* out, hipStream_t s) {
+  if (n % 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(features_kernel, dim3(blocks_for((long)B * (n / 4) * (n / 4))), dim3(256), 0, s, q, v, m, idx, n,
+                     B, f, out);
+  return hipGetLastError();
+}
+
+hipError_t nn_mse_grad(const float* y, const float* t, const int* idx, int n, int B, float out_scale, uint16_t* dh,
+                       float* part, hipStream_t s) {
+  if (n % 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mse_grad_kernel, dim3(kNnMseBlocks), dim3(256), 0, s, y, t, idx, n, B, out_scale, dh, part);
+  return hipGetLastError();
+}
+
+hipError_t nn_adam(float* p, float* m, float* v, const float* g, long n, float lr, float b1, float b2, float eps,
+                   float bc1, float bc2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, s, p, m, v, g, n, lr, b1, b2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t nn_weight_cast(const float* src, int cout, int taps, int cin_src, int cin_pad, uint16_t* dst,
+                          uint16_t* dstT, hipStream_t s) {
+  const long n = (long)cout * taps * cin_pad;
+  hipLaunchKernelGGL(weight_cast_kernel<float>, dim3(blocks_for(n)), dim3(256), 0, s, src, cout, taps, cin_src, cin_pad,
+                     dst, dstT);
+  return hipGetLastError();
+}
+
+hipError_t nn_weight_cast_bf16(const uint16_t* src, int cout, int taps, int cin_src, int cin_pad, uint16_t* dst,
+                               uint16_t* dstT, hipStream_t s) {
+  const long n = (long)cout * taps * cin_pad;
+  hipLaunchKernelGGL(weight_cast_kernel<uint16_t>, dim3(blocks_for(n)), dim3(256), 0, s, src, cout, taps, cin_src,
+                     cin_pad, dst, dstT);
+  return hipGetLastError();
+}
+
+}  // namespace vs

@@ -1,0 +1,78 @@
+// Host-side declarations of the surrogate's device kernels (BF16 MFMA convolutions and the
+// elementwise / reduction pieces of its training step).
+#pragma once
+
+#include "common.hpp"
+
+namespace vs {
+
+// One convolution launch.  Activations are [B][H][W][C] BF16 (bit patterns), channels last.
+// The input is the concatenation of two sources along channels: the first `cu` channels come
+// from `xu`, a [B][H/2][W/2][cu] tensor read through nearest 2x upsampling (or cu = 0), the
+// remaining `cx` channels from `x` ([B][H][W][cx]).  Weights: [cout][ks*ks][cu + cx] BF16.
+struct NnConv {
+  const uint16_t* x;
+  const uint16_t* xu;
+  int cu, cx;
+  const uint16_t* w;
+  const float* bias;  // [cout] or null
+  void* y;            // output, see NnEpi
+  int B, H, W, cout;
+  float out_scale;    // NN_EPI_SHUFFLE only
+};
+
+enum NnEpi : int {
+  NN_EPI_BF16 = 0,       // y: [B][H][W][cout] BF16 of (acc + bias), ReLU if requested
+  NN_EPI_F32 = 1,        // y: [B][H][W][cout] FP32 of (acc + bias)
+  NN_EPI_SHUFFLE = 2,    // cout = 16: y[b][4Y + j/4][4X + j%4] = out_scale (acc_j + bias_j), [B][4H][4W] FP32
+};
+
+hipError_t nn_conv(int ks, int epi, bool relu, const NnConv& a, hipStream_t s);
+
+// Weight gradient: part[s][cout][ks*ks][cin] = sum over pixel chunk s of dz (x) shifted input.
+// Returns the number of chunks through *n_split (<= kNnMaxSplit).
+constexpr int kNnMaxSplit = 256;
+int nn_wgrad_splits(long pixels);
+hipError_t nn_wgrad(int ks, const NnConv& a, const uint16_t* dz, float* part, int n_split, hipStream_t s);
+// out[co][t][ci] (ci < cin_dst) = sum_s part[s][co][t][ci] (part has cin_src columns)
+hipError_t nn_reduce_parts(const float* part, int n_split, int cout, int taps, int cin_src, int cin_dst, float* out,
+                           hipStream_t s);
+
+// dz = BF16 of g * [act > 0] (act may be null: no mask), g = da[p][c] + 0.25 dpool[coarse(p)][c]
+// (either may be null); per-channel sums of g into part[block][C].
+constexpr int kNnReluBlocks = 512;
+hipError_t nn_relu_bwd(const float* da, const float* dpool, const uint16_t* act, uint16_t* dz, int B, int H, int W,
+                       int C, float* part, hipStream_t s);
+// out[c] = scale * sum_b part[b * stride + c], b < nb, c < C
+hipError_t nn_colsum(const float* part, int nb, int stride, int C, float scale, float* out, hipStream_t s);
+
+hipError_t nn_avgpool(const uint16_t* x, uint16_t* y, int B, int Hc, int Wc, int C, hipStream_t s);
+// dcoarse[b][Y][X][c] = sum of the 2x2 fine values of dcat[.][c] (c < cu); dskip[p][c] = dcat[p][cu + c]
+hipError_t nn_split_cat_grad(const float* dcat, int cu, int cx, float* dcoarse, float* dskip, int B, int H, int W,
+                             hipStream_t s);
+
+struct NnFeat {
+  float shift[3], scale[3];
+  float k0;
+};
+// [B][n][n] FP32 maps (sample b at idx[b] when idx is given; v, m may be null = 1) ->
+// [B][n/4][n/4][64] BF16: feature (py*4 + px)*3 + c of the 4x4 patch, 48..63 zero
+hipError_t nn_features(const float* q, const float* v, const float* m, const int* idx, int n, int B, NnFeat f,
+                       uint16_t* out, hipStream_t s);
+// dh[b][Y][X][j] = BF16 of out_scale * 2 (y - t) / (B n^2) at fine pixel (4Y + j/4, 4X + j%4);
+// part[block][17] = per-block sums of the 16 FP32 dh values and of (y - t)^2
+constexpr int kNnMseBlocks = 256;
+hipError_t nn_mse_grad(const float* y, const float* t, const int* idx, int n, int B, float out_scale, uint16_t* dh,
+                       float* part, hipStream_t s);
+
+hipError_t nn_adam(float* p, float* m, float* v, const float* g, long n, float lr, float b1, float b2, float eps,
+                   float bc1, float bc2, hipStream_t s);
+// BF16 copies of one layer's weights src[cout][taps][cin_src] (FP32, or BF16 bit patterns):
+// dst[cout][taps][cin_pad] (zero padded) and dstT[cin_pad][taps][cout] with the taps reversed
+// (the input-gradient weights); either output may be null
+hipError_t nn_weight_cast(const float* src, int cout, int taps, int cin_src, int cin_pad, uint16_t* dst,
+                          uint16_t* dstT, hipStream_t s);
+hipError_t nn_weight_cast_bf16(const uint16_t* src, int cout, int taps, int cin_src, int cin_pad, uint16_t* dst,
+                               uint16_t* dstT, hipStream_t s);
+
+}  // namespace vs

@@ -61,6 +61,13 @@ class Transient(Structure):
                 ("block_rects", c_void_p), ("trace", c_void_p), ("tau_model", c_int32)]
 
 
+class NetConfig(Structure):
+    _fields_ = [("n", c_int32), ("width", c_int32 * 5), ("shift", ctypes.c_float * 3), ("scale", ctypes.c_float * 3),
+                ("out_scale", ctypes.c_float), ("k0_W_mK", ctypes.c_float)]
+
+
+NN_FWD, NN_DGRAD, NN_WGRAD = 0, 1, 2
+
 EXPORTS = {
     "varsim_create": (c_int, [c_int, POINTER(c_void_p)]),
     "varsim_destroy": (None, [c_void_p]),
@@ -77,6 +84,22 @@ EXPORTS = {
                                        c_void_p, c_size_t, POINTER(Stats), c_void_p]),
     "varsim_transient_workspace_size": (c_int, [c_void_p, POINTER(Problem), POINTER(Transient), POINTER(Options),
                                                 POINTER(c_size_t)]),
+    "varsim_net_create": (c_int, [c_void_p, POINTER(NetConfig), POINTER(c_void_p)]),
+    "varsim_net_destroy": (None, [c_void_p]),
+    "varsim_net_param_count": (c_int, [c_void_p, POINTER(c_int64)]),
+    "varsim_net_set_params": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "varsim_net_get_params": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "varsim_net_workspace_size": (c_int, [c_void_p, c_int32, c_int32, POINTER(c_size_t)]),
+    "varsim_net_forward": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_size_t, c_void_p]),
+    "varsim_net_gradient": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_void_p, c_size_t, c_void_p]),
+    "varsim_net_adam": (c_int, [c_void_p, c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                c_void_p]),
+    "varsim_nn_conv_workspace": (c_int, [c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32,
+                                         POINTER(c_size_t)]),
+    "varsim_nn_conv": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, c_void_p,
+                               c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "varsim_set_timing": (c_int, [c_void_p, c_int32]),
     "varsim_kernel_times": (c_int, [c_void_p, POINTER(c_char_p), POINTER(c_int64), POINTER(c_double),
                                     POINTER(c_int32)]),
@@ -297,3 +320,113 @@ class Context:
         n = c_int32(cap)
         self._check(self.lib.varsim_kernel_times(self.handle, names, counts, tot, ctypes.byref(n)))
         return {names[i].decode(): {"count": counts[i], "total_ms": tot[i]} for i in range(n.value)}
+
+
+# ------------------------------------------------------------------------------- surrogate
+@dataclass
+class NetSpec:
+    """Configuration of the learned warm start (fields of varsim_net_config)."""
+    n: int = 512
+    width: tuple = (32, 48, 64, 96, 128)
+    shift: tuple = (1.0, 0.0, 1.0)
+    scale: tuple = (1.0, 1.0 / 0.73, 20.0)
+    out_scale: float = 10.0
+    k0: float = 150.0
+
+    def c_config(self) -> NetConfig:
+        c = NetConfig()
+        c.n = self.n
+        for i in range(5):
+            c.width[i] = self.width[i]
+        for i in range(3):
+            c.shift[i] = self.shift[i]
+            c.scale[i] = self.scale[i]
+        c.out_scale = self.out_scale
+        c.k0_W_mK = self.k0
+        return c
+
+
+class Net:
+    """The learned warm start on one context (parameters live on the device)."""
+
+    def __init__(self, ctx: "Context", spec: NetSpec):
+        self.ctx, self.spec = ctx, spec
+        self.lib = ctx.lib
+        h = c_void_p()
+        ctx._check(self.lib.varsim_net_create(ctx.handle, ctypes.byref(spec.c_config()), ctypes.byref(h)))
+        self.handle = h
+        n = c_int64()
+        ctx._check(self.lib.varsim_net_param_count(self.handle, ctypes.byref(n)))
+        self.param_count = n.value
+
+    def close(self):
+        if self.handle:
+            self.lib.varsim_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        """params: float32 device tensor [param_count] (the header's order)."""
+        assert params.numel() == self.param_count and params.is_contiguous()
+        self.ctx._check(self.lib.varsim_net_set_params(self.handle, _ptr(params), _stream()))
+
+    def get_params(self):
+        import torch
+
+        out = torch.empty(self.param_count, dtype=torch.float32, device=torch.device("cuda", self.ctx.device))
+        self.ctx._check(self.lib.varsim_net_get_params(self.handle, _ptr(out), _stream()))
+        return out
+
+    def workspace_bytes(self, batch: int, training: bool) -> int:
+        n = c_size_t(0)
+        self.ctx._check(self.lib.varsim_net_workspace_size(self.handle, batch, int(training), ctypes.byref(n)))
+        return n.value
+
+    def _ws(self, workspace, batch, training):
+        import torch
+
+        need = self.workspace_bytes(batch, training)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=torch.device("cuda", self.ctx.device))
+        return workspace
+
+    def forward(self, q, v, m, out, batch=None, sample_idx=None, workspace=None):
+        """Predicted rise into out [batch][n][n] (float32 device tensors; v, m may be None)."""
+        batch = batch or out.shape[0]
+        workspace = self._ws(workspace, batch, False)
+        self.ctx._check(self.lib.varsim_net_forward(self.handle, batch, _ptr(q), _ptr(v), _ptr(m), _ptr(sample_idx),
+                                                    _ptr(out), _ptr(workspace), workspace.numel(), _stream()))
+        return out
+
+    def gradient(self, q, v, m, target, grad, loss, batch, sample_idx=None, workspace=None):
+        workspace = self._ws(workspace, batch, True)
+        self.ctx._check(self.lib.varsim_net_gradient(self.handle, batch, _ptr(q), _ptr(v), _ptr(m), _ptr(sample_idx),
+                                                     _ptr(target), _ptr(grad), _ptr(loss), _ptr(workspace),
+                                                     workspace.numel(), _stream()))
+
+    def adam(self, grad, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.ctx._check(self.lib.varsim_net_adam(self.handle, _ptr(grad), lr, beta1, beta2, eps, _stream()))
+
+
+def nn_conv(ctx: "Context", op: int, k: int, a, b, out, bias=None, relu: bool = False, workspace=None):
+    """One convolution layer op (varsim_nn_conv) on BF16 tensors stored as int16 / uint16 bits."""
+    import torch
+
+    if op == NN_WGRAD:
+        batch, h, w, cin = a.shape
+        cout = b.shape[-1]
+    else:
+        batch, h, w, c = a.shape
+        cout, cin = b.shape[0], b.shape[-1]
+    need = c_size_t(0)
+    ctx._check(ctx.lib.varsim_nn_conv_workspace(op, k, batch, h, w, cin, cout, ctypes.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=a.device)
+    ctx._check(ctx.lib.varsim_nn_conv(ctx.handle, op, k, batch, h, w, cin, cout, _ptr(a), _ptr(b), _ptr(bias),
+                                      int(relu), _ptr(out), _ptr(workspace), workspace.numel(), _stream()))
+    return out

@@ -39,7 +39,8 @@ def test_struct_layouts_match_c(tmp_path):
     from paper_2307_12119_amd import varsim as V
 
     structs = {"varsim_layer": V.Layer, "varsim_geometry": V.Geometry, "varsim_options": V.Options,
-               "varsim_problem": V.Problem, "varsim_stats": V.Stats, "varsim_transient": V.Transient}
+               "varsim_problem": V.Problem, "varsim_stats": V.Stats, "varsim_transient": V.Transient,
+               "varsim_net_config": V.NetConfig}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "varsim.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
