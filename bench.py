@@ -104,6 +104,7 @@ def main() -> int:
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (counter calibration)")
     ap.add_argument("--no-transient", action="store_true", help="skip the 1024^2 x 1000-step transient run")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-warm-started solve")
     ap.add_argument("--transient-runs", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -148,10 +149,11 @@ def main() -> int:
         del src, dst
     ctx = V.Context(0)
     opts = V.make_options(V.F32, V.LEAK_EXP, 0.017, 50, 1e-3, f64_residual=True)
-    ws = torch.empty(ctx.workspace_bytes(items, opts), dtype=torch.uint8, device=dev)
+    batch = ctx.prepare(items)
+    ws = torch.empty(ctx.workspace_bytes(batch, opts), dtype=torch.uint8, device=dev)
 
     for _ in range(args.warmup):
-        ctx.solve_batch(items, opts, ws)
+        ctx.solve_batch(batch, opts, ws)
     torch.cuda.synchronize()
     print(f"[bench] warm-up done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
@@ -161,15 +163,15 @@ def main() -> int:
     t0 = time.perf_counter()
     iters = []
     for _ in range(args.steps):
-        stats = ctx.solve_batch(items, opts, ws)
-        iters.append([s["iterations"] for s in stats])
+        stats = ctx.solve_batch(batch, opts, ws)
+        iters.append(stats["iterations"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ctx.set_timing(False)
     ktimes = ctx.kernel_times()
     print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
-    statuses = sorted({s["status"] for s in stats})
+    statuses = sorted({int(x) for x in stats["status"]})
     it = np.array(iters)
     maps_per_s = args.batch * args.steps / elapsed
     per_map = algorithmic_bytes(args.n)
@@ -196,7 +198,7 @@ def main() -> int:
     traffic = None if per_pass is None else int(per_pass * passes[dom] / kernels[dom]["launches"])
     achieved = kernels[dom]["GB/s"]
     total_alg = sum(per_map[k] * passes[k] for k in kernels)
-    resid = [s["residual_f64_K"] for s in stats]
+    resid = stats["residual_f64_K"]
 
     result = {
         "metric": METRIC,
@@ -223,13 +225,95 @@ def main() -> int:
         "surrogate": None,
     }
 
+    out_w = None
+    if not args.no_surrogate:
+        result["surrogate"], out_w = surrogate_bench(ctx, items, qd, lv, cm, out, opts, ws, args, maps_per_s,
+                                                     float(it.mean()))
     if not args.no_transient:
         del ws
         result["transient"] = transient_bench(ctx, args.transient_runs)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"], result["max_err_K"] = cpu_baseline(args.n, out[0].cpu().numpy())
+        warm0 = None if out_w is None else out_w[0].cpu().numpy()
+        result["cpu_baseline"], result["max_err_K"], err_w = cpu_baseline(args.n, out[0].cpu().numpy(), warm0)
+        if err_w is not None:
+            result["surrogate"]["max_err_vs_oracle_K"] = err_w
     print(json.dumps(result))
     return 0
+
+
+SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2307_12119_amd", "weights", "surrogate_512.npy")
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def conv_flops_per_map(spec) -> float:
+    """Dense multiply-adds (x2) of the network's convolutions for one map (stem: 48 inputs)."""
+    w, m = spec.width, spec.n // 4
+    f = 2.0 * 48 * w[0] * m * m + 2.0 * w[0] * 16 * m * m
+    for l in range(5):
+        px = (m >> l) ** 2
+        cin = w[0] if l == 0 else w[l - 1]
+        f += 2.0 * 9 * px * (cin * w[l] + w[l] * w[l])
+        if l < 4:
+            f += 2.0 * 9 * px * (w[l + 1] + w[l]) * w[l]
+    return f
+
+
+def surrogate_bench(ctx, items, qd, lv, cm, out_plain, opts, ws, args, plain_maps_per_s, plain_iters):
+    """The same batch solved from the network's prediction (inference time included), against the
+    plain cold start: throughput, iterations, agreement with the plain result."""
+    import numpy as np
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    if not os.path.exists(SURROGATE_WEIGHTS):
+        return {"status": "no trained weights"}, None
+    dev = qd.device
+    spec = V.NetSpec(n=args.n)
+    net = V.Net(ctx, spec)
+    net.set_params(torch.from_numpy(np.load(SURROGATE_WEIGHTS)).to(dev))
+    init = torch.empty_like(qd)
+    out_w = torch.empty_like(qd)
+    items_w = ctx.prepare([dict(it, dT_init=init[i], dT_out=out_w[i]) for i, it in enumerate(items)])
+    wsf = torch.empty(net.workspace_bytes(args.batch, False), dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        net.forward(qd, lv, cm, init, workspace=wsf)
+        ctx.solve_batch(items_w, opts, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(args.steps):
+        net.forward(qd, lv, cm, init, workspace=wsf)
+        stats = ctx.solve_batch(items_w, opts, ws)
+        iters.append(stats["iterations"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # network alone, with per-kernel events
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        net.forward(qd, lv, cm, init, workspace=wsf)
+    torch.cuda.synchronize()
+    t_net = (time.perf_counter() - t1) / args.steps
+    ctx.set_timing(False)
+    kt = ctx.kernel_times()
+    conv_ms = kt.get("nn_conv_fwd", {}).get("total_ms", 0.0) / args.steps
+    flops = conv_flops_per_map(spec) * args.batch
+    achieved = flops / (conv_ms * 1e-3) / 1e12 if conv_ms else None
+    maps_per_s = args.batch * args.steps / elapsed
+    pred_err = (init - out_plain).abs()
+    return ({"value": round(maps_per_s, 2), "unit": "maps/s", "speedup_vs_plain": round(maps_per_s / plain_maps_per_s, 4),
+             "ms_per_step": round(elapsed / args.steps * 1e3, 4), "iterations_mean": float(np.mean(iters)),
+             "plain_iterations_mean": plain_iters, "statuses": sorted({int(x) for x in stats["status"]}),
+             "max_diff_vs_plain_K": float((out_w - out_plain).abs().max()),
+             "prediction_mae_K": float(pred_err.mean()), "prediction_max_err_K": float(pred_err.max()),
+             "network_ms_per_batch": round(t_net * 1e3, 4),
+             "roofline": {"bound": "mfma", "kernel": "nn_conv_fwd", "achieved": None if achieved is None else
+                          round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": None if achieved is None else round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
+                          "flops_per_launch_batch": flops, "conv_ms_per_batch": conv_ms},
+             "weights": os.path.relpath(SURROGATE_WEIGHTS, ROOT)}, out_w)
 
 
 TRANSIENT_BYTES_PER_CELL = {"tr_row": 20, "tr_col": 24}  # FP32: see transient_bench
@@ -301,8 +385,9 @@ def transient_bench(ctx, runs: int) -> dict:
             "kernels": kernels}
 
 
-def cpu_baseline(n: int, gpu_map0):
-    """The oracle (FP64 direct sum + Picard) on sample 0, timed on this host; table build excluded."""
+def cpu_baseline(n: int, gpu_map0, warm_map0=None):
+    """The oracle (FP64 direct sum + Picard) on sample 0, timed on this host; table build excluded.
+    Returns the baseline record, the plain solve's max error and the warm-started one's (or None)."""
     import numpy as np
 
     import workloads.gen as W
@@ -321,9 +406,10 @@ def cpu_baseline(n: int, gpu_map0):
     ref, st = S.solve_steady(prob, opts, residual=False)
     dt = time.perf_counter() - t0
     err = float(np.max(np.abs(gpu_map0.astype(np.float64) - ref)))
+    err_w = None if warm_map0 is None else float(np.max(np.abs(warm_map0.astype(np.float64) - ref)))
     return ({"value": round(1.0 / dt, 6), "unit": "maps/s", "cores": threads, "kind": "oracle",
              "sample": f"1 converged {n}x{n} map (sample 0, {st.iterations} iterations, {dt:.1f} s), "
-                       "FP64 direct image sum with numpy/BLAS, Green's table build excluded"}, err)
+                       "FP64 direct image sum with numpy/BLAS, Green's table build excluded"}, err, err_w)
 
 
 if __name__ == "__main__":

@@ -239,33 +239,51 @@ class Context:
                                _ptr(it["dT_out"]))
         return probs, (geoms, layers)
 
-    def workspace_bytes(self, items: list[dict], opts: Options) -> int:
-        probs, keep = self._problems(items)
+    def prepare(self, items: list[dict]) -> "PreparedBatch":
+        """Descriptors of a batch built once, for repeated solves of the same tensors."""
+        return PreparedBatch(self, items)
+
+    def _ws_query(self, probs, n: int, opts: Options) -> int:
         nbytes = c_size_t()
-        self._check(self.lib.varsim_workspace_size(self.handle, probs, len(items), ctypes.byref(opts),
-                                                   ctypes.byref(nbytes)))
+        self._check(self.lib.varsim_workspace_size(self.handle, probs, n, ctypes.byref(opts), ctypes.byref(nbytes)))
         return nbytes.value
 
-    def solve_batch(self, items: list[dict], opts: Options, workspace=None, raise_on=(ERR_INVALID,
-                    ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY)) -> list[dict]:
+    def workspace_bytes(self, items, opts: Options) -> int:
+        if isinstance(items, PreparedBatch):
+            return items.workspace_bytes(opts)
+        probs, keep = self._problems(items)
+        return self._ws_query(probs, len(items), opts)
+
+    def solve_batch(self, items, opts: Options, workspace=None, raise_on=(ERR_INVALID,
+                    ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY)):
         """Solve every problem (dicts of device tensors: die, q_dyn, dT_out, optional q_leak0,
-        leak_var, cond_map, dT_init); returns per-problem stats dicts."""
+        leak_var, cond_map, dT_init); returns per-problem stats dicts.  Given a PreparedBatch,
+        returns the stats as a numpy structured array (one record per problem)."""
+        import numpy as np
         import torch
 
-        probs, keep = self._problems(items)
-        need = self.workspace_bytes(items, opts)
+        if isinstance(items, PreparedBatch):
+            prep = items
+            probs, n, stats, need = prep.probs, prep.n, prep.stats, prep.workspace_bytes(opts)
+        else:
+            prep = None
+            probs, keep = self._problems(items)
+            n = len(items)
+            stats = (Stats * n)()
+            need = self._ws_query(probs, n, opts)
         if workspace is None or workspace.numel() < need:
             workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=torch.device("cuda", self.device))
-        stats = (Stats * len(items))()
-        for i in range(len(items)):
-            stats[i].status = -1
-        st = self.lib.varsim_solve_batch(self.handle, probs, len(items), ctypes.byref(opts), _ptr(workspace),
+        arr = np.ctypeslib.as_array(stats)
+        arr["status"] = -1
+        st = self.lib.varsim_solve_batch(self.handle, probs, n, ctypes.byref(opts), _ptr(workspace),
                                          workspace.numel(), stats, _stream())
-        filled = all(stats[i].status >= 0 for i in range(len(items)))
+        filled = bool((arr["status"] >= 0).all())
         # argument / device errors leave the stats unfilled; per-problem statuses are returned
         if st in raise_on and not (filled and st == ERR_INVALID):
             self._check(st, allow=())
-        return [stats[i].as_dict() for i in range(len(items))]
+        if prep is not None:
+            return arr.copy()
+        return [stats[i].as_dict() for i in range(n)]
 
     def solve_steady(self, item: dict, opts: Options, workspace=None) -> dict:
         return self.solve_batch([item], opts, workspace)[0]
@@ -322,6 +340,24 @@ class Context:
         return {names[i].decode(): {"count": counts[i], "total_ms": tot[i]} for i in range(n.value)}
 
 
+class PreparedBatch:
+    """ctypes descriptors of a batch of problems, built once (the tensors must stay alive)."""
+
+    def __init__(self, ctx: "Context", items: list[dict]):
+        self.ctx = ctx
+        self.probs, self._keep = ctx._problems(items)
+        self._items = items
+        self.n = len(items)
+        self.stats = (Stats * self.n)()
+        self._ws = {}
+
+    def workspace_bytes(self, opts: Options) -> int:
+        key = bytes(opts)
+        if key not in self._ws:
+            self._ws[key] = self.ctx._ws_query(self.probs, self.n, opts)
+        return self._ws[key]
+
+
 # ------------------------------------------------------------------------------- surrogate
 @dataclass
 class NetSpec:
@@ -332,6 +368,32 @@ class NetSpec:
     scale: tuple = (1.0, 1.0 / 0.73, 20.0)
     out_scale: float = 10.0
     k0: float = 150.0
+
+    def param_shapes(self) -> list:
+        """(name, shape) of every parameter tensor in the flat order of varsim.h."""
+        w = self.width
+        out = [("stem.w", (w[0], 48)), ("stem.b", (w[0],))]
+        for l in range(5):
+            cin = w[0] if l == 0 else w[l - 1]
+            out += [(f"enc{l}a.w", (w[l], 3, 3, cin)), (f"enc{l}a.b", (w[l],)),
+                    (f"enc{l}b.w", (w[l], 3, 3, w[l])), (f"enc{l}b.b", (w[l],))]
+        for l in range(3, -1, -1):
+            out += [(f"dec{l}.w", (w[l], 3, 3, w[l + 1] + w[l])), (f"dec{l}.b", (w[l],))]
+        return out + [("head.w", (16, w[0])), ("head.b", (16,))]
+
+    def he_init(self, seed: int = 0):
+        """He-normal weights (fan-in; gain 1 for the linear head), zero biases: float32 flat vector."""
+        import numpy as np
+
+        rng = np.random.default_rng(seed)
+        parts = []
+        for name, shp in self.param_shapes():
+            if name.endswith(".b"):
+                parts.append(np.zeros(shp))
+            else:
+                fan_in = int(np.prod(shp[1:]))
+                parts.append(rng.standard_normal(shp) * np.sqrt((1.0 if name.startswith("head") else 2.0) / fan_in))
+        return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
 
     def c_config(self) -> NetConfig:
         c = NetConfig()

@@ -229,3 +229,37 @@ def test_warm_start_reaches_cold_fixed_point(ctx):
     st_warm = ctx.solve_steady(warm, opts)
     assert st_cold["status"] == V.OK and st_warm["status"] == V.OK
     assert torch.max(torch.abs(warm["dT_out"] - cold["dT_out"])).item() <= 2e-4
+
+
+def test_trained_network_gains_over_cold_start(ctx):
+    """The committed trained weights, on held-out maps (floorplan 0, samples 0-15, never trained
+    on): the prediction is within a fraction of a kelvin, the warm-started solve needs fewer
+    iterations than the cold start, and both reach the same rise within the tolerance."""
+    import os
+
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    path = os.path.join(os.path.dirname(V.__file__), "weights", "surrogate_512.npy")
+    n, batch = 512, 16
+    net = V.Net(ctx, V.NetSpec(n=n))
+    net.set_params(torch.from_numpy(np.load(path)).cuda())
+    inps = [W.config2(sample=i, n=n) for i in range(batch)]
+    cold = [gpu_item(i, torch.float32) for i in inps]
+    opts = V.make_options(V.F32, leak_code(inps[0]), inps[0].beta, 50, 1e-3)
+    st_cold = ctx.solve_batch(cold, opts)
+    q = torch.stack([c["q_dyn"] for c in cold])
+    v = torch.stack([c["leak_var"] for c in cold])
+    m = torch.stack([c["cond_map"] for c in cold])
+    init = torch.empty_like(q)
+    net.forward(q, v, m, init)
+    warm = [dict(gpu_item(inp, torch.float32), dT_init=init[i]) for i, inp in enumerate(inps)]
+    st_warm = ctx.solve_batch(warm, opts)
+    ref = torch.stack([c["dT_out"] for c in cold])
+    got = torch.stack([w["dT_out"] for w in warm])
+    assert all(s["status"] == V.OK for s in st_cold + st_warm)
+    it_cold = np.mean([s["iterations"] for s in st_cold])
+    it_warm = np.mean([s["iterations"] for s in st_warm])
+    assert it_warm < it_cold - 1.0
+    assert float((init - ref).abs().mean()) < 0.1
+    assert float((got - ref).abs().max()) <= 5e-3
