@@ -148,6 +148,7 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     ctx = V.Context(0)
+    ctx.set_autotune(1)  # column-pass strip width timed during warm-up
     opts = V.make_options(V.F32, V.LEAK_EXP, 0.017, 50, 1e-3, f64_residual=True)
     batch = ctx.prepare(items)
     ws = torch.empty(ctx.workspace_bytes(batch, opts), dtype=torch.uint8, device=dev)
@@ -221,7 +222,8 @@ def main() -> int:
                      "bytes_per_launch": int(dom_bytes_per_launch), "avg_launch_ms": kernels[dom]["avg_ms"]},
         "solve": {"iterations_mean": float(it.mean()), "iterations_max": int(it.max()), "statuses": statuses,
                   "residual_f64_max_K": float(np.max(resid)),
-                  "effective_GBps_all_kernels": round(total_alg / elapsed / 1e9, 1), "kernels": kernels},
+                  "effective_GBps_all_kernels": round(total_alg / elapsed / 1e9, 1), "kernels": kernels,
+                  "autotune": ctx.autotune_report().strip().split("\n")},
         "surrogate": None,
     }
 

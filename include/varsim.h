@@ -293,6 +293,22 @@ VARSIM_API varsim_status varsim_nn_conv(varsim_ctx* ctx, int32_t op, int32_t k, 
                              void* workspace, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------
+ * Autotuning of launch shapes.  With autotuning on (enable = 1), the first solve of a group of
+ * maps with a given (grid size, precision, power-of-two group size) times every column-pass
+ * strip width on that group's own workspace arrays and keeps the fastest for later solves of
+ * the same kind; results do not depend on the choice (the same arithmetic in a different
+ * tiling).  enable = 0 stops tuning (kept choices still apply); enable = -1 also forgets them.
+ * varsim_autotune_report writes one line per tuned kind into buf (NUL-terminated; returns
+ * VARSIM_ERR_NO_MEMORY if truncated).
+ */
+VARSIM_API varsim_status varsim_set_autotune(varsim_ctx* ctx, int32_t enable);
+VARSIM_API varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len);
+/* Testing / manual tuning: every later column pass (solves and varsim_conv) uses strip-width
+ * candidate `variant` (0 = default, 1 = half, 2 = quarter width); -1 returns to the default or
+ * tuned choice. */
+VARSIM_API varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t variant);
+
+/* ----------------------------------------------------------------------------------------
  * Kernel timing.  When enabled, every kernel launch of the solves is bracketed by HIP events
  * on the launch stream; varsim_kernel_times reports, per kernel class, the launch count and
  * the summed durations (ms) since the last reset.  Class names are returned in names[i]

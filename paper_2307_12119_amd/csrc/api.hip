@@ -301,6 +301,53 @@ TransLayout make_transient_layout(const varsim_problem* p, const varsim_options*
   return L;
 }
 
+// Column-pass strip width for a group: the tuned choice if the context has one (timing the
+// candidates on this group's own arrays first if autotuning is on), else the default.
+varsim_status col_variant_for(varsim_ctx* ctx, const PassArgs& group, int compute, const void* coef, hipStream_t s,
+                              int* variant) {
+  *variant = ctx->force_col >= 0 ? ctx->force_col : 0;
+  if (ctx->force_col >= 0) return VARSIM_OK;
+  const auto key = std::make_tuple(group.n, compute, ilog2(group.n_maps));
+  auto it = ctx->col_choice.find(key);
+  if (it != ctx->col_choice.end()) {
+    *variant = it->second;
+    return VARSIM_OK;
+  }
+  if (!ctx->autotune) return VARSIM_OK;
+  PassArgs a = group;
+  a.iter = -1;  // plain transform: no solver state is read or written
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  std::vector<float> ms(kColVariants, 0.f);
+  int best = 0;
+  for (int v = 0; v < kColVariants; ++v) {
+    int dup = -1;
+    for (int u = 0; u < v; ++u)
+      if (col_pass_columns(compute, a.n, u) == col_pass_columns(compute, a.n, v)) dup = u;
+    if (dup >= 0) {
+      ms[v] = ms[dup];
+      continue;
+    }
+    constexpr int kReps = 3;
+    HIP_TRY(launch_col_pass(compute, a, coef, s, v));  // warm-up
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < kReps; ++r) HIP_TRY(launch_col_pass(compute, a, coef, s, v));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    ms[v] = t / kReps;
+    if (ms[v] < ms[best]) best = v;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->col_choice[key] = best;
+  ctx->col_ms[key] = ms;
+  *variant = best;
+  return VARSIM_OK;
+}
+
 }  // namespace
 
 // =========================================================================================
@@ -425,7 +472,8 @@ varsim_status varsim_conv(varsim_ctx* ctx, const varsim_geometry* geom, int32_t 
   a.iter = -1;
   HIP_TRY(timed(ctx, "row_conv_head", s, [&] { return launch_row_pass(ROW_CONV_HEAD, precision, precision, a, s); }));
   HIP_TRY(timed(ctx, "col", s, [&] {
-    return launch_col_pass(precision, a, precision == VARSIM_F32 ? (const void*)tab.coef32 : (const void*)tab.coef64, s);
+    return launch_col_pass(precision, a, precision == VARSIM_F32 ? (const void*)tab.coef32 : (const void*)tab.coef64, s,
+                           ctx->force_col >= 0 ? ctx->force_col : 0);
   }));
   HIP_TRY(timed(ctx, "row_conv_tail", s, [&] { return launch_row_pass(ROW_CONV_TAIL, precision, precision, a, s); }));
   HIP_TRY(hipStreamSynchronize(s));
@@ -534,6 +582,19 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
     return a;
   };
 
+  // column-pass strip widths (timed on the group's own spectrum arrays before they are used)
+  std::vector<int> col_var(groups.size(), 0), col_var64(groups.size(), 0);
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group& g = groups[gi];
+    PassArgs a = group_args(g, 1);
+    const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
+    if ((st = col_variant_for(ctx, a, io, lam, s, &col_var[gi])) != VARSIM_OK) return st;
+    if (want_res) {
+      a.use_s64 = io == VARSIM_F32 ? 1 : 0;
+      if ((st = col_variant_for(ctx, a, VARSIM_F64, g.table.coef64, s, &col_var64[gi])) != VARSIM_OK) return st;
+    }
+  }
+
   for (const Group& g : groups) {
     const long cells = (long)g.geom->nx * g.geom->ny;
     HIP_TRY(timed(ctx, "prep", s, [&] { return launch_prep(io, d_prep + g.first, g.count, cells, s); }));
@@ -557,13 +618,14 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
 
   int iters_run = 0;
   for (int k = 1; k <= opts->max_iter; ++k) {
-    for (const Group& g : groups) {
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const Group& g = groups[gi];
       PassArgs a = group_args(g, k);
       bool all_zero = true;
       for (int i = g.first; i < g.first + g.count; ++i) all_zero = all_zero && !sorted[i]->dT_init;
       a.zero_start = all_zero ? 1 : 0;
       const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
-      HIP_TRY(timed(ctx, "col", s, [&] { return launch_col_pass(io, a, lam, s); }));
+      HIP_TRY(timed(ctx, "col", s, [&] { return launch_col_pass(io, a, lam, s, col_var[gi]); }));
       const int mode = k < opts->max_iter ? ROW_MERGED : ROW_LAST;
       HIP_TRY(timed(ctx, mode == ROW_MERGED ? "row_merged" : "row_last", s,
                     [&] { return launch_row_pass(mode, io, io, a, s); }));
@@ -588,12 +650,14 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
   }
 
   if (want_res) {
-    for (const Group& g : groups) {
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const Group& g = groups[gi];
       PassArgs a = group_args(g, 0);
       a.resid_pass = 1;
       a.use_s64 = io == VARSIM_F32 ? 1 : 0;
       HIP_TRY(timed(ctx, "resid_head", s, [&] { return launch_row_pass(ROW_HEAD, io, VARSIM_F64, a, s); }));
-      HIP_TRY(timed(ctx, "resid_col", s, [&] { return launch_col_pass(VARSIM_F64, a, g.table.coef64, s); }));
+      HIP_TRY(timed(ctx, "resid_col", s,
+                    [&] { return launch_col_pass(VARSIM_F64, a, g.table.coef64, s, col_var64[gi]); }));
       HIP_TRY(timed(ctx, "resid_tail", s, [&] { return launch_row_pass(ROW_RESID, io, VARSIM_F64, a, s); }));
     }
   }
@@ -732,6 +796,42 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   if (stats->status != VARSIM_OK)
     return fail(ctx, (varsim_status)stats->status, "transient: %s", varsim_status_string((varsim_status)stats->status));
   return VARSIM_OK;
+}
+
+varsim_status varsim_set_autotune(varsim_ctx* ctx, int32_t enable) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  ctx->autotune = enable != 0;
+  if (enable < 0) {
+    ctx->col_choice.clear();
+    ctx->col_ms.clear();
+  }
+  return VARSIM_OK;
+}
+
+varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t variant) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  if (variant < -1 || variant >= kColVariants) return fail(ctx, VARSIM_ERR_INVALID, "variant must be in [-1, %d]", kColVariants - 1);
+  ctx->force_col = variant;
+  return VARSIM_OK;
+}
+
+varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
+  if (!ctx || !buf || !len) return VARSIM_ERR_INVALID;
+  std::string out;
+  char line[256];
+  for (const auto& kv : ctx->col_choice) {
+    const int n = std::get<0>(kv.first), c = std::get<1>(kv.first), b = std::get<2>(kv.first);
+    snprintf(line, sizeof line, "col n=%d %s maps>=%d:", n, c == VARSIM_F32 ? "f32" : "f64", 1 << b);
+    out += line;
+    const auto& ms = ctx->col_ms[kv.first];
+    for (int v = 0; v < (int)ms.size(); ++v) {
+      snprintf(line, sizeof line, " %d cols %.4f ms%s", col_pass_columns(c, n, v), ms[v], v == kv.second ? "*" : "");
+      out += line;
+    }
+    out += "\n";
+  }
+  snprintf(buf, len, "%s", out.c_str());
+  return out.size() < len ? VARSIM_OK : VARSIM_ERR_NO_MEMORY;
 }
 
 varsim_status varsim_set_timing(varsim_ctx* ctx, int32_t enable) {

@@ -1,0 +1,169 @@
+// Column pass of the steady solve and of the plain convolution: per strip of COLS columns of
+// one map, the column DCT-II, the multiplication by the cosine eigenvalues lambda of the
+// mirrored Green's operator (folded into one step with the split of the two packed columns and
+// the merge for the inverse), and the column DCT-III, in place.  The strip width is a tuning
+// parameter: the library times the candidates on the actual batch and keeps the fastest.
+#include <cmath>
+
+#include "common.hpp"
+#include "fft.hpp"
+#include "internal.hpp"
+#include "passes.hpp"
+
+namespace vs {
+
+namespace {
+
+template <typename Tc, int N, int COLS>
+__global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
+    col_pass_kernel(PassArgs a, const Tc* __restrict__ coef, const Cx<Tc>* __restrict__ tw,
+                    const Cx<Tc>* __restrict__ qw) {
+  using Cfg = ColCfg<Tc, N, COLS>;
+  constexpr int TPF = Cfg::TPF;
+  constexpr int E = Shape<N>::E;
+  constexpr int ST = Shape<N>::STRIDE;
+  constexpr int VEC = Cfg::VEC;
+  constexpr int VPR = Cfg::COLS / VEC;
+  constexpr int P = Cfg::PITCH;
+  // one LDS block: first the staging tile, then (after a barrier) the transform scratch
+  __shared__ Tc lds[Cfg::LDS];
+
+  int strip, map;
+  xcd_tile(strip, map);
+  if (a.iter >= 0) {  // iter < 0: plain convolution, no solver state
+    if (a.st.flags[map] & kFlagSkip) return;
+    if (!a.resid_pass && finished_before(a.st, map, a.iter, a.pp.tol)) return;
+  }
+  const MapPtrs mp = a.maps[map];
+  Tc* S = (Tc*)(a.use_s64 ? mp.S64 : mp.S);
+  const int c0 = strip * Cfg::COLS;
+
+  for (int it = threadIdx.x; it < N * VPR; it += Cfg::THREADS) {
+    const int y = it / VPR, j = it % VPR;
+    const Vec<Tc, VEC> v = *reinterpret_cast<const Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) lds[y * P + j * VEC + e] = v.v[e];
+  }
+  __syncthreads();
+
+  // column pair (2f, 2f+1) -> one complex sequence in reordered slots
+  int f = threadIdx.x / TPF;
+  if constexpr (TPF == 64) f = __builtin_amdgcn_readfirstlane(f);
+  const int t = threadIdx.x % TPF;
+  Tc zr[E], zi[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int y = unperm<N>(t + TPF * m);
+    zr[m] = lds[y * P + 2 * f];
+    zi[m] = lds[y * P + 2 * f + 1];
+  }
+  __syncthreads();
+
+  Tc* re = lds + f * 2 * ST;
+  Tc* im = re + ST;
+  fft_reg<Tc, N, -1>(zr, zi, re, im, tw, t);
+  Tc pr[E], pim[E];
+  partner<Tc, N, true>(zr, pr, t);
+  partner<Tc, N, true>(zi, pim, t);
+  // split, multiply by lambda and merge in one step (coefficients alpha, beta, gamma per column)
+  const Vec<Tc, 4>* ca = reinterpret_cast<const Vec<Tc, 4>*>(coef) + (long)(c0 + 2 * f) * (N / 2 + 1);
+  const Vec<Tc, 4>* cb = ca + (N / 2 + 1);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int p = t + TPF * m;
+    const bool hi = m >= E / 2;  // p >= N/2: stored at N - p with beta negated
+    const int pi = hi ? N - p : p;
+    const Vec<Tc, 4> ka = ca[pi], kb = cb[pi];
+    const Tc ba = hi ? -ka.v[1] : ka.v[1], bb = hi ? -kb.v[1] : kb.v[1];
+    const Tc u = zr[m] + pr[m], v = zi[m] - pim[m], w = zi[m] + pim[m], x = pr[m] - zr[m];
+    zr[m] = ka.v[0] * u + ba * v - bb * w - kb.v[2] * x;
+    zi[m] = ba * u + ka.v[2] * v + kb.v[0] * w + bb * x;
+  }
+  wave_sync();
+  fft_reg<Tc, N, +1>(zr, zi, re, im, tw, t);
+  __syncthreads();
+
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int y = unperm<N>(t + TPF * m);
+    lds[y * P + 2 * f] = zr[m];
+    lds[y * P + 2 * f + 1] = zi[m];
+  }
+  __syncthreads();
+
+  for (int it = threadIdx.x; it < N * VPR; it += Cfg::THREADS) {
+    const int y = it / VPR, j = it % VPR;
+    Vec<Tc, VEC> v;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v.v[e] = lds[y * P + j * VEC + e];
+    *reinterpret_cast<Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC) = v;
+  }
+}
+
+template <typename Tc, int N, int V>
+constexpr int col_candidate() {
+  constexpr int c0 = ColCfg<Tc, N>::COLS;
+  constexpr int c = V == 0 ? c0 : (V == 1 ? c0 / 2 : c0 / 4);
+  return c < 2 ? 2 : c;
+}
+
+template <typename Tc, int N, int COLS>
+hipError_t col_launch(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+  using Cfg = ColCfg<Tc, N, COLS>;
+  hipLaunchKernelGGL((col_pass_kernel<Tc, N, COLS>), dim3(N / Cfg::COLS, a.n_maps), dim3(Cfg::THREADS), 0, s, a, coef,
+                     tw, qw);
+  return hipGetLastError();
+}
+
+template <typename Tc, int N>
+hipError_t col_variant(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+  switch (v) {
+    case 0: return col_launch<Tc, N, col_candidate<Tc, N, 0>()>(a, coef, tw, qw, s);
+    case 1: return col_launch<Tc, N, col_candidate<Tc, N, 1>()>(a, coef, tw, qw, s);
+    case 2: return col_launch<Tc, N, col_candidate<Tc, N, 2>()>(a, coef, tw, qw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename Tc>
+hipError_t col_dispatch_n(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw,
+                          hipStream_t s) {
+  switch (a.n) {
+    case 16: return col_variant<Tc, 16>(v, a, coef, tw, qw, s);
+    case 32: return col_variant<Tc, 32>(v, a, coef, tw, qw, s);
+    case 64: return col_variant<Tc, 64>(v, a, coef, tw, qw, s);
+    case 128: return col_variant<Tc, 128>(v, a, coef, tw, qw, s);
+    case 256: return col_variant<Tc, 256>(v, a, coef, tw, qw, s);
+    case 512: return col_variant<Tc, 512>(v, a, coef, tw, qw, s);
+    case 1024: return col_variant<Tc, 1024>(v, a, coef, tw, qw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename Tc, int N>
+int col_cols_of(int v) {
+  return v == 0 ? col_candidate<Tc, N, 0>() : (v == 1 ? col_candidate<Tc, N, 1>() : col_candidate<Tc, N, 2>());
+}
+
+}  // namespace
+
+hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream, int variant) {
+  if (compute == VARSIM_F32) return col_dispatch_n<float>(variant, a, (const float*)coef, a.tw.tw32, a.tw.qw32, stream);
+  return col_dispatch_n<double>(variant, a, (const double*)coef, a.tw.tw64, a.tw.qw64, stream);
+}
+
+int col_pass_columns(int compute, int n, int variant) {
+  const bool f = compute == VARSIM_F32;
+  switch (n) {
+    case 16: return f ? col_cols_of<float, 16>(variant) : col_cols_of<double, 16>(variant);
+    case 32: return f ? col_cols_of<float, 32>(variant) : col_cols_of<double, 32>(variant);
+    case 64: return f ? col_cols_of<float, 64>(variant) : col_cols_of<double, 64>(variant);
+    case 128: return f ? col_cols_of<float, 128>(variant) : col_cols_of<double, 128>(variant);
+    case 256: return f ? col_cols_of<float, 256>(variant) : col_cols_of<double, 256>(variant);
+    case 512: return f ? col_cols_of<float, 512>(variant) : col_cols_of<double, 512>(variant);
+    case 1024: return f ? col_cols_of<float, 1024>(variant) : col_cols_of<double, 1024>(variant);
+    default: return 0;
+  }
+}
+
+}  // namespace vs

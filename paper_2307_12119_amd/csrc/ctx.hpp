@@ -64,6 +64,11 @@ struct varsim_ctx {
   std::vector<varsim_stats> h_stats;
   MapPtrs* conv_maps = nullptr;
   size_t conv_maps_cap = 0;
+  // column-pass strip width chosen by timing, per (n, compute type, log2 of the group size)
+  bool autotune = false;
+  int force_col = -1;  // >= 0: every column pass uses this strip-width candidate
+  std::map<std::tuple<int, int, int>, int> col_choice;
+  std::map<std::tuple<int, int, int>, std::vector<float>> col_ms;
 };
 
 namespace {

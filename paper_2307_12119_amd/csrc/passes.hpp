@@ -38,10 +38,11 @@ __device__ __forceinline__ void xcd_tile(int& strip, int& map) {
   map = l / gx;
 }
 
-template <typename Tc, int N>
+// COLS_ = 0: the default strip width (col_count); otherwise an explicit even width
+template <typename Tc, int N, int COLS_ = 0>
 struct ColCfg {
   static constexpr int TPF = Shape<N>::TPF;
-  static constexpr int COLS = col_count(N, (int)sizeof(Tc), TPF);
+  static constexpr int COLS = COLS_ ? (COLS_ < N ? COLS_ : N) : col_count(N, (int)sizeof(Tc), TPF);
   static constexpr int FFTS = COLS / 2;
   static constexpr int THREADS = FFTS * TPF;
   static constexpr int VEC = (int)(16 / sizeof(Tc)) < COLS ? (int)(16 / sizeof(Tc)) : COLS;

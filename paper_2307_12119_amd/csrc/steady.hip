@@ -7,7 +7,8 @@
 //                 and statistics, the new total power P = hx hy (q_dyn + QL L(dT)), and the
 //                 row DCT-II of P into the spectrum array (in place, same rows);
 //   column pass : column DCT-II, multiplication by the cosine eigenvalues lambda of the
-//                 mirrored Green's operator, column DCT-III (in place, column tiles in LDS).
+//                 mirrored Green's operator, column DCT-III (in place, column tiles in LDS;
+//                 colpass.hip).
 // The first row pass of a solve starts from dT_init (or 0), the last one skips the forward part.
 #include <cmath>
 
@@ -225,92 +226,6 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
   }
 }
 
-template <typename Tc, int N>
-__global__ void __launch_bounds__((ColCfg<Tc, N>::THREADS))
-    col_pass_kernel(PassArgs a, const Tc* __restrict__ coef, const Cx<Tc>* __restrict__ tw,
-                    const Cx<Tc>* __restrict__ qw) {
-  using Cfg = ColCfg<Tc, N>;
-  constexpr int TPF = Cfg::TPF;
-  constexpr int E = Shape<N>::E;
-  constexpr int ST = Shape<N>::STRIDE;
-  constexpr int VEC = Cfg::VEC;
-  constexpr int VPR = Cfg::COLS / VEC;
-  constexpr int P = Cfg::PITCH;
-  // one LDS block: first the staging tile, then (after a barrier) the transform scratch
-  __shared__ Tc lds[Cfg::LDS];
-
-  int strip, map;
-  xcd_tile(strip, map);
-  if (a.iter >= 0) {  // iter < 0: plain convolution, no solver state
-    if (a.st.flags[map] & kFlagSkip) return;
-    if (!a.resid_pass && finished_before(a.st, map, a.iter, a.pp.tol)) return;
-  }
-  const MapPtrs mp = a.maps[map];
-  Tc* S = (Tc*)(a.use_s64 ? mp.S64 : mp.S);
-  const int c0 = strip * Cfg::COLS;
-
-  for (int it = threadIdx.x; it < N * VPR; it += Cfg::THREADS) {
-    const int y = it / VPR, j = it % VPR;
-    const Vec<Tc, VEC> v = *reinterpret_cast<const Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC);
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) lds[y * P + j * VEC + e] = v.v[e];
-  }
-  __syncthreads();
-
-  // column pair (2f, 2f+1) -> one complex sequence in reordered slots
-  int f = threadIdx.x / TPF;
-  if constexpr (TPF == 64) f = __builtin_amdgcn_readfirstlane(f);
-  const int t = threadIdx.x % TPF;
-  Tc zr[E], zi[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int y = unperm<N>(t + TPF * m);
-    zr[m] = lds[y * P + 2 * f];
-    zi[m] = lds[y * P + 2 * f + 1];
-  }
-  __syncthreads();
-
-  Tc* re = lds + f * 2 * ST;
-  Tc* im = re + ST;
-  fft_reg<Tc, N, -1>(zr, zi, re, im, tw, t);
-  Tc pr[E], pim[E];
-  partner<Tc, N, true>(zr, pr, t);
-  partner<Tc, N, true>(zi, pim, t);
-  // split, multiply by lambda and merge in one step (coefficients alpha, beta, gamma per column)
-  const Vec<Tc, 4>* ca = reinterpret_cast<const Vec<Tc, 4>*>(coef) + (long)(c0 + 2 * f) * (N / 2 + 1);
-  const Vec<Tc, 4>* cb = ca + (N / 2 + 1);
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int p = t + TPF * m;
-    const bool hi = m >= E / 2;  // p >= N/2: stored at N - p with beta negated
-    const int pi = hi ? N - p : p;
-    const Vec<Tc, 4> ka = ca[pi], kb = cb[pi];
-    const Tc ba = hi ? -ka.v[1] : ka.v[1], bb = hi ? -kb.v[1] : kb.v[1];
-    const Tc u = zr[m] + pr[m], v = zi[m] - pim[m], w = zi[m] + pim[m], x = pr[m] - zr[m];
-    zr[m] = ka.v[0] * u + ba * v - bb * w - kb.v[2] * x;
-    zi[m] = ba * u + ka.v[2] * v + kb.v[0] * w + bb * x;
-  }
-  wave_sync();
-  fft_reg<Tc, N, +1>(zr, zi, re, im, tw, t);
-  __syncthreads();
-
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int y = unperm<N>(t + TPF * m);
-    lds[y * P + 2 * f] = zr[m];
-    lds[y * P + 2 * f + 1] = zi[m];
-  }
-  __syncthreads();
-
-  for (int it = threadIdx.x; it < N * VPR; it += Cfg::THREADS) {
-    const int y = it / VPR, j = it % VPR;
-    Vec<Tc, VEC> v;
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) v.v[e] = lds[y * P + j * VEC + e];
-    *reinterpret_cast<Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC) = v;
-  }
-}
-
 // ---------------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) prep_kernel(const PrepArgs* __restrict__ args, long count) {
@@ -440,28 +355,6 @@ hipError_t row_dispatch_n(int mode, const PassArgs& a, const Cx<Tc>* tw, const C
   }
 }
 
-template <typename Tc, int N>
-hipError_t col_launch(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
-  using Cfg = ColCfg<Tc, N>;
-  hipLaunchKernelGGL((col_pass_kernel<Tc, N>), dim3(N / Cfg::COLS, a.n_maps), dim3(Cfg::THREADS), 0, s, a, coef, tw,
-                     qw);
-  return hipGetLastError();
-}
-
-template <typename Tc>
-hipError_t col_dispatch_n(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
-  switch (a.n) {
-    case 16: return col_launch<Tc, 16>(a, coef, tw, qw, s);
-    case 32: return col_launch<Tc, 32>(a, coef, tw, qw, s);
-    case 64: return col_launch<Tc, 64>(a, coef, tw, qw, s);
-    case 128: return col_launch<Tc, 128>(a, coef, tw, qw, s);
-    case 256: return col_launch<Tc, 256>(a, coef, tw, qw, s);
-    case 512: return col_launch<Tc, 512>(a, coef, tw, qw, s);
-    case 1024: return col_launch<Tc, 1024>(a, coef, tw, qw, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 }  // namespace
 
 hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hipStream_t stream) {
@@ -471,11 +364,6 @@ hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hip
   }
   if (io == VARSIM_F32) return row_dispatch_n<float, double>(mode, a, a.tw.tw64, a.tw.qw64, stream);
   return row_dispatch_n<double, double>(mode, a, a.tw.tw64, a.tw.qw64, stream);
-}
-
-hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream) {
-  if (compute == VARSIM_F32) return col_dispatch_n<float>(a, (const float*)coef, a.tw.tw32, a.tw.qw32, stream);
-  return col_dispatch_n<double>(a, (const double*)coef, a.tw.tw64, a.tw.qw64, stream);
 }
 
 hipError_t launch_prep(int io, const PrepArgs* args, int n_maps, long count, hipStream_t stream) {

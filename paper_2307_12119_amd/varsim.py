@@ -100,6 +100,9 @@ EXPORTS = {
                                          POINTER(c_size_t)]),
     "varsim_nn_conv": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, c_void_p,
                                c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "varsim_set_autotune": (c_int, [c_void_p, c_int32]),
+    "varsim_autotune_report": (c_int, [c_void_p, c_char_p, c_size_t]),
+    "varsim_force_col_variant": (c_int, [c_void_p, c_int32]),
     "varsim_set_timing": (c_int, [c_void_p, c_int32]),
     "varsim_kernel_times": (c_int, [c_void_p, POINTER(c_char_p), POINTER(c_int64), POINTER(c_double),
                                     POINTER(c_int32)]),
@@ -322,6 +325,19 @@ class Context:
         if st in raise_on and not (stats.status >= 0 and st == ERR_INVALID):
             self._check(st, allow=())
         return stats.as_dict()
+
+    # ------------------------------------------------------------------------------ autotune
+    def set_autotune(self, enable: int):
+        """1: time launch-shape candidates at first use; 0: stop; -1: stop and forget choices."""
+        self._check(self.lib.varsim_set_autotune(self.handle, int(enable)))
+
+    def force_col_variant(self, variant: int):
+        self._check(self.lib.varsim_force_col_variant(self.handle, int(variant)))
+
+    def autotune_report(self) -> str:
+        buf = ctypes.create_string_buffer(8192)
+        self._check(self.lib.varsim_autotune_report(self.handle, buf, len(buf)))
+        return buf.value.decode()
 
     # -------------------------------------------------------------------------------- timing
     def set_timing(self, enable: bool):

@@ -285,3 +285,39 @@ def test_zero_power_and_uniform_power(ctx):
     expect = 2.048e6 * u.die.t_m / u.die.k0
     assert st["status"] == V.OK
     assert float((item["dT_out"] - expect).abs().max()) <= 1e-5 * expect
+
+
+# ----------------------------------------------------------------------------- launch-shape tuning
+@pytest.mark.parametrize("n", [16, 64, 256, 512])
+def test_column_strip_widths_give_identical_results(ctx, n):
+    """Every column-pass strip width computes the same arithmetic: bitwise equal convolutions and
+    solves; autotuning picks one of them and leaves the results unchanged."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    inp = W.config2(sample=1, n=n)
+    die = die_of(inp)
+    p = to_dev(np.random.default_rng(n).uniform(0, 1, (3, n, n)), torch.float32)
+    opts = _opts(V.F32, inp, 50, 1e-3, res=True)
+    convs, maps = [], []
+    try:
+        for v in range(3):
+            ctx.force_col_variant(v)
+            convs.append(ctx.conv(die, p).cpu())
+            item = gpu_item(inp, torch.float32)
+            st = ctx.solve_steady(item, opts)
+            assert st["status"] == V.OK
+            maps.append(item["dT_out"].cpu())
+        ctx.force_col_variant(-1)
+        ctx.set_autotune(1)
+        item = gpu_item(inp, torch.float32)
+        ctx.solve_steady(item, opts)
+        maps.append(item["dT_out"].cpu())
+        assert "col n=%d" % n in ctx.autotune_report()
+    finally:
+        ctx.force_col_variant(-1)
+        ctx.set_autotune(-1)
+    for c in convs[1:]:
+        assert torch.equal(c, convs[0])
+    for m in maps[1:]:
+        assert torch.equal(m, maps[0])
