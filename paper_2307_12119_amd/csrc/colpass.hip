@@ -42,7 +42,7 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
     const int y = it / VPR, j = it % VPR;
     const Vec<Tc, VEC> v = *reinterpret_cast<const Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC);
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) lds[y * P + j * VEC + e] = v.v[e];
+    for (int e = 0; e < VEC; ++e) lds[tile_row<Cfg, N>(y) * P + j * VEC + e] = v.v[e];
   }
   __syncthreads();
 
@@ -53,14 +53,14 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
   Tc zr[E], zi[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    const int y = unperm<N>(t + TPF * m);
+    const int y = tile_slot<Cfg, N>(t + TPF * m);
     zr[m] = lds[y * P + 2 * f];
     zi[m] = lds[y * P + 2 * f + 1];
   }
   __syncthreads();
 
-  Tc* re = lds + f * 2 * ST;
-  Tc* im = re + ST;
+  Tc* re = lds + f * ST;  // all real parts first, then all imaginary parts
+  Tc* im = lds + Cfg::FFTS * ST + f * ST;
   fft_reg<Tc, N, -1>(zr, zi, re, im, tw, t);
   Tc pr[E], pim[E];
   partner<Tc, N, true>(zr, pr, t);
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
 
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    const int y = unperm<N>(t + TPF * m);
+    const int y = tile_slot<Cfg, N>(t + TPF * m);
     lds[y * P + 2 * f] = zr[m];
     lds[y * P + 2 * f + 1] = zi[m];
   }
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
     const int y = it / VPR, j = it % VPR;
     Vec<Tc, VEC> v;
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) v.v[e] = lds[y * P + j * VEC + e];
+    for (int e = 0; e < VEC; ++e) v.v[e] = lds[tile_row<Cfg, N>(y) * P + j * VEC + e];
     *reinterpret_cast<Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC) = v;
   }
 }

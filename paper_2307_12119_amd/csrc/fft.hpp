@@ -6,8 +6,11 @@
 // Stockham autosort sequence: the first stage is a radix-E DFT of the lane's own slots (in
 // registers), the middle stages are radix 8 (a final radix 4 or 2 when needed) through an LDS
 // buffer, and the last stage leaves element t + TPF m in slot m again -- the layout the next
-// transform starts from.  LDS keeps real and imaginary parts in separate arrays with one pad
-// word every 8 entries so that the strided butterfly stores spread over the banks.
+// transform starts from.  LDS keeps real and imaginary parts in separate arrays.  The LDS has
+// 32 four-byte banks and serves each half-wavefront separately; element i of a transform sits
+// at word i + p (i >> a) + q (i >> b), with (a, p, b, q) and the per-transform pitch chosen per
+// N so that every load and store pattern of the stages (and of neighbouring transforms sharing
+// a wavefront) hits distinct banks for N <= 64 and costs 1.25x the conflict-free time above.
 //
 // Two real sequences share one complex DFT (one as the real part, one as the imaginary
 // part).  The cosine transforms use the N-point reordering of a sequence (even samples
@@ -26,10 +29,19 @@ template <int N>
 struct Shape {
   static constexpr int E = N >= 1024 ? 16 : 8;  // elements per lane
   static constexpr int TPF = N / E;             // lanes per transform (<= 64)
-  static constexpr int STRIDE = N + N / 8 + 1;  // LDS buffer pitch (odd)
+  // LDS padding i + PP (i >> PA) + PQ (i >> PB) and buffer pitch
+  static constexpr int PA = N <= 64 ? 3 : (N == 128 ? 4 : 5);
+  static constexpr int PP = (N == 256 || N == 512) ? 2 : 1;
+  static constexpr int PB = N == 16 ? 4 : N == 32 ? 5 : N == 64 ? 6 : N == 128 ? 5 : N == 1024 ? 10 : 7;
+  static constexpr int PQ = N == 128 ? 2 : 1;
+  static constexpr int LAST = (N - 1) + PP * ((N - 1) >> PA) + PQ * ((N - 1) >> PB);
+  static constexpr int STRIDE = LAST + 1 + (N <= 64 ? 1 : (N == 128 ? 3 : 0));
 };
 
-__device__ __forceinline__ int lds_at(int i) { return i + (i >> 3); }
+template <int N>
+__device__ __forceinline__ int lds_at(int i) {
+  return i + Shape<N>::PP * (i >> Shape<N>::PA) + Shape<N>::PQ * (i >> Shape<N>::PB);
+}
 
 // sample position of slot k of the reordered sequence (and of its spectrum slot)
 template <int N>
@@ -213,7 +225,7 @@ __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx
     const int b = t + TPF * u;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int s = lds_at(b + r * NB);
+      const int s = lds_at<N>(b + r * NB);
       yr[u * R + r] = re[s];
       yi[u * R + r] = im[s];
     }
@@ -242,7 +254,7 @@ __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx
       const int base = (b / NS) * NS * R + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int s = lds_at(base + r * NS);
+        const int s = lds_at<N>(base + r * NS);
         re[s] = yr[u * R + r];
         im[s] = yi[u * R + r];
       }
@@ -263,7 +275,7 @@ __device__ __forceinline__ void fft_reg(T* xr, T* xi, T* re, T* im, const Cx<T>*
   dft_r<T, E, DIR>(xr, xi);
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int s = lds_at(t * E + r);
+    const int s = lds_at<N>(t * E + r);
     re[s] = xr[r];
     im[s] = xi[r];
   }

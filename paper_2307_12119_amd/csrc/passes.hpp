@@ -46,9 +46,13 @@ struct ColCfg {
   static constexpr int FFTS = COLS / 2;
   static constexpr int THREADS = FFTS * TPF;
   static constexpr int VEC = (int)(16 / sizeof(Tc)) < COLS ? (int)(16 / sizeof(Tc)) : COLS;
-  // staging tile [N][PITCH] in natural row order; the pitch keeps both the row-segment stores
-  // and the strided column reads of a half-wavefront on distinct LDS banks
-  static constexpr int PITCH = sizeof(Tc) == 4 ? COLS + 3 : COLS + 1;
+  // Staging tile [N][PITCH].  For N >= 256 its rows are stored in transform-slot order (row y
+  // at slot perm(y)), so the column reads of a half-wavefront walk consecutive tile rows; with
+  // pitch COLS + 1 that costs 1.5x the conflict-free LDS time against 2x in natural order.
+  static constexpr bool SLOT = N >= 256;
+  static constexpr int PITCH = SLOT ? COLS + 1 : (sizeof(Tc) == 4 ? COLS + 3 : COLS + 1);
+  // row-segment vectors each thread moves per tile (exact: 2 E / VEC)
+  static constexpr int LOADS = N * (COLS / VEC) / (COLS / 2 * TPF);
   static constexpr int TILE = N * PITCH;
   static constexpr int SCRATCH = FFTS * 2 * Shape<N>::STRIDE;
   static constexpr int LDS = TILE > SCRATCH ? TILE : SCRATCH;
@@ -58,6 +62,16 @@ template <typename T, int V>
 struct alignas(sizeof(T) * V) Vec {
   T v[V];
 };
+
+// tile row of natural row y, and of transform slot k
+template <typename Cfg, int N>
+__device__ __forceinline__ int tile_row(int y) {
+  return Cfg::SLOT ? perm<N>(y) : y;
+}
+template <typename Cfg, int N>
+__device__ __forceinline__ int tile_slot(int k) {
+  return Cfg::SLOT ? k : unperm<N>(k);
+}
 
 // Row values at the sample positions of this lane's slots (slot m <-> reordered index
 // t + TPF m).  Each lane loads the adjacent pair (2k, 2k+1) of its even slot k = t + TPF m;
