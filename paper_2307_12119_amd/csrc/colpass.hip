@@ -14,17 +14,18 @@ namespace vs {
 
 namespace {
 
-template <typename Tc, int N, int COLS>
-__global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
+template <typename Tc, int N, int COLS, int PAIRS>
+__global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
     col_pass_kernel(PassArgs a, const Tc* __restrict__ coef, const Cx<Tc>* __restrict__ tw,
                     const Cx<Tc>* __restrict__ qw) {
-  using Cfg = ColCfg<Tc, N, COLS>;
+  using Cfg = ColCfg<Tc, N, COLS, PAIRS>;
   constexpr int TPF = Cfg::TPF;
   constexpr int E = Shape<N>::E;
   constexpr int ST = Shape<N>::STRIDE;
   constexpr int VEC = Cfg::VEC;
   constexpr int VPR = Cfg::COLS / VEC;
   constexpr int P = Cfg::PITCH;
+  constexpr int NP = Cfg::PAIRS;
   // one LDS block: first the staging tile, then (after a barrier) the transform scratch
   __shared__ Tc lds[Cfg::LDS];
 
@@ -38,7 +39,9 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
   Tc* S = (Tc*)(a.use_s64 ? mp.S64 : mp.S);
   const int c0 = strip * Cfg::COLS;
 
-  for (int it = threadIdx.x; it < N * VPR; it += Cfg::THREADS) {
+#pragma unroll
+  for (int k = 0; k < Cfg::LOADS; ++k) {
+    const int it = threadIdx.x + k * Cfg::THREADS;
     const int y = it / VPR, j = it % VPR;
     const Vec<Tc, VEC> v = *reinterpret_cast<const Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC);
 #pragma unroll
@@ -46,52 +49,64 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
   }
   __syncthreads();
 
-  // column pair (2f, 2f+1) -> one complex sequence in reordered slots
+  // pair q of group f: tile columns (2 (f + FFTS q), 2 (f + FFTS q) + 1) -> one complex sequence
   int f = threadIdx.x / TPF;
   if constexpr (TPF == 64) f = __builtin_amdgcn_readfirstlane(f);
   const int t = threadIdx.x % TPF;
-  Tc zr[E], zi[E];
+  Tc zr[NP][E], zi[NP][E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int y = tile_slot<Cfg, N>(t + TPF * m);
-    zr[m] = lds[y * P + 2 * f];
-    zi[m] = lds[y * P + 2 * f + 1];
-  }
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int y = tile_slot<Cfg, N>(t + TPF * m);
+      const int c = 2 * (f + Cfg::FFTS * q);
+      zr[q][m] = lds[y * P + c];
+      zi[q][m] = lds[y * P + c + 1];
+    }
   __syncthreads();
 
   Tc* re = lds + f * ST;  // all real parts first, then all imaginary parts
   Tc* im = lds + Cfg::FFTS * ST + f * ST;
-  fft_reg<Tc, N, -1>(zr, zi, re, im, tw, t);
-  Tc pr[E], pim[E];
-  partner<Tc, N, true>(zr, pr, t);
-  partner<Tc, N, true>(zi, pim, t);
-  // split, multiply by lambda and merge in one step (coefficients alpha, beta, gamma per column)
-  const Vec<Tc, 4>* ca = reinterpret_cast<const Vec<Tc, 4>*>(coef) + (long)(c0 + 2 * f) * (N / 2 + 1);
-  const Vec<Tc, 4>* cb = ca + (N / 2 + 1);
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int p = t + TPF * m;
-    const bool hi = m >= E / 2;  // p >= N/2: stored at N - p with beta negated
-    const int pi = hi ? N - p : p;
-    const Vec<Tc, 4> ka = ca[pi], kb = cb[pi];
-    const Tc ba = hi ? -ka.v[1] : ka.v[1], bb = hi ? -kb.v[1] : kb.v[1];
-    const Tc u = zr[m] + pr[m], v = zi[m] - pim[m], w = zi[m] + pim[m], x = pr[m] - zr[m];
-    zr[m] = ka.v[0] * u + ba * v - bb * w - kb.v[2] * x;
-    zi[m] = ba * u + ka.v[2] * v + kb.v[0] * w + bb * x;
-  }
-  wave_sync();
-  fft_reg<Tc, N, +1>(zr, zi, re, im, tw, t);
-  __syncthreads();
-
+  for (int q = 0; q < NP; ++q) {
+    if (q > 0) wave_sync();
+    fft_reg<Tc, N, -1>(zr[q], zi[q], re, im, tw, t);
+    Tc pr[E], pim[E];
+    partner<Tc, N, true>(zr[q], pr, t);
+    partner<Tc, N, true>(zi[q], pim, t);
+    // split, multiply by lambda and merge in one step (coefficients alpha, beta, gamma per column)
+    const Vec<Tc, 4>* ca = reinterpret_cast<const Vec<Tc, 4>*>(coef) + (long)(c0 + 2 * (f + Cfg::FFTS * q)) * (N / 2 + 1);
+    const Vec<Tc, 4>* cb = ca + (N / 2 + 1);
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int y = tile_slot<Cfg, N>(t + TPF * m);
-    lds[y * P + 2 * f] = zr[m];
-    lds[y * P + 2 * f + 1] = zi[m];
+    for (int m = 0; m < E; ++m) {
+      const int p = t + TPF * m;
+      const bool hi = m >= E / 2;  // p >= N/2: stored at N - p with beta negated
+      const int pi = hi ? N - p : p;
+      const Vec<Tc, 4> ka = ca[pi], kb = cb[pi];
+      const Tc ba = hi ? -ka.v[1] : ka.v[1], bb = hi ? -kb.v[1] : kb.v[1];
+      const Tc u = zr[q][m] + pr[m], v = zi[q][m] - pim[m], w = zi[q][m] + pim[m], x = pr[m] - zr[q][m];
+      zr[q][m] = ka.v[0] * u + ba * v - bb * w - kb.v[2] * x;
+      zi[q][m] = ba * u + ka.v[2] * v + kb.v[0] * w + bb * x;
+    }
+    wave_sync();
+    fft_reg<Tc, N, +1>(zr[q], zi[q], re, im, tw, t);
   }
   __syncthreads();
 
-  for (int it = threadIdx.x; it < N * VPR; it += Cfg::THREADS) {
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int y = tile_slot<Cfg, N>(t + TPF * m);
+      const int c = 2 * (f + Cfg::FFTS * q);
+      lds[y * P + c] = zr[q][m];
+      lds[y * P + c + 1] = zi[q][m];
+    }
+  __syncthreads();
+
+#pragma unroll
+  for (int k = 0; k < Cfg::LOADS; ++k) {
+    const int it = threadIdx.x + k * Cfg::THREADS;
     const int y = it / VPR, j = it % VPR;
     Vec<Tc, VEC> v;
 #pragma unroll
@@ -100,27 +115,33 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
   }
 }
 
+// Strip-width candidates: 0 = the default width, 1 = twice as wide with two column pairs per
+// transform group (128-byte row segments at N >= 512), 2 = half the default width.
 template <typename Tc, int N, int V>
 constexpr int col_candidate() {
   constexpr int c0 = ColCfg<Tc, N>::COLS;
-  constexpr int c = V == 0 ? c0 : (V == 1 ? c0 / 2 : c0 / 4);
-  return c < 2 ? 2 : c;
+  constexpr int c = V == 0 ? c0 : (V == 1 ? 2 * c0 : c0 / 2);
+  return c < 2 ? 2 : (c > N ? N : c);
+}
+template <int V>
+constexpr int col_pairs() {
+  return V == 1 ? 2 : 1;
 }
 
-template <typename Tc, int N, int COLS>
+template <typename Tc, int N, int COLS, int PAIRS>
 hipError_t col_launch(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
-  using Cfg = ColCfg<Tc, N, COLS>;
-  hipLaunchKernelGGL((col_pass_kernel<Tc, N, COLS>), dim3(N / Cfg::COLS, a.n_maps), dim3(Cfg::THREADS), 0, s, a, coef,
-                     tw, qw);
+  using Cfg = ColCfg<Tc, N, COLS, PAIRS>;
+  hipLaunchKernelGGL((col_pass_kernel<Tc, N, COLS, PAIRS>), dim3(N / Cfg::COLS, a.n_maps), dim3(Cfg::THREADS), 0, s, a,
+                     coef, tw, qw);
   return hipGetLastError();
 }
 
 template <typename Tc, int N>
 hipError_t col_variant(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   switch (v) {
-    case 0: return col_launch<Tc, N, col_candidate<Tc, N, 0>()>(a, coef, tw, qw, s);
-    case 1: return col_launch<Tc, N, col_candidate<Tc, N, 1>()>(a, coef, tw, qw, s);
-    case 2: return col_launch<Tc, N, col_candidate<Tc, N, 2>()>(a, coef, tw, qw, s);
+    case 0: return col_launch<Tc, N, col_candidate<Tc, N, 0>(), col_pairs<0>()>(a, coef, tw, qw, s);
+    case 1: return col_launch<Tc, N, col_candidate<Tc, N, 1>(), col_pairs<1>()>(a, coef, tw, qw, s);
+    case 2: return col_launch<Tc, N, col_candidate<Tc, N, 2>(), col_pairs<2>()>(a, coef, tw, qw, s);
     default: return hipErrorInvalidValue;
   }
 }

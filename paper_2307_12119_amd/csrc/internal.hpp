@@ -54,7 +54,8 @@ struct PassArgs {
 // io: element type of the maps (VARSIM_F32 / VARSIM_F64); compute: type of the transforms.
 hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hipStream_t stream);
 // coef: the column-pass coefficient table of the compute type; variant: strip-width candidate
-// 0 (default), 1 (half), 2 (quarter), see col_pass_columns
+// 0 (default), 1 (double width, two column pairs per transform group), 2 (half), see
+// col_pass_columns
 constexpr int kColVariants = 3;
 hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream, int variant = 0);
 int col_pass_columns(int compute, int n, int variant);

@@ -38,12 +38,15 @@ __device__ __forceinline__ void xcd_tile(int& strip, int& map) {
   map = l / gx;
 }
 
-// COLS_ = 0: the default strip width (col_count); otherwise an explicit even width
-template <typename Tc, int N, int COLS_ = 0>
+// COLS_ = 0: the default strip width (col_count); otherwise an explicit even width.  Each
+// transform group (one wavefront at N >= 512) handles PAIRS column pairs one after the other,
+// so a strip can be wider (longer contiguous row segments) without more threads.
+template <typename Tc, int N, int COLS_ = 0, int PAIRS_ = 1>
 struct ColCfg {
   static constexpr int TPF = Shape<N>::TPF;
   static constexpr int COLS = COLS_ ? (COLS_ < N ? COLS_ : N) : col_count(N, (int)sizeof(Tc), TPF);
-  static constexpr int FFTS = COLS / 2;
+  static constexpr int PAIRS = COLS / 2 >= PAIRS_ ? PAIRS_ : 1;
+  static constexpr int FFTS = COLS / (2 * PAIRS);
   static constexpr int THREADS = FFTS * TPF;
   static constexpr int VEC = (int)(16 / sizeof(Tc)) < COLS ? (int)(16 / sizeof(Tc)) : COLS;
   // Staging tile [N][PITCH].  For N >= 256 its rows are stored in transform-slot order (row y
@@ -51,11 +54,11 @@ struct ColCfg {
   // pitch COLS + 1 that costs 1.5x the conflict-free LDS time against 2x in natural order.
   static constexpr bool SLOT = N >= 256;
   static constexpr int PITCH = SLOT ? COLS + 1 : (sizeof(Tc) == 4 ? COLS + 3 : COLS + 1);
-  // row-segment vectors each thread moves per tile (exact: 2 E / VEC)
-  static constexpr int LOADS = N * (COLS / VEC) / (COLS / 2 * TPF);
   static constexpr int TILE = N * PITCH;
   static constexpr int SCRATCH = FFTS * 2 * Shape<N>::STRIDE;
   static constexpr int LDS = TILE > SCRATCH ? TILE : SCRATCH;
+  // row-segment vectors each thread moves per tile
+  static constexpr int LOADS = N * (COLS / VEC) / THREADS;
 };
 
 template <typename T, int V>
