@@ -105,6 +105,7 @@ def main() -> int:
                     help="run one plain device-to-device copy of this size first (counter calibration)")
     ap.add_argument("--no-transient", action="store_true", help="skip the 1024^2 x 1000-step transient run")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-warm-started solve")
+    ap.add_argument("--no-autotune", action="store_true", help="default launch shapes (no timing of candidates)")
     ap.add_argument("--transient-runs", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -148,7 +149,7 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     ctx = V.Context(0)
-    ctx.set_autotune(1)  # column-pass strip width timed during warm-up
+    ctx.set_autotune(0 if args.no_autotune else 1)  # column-pass strip width timed during warm-up
     opts = V.make_options(V.F32, V.LEAK_EXP, 0.017, 50, 1e-3, f64_residual=True)
     batch = ctx.prepare(items)
     ws = torch.empty(ctx.workspace_bytes(batch, opts), dtype=torch.uint8, device=dev)
