@@ -303,6 +303,12 @@ VARSIM_API varsim_status varsim_nn_conv(varsim_ctx* ctx, int32_t op, int32_t k, 
  */
 VARSIM_API varsim_status varsim_set_autotune(varsim_ctx* ctx, int32_t enable);
 VARSIM_API varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len);
+/* Small grids: a map with N <= max_n is solved start to finish by one workgroup that keeps its
+ * spectrum in LDS (one launch for the whole fixed point, convergence decided on the device);
+ * larger maps use two HBM passes per iteration.  The limit is capped at 128 (FP32) / 64 (FP64),
+ * the sizes whose working set fits one CU's LDS; max_n = -1 restores that default, 0 turns the
+ * path off.  Both paths compute the same iterates. */
+VARSIM_API varsim_status varsim_set_small_path(varsim_ctx* ctx, int32_t max_n);
 /* Testing / manual tuning: every later column pass (solves and varsim_conv) uses strip-width
  * candidate `variant` (0 = default, 1 = half, 2 = quarter width); -1 returns to the default or
  * tuned choice. */

@@ -588,7 +588,8 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
     const Group& g = groups[gi];
     PassArgs a = group_args(g, 1);
     const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
-    if ((st = col_variant_for(ctx, a, io, lam, s, &col_var[gi])) != VARSIM_OK) return st;
+    const int lim = ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
+    if (g.geom->nx > lim && (st = col_variant_for(ctx, a, io, lam, s, &col_var[gi])) != VARSIM_OK) return st;
     if (want_res) {
       a.use_s64 = io == VARSIM_F32 ? 1 : 0;
       if ((st = col_variant_for(ctx, a, VARSIM_F64, g.table.coef64, s, &col_var64[gi])) != VARSIM_OK) return st;
@@ -600,25 +601,37 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
     HIP_TRY(timed(ctx, "prep", s, [&] { return launch_prep(io, d_prep + g.first, g.count, cells, s); }));
     if (any_init) HIP_TRY(timed(ctx, "prep", s, [&] { return launch_init_copy(io, d_prep + g.first, g.count, cells, s); }));
   }
-  // iteration 1 head: P(dT_0) -> row spectrum.  Maps without a warm start use zero_start.
-  for (const Group& g : groups) {
+  // Groups of small maps are solved start to finish by one LDS-resident workgroup per map; the
+  // others start with the iteration-1 head P(dT_0) -> row spectrum.  Maps without a warm start
+  // use zero_start; in a group mixing warm and cold starts the cold maps get dT_out zeroed.
+  std::vector<char> own(groups.size(), 0);
+  bool any_loop = false;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group& g = groups[gi];
     PassArgs a = group_args(g, 1);
-    // a map without dT_init starts from 0; with one, from dT_out (which holds the copy)
     bool all_zero = true;
     for (int i = g.first; i < g.first + g.count; ++i) all_zero = all_zero && !sorted[i]->dT_init;
     a.zero_start = all_zero ? 1 : 0;
     if (!all_zero) {
-      // mixed warm / cold starts inside a group: cold maps get dT_out zeroed first
       for (int i = g.first; i < g.first + g.count; ++i)
         if (!sorted[i]->dT_init)
           HIP_TRY(launch_zero_words(sorted[i]->dT_out, (size_t)g.geom->nx * g.geom->ny * esize(io), s));
     }
-    HIP_TRY(timed(ctx, "row_head", s, [&] { return launch_row_pass(ROW_HEAD, io, io, a, s); }));
+    const int lim = ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
+    own[gi] = g.geom->nx <= lim;
+    if (own[gi]) {
+      const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
+      HIP_TRY(timed(ctx, "small_solve", s, [&] { return launch_small_solve(io, a, opts->max_iter, lam, s); }));
+    } else {
+      any_loop = true;
+      HIP_TRY(timed(ctx, "row_head", s, [&] { return launch_row_pass(ROW_HEAD, io, io, a, s); }));
+    }
   }
 
   int iters_run = 0;
-  for (int k = 1; k <= opts->max_iter; ++k) {
+  for (int k = 1; any_loop && k <= opts->max_iter; ++k) {
     for (size_t gi = 0; gi < groups.size(); ++gi) {
+      if (own[gi]) continue;
       const Group& g = groups[gi];
       PassArgs a = group_args(g, k);
       bool all_zero = true;
@@ -805,6 +818,12 @@ varsim_status varsim_set_autotune(varsim_ctx* ctx, int32_t enable) {
     ctx->col_choice.clear();
     ctx->col_ms.clear();
   }
+  return VARSIM_OK;
+}
+
+varsim_status varsim_set_small_path(varsim_ctx* ctx, int32_t max_n) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  ctx->small_limit = max_n < 0 ? -1 : max_n;
   return VARSIM_OK;
 }
 

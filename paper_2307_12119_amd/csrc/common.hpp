@@ -24,6 +24,7 @@ constexpr unsigned kFlagRunaway = 1u;       // non-finite / above cap / Kirchhof
 constexpr unsigned kFlagWarmRejected = 2u;  // dT_init had a non-finite entry: start from 0
 constexpr unsigned kFlagInvalid = 4u;       // conductivity map not strictly positive
 constexpr unsigned kFlagSkip = kFlagRunaway | kFlagInvalid;
+constexpr unsigned kFlagOwnLoop = 8u;  // solved start to finish by one LDS-resident workgroup
 
 // Device pointers of one map (all [n][n] row-major).
 struct MapPtrs {

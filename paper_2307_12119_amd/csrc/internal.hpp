@@ -80,6 +80,11 @@ hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t stream);
 // Convergence count: number of maps not yet finished after iteration `iter`.
 hipError_t launch_count_active(const IterState& st, int n_maps, int iter, double tol, int* out, hipStream_t stream);
 
+// The whole fixed point of every map of a group by one LDS-resident workgroup per map
+// (n <= small_max_n(io)); coef: the column coefficients of the io type.
+int small_max_n(int io);
+hipError_t launch_small_solve(int io, const PassArgs& a, int max_iter, const void* coef, hipStream_t stream);
+
 // Final statistics of every map into a device varsim_stats array.
 hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, long cells, int max_iter,
                            int iters_run, double tol, int residual_done, varsim_stats* out, hipStream_t stream);

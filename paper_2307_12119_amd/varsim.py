@@ -103,6 +103,7 @@ EXPORTS = {
     "varsim_set_autotune": (c_int, [c_void_p, c_int32]),
     "varsim_autotune_report": (c_int, [c_void_p, c_char_p, c_size_t]),
     "varsim_force_col_variant": (c_int, [c_void_p, c_int32]),
+    "varsim_set_small_path": (c_int, [c_void_p, c_int32]),
     "varsim_set_timing": (c_int, [c_void_p, c_int32]),
     "varsim_kernel_times": (c_int, [c_void_p, POINTER(c_char_p), POINTER(c_int64), POINTER(c_double),
                                     POINTER(c_int32)]),
@@ -330,6 +331,10 @@ class Context:
     def set_autotune(self, enable: int):
         """1: time launch-shape candidates at first use; 0: stop; -1: stop and forget choices."""
         self._check(self.lib.varsim_set_autotune(self.handle, int(enable)))
+
+    def set_small_path(self, max_n: int):
+        """Largest N solved by one LDS-resident workgroup per map (-1 default, 0 off)."""
+        self._check(self.lib.varsim_set_small_path(self.handle, int(max_n)))
 
     def force_col_variant(self, variant: int):
         self._check(self.lib.varsim_force_col_variant(self.handle, int(variant)))

@@ -321,3 +321,39 @@ def test_column_strip_widths_give_identical_results(ctx, n):
         assert torch.equal(c, convs[0])
     for m in maps[1:]:
         assert torch.equal(m, maps[0])
+
+
+@pytest.mark.parametrize("prec,n", [("f32", 16), ("f32", 32), ("f32", 64), ("f32", 128), ("f64", 16), ("f64", 32),
+                                    ("f64", 64)])
+def test_lds_resident_path_equals_two_pass_path(ctx, prec, n):
+    """Small maps solved start to finish by one LDS-resident workgroup give the two-pass path's
+    iterates bitwise: cold and warm starts, a mixed batch, a not-converged and a runaway map."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    dt = torch.float32 if prec == "f32" else torch.float64
+    p = V.F32 if prec == "f32" else V.F64
+    inps = [W.config2(sample=s, n=n) for s in range(3)]
+    hot = W.config2(sample=3, n=n)
+    hot.q_leak0 = hot.q_leak0 * 60.0  # leakage far past the stable branch
+    warm = np.full((n, n), 5.0)
+    runs = []
+    try:
+        for limit in (0, -1):
+            ctx.set_small_path(limit)
+            items = [gpu_item(i, dt) for i in inps] + [gpu_item(inps[0], dt, dT_init=warm), gpu_item(hot, dt)]
+            st = ctx.solve_batch(items, _opts(p, inps[0], 50, 1e-6 if prec == "f64" else 1e-4, res=True))
+            st2 = ctx.solve_batch([gpu_item(inps[1], dt)], _opts(p, inps[1], 2, 1e-9))  # not converged
+            runs.append(([it["dT_out"].cpu() for it in items[:4]], st, st2))
+    finally:
+        ctx.set_small_path(-1)
+    (m0, s0, t0), (m1, s1, t1) = runs
+    for a, b in zip(m0, m1):
+        assert torch.equal(a, b)
+    for a, b in zip(s0[:4], s1[:4]):
+        assert a == b
+    assert s0[4]["status"] == s1[4]["status"] == V.ERR_RUNAWAY
+    assert s0[4]["iterations"] == s1[4]["iterations"]
+    assert t0[0]["status"] == t1[0]["status"] == V.ERR_NOT_CONVERGED
+    assert t0[0]["iterations"] == t1[0]["iterations"] == 2
+    assert t0[0]["last_increment_K"] == t1[0]["last_increment_K"]
