@@ -36,6 +36,51 @@ def _sample(i: int, n: int, fft_workers: int = 1):
     return f(inp.q_dyn), f(inp.q_leak0), f(inp.leak_var), f(inp.cond_map)
 
 
+def _sample_small(seed: int):
+    import numpy as np
+
+    import workloads.gen as W
+
+    inp = W.config1(seed=seed, n=64)
+    return inp.q_dyn.astype(np.float64), inp.q_leak0.astype(np.float64)
+
+
+def _sample_mixed(size_class: int, i: int):
+    import numpy as np
+
+    import workloads.gen as W
+
+    W.FFT_WORKERS = 1
+    inp = W.config3(size_class, i)
+    f = lambda a: a.astype(np.float32)
+    return size_class, f(inp.q_dyn), f(inp.q_leak0), f(inp.leak_var), f(inp.cond_map)
+
+
+def generate_extra(args):
+    """Inputs of the small-grid and mixed-size legs, made before the GPU is touched."""
+    import multiprocessing as mp
+
+    small = mixed = None
+    jobs = []
+    if not args.no_small:
+        jobs.append("small")
+    if not args.no_mixed:
+        jobs.append("mixed")
+    if not jobs:
+        return None, None
+    pool = mp.get_context("fork").Pool(max(1, args.workers))
+    try:
+        if "small" in jobs:
+            small = pool.map(_sample_small, range(args.small_batch))
+        if "mixed" in jobs:
+            # size classes interleaved in the problem array
+            mixed = pool.starmap(_sample_mixed, [(c, i) for i in range(args.mixed_batch) for c in range(4)])
+    finally:
+        pool.close()
+        pool.join()
+    return small, mixed
+
+
 def generate(batch: int, n: int, workers: int):
     if workers <= 1:
         import workloads.gen as W
@@ -106,6 +151,10 @@ def main() -> int:
     ap.add_argument("--no-transient", action="store_true", help="skip the 1024^2 x 1000-step transient run")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-warm-started solve")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes (no timing of candidates)")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64^2 FP64 small-grid leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size Monte Carlo leg")
+    ap.add_argument("--small-batch", type=int, default=4096)
+    ap.add_argument("--mixed-batch", type=int, default=256, help="samples per size class")
     ap.add_argument("--transient-runs", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -125,8 +174,10 @@ def main() -> int:
             import numpy as np
 
             np.save(args.inputs_cache, np.stack([np.stack(s) for s in samples]))
+    small_in, mixed_in = generate_extra(args)
     t_gen = time.perf_counter() - t_gen
-    print(f"[bench] generated {args.batch} samples of {args.n}^2 in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    print(f"[bench] generated {args.batch} samples of {args.n}^2 (+ extra legs) in {t_gen:.1f} s", file=sys.stderr,
+          flush=True)
 
     import numpy as np
     import torch
@@ -235,6 +286,10 @@ def main() -> int:
     if not args.no_transient:
         del ws
         result["transient"] = transient_bench(ctx, args.transient_runs)
+    if small_in is not None:
+        result["small"] = small_bench(ctx, small_in, args)
+    if mixed_in is not None:
+        result["mixed"] = mixed_bench(ctx, mixed_in, args)
     if not args.no_cpu_baseline:
         warm0 = None if out_w is None else out_w[0].cpu().numpy()
         result["cpu_baseline"], result["max_err_K"], err_w = cpu_baseline(args.n, out[0].cpu().numpy(), warm0)
@@ -242,6 +297,101 @@ def main() -> int:
             result["surrogate"]["max_err_vs_oracle_K"] = err_w
     print(json.dumps(result))
     return 0
+
+
+def small_bench(ctx, samples, args) -> dict:
+    """64 x 64 FP64 steady solves (16 blocks, no variation, k constant, exp leakage), tol 1e-6 K,
+    at most 20 iterations: one map at a time (latency) and a batch of all seeds (throughput),
+    with the LDS-resident path and with the two-pass path."""
+    import numpy as np
+    import torch
+
+    import workloads.gen as W
+    from paper_2307_12119_amd import varsim as V
+
+    dev = torch.device("cuda", 0)
+    d = W.Die(eta=0.0)
+    die = V.Die(d.lx_m, d.ly_m, d.t_m, d.k0, d.eta, d.t_amb, d.rho_c)
+    q = torch.from_numpy(np.stack([s[0] for s in samples])).to(dev)
+    ql = torch.from_numpy(np.stack([s[1] for s in samples])).to(dev)
+    out = torch.zeros_like(q)
+    B = q.shape[0]
+    opts = V.make_options(V.F64, V.LEAK_EXP, 0.017, 20, 1e-6)
+    one = ctx.prepare([{"die": die, "q_dyn": q[0], "q_leak0": ql[0], "dT_out": out[0]}])
+    many = ctx.prepare([{"die": die, "q_dyn": q[i], "q_leak0": ql[i], "dT_out": out[i]} for i in range(B)])
+    res = {"workload": f"steady 64x64 FP64, 16 blocks, no variation, tol 1e-6 K, max 20 iterations; "
+                       f"single map and a batch of {B} seeds"}
+    try:
+        for name, limit in (("lds_resident", -1), ("two_pass", 0)):
+            ctx.set_small_path(limit)
+            ws1 = torch.empty(ctx.workspace_bytes(one, opts), dtype=torch.uint8, device=dev)
+            wsb = torch.empty(ctx.workspace_bytes(many, opts), dtype=torch.uint8, device=dev)
+            for _ in range(3):
+                ctx.solve_batch(one, opts, ws1)
+            torch.cuda.synchronize()
+            reps = 50
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                st1 = ctx.solve_batch(one, opts, ws1)
+            torch.cuda.synchronize()
+            lat = (time.perf_counter() - t0) / reps
+            ctx.solve_batch(many, opts, wsb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                stb = ctx.solve_batch(many, opts, wsb)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / args.steps
+            res[name] = {"us_per_single_solve": round(lat * 1e6, 1), "batch_maps_per_s": round(B / el, 1),
+                         "batch_ms": round(el * 1e3, 3), "iterations_mean": float(np.mean(stb["iterations"])),
+                         "statuses": sorted({int(x) for x in stb["status"]})}
+    finally:
+        ctx.set_small_path(-1)
+    return res
+
+
+def mixed_bench(ctx, samples, args) -> dict:
+    """Mixed-size Monte Carlo batch: per size class 128, 256, 512, 1024 the same number of
+    variation samples of that class's floorplan, classes interleaved in one varsim_solve_batch
+    (FP32, tol 1e-3 K, FP64 residual per map); per-sample mean / max rises come with the stats."""
+    import numpy as np
+    import torch
+
+    import workloads.gen as W
+    from paper_2307_12119_amd import varsim as V
+
+    dev = torch.device("cuda", 0)
+    d = W.Die(eta=1.3)
+    die = V.Die(d.lx_m, d.ly_m, d.t_m, d.k0, d.eta, d.t_amb, d.rho_c)
+    items, cls = [], []
+    for c, qd, ql, lv, cm in samples:
+        t = lambda a: torch.from_numpy(a).to(dev)
+        items.append({"die": die, "q_dyn": t(qd), "q_leak0": t(ql), "leak_var": t(lv), "cond_map": t(cm),
+                      "dT_out": torch.zeros_like(t(qd))})
+        cls.append(c)
+    cls = np.array(cls)
+    opts = V.make_options(V.F32, V.LEAK_EXP, 0.017, 50, 1e-3, f64_residual=True)
+    batch = ctx.prepare(items)
+    ws = torch.empty(ctx.workspace_bytes(batch, opts), dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        ctx.solve_batch(batch, opts, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = ctx.solve_batch(batch, opts, ws)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    per = {}
+    for c in range(4):
+        sel = st[cls == c]
+        n = 128 << c
+        per[f"{n}x{n}"] = {"maps": int(sel.size), "iterations_mean": float(sel["iterations"].mean()),
+                           "dT_max_K_mean": float(sel["dT_max_K"].mean()),
+                           "residual_f64_max_K": float(sel["residual_f64_K"].max())}
+    return {"workload": f"{len(items)} steady FP32 problems, {args.mixed_batch} variation samples per size class "
+                        "128/256/512/1024 (one floorplan per class), classes interleaved, tol 1e-3 K, FP64 residual",
+            "maps_per_s": round(len(items) / el, 1), "ms_per_step": round(el * 1e3, 3),
+            "statuses": sorted({int(x) for x in st["status"]}), "classes": per}
 
 
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2307_12119_amd", "weights", "surrogate_512.npy")

@@ -1,0 +1,90 @@
+// Row-pass building blocks shared by the two-pass steady solve and the LDS-resident small-grid
+// solve: per-lane statistics of a new iterate and the pointwise update of one row (theta ->
+// conductivity factor -> Kirchhoff inverse -> increment / statistics -> new total power).
+#pragma once
+
+#include <cmath>
+
+#include "common.hpp"
+#include "fft.hpp"
+#include "internal.hpp"
+#include "passes.hpp"
+
+namespace vs {
+
+// Per-lane running statistics of the new iterate.
+template <typename Tc>
+struct LaneStats {
+  Tc inc = (Tc)0;       // max |dT_new - dT_old|
+  Tc sum = (Tc)0;       // sum of dT_new (NaN / inf propagate: runaway detection)
+  Tc xmax = (Tc)-INFINITY;
+  int imax = 0x7fffffff;
+  __device__ __forceinline__ void add(Tc x, Tc old, int idx) {
+    inc = fmax(inc, fabs(x - old));
+    sum += x;
+    if (x > xmax || (x == xmax && idx < imax)) {
+      xmax = x;
+      imax = idx;
+    }
+  }
+};
+
+// one map's pointwise update of one row: theta slots -> dT (stored) -> total power slots
+template <typename Tio, typename Tc, int N, int MODE>
+__device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off, int t, int mirror, bool zero_old,
+                                              const PointParams& pp, LaneStats<Tc>& ls) {
+  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
+  Tc x[E];
+  if constexpr (MODE == ROW_HEAD) {
+    if (zero_old) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) x[m] = (Tc)0;
+    } else {
+      load_slots<Tio, Tc, N>((const Tio*)mp.dT + off, x, t, mirror);
+    }
+  } else {
+    Tc old[E];
+    if (mp.minv) {
+      Tc mv[E];
+      load_slots<Tio, Tc, N>((const Tio*)mp.minv + off, mv, t, mirror);
+#pragma unroll
+      for (int m = 0; m < E; ++m) z[m] *= mv[m];
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) x[m] = kirchhoff_inv<Tc>(z[m], pp);
+    if (zero_old) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) old[m] = (Tc)0;
+    } else {
+      load_slots<Tio, Tc, N>((const Tio*)mp.dT + off, old, t, mirror);
+    }
+    if constexpr (MODE == ROW_RESID) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        ls.inc = fmax(ls.inc, fabs(x[m] - old[m]));
+        ls.sum += x[m];
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        x[m] = (Tc)(Tio)x[m];  // the iterate as stored
+        ls.add(x[m], old[m], (int)off + unperm<N>(t + TPF * m));
+      }
+      store_slots<Tio, Tc, N>((Tio*)mp.dT + off, x, t, mirror);
+    }
+  }
+  if constexpr (MODE == ROW_HEAD || MODE == ROW_MERGED) {
+    Tc q[E];
+    load_slots<Tio, Tc, N>((const Tio*)mp.qd + off, q, t, mirror);
+    if (mp.ql) {
+      Tc ql[E];
+      load_slots<Tio, Tc, N>((const Tio*)mp.ql + off, ql, t, mirror);
+#pragma unroll
+      for (int m = 0; m < E; ++m) q[m] += ql[m] * leak_factor<Tc>(x[m], pp);
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) z[m] = (Tc)pp.hxhy * q[m];
+  }
+}
+
+}  // namespace vs
