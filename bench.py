@@ -451,7 +451,8 @@ def surrogate_bench(ctx, items, qd, lv, cm, out_plain, opts, ws, args, plain_map
     t_net = (time.perf_counter() - t1) / args.steps
     ctx.set_timing(False)
     kt = ctx.kernel_times()
-    conv_ms = kt.get("nn_conv_fwd", {}).get("total_ms", 0.0) / args.steps
+    layer_ms = {k: round(v["total_ms"] / args.steps, 4) for k, v in kt.items() if k.startswith("fwd:")}
+    conv_ms = sum(v for k, v in layer_ms.items() if k.startswith("fwd:conv:"))
     flops = conv_flops_per_map(spec) * args.batch
     achieved = flops / (conv_ms * 1e-3) / 1e12 if conv_ms else None
     maps_per_s = args.batch * args.steps / elapsed
@@ -461,8 +462,8 @@ def surrogate_bench(ctx, items, qd, lv, cm, out_plain, opts, ws, args, plain_map
              "plain_iterations_mean": plain_iters, "statuses": sorted({int(x) for x in stats["status"]}),
              "max_diff_vs_plain_K": float((out_w - out_plain).abs().max()),
              "prediction_mae_K": float(pred_err.mean()), "prediction_max_err_K": float(pred_err.max()),
-             "network_ms_per_batch": round(t_net * 1e3, 4),
-             "roofline": {"bound": "mfma", "kernel": "nn_conv_fwd", "achieved": None if achieved is None else
+             "network_ms_per_batch": round(t_net * 1e3, 4), "layer_ms_per_batch": layer_ms,
+             "roofline": {"bound": "mfma", "kernel": "conv_kernel (all forward convolutions)", "achieved": None if achieved is None else
                           round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                           "frac": None if achieved is None else round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
                           "flops_per_launch_batch": flops, "conv_ms_per_batch": conv_ms},

@@ -57,7 +57,7 @@ NetBufs plan(const varsim_net* net, int B, bool training, char* base) {
   };
   const int* w = net->cfg.width;
   auto P = [&](int l) { return (size_t)B * level_size(net, l) * level_size(net, l); };
-  b.feat = (uint16_t*)take(P(0) * 64 * 2);
+  b.feat = training ? (uint16_t*)take(P(0) * 64 * 2) : nullptr;
   b.stem = (uint16_t*)take(P(0) * w[0] * 2);
   for (int l = 0; l < 5; ++l) {
     if (l > 0) b.pool[l] = (uint16_t*)take(P(l) * w[l - 1] * 2);
@@ -182,42 +182,59 @@ NnConv dgrad_args(const varsim_net* net, const NetLayer& L, const uint16_t* dz, 
   return a;
 }
 
+// timing classes of the forward pass, one per layer ("fwd:conv:*" are the convolutions)
+const char* const kFwdEncA[5] = {"fwd:conv:enc0a", "fwd:conv:enc1a", "fwd:conv:enc2a", "fwd:conv:enc3a",
+                                 "fwd:conv:enc4a"};
+const char* const kFwdEncB[5] = {"fwd:conv:enc0b", "fwd:conv:enc1b", "fwd:conv:enc2b", "fwd:conv:enc3b",
+                                 "fwd:conv:enc4b"};
+const char* const kFwdDec[4] = {"fwd:conv:dec0", "fwd:conv:dec1", "fwd:conv:dec2", "fwd:conv:dec3"};
+const char* const kFwdPool[5] = {"", "fwd:elem:pool1", "fwd:elem:pool2", "fwd:elem:pool3", "fwd:elem:pool4"};
+
+// training: also keep the features and the last decoder output (the gradient pass reads them);
+// inference fuses the head into the last decoder convolution.
 varsim_status run_forward(varsim_net* net, int B, const float* q, const float* v, const float* m, const int* idx,
-                          float* out, const NetBufs& b, hipStream_t s) {
+                          float* out, const NetBufs& b, bool training, hipStream_t s) {
   varsim_ctx* ctx = net->ctx;
   const int* w = net->cfg.width;
   NnFeat f;
   for (int c = 0; c < 3; ++c) f.shift[c] = net->cfg.shift[c], f.scale[c] = net->cfg.scale[c];
   f.k0 = net->cfg.k0_W_mK;
-  HIP_TRY(timed(ctx, "nn_elementwise", s, [&] { return nn_features(q, v, m, idx, net->cfg.n, B, f, b.feat, s); }));
-  HIP_TRY(timed(ctx, "nn_conv_fwd", s, [&] {
-    return nn_conv(1, NN_EPI_BF16, true, conv_args(net, net->stem, b.feat, 64, nullptr, 0, b.stem, B, 0, true), s);
+  HIP_TRY(timed(ctx, "fwd:conv:stem", s, [&] {
+    return nn_stem(q, v, m, idx, net->cfg.n, B, f, net->wbf + net->stem.wb, net->p + net->stem.b_off, w[0], b.stem,
+                   training ? b.feat : nullptr, s);
   }));
   for (int l = 0; l < 5; ++l) {
     const uint16_t* in = b.stem;
     int cin = w[0];
     if (l > 0) {
       const int ml = level_size(net, l);
-      HIP_TRY(timed(ctx, "nn_elementwise", s, [&] { return nn_avgpool(b.eb[l - 1], b.pool[l], B, ml, ml, w[l - 1], s); }));
+      HIP_TRY(timed(ctx, kFwdPool[l], s, [&] { return nn_avgpool(b.eb[l - 1], b.pool[l], B, ml, ml, w[l - 1], s); }));
       in = b.pool[l];
       cin = w[l - 1];
     }
-    HIP_TRY(timed(ctx, "nn_conv_fwd", s, [&] {
+    HIP_TRY(timed(ctx, kFwdEncA[l], s, [&] {
       return nn_conv(3, NN_EPI_BF16, true, conv_args(net, net->enc[l][0], in, cin, nullptr, 0, b.ea[l], B, l, true), s);
     }));
-    HIP_TRY(timed(ctx, "nn_conv_fwd", s, [&] {
+    HIP_TRY(timed(ctx, kFwdEncB[l], s, [&] {
       return nn_conv(3, NN_EPI_BF16, true, conv_args(net, net->enc[l][1], b.ea[l], w[l], nullptr, 0, b.eb[l], B, l, true),
                      s);
     }));
   }
   for (int l = 3; l >= 0; --l) {
     const uint16_t* up = l == 3 ? b.eb[4] : b.d[l + 1];
-    HIP_TRY(timed(ctx, "nn_conv_fwd", s, [&] {
+    if (l == 0 && !training && w[0] == 32) {  // last decoder layer with the head in its epilogue
+      NnConv a = conv_args(net, net->dec[0], b.eb[0], w[0], up, w[1], out, B, 0, true);
+      a.w2 = net->wbf + net->head.wb;
+      a.bias2 = net->p + net->head.b_off;
+      HIP_TRY(timed(ctx, "fwd:conv:dec0+head", s, [&] { return nn_conv(3, NN_EPI_HEAD, true, a, s); }));
+      return VARSIM_OK;
+    }
+    HIP_TRY(timed(ctx, kFwdDec[l], s, [&] {
       return nn_conv(3, NN_EPI_BF16, true, conv_args(net, net->dec[l], b.eb[l], w[l], up, w[l + 1], b.d[l], B, l, true),
                      s);
     }));
   }
-  HIP_TRY(timed(ctx, "nn_conv_fwd", s, [&] {
+  HIP_TRY(timed(ctx, "fwd:conv:head", s, [&] {
     return nn_conv(1, NN_EPI_SHUFFLE, false, conv_args(net, net->head, b.d[0], w[0], nullptr, 0, out, B, 0, true), s);
   }));
   return VARSIM_OK;
@@ -394,7 +411,7 @@ varsim_status varsim_net_forward(varsim_net* net, int32_t batch, const float* q_
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const NetBufs b = plan(net, batch, false, (char*)workspace);
-  st = run_forward(net, batch, q_dyn, leak_var, cond_map, sample_idx, dT_out, b, s);
+  st = run_forward(net, batch, q_dyn, leak_var, cond_map, sample_idx, dT_out, b, false, s);
   if (ctx->timing && st == VARSIM_OK) {
     HIP_TRY(hipStreamSynchronize(s));
     flush_timing(ctx);
@@ -413,7 +430,7 @@ varsim_status varsim_net_gradient(varsim_net* net, int32_t batch, const float* q
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const NetBufs b = plan(net, batch, true, (char*)workspace);
-  if ((st = run_forward(net, batch, q_dyn, leak_var, cond_map, sample_idx, b.y, b, s)) != VARSIM_OK) return st;
+  if ((st = run_forward(net, batch, q_dyn, leak_var, cond_map, sample_idx, b.y, b, true, s)) != VARSIM_OK) return st;
   if ((st = run_gradient(net, batch, sample_idx, target, grad, loss, b, s)) != VARSIM_OK) return st;
   if (ctx->timing) {
     HIP_TRY(hipStreamSynchronize(s));

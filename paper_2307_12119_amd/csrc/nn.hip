@@ -11,6 +11,7 @@
 // of pixels write partial sums that a second kernel adds in a fixed order.
 #include <cmath>
 
+#include "fft.hpp"
 #include "nn.hpp"
 
 namespace vs {
@@ -84,6 +85,41 @@ __global__ void __launch_bounds__(256) conv_kernel(NnConv a) {
     }
   }
 
+  if constexpr (EPI == NN_EPI_HEAD) {
+    // this layer's 32 channels -> BF16 -> B operand of the 16-output layer.  Lane (lr, lg) holds
+    // channels 4 lg + r (tile 0) and 16 + 4 lg + r (tile 1) of pixel lr: that is its K group, and
+    // the head's A operand is loaded in the same channel order.
+    static_assert(MW == 2, "head epilogue needs the 32 channels in two tiles");
+    float b1[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      b1[r] = a.bias[4 * lg + r];
+      b1[4 + r] = a.bias[16 + 4 * lg + r];
+    }
+    const uint2 wl = *reinterpret_cast<const uint2*>(a.w2 + lr * 32 + 4 * lg);
+    const uint2 wh = *reinterpret_cast<const uint2*>(a.w2 + lr * 32 + 16 + 4 * lg);
+    const bf16x8 hw = as_bf(make_uint4(wl.x, wl.y, wh.x, wh.y));
+    float hb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hb[r] = a.bias2[4 * lg + r];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      float v[8];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = fmaxf(acc[0][j][r] + b1[r], 0.f);
+        v[4 + r] = fmaxf(acc[1][j][r] + b1[4 + r], 0.f);
+      }
+      const uint4 d = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7]));
+      f32x4 h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hw, as_bf(d), f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      if (!pv[j]) continue;
+      float* out = (float*)a.y + ((long)pb[j] * (4 * H) + 4 * py[j] + lg) * (4L * W) + 4 * px[j];
+      const float sc = a.out_scale;
+      *reinterpret_cast<float4*>(out) =
+          make_float4(sc * (h[0] + hb[0]), sc * (h[1] + hb[1]), sc * (h[2] + hb[2]), sc * (h[3] + hb[3]));
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < MW; ++i) {
     const int co = co0 + i * 16 + 4 * lg;
@@ -126,6 +162,7 @@ hipError_t conv_launch(const NnConv& a, hipStream_t s) {
 template <int KS, int EPI, bool RELU>
 hipError_t conv_tile(const NnConv& a, hipStream_t s) {
   if (a.cout % 64 == 0) return conv_launch<KS, 4, 2, EPI, RELU>(a, s);
+  if (a.cout % 48 == 0) return conv_launch<KS, 3, 2, EPI, RELU>(a, s);
   if (a.cout % 32 == 0) return conv_launch<KS, 2, 4, EPI, RELU>(a, s);
   return conv_launch<KS, 1, 8, EPI, RELU>(a, s);
 }
@@ -138,6 +175,9 @@ hipError_t conv_ks(int epi, bool relu, const NnConv& a, hipStream_t s) {
     case NN_EPI_SHUFFLE:
       if (a.cout != 16) return hipErrorInvalidValue;
       return conv_launch<KS, 1, 8, NN_EPI_SHUFFLE, false>(a, s);
+    case NN_EPI_HEAD:
+      if (a.cout != 32 || !a.w2 || !a.bias2) return hipErrorInvalidValue;
+      return conv_launch<KS, 2, 4, NN_EPI_HEAD, true>(a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -337,40 +377,80 @@ __global__ void __launch_bounds__(256) slice_kernel(const float* __restrict__ dc
   }
 }
 
-// one thread per coarse pixel: the 48 standardized patch features, padded to 64
-__global__ void __launch_bounds__(256) features_kernel(const float* __restrict__ q, const float* __restrict__ v,
-                                                       const float* __restrict__ m, const int* __restrict__ idx, int n,
-                                                       int B, NnFeat f, uint16_t* __restrict__ out) {
+// Features + 1x1 stem.  Wave = 16 coarse pixels.  Lane (lr, lg) reads row lg of pixel lr's 4x4
+// patch (one 16-byte load per map) and forms its 12 features; they meet in LDS as [pixel][64]
+// BF16 (slots 48..63 zero), from which each lane takes its B operand: slots 32 c + 8 lg .. + 7
+// of pixel lr for the two K chunks c.
+template <int MT>
+__global__ void __launch_bounds__(256) stem_kernel(const float* __restrict__ q, const float* __restrict__ v,
+                                                   const float* __restrict__ m, const int* __restrict__ idx, int n,
+                                                   int B, NnFeat f, const uint16_t* __restrict__ w,
+                                                   const float* __restrict__ bias, uint16_t* __restrict__ y,
+                                                   uint16_t* __restrict__ feat_out) {
+  constexpr int COUT = 16 * MT;
+  constexpr int FP = 72;  // LDS pitch of a pixel's feature row (BF16 elements; rows stay 16-byte aligned)
+  __shared__ __attribute__((aligned(16))) uint16_t sf[4][16 * FP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
   const int mc = n / 4;
-  const long total = (long)B * mc * mc;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
-    const int b = (int)(i / ((long)mc * mc));
-    const int rem = (int)(i - (long)b * mc * mc);
-    const int Y = rem / mc, X = rem % mc;
-    const long s = idx ? idx[b] : b;
-    float feat[64];
-#pragma unroll
-    for (int py = 0; py < 4; ++py) {
-      const long o = s * n * n + (long)(4 * Y + py) * n + 4 * X;
+  const long P = (long)B * mc * mc;
+  const long p = ((long)blockIdx.x * 4 + wave) * 16 + lr;
+  const bool pv = p < P;
+  uint16_t* row = sf[wave] + lr * FP;
+  {
+    float fv[12];
+    if (pv) {
+      const int b = (int)(p / ((long)mc * mc));
+      const int rem = (int)(p - (long)b * mc * mc);
+      const int Y = rem / mc, X = rem % mc;
+      const long sidx = idx ? idx[b] : b;
+      const long o = sidx * n * n + (long)(4 * Y + lg) * n + 4 * X;
       const float4 qq = *reinterpret_cast<const float4*>(q + o);
       const float4 vv = v ? *reinterpret_cast<const float4*>(v + o) : make_float4(1.f, 1.f, 1.f, 1.f);
       const float4 mm = m ? *reinterpret_cast<const float4*>(m + o) : make_float4(1.f, 1.f, 1.f, 1.f);
       const float qa[4] = {qq.x, qq.y, qq.z, qq.w}, va[4] = {vv.x, vv.y, vv.z, vv.w}, ma[4] = {mm.x, mm.y, mm.z, mm.w};
 #pragma unroll
       for (int px = 0; px < 4; ++px) {
-        const int k = (py * 4 + px) * 3;
-        feat[k] = (qa[px] * 1e-6f - f.shift[0]) * f.scale[0];
-        feat[k + 1] = (logf(va[px]) - f.shift[1]) * f.scale[1];
-        feat[k + 2] = (f.k0 * ma[px] * (1.f / 150.f) - f.shift[2]) * f.scale[2];
+        fv[3 * px] = (qa[px] * 1e-6f - f.shift[0]) * f.scale[0];
+        fv[3 * px + 1] = (__logf(va[px]) - f.shift[1]) * f.scale[1];
+        fv[3 * px + 2] = (f.k0 * ma[px] * (1.f / 150.f) - f.shift[2]) * f.scale[2];
       }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) fv[i] = 0.f;
     }
+    // patch row lg holds slots 12 lg .. 12 lg + 11 (6 BF16 pairs)
+    unsigned* dst = reinterpret_cast<unsigned*>(row + 12 * lg);
 #pragma unroll
-    for (int k = 48; k < 64; ++k) feat[k] = 0.f;
-    uint4* o = reinterpret_cast<uint4*>(out + i * 64);
+    for (int i = 0; i < 6; ++i) dst[i] = pack2(fv[2 * i], fv[2 * i + 1]);
+    if (lg == 0) {
+      uint4* z = reinterpret_cast<uint4*>(row + 48);
+      z[0] = make_uint4(0u, 0u, 0u, 0u);
+      z[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+  wave_sync();
+  f32x4 acc[MT];
 #pragma unroll
-    for (int w = 0; w < 8; ++w)
-      o[w] = make_uint4(pack2(feat[8 * w], feat[8 * w + 1]), pack2(feat[8 * w + 2], feat[8 * w + 3]),
-                        pack2(feat[8 * w + 4], feat[8 * w + 5]), pack2(feat[8 * w + 6], feat[8 * w + 7]));
+  for (int i = 0; i < MT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const uint4 bv = *reinterpret_cast<const uint4*>(row + 32 * c + 8 * lg);
+    if (feat_out && pv) *reinterpret_cast<uint4*>(feat_out + p * 64 + 32 * c + 8 * lg) = bv;
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      const uint4 av = ld16(w + (long)(i * 16 + lr) * 64 + 32 * c + 8 * lg);
+      acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(bv), acc[i], 0, 0, 0);
+    }
+  }
+  if (!pv) return;
+#pragma unroll
+  for (int i = 0; i < MT; ++i) {
+    const int co = i * 16 + 4 * lg;
+    float r4[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) r4[r] = fmaxf(acc[i][r] + bias[co + r], 0.f);
+    *reinterpret_cast<uint2*>(y + p * COUT + co) = make_uint2(pack2(r4[0], r4[1]), pack2(r4[2], r4[3]));
   }
 }
 
@@ -524,11 +604,17 @@ hipError_t nn_split_cat_grad(const float* dcat, int cu, int cx, float* dcoarse, 
   return hipGetLastError();
 }
 
-hipError_t nn_features(const float* q, const float* v, const float* m, const int* idx, int n, int B, NnFeat f,
-                       uint16_t* out, hipStream_t s) {
+hipError_t nn_stem(const float* q, const float* v, const float* m, const int* idx, int n, int B, const NnFeat& f,
+                   const uint16_t* w, const float* bias, int cout, uint16_t* y, uint16_t* feat_out, hipStream_t s) {
   if (n % 4) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(features_kernel, dim3(blocks_for((long)B * (n / 4) * (n / 4))), dim3(256), 0, s, q, v, m, idx, n,
-                     B, f, out);
+  const long P = (long)B * (n / 4) * (n / 4);
+  const dim3 grid((unsigned)((P + 63) / 64));
+  if (cout == 32)
+    hipLaunchKernelGGL(stem_kernel<2>, grid, dim3(256), 0, s, q, v, m, idx, n, B, f, w, bias, y, feat_out);
+  else if (cout == 64)
+    hipLaunchKernelGGL(stem_kernel<4>, grid, dim3(256), 0, s, q, v, m, idx, n, B, f, w, bias, y, feat_out);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

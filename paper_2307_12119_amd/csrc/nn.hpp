@@ -18,14 +18,19 @@ struct NnConv {
   const float* bias;  // [cout] or null
   void* y;            // output, see NnEpi
   int B, H, W, cout;
-  float out_scale;    // NN_EPI_SHUFFLE only
+  float out_scale;    // NN_EPI_SHUFFLE / NN_EPI_HEAD
+  // NN_EPI_HEAD: a 1x1 layer of 16 outputs applied to this layer's ReLU output in registers
+  const uint16_t* w2;  // [16][cout] BF16
+  const float* bias2;  // [16]
 };
 
 enum NnEpi : int {
   NN_EPI_BF16 = 0,       // y: [B][H][W][cout] BF16 of (acc + bias), ReLU if requested
   NN_EPI_F32 = 1,        // y: [B][H][W][cout] FP32 of (acc + bias)
   NN_EPI_SHUFFLE = 2,    // cout = 16: y[b][4Y + j/4][4X + j%4] = out_scale (acc_j + bias_j), [B][4H][4W] FP32
+  NN_EPI_HEAD = 3,       // cout = 32, ReLU: then y as NN_EPI_SHUFFLE of the 16-output layer (w2, bias2)
 };
+
 
 hipError_t nn_conv(int ks, int epi, bool relu, const NnConv& a, hipStream_t s);
 
@@ -55,10 +60,13 @@ struct NnFeat {
   float shift[3], scale[3];
   float k0;
 };
-// [B][n][n] FP32 maps (sample b at idx[b] when idx is given; v, m may be null = 1) ->
-// [B][n/4][n/4][64] BF16: feature (py*4 + px)*3 + c of the 4x4 patch, 48..63 zero
-hipError_t nn_features(const float* q, const float* v, const float* m, const int* idx, int n, int B, NnFeat f,
-                       uint16_t* out, hipStream_t s);
+// Features + 1x1 stem (48 -> cout = 32 or 64, ReLU) in one kernel.  Inputs: [B][n][n] FP32
+// maps (sample b at idx[b] when idx is given; v, m may be null = 1).  Feature (py*4 + px)*3 + c
+// of a coarse pixel's 4x4 patch is formed in the lane that feeds it to the matrix cores;
+// feat_out ([B][n/4][n/4][64] BF16, features 48..63 zero) is written too when given (the
+// training pass needs it).
+hipError_t nn_stem(const float* q, const float* v, const float* m, const int* idx, int n, int B, const NnFeat& f,
+                   const uint16_t* w, const float* bias, int cout, uint16_t* y, uint16_t* feat_out, hipStream_t s);
 // dh[b][Y][X][j] = BF16 of out_scale * 2 (y - t) / (B n^2) at fine pixel (4Y + j/4, 4X + j%4);
 // part[block][17] = per-block sums of the 16 FP32 dh values and of (y - t)^2
 constexpr int kNnMseBlocks = 256;

@@ -352,7 +352,7 @@ class Context:
         self._check(self.lib.varsim_reset_timing(self.handle))
 
     def kernel_times(self) -> dict:
-        cap = 64
+        cap = 256
         names = (c_char_p * cap)()
         counts = (c_int64 * cap)()
         tot = (c_double * cap)()
