@@ -536,7 +536,8 @@ def transient_bench(ctx, runs: int) -> dict:
             "ms_per_run": round(wall_untimed * 1e3, 3), "ms_per_run_with_kernel_events": round(wall * 1e3, 3),
             "steps_per_s": round(steps / wall_untimed, 1), "status": st["status"],
             "dT_max_K": st["dT_max_K"], "fp64_shadow_max_diff_K": float(np.max(np.abs(got - ref))),
-            "kernels": kernels}
+            "kernels": kernels,
+            "autotune": [l for l in ctx.autotune_report().strip().split("\n") if l.startswith("transient")]}
 
 
 def cpu_baseline(n: int, gpu_map0, warm_map0=None):

@@ -794,13 +794,54 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
     return fail(ctx, VARSIM_ERR_INVALID, "conductivity map must be positive and finite");
   }
 
+  // launch shapes: tuned once per (n, precision) when autotuning is on.  The candidates run on
+  // this call's workspace (no snapshots), after which the spectral state and flags are reset.
+  int rv = 0, cv = 0;
+  if (ctx->force_col >= 0) {
+    rv = cv = ctx->force_col;
+  } else {
+    const auto key = std::make_pair(g->nx, io);
+    auto it = ctx->tr_choice.find(key);
+    if (it != ctx->tr_choice.end()) {
+      rv = it->second.first;
+      cv = it->second.second;
+    } else if (ctx->autotune) {
+      TransArgs t = a;
+      t.snaps = nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      std::vector<float> ms(6, 0.f);
+      for (int k = 0; k < 6; ++k) {
+        const int v = k % 3;
+        auto run = [&] {
+          return k < 3 ? launch_transient_row(TR_MERGED, io, t, 1, s, v) : launch_transient_col(io, t, s, v);
+        };
+        HIP_TRY(run());
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < 5; ++r) HIP_TRY(run());
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(&ms[k], e0, e1));
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      rv = (int)(std::min_element(ms.begin(), ms.begin() + 3) - ms.begin());
+      cv = (int)(std::min_element(ms.begin() + 3, ms.end()) - (ms.begin() + 3));
+      ctx->tr_choice[key] = {rv, cv};
+      ctx->tr_ms[key] = ms;
+      HIP_TRY(launch_zero_words(a.state, (size_t)cells * esize(io), s));
+      HIP_TRY(launch_zero_words(d_flags, sizeof(unsigned), s));
+    }
+  }
+
   // step n: column pass (mode update with P_n) then row pass (dT_n, and P_{n+1} unless last)
-  HIP_TRY(timed(ctx, "tr_row_head", s, [&] { return launch_transient_row(TR_HEAD, io, a, 0, s); }));
+  HIP_TRY(timed(ctx, "tr_row_head", s, [&] { return launch_transient_row(TR_HEAD, io, a, 0, s, rv); }));
   for (int n = 1; n <= tr->n_steps; ++n) {
-    HIP_TRY(timed(ctx, "tr_col", s, [&] { return launch_transient_col(io, a, s); }));
+    HIP_TRY(timed(ctx, "tr_col", s, [&] { return launch_transient_col(io, a, s, cv); }));
     const bool last = n == tr->n_steps;
     HIP_TRY(timed(ctx, last ? "tr_row_last" : "tr_row", s,
-                  [&] { return launch_transient_row(last ? TR_LAST : TR_MERGED, io, a, n, s); }));
+                  [&] { return launch_transient_row(last ? TR_LAST : TR_MERGED, io, a, n, s, rv); }));
   }
   HIP_TRY(launch_map_stats(io, problem->dT_out, cells, d_flags, tr->n_steps, d_stats, s));
   HIP_TRY(hipMemcpyAsync(stats, d_stats, sizeof(varsim_stats), hipMemcpyDeviceToHost, s));
@@ -848,6 +889,13 @@ varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
       out += line;
     }
     out += "\n";
+  }
+  for (const auto& kv : ctx->tr_choice) {
+    const auto& ms = ctx->tr_ms[kv.first];
+    snprintf(line, sizeof line, "transient n=%d %s: row %.4f %.4f %.4f ms -> %d; col %.4f %.4f %.4f ms -> %d\n",
+             kv.first.first, kv.first.second == VARSIM_F32 ? "f32" : "f64", ms[0], ms[1], ms[2], kv.second.first,
+             ms[3], ms[4], ms[5], kv.second.second);
+    out += line;
   }
   snprintf(buf, len, "%s", out.c_str());
   return out.size() < len ? VARSIM_OK : VARSIM_ERR_NO_MEMORY;

@@ -70,6 +70,9 @@ struct varsim_ctx {
   int small_limit = -1;  // largest N solved by one LDS-resident workgroup (-1: library default, 0: off)
   std::map<std::tuple<int, int, int>, int> col_choice;
   std::map<std::tuple<int, int, int>, std::vector<float>> col_ms;
+  // transient launch shapes per (n, precision): (row variant, column variant) and their timings
+  std::map<std::pair<int, int>, std::pair<int, int>> tr_choice;
+  std::map<std::pair<int, int>, std::vector<float>> tr_ms;
 };
 
 namespace {

@@ -115,8 +115,10 @@ hipError_t launch_transient_coef(const TableSpec& sp, const double* lam64T, int 
 hipError_t launch_block_ids(const int* rects, int n_blocks, int* ids, int nx, int ny, hipStream_t stream);
 // TR_HEAD: P_1 -> row spectrum; TR_MERGED (step n): row synthesis -> dT_n -> P_{n+1} -> row
 // spectrum; TR_LAST: row synthesis -> dT_n (final)
-hipError_t launch_transient_row(int mode, int io, const TransArgs& a, int step, hipStream_t stream);
-hipError_t launch_transient_col(int io, const TransArgs& a, hipStream_t stream);
+// variant: launch-shape candidate 0..2 (row: rows per workgroup default / half / one pair;
+// column: strip width default / half / quarter)
+hipError_t launch_transient_row(int mode, int io, const TransArgs& a, int step, hipStream_t stream, int variant = 0);
+hipError_t launch_transient_col(int io, const TransArgs& a, hipStream_t stream, int variant = 0);
 hipError_t launch_map_stats(int io, const void* dT, long cells, const unsigned* flags, int steps, varsim_stats* out,
                             hipStream_t stream);
 

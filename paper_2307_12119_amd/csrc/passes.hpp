@@ -133,17 +133,23 @@ __device__ __forceinline__ Tc kirchhoff_inv(Tc theta, const PointParams& pp) {
   if (pp.eta_mode == 0) return theta;
   const Tc u = (Tc)pp.u_scale * theta;
   if constexpr (sizeof(Tc) == 4) {
-    // FP32: Horner form of the Taylor series of (1 + u)^a - 1 (exp(u) - 1 for eta = 1)
+    // FP32: Horner form of the Taylor series of (1 + u)^a - 1 (exp(u) - 1 for eta = 1) where
+    // the first dropped term is negligible (|u| <= poly_umax <= 0.1); beyond it there is no
+    // cancellation and the hardware exp2 / log2 (relative error ~1e-6) keep the code short.
     if (fabsf(u) <= (float)pp.poly_umax) {
       float acc = pp.polyf[kPoly - 1];
 #pragma unroll
       for (int k = kPoly - 2; k >= 0; --k) acc = fmaf(acc, u, pp.polyf[k]);
       return (float)pp.t_amb * u * acc;
     }
+    if (pp.eta_mode == 1) return (float)pp.t_amb * (__expf(u) - 1.f);
+    if (!(u > -1.f)) return NAN;
+    return (float)pp.t_amb * (__expf((float)pp.inv_1m_eta * __logf(1.f + u)) - 1.f);
+  } else {
+    if (pp.eta_mode == 1) return (Tc)pp.t_amb * expm1(u);
+    if (!(u > (Tc)-1)) return (Tc)NAN;
+    return (Tc)pp.t_amb * expm1((Tc)pp.inv_1m_eta * log1p(u));
   }
-  if (pp.eta_mode == 1) return (Tc)pp.t_amb * expm1(u);
-  if (!(u > (Tc)-1)) return (Tc)NAN;
-  return (Tc)pp.t_amb * expm1((Tc)pp.inv_1m_eta * log1p(u));
 }
 
 template <int W>

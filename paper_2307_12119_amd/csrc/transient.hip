@@ -80,10 +80,19 @@ __global__ void __launch_bounds__(256) block_id_kernel(const int* __restrict__ r
   ids[c] = id;
 }
 
-template <typename Tio, typename Tc, int N, int MODE>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS)
+// Row-pass launch shape of the transient: FFTS_ row pairs per workgroup (0: the steady pass's
+// default).  A single map has only N/2 row pairs, so fewer per workgroup spreads them over more CUs.
+template <int N, int FFTS_>
+struct TrRowCfg {
+  static constexpr int TPF = Shape<N>::TPF;
+  static constexpr int FFTS = FFTS_ ? FFTS_ : RowCfg<N>::FFTS;
+  static constexpr int THREADS = FFTS * TPF;
+};
+
+template <typename Tio, typename Tc, int N, int MODE, int FFTS_>
+__global__ void __launch_bounds__((TrRowCfg<N, FFTS_>::THREADS))
     transient_row_kernel(TransArgs a, int step, const Cx<Tc>* __restrict__ tw, const Cx<Tc>* __restrict__ qw) {
-  using Cfg = RowCfg<N>;
+  using Cfg = TrRowCfg<N, FFTS_>;
   constexpr int TPF = Cfg::TPF;
   constexpr int E = Shape<N>::E;
   constexpr int ST = Shape<N>::STRIDE;
@@ -186,10 +195,10 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
   }
 }
 
-template <typename Tc, int N>
-__global__ void __launch_bounds__((ColCfg<Tc, N>::THREADS))
+template <typename Tc, int N, int COLS>
+__global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
     transient_col_kernel(TransArgs a, const Cx<Tc>* __restrict__ tw, const Cx<Tc>* __restrict__ qw) {
-  using Cfg = ColCfg<Tc, N>;
+  using Cfg = ColCfg<Tc, N, COLS>;
   constexpr int TPF = Cfg::TPF;
   constexpr int E = Shape<N>::E;
   constexpr int ST = Shape<N>::STRIDE;
@@ -318,36 +327,76 @@ __global__ void __launch_bounds__(1024) map_stats_kernel(const Tio* __restrict__
   }
 }
 
-template <typename Tio, typename Tc, int N>
-hipError_t tr_row_launch(int mode, const TransArgs& a, int step, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
-  using Cfg = RowCfg<N>;
+template <typename Tio, typename Tc, int N, int FFTS>
+hipError_t tr_row_shape(int mode, const TransArgs& a, int step, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+  using Cfg = TrRowCfg<N, FFTS>;
   const dim3 grid((N / 2) / Cfg::FFTS), block(Cfg::THREADS);
   switch (mode) {
-    case TR_HEAD: hipLaunchKernelGGL((transient_row_kernel<Tio, Tc, N, TR_HEAD>), grid, block, 0, s, a, step, tw, qw); break;
-    case TR_MERGED:
-      hipLaunchKernelGGL((transient_row_kernel<Tio, Tc, N, TR_MERGED>), grid, block, 0, s, a, step, tw, qw);
+    case TR_HEAD:
+      hipLaunchKernelGGL((transient_row_kernel<Tio, Tc, N, TR_HEAD, FFTS>), grid, block, 0, s, a, step, tw, qw);
       break;
-    case TR_LAST: hipLaunchKernelGGL((transient_row_kernel<Tio, Tc, N, TR_LAST>), grid, block, 0, s, a, step, tw, qw); break;
+    case TR_MERGED:
+      hipLaunchKernelGGL((transient_row_kernel<Tio, Tc, N, TR_MERGED, FFTS>), grid, block, 0, s, a, step, tw, qw);
+      break;
+    case TR_LAST:
+      hipLaunchKernelGGL((transient_row_kernel<Tio, Tc, N, TR_LAST, FFTS>), grid, block, 0, s, a, step, tw, qw);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <typename Tc, int N>
-hipError_t tr_col_launch(const TransArgs& a, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
-  using Cfg = ColCfg<Tc, N>;
-  hipLaunchKernelGGL((transient_col_kernel<Tc, N>), dim3(N / Cfg::COLS, 1), dim3(Cfg::THREADS), 0, s, a, tw, qw);
+// row-pass candidates: 0 = default rows per workgroup, 1 = half of them, 2 = one row pair
+template <int N, int V>
+constexpr int tr_row_ffts() {
+  constexpr int f0 = RowCfg<N>::FFTS;
+  return V == 0 ? f0 : (V == 1 ? (f0 / 2 > 0 ? f0 / 2 : 1) : 1);
+}
+
+template <typename Tio, typename Tc, int N>
+hipError_t tr_row_launch(int mode, int v, const TransArgs& a, int step, const Cx<Tc>* tw, const Cx<Tc>* qw,
+                         hipStream_t s) {
+  switch (v) {
+    case 0: return tr_row_shape<Tio, Tc, N, tr_row_ffts<N, 0>()>(mode, a, step, tw, qw, s);
+    case 1: return tr_row_shape<Tio, Tc, N, tr_row_ffts<N, 1>()>(mode, a, step, tw, qw, s);
+    case 2: return tr_row_shape<Tio, Tc, N, tr_row_ffts<N, 2>()>(mode, a, step, tw, qw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// column-pass candidates: 0 = default strip width, 1 = half, 2 = quarter (at least 2 columns)
+template <typename Tc, int N, int V>
+constexpr int tr_col_cols() {
+  constexpr int c0 = ColCfg<Tc, N>::COLS;
+  constexpr int c = V == 0 ? c0 : (V == 1 ? c0 / 2 : c0 / 4);
+  return c < 2 ? 2 : c;
+}
+
+template <typename Tc, int N, int COLS>
+hipError_t tr_col_shape(const TransArgs& a, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+  using Cfg = ColCfg<Tc, N, COLS>;
+  hipLaunchKernelGGL((transient_col_kernel<Tc, N, COLS>), dim3(N / Cfg::COLS, 1), dim3(Cfg::THREADS), 0, s, a, tw, qw);
   return hipGetLastError();
 }
 
+template <typename Tc, int N>
+hipError_t tr_col_launch(int v, const TransArgs& a, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+  switch (v) {
+    case 0: return tr_col_shape<Tc, N, tr_col_cols<Tc, N, 0>()>(a, tw, qw, s);
+    case 1: return tr_col_shape<Tc, N, tr_col_cols<Tc, N, 1>()>(a, tw, qw, s);
+    case 2: return tr_col_shape<Tc, N, tr_col_cols<Tc, N, 2>()>(a, tw, qw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
-hipError_t tr_dispatch(int which, int mode, int n, const TransArgs& a, int step, hipStream_t s) {
+hipError_t tr_dispatch(int which, int mode, int v, int n, const TransArgs& a, int step, hipStream_t s) {
   const Cx<T>* tw = sizeof(T) == 4 ? (const Cx<T>*)a.tw.tw32 : (const Cx<T>*)a.tw.tw64;
   const Cx<T>* qw = sizeof(T) == 4 ? (const Cx<T>*)a.tw.qw32 : (const Cx<T>*)a.tw.qw64;
 #define VS_TR_CASE(NN)                                                       \
   case NN:                                                                   \
-    return which == 0 ? tr_row_launch<T, T, NN>(mode, a, step, tw, qw, s) : \
-                        tr_col_launch<T, NN>(a, tw, qw, s);
+    return which == 0 ? tr_row_launch<T, T, NN>(mode, v, a, step, tw, qw, s) : \
+                        tr_col_launch<T, NN>(v, a, tw, qw, s);
   switch (n) {
     VS_TR_CASE(16)
     VS_TR_CASE(32)
@@ -384,13 +433,14 @@ hipError_t launch_block_ids(const int* rects, int n_blocks, int* ids, int nx, in
   return hipGetLastError();
 }
 
-hipError_t launch_transient_row(int mode, int io, const TransArgs& a, int step, hipStream_t stream) {
-  return io == VARSIM_F32 ? tr_dispatch<float>(0, mode, a.n, a, step, stream)
-                          : tr_dispatch<double>(0, mode, a.n, a, step, stream);
+hipError_t launch_transient_row(int mode, int io, const TransArgs& a, int step, hipStream_t stream, int variant) {
+  return io == VARSIM_F32 ? tr_dispatch<float>(0, mode, variant, a.n, a, step, stream)
+                          : tr_dispatch<double>(0, mode, variant, a.n, a, step, stream);
 }
 
-hipError_t launch_transient_col(int io, const TransArgs& a, hipStream_t stream) {
-  return io == VARSIM_F32 ? tr_dispatch<float>(1, 0, a.n, a, 0, stream) : tr_dispatch<double>(1, 0, a.n, a, 0, stream);
+hipError_t launch_transient_col(int io, const TransArgs& a, hipStream_t stream, int variant) {
+  return io == VARSIM_F32 ? tr_dispatch<float>(1, 0, variant, a.n, a, 0, stream)
+                          : tr_dispatch<double>(1, 0, variant, a.n, a, 0, stream);
 }
 
 hipError_t launch_map_stats(int io, const void* dT, long cells, const unsigned* flags, int steps, varsim_stats* out,

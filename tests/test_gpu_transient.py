@@ -230,3 +230,22 @@ def test_transient_statuses_and_edges(ctx):
         _run_gpu(ctx, bad_dt, torch.float64)
     with pytest.raises(V.VarsimError):
         _run_gpu(ctx, _case_input(24, 3, 50e-6, False), torch.float64)  # not a power of two
+
+
+@pytest.mark.parametrize("n", [32, 256])
+def test_transient_launch_shapes_give_identical_results(ctx, n):
+    """Every row / column launch shape of the transient passes computes the same arithmetic."""
+    import torch
+
+    inp = _case_input(n, 6, 100e-6, True)
+    got = []
+    try:
+        for v in range(3):
+            ctx.force_col_variant(v)
+            st, rec, last = _run_gpu(ctx, inp, torch.float32, out_every=2)
+            assert st["status"] == 0
+            got.append((rec, last))
+    finally:
+        ctx.force_col_variant(-1)
+    for rec, last in got[1:]:
+        assert np.array_equal(rec, got[0][0]) and np.array_equal(last, got[0][1])
