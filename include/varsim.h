@@ -315,6 +315,15 @@ VARSIM_API varsim_status varsim_set_small_path(varsim_ctx* ctx, int32_t max_n);
  * default, half, one pair) and column candidate `variant` (default, half, quarter width);
  * -1 returns to the default or tuned choices. */
 VARSIM_API varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t variant);
+/* Testing / manual tuning of transient solves: row-pass candidate `row_variant` and column-pass
+ * candidate `col_variant`, each in [0, 6): 0..2 transform two rows (columns) per DFT (row: rows
+ * per workgroup default / half / one pair; column: strip width default / half / quarter); 3..5
+ * transform one row (column) per DFT of half the length (row: 1 / 2 / 4 wavefronts per
+ * workgroup; column: widest strip / half / quarter), available for N >= 64 (an N below that
+ * falls back to candidate 0).  Results agree to rounding.  -1 returns to the tuned, forced
+ * (varsim_force_col_variant) or default choice.  VARSIM_ERR_INVALID outside [-1, 6). */
+VARSIM_API varsim_status varsim_force_transient_variant(varsim_ctx* ctx, int32_t row_variant,
+                                                        int32_t col_variant);
 
 /* ----------------------------------------------------------------------------------------
  * Kernel timing.  When enabled, every kernel launch of the solves is bracketed by HIP events

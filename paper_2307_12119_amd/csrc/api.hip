@@ -267,7 +267,7 @@ varsim_status check_transient(varsim_ctx* ctx, const varsim_problem* p, const va
 // Workspace of one transient solve.
 struct TransLayout {
   size_t flags = 0, state_end = 0, stats = 0, prep = 0, S = 0, state = 0, ab = 0, ids = 0;
-  size_t QL = (size_t)-1, MINV = (size_t)-1, total = 0;
+  size_t QL = (size_t)-1, MINV = (size_t)-1, IDZ = 0, QLZ = (size_t)-1, MINVZ = (size_t)-1, total = 0;
 };
 
 TransLayout make_transient_layout(const varsim_problem* p, const varsim_options* o) {
@@ -295,6 +295,17 @@ TransLayout make_transient_layout(const varsim_problem* p, const varsim_options*
   }
   if (p->cond_map) {
     L.MINV = off;
+    off = align_up(off + cells * es);
+  }
+  // z-order copies for the one-row passes
+  L.IDZ = off;
+  off = align_up(off + cells * 4);
+  if (p->q_leak0 && o->leak != VARSIM_LEAK_NONE) {
+    L.QLZ = off;
+    off = align_up(off + cells * es);
+  }
+  if (p->cond_map) {
+    L.MINVZ = off;
     off = align_up(off + cells * es);
   }
   L.total = off;
@@ -756,6 +767,9 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   a.flags = d_flags;
   a.pp = point_params(g, opts);
   a.tw = Twiddles{tw.tw64, tw.tw32, tw.qw64, tw.qw32};
+  a.idz = (const int*)(ws + L.IDZ);
+  a.qlz = a.ql ? ws + L.QLZ : nullptr;
+  a.minvz = a.minv ? ws + L.MINVZ : nullptr;
 
   ctx->h_prep.assign(1, PrepArgs{});
   PrepArgs& q = ctx->h_prep[0];
@@ -781,6 +795,13 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
     return launch_transient_coef(sp, tab.lam64T, io, (void*)a.ab, alpha, tr->dt_s, tr->tau_model,
                                  g->layers[0].rho_c_J_m3K, s);
   }));
+  if (transient_single_ok(g->nx)) {
+    HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zorder(4, a.ids, (void*)a.idz, g->nx, s); }));
+    if (a.ql)
+      HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zorder((int)esize(io), a.ql, (void*)a.qlz, g->nx, s); }));
+    if (a.minv)
+      HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zorder((int)esize(io), a.minv, (void*)a.minvz, g->nx, s); }));
+  }
   unsigned h_flags = 0;
   HIP_TRY(hipMemcpyAsync(&h_flags, d_flags, sizeof h_flags, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -796,44 +817,51 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
 
   // launch shapes: tuned once per (n, precision) when autotuning is on.  The candidates run on
   // this call's workspace (no snapshots), after which the spectral state and flags are reset.
+  const int nv = transient_variants(g->nx);
   int rv = 0, cv = 0;
+  const auto key = std::make_pair(g->nx, io);
+  auto it = ctx->tr_choice.find(key);
   if (ctx->force_col >= 0) {
     rv = cv = ctx->force_col;
-  } else {
-    const auto key = std::make_pair(g->nx, io);
-    auto it = ctx->tr_choice.find(key);
-    if (it != ctx->tr_choice.end()) {
-      rv = it->second.first;
-      cv = it->second.second;
-    } else if (ctx->autotune) {
-      TransArgs t = a;
-      t.snaps = nullptr;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      HIP_TRY(hipEventCreate(&e0));
-      HIP_TRY(hipEventCreate(&e1));
-      std::vector<float> ms(6, 0.f);
-      for (int k = 0; k < 6; ++k) {
-        const int v = k % 3;
+  } else if (it != ctx->tr_choice.end()) {
+    rv = it->second.first;
+    cv = it->second.second;
+  } else if (ctx->autotune && ctx->force_tr_row < 0 && ctx->force_tr_col < 0) {
+    TransArgs t = a;
+    t.snaps = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    // the GPU may have idled before this call: a short untimed burst first, then two rounds
+    // over the candidates keeping each one's faster round
+    for (int r = 0; r < 40; ++r) HIP_TRY(launch_transient_col(io, t, s, 0));
+    std::vector<float> ms(2 * nv, 1e30f);
+    for (int round = 0; round < 2; ++round)
+      for (int k = 0; k < 2 * nv; ++k) {
+        const int v = k % nv;
         auto run = [&] {
-          return k < 3 ? launch_transient_row(TR_MERGED, io, t, 1, s, v) : launch_transient_col(io, t, s, v);
+          return k < nv ? launch_transient_row(TR_MERGED, io, t, 1, s, v) : launch_transient_col(io, t, s, v);
         };
         HIP_TRY(run());
         HIP_TRY(hipEventRecord(e0, s));
         for (int r = 0; r < 5; ++r) HIP_TRY(run());
         HIP_TRY(hipEventRecord(e1, s));
         HIP_TRY(hipEventSynchronize(e1));
-        HIP_TRY(hipEventElapsedTime(&ms[k], e0, e1));
+        float el = 0.f;
+        HIP_TRY(hipEventElapsedTime(&el, e0, e1));
+        ms[k] = std::min(ms[k], el / 5.f);
       }
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      rv = (int)(std::min_element(ms.begin(), ms.begin() + 3) - ms.begin());
-      cv = (int)(std::min_element(ms.begin() + 3, ms.end()) - (ms.begin() + 3));
-      ctx->tr_choice[key] = {rv, cv};
-      ctx->tr_ms[key] = ms;
-      HIP_TRY(launch_zero_words(a.state, (size_t)cells * esize(io), s));
-      HIP_TRY(launch_zero_words(d_flags, sizeof(unsigned), s));
-    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    rv = (int)(std::min_element(ms.begin(), ms.begin() + nv) - ms.begin());
+    cv = (int)(std::min_element(ms.begin() + nv, ms.end()) - (ms.begin() + nv));
+    ctx->tr_choice[key] = {rv, cv};
+    ctx->tr_ms[key] = ms;
+    HIP_TRY(launch_zero_words(a.state, (size_t)cells * esize(io), s));
+    HIP_TRY(launch_zero_words(d_flags, sizeof(unsigned), s));
   }
+  if (ctx->force_tr_row >= 0) rv = ctx->force_tr_row < nv ? ctx->force_tr_row : 0;
+  if (ctx->force_tr_col >= 0) cv = ctx->force_tr_col < nv ? ctx->force_tr_col : 0;
 
   // step n: column pass (mode update with P_n) then row pass (dT_n, and P_{n+1} unless last)
   HIP_TRY(timed(ctx, "tr_row_head", s, [&] { return launch_transient_row(TR_HEAD, io, a, 0, s, rv); }));
@@ -875,6 +903,15 @@ varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t variant) {
   return VARSIM_OK;
 }
 
+varsim_status varsim_force_transient_variant(varsim_ctx* ctx, int32_t row_variant, int32_t col_variant) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  if (row_variant < -1 || row_variant >= kTrVariants || col_variant < -1 || col_variant >= kTrVariants)
+    return fail(ctx, VARSIM_ERR_INVALID, "transient variants must be in [-1, %d]", kTrVariants - 1);
+  ctx->force_tr_row = row_variant;
+  ctx->force_tr_col = col_variant;
+  return VARSIM_OK;
+}
+
 varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
   if (!ctx || !buf || !len) return VARSIM_ERR_INVALID;
   std::string out;
@@ -892,10 +929,20 @@ varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
   }
   for (const auto& kv : ctx->tr_choice) {
     const auto& ms = ctx->tr_ms[kv.first];
-    snprintf(line, sizeof line, "transient n=%d %s: row %.4f %.4f %.4f ms -> %d; col %.4f %.4f %.4f ms -> %d\n",
-             kv.first.first, kv.first.second == VARSIM_F32 ? "f32" : "f64", ms[0], ms[1], ms[2], kv.second.first,
-             ms[3], ms[4], ms[5], kv.second.second);
+    const int nv = (int)ms.size() / 2;
+    snprintf(line, sizeof line, "transient n=%d %s ms per pass: row", kv.first.first,
+             kv.first.second == VARSIM_F32 ? "f32" : "f64");
     out += line;
+    for (int v = 0; v < nv; ++v) {
+      snprintf(line, sizeof line, " %.4f%s", ms[v], v == kv.second.first ? "*" : "");
+      out += line;
+    }
+    out += "; col";
+    for (int v = 0; v < nv; ++v) {
+      snprintf(line, sizeof line, " %.4f%s", ms[nv + v], v == kv.second.second ? "*" : "");
+      out += line;
+    }
+    out += "\n";
   }
   snprintf(buf, len, "%s", out.c_str());
   return out.size() < len ? VARSIM_OK : VARSIM_ERR_NO_MEMORY;

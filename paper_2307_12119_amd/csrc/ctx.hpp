@@ -67,6 +67,7 @@ struct varsim_ctx {
   // column-pass strip width chosen by timing, per (n, compute type, log2 of the group size)
   bool autotune = false;
   int force_col = -1;  // >= 0: every column pass uses this strip-width candidate
+  int force_tr_row = -1, force_tr_col = -1;  // >= 0: transient passes use these candidates
   int small_limit = -1;  // largest N solved by one LDS-resident workgroup (-1: library default, 0: off)
   std::map<std::tuple<int, int, int>, int> col_choice;
   std::map<std::tuple<int, int, int>, std::vector<float>> col_ms;

@@ -80,10 +80,14 @@ __device__ __forceinline__ void partner(const T* own, T* out, int t) {
   const int lane = __lane_id();
   const int src = (lane & ~(TPF - 1)) + ((TPF - t) & (TPF - 1));
   const bool head = t == 0;
+  // Lane t > 0 reads slot E-1-r of lane TPF-t; lane 0 reads itself and keeps its own slot
+  // (E-r) mod E instead.  The choice is made after the exchange so that it stays a select
+  // between two values: a select between two slots of own[] is folded by the compiler into a
+  // lane-varying register index, which it expands into a compare/select chain per element.
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const T send = head ? own[(E - r) & (E - 1)] : own[E - 1 - r];
-    out[r] = lane_get(send, src);
+    const T got = lane_get(own[E - 1 - r], src);
+    out[r] = head ? own[(E - r) & (E - 1)] : got;
   }
   if (!PERIODIC && head) out[0] = (T)0;
 }
@@ -213,7 +217,8 @@ __device__ __forceinline__ void dft_r(T* r, T* i) {
 }
 
 // Stockham stages of span NS onwards: LDS in, LDS out (middle) or registers out (last).
-template <typename T, int N, int NS, int DIR>
+// tw[TS k] = exp(-2 pi i k / N): TS = 1 with the table of N, TS = 2 with the table of 2N.
+template <typename T, int N, int NS, int DIR, int TS = 1>
 __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx<T>* __restrict__ tw, int t) {
   constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
   constexpr int R = (N / NS >= 8) ? 8 : (N / NS);
@@ -237,7 +242,7 @@ __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx
     const int j = b & (NS - 1);
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      const Cx<T> w = tw[j * r * (N / (NS * R))];
+      const Cx<T> w = tw[TS * j * r * (N / (NS * R))];
       const T wi = DIR < 0 ? w.i : -w.i;
       const T a = yr[u * R + r], c = yi[u * R + r];
       yr[u * R + r] = a * w.r - c * wi;
@@ -262,14 +267,14 @@ __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx
   }
   if constexpr (!LAST) {
     wave_sync();
-    stages_from<T, N, NS * R, DIR>(xr, xi, re, im, tw, t);
+    stages_from<T, N, NS * R, DIR, TS>(xr, xi, re, im, tw, t);
   }
 }
 
 // Unnormalised DFT (DIR = -1) or inverse DFT (DIR = +1) of the group's sequence, slot m of lane
 // t holding element t + TPF m on entry and on exit.  (re, im): this group's LDS buffer; the
 // caller must have finished its own reads of that buffer (wave_sync) before the call.
-template <typename T, int N, int DIR>
+template <typename T, int N, int DIR, int TS = 1>
 __device__ __forceinline__ void fft_reg(T* xr, T* xi, T* re, T* im, const Cx<T>* __restrict__ tw, int t) {
   constexpr int E = Shape<N>::E;
   dft_r<T, E, DIR>(xr, xi);
@@ -280,7 +285,7 @@ __device__ __forceinline__ void fft_reg(T* xr, T* xi, T* re, T* im, const Cx<T>*
     im[s] = xi[r];
   }
   wave_sync();
-  stages_from<T, N, E, DIR>(xr, xi, re, im, tw, t);
+  stages_from<T, N, E, DIR, TS>(xr, xi, re, im, tw, t);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -106,6 +106,11 @@ struct TransArgs {
   unsigned* flags;    // runaway flag word
   PointParams pp;
   Twiddles tw;
+  // z-order copies (single.hpp) of ids, ql and minv for the one-row passes (null where the
+  // natural array is null)
+  const int* idz;
+  const void* qlz;
+  const void* minvz;
 };
 enum TransMode : int { TR_HEAD = 0, TR_MERGED = 1, TR_LAST = 2 };
 
@@ -115,10 +120,19 @@ hipError_t launch_transient_coef(const TableSpec& sp, const double* lam64T, int 
 hipError_t launch_block_ids(const int* rects, int n_blocks, int* ids, int nx, int ny, hipStream_t stream);
 // TR_HEAD: P_1 -> row spectrum; TR_MERGED (step n): row synthesis -> dT_n -> P_{n+1} -> row
 // spectrum; TR_LAST: row synthesis -> dT_n (final)
-// variant: launch-shape candidate 0..2 (row: rows per workgroup default / half / one pair;
-// column: strip width default / half / quarter)
+// variant: launch-shape candidate.  0..2: two sequences per transform (row: rows per workgroup
+// default / half / one pair; column: strip width default / half / quarter); 3..5: one sequence
+// per transform (row: 1 / 2 / 4 wavefronts per workgroup; column: widest strip / half /
+// quarter), available where transient_single_ok(n).
+constexpr int kTrVariants = 6;
+bool transient_single_ok(int n);
+int transient_variants(int n);
 hipError_t launch_transient_row(int mode, int io, const TransArgs& a, int step, hipStream_t stream, int variant = 0);
 hipError_t launch_transient_col(int io, const TransArgs& a, hipStream_t stream, int variant = 0);
+hipError_t launch_transient_row1(int mode, int io, const TransArgs& a, int step, hipStream_t stream, int variant);
+hipError_t launch_transient_col1(int io, const TransArgs& a, hipStream_t stream, int variant);
+// dst[row][2j + k] = src[row][z_sample(j, k)] for an n x n array of esz-byte elements
+hipError_t launch_zorder(int esz, const void* src, void* dst, int n, hipStream_t stream);
 hipError_t launch_map_stats(int io, const void* dT, long cells, const unsigned* flags, int steps, varsim_stats* out,
                             hipStream_t stream);
 

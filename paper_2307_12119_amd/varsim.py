@@ -103,6 +103,7 @@ EXPORTS = {
     "varsim_set_autotune": (c_int, [c_void_p, c_int32]),
     "varsim_autotune_report": (c_int, [c_void_p, c_char_p, c_size_t]),
     "varsim_force_col_variant": (c_int, [c_void_p, c_int32]),
+    "varsim_force_transient_variant": (c_int, [c_void_p, c_int32, c_int32]),
     "varsim_set_small_path": (c_int, [c_void_p, c_int32]),
     "varsim_set_timing": (c_int, [c_void_p, c_int32]),
     "varsim_kernel_times": (c_int, [c_void_p, POINTER(c_char_p), POINTER(c_int64), POINTER(c_double),
@@ -338,6 +339,11 @@ class Context:
 
     def force_col_variant(self, variant: int):
         self._check(self.lib.varsim_force_col_variant(self.handle, int(variant)))
+
+    def force_transient_variant(self, row: int, col: int):
+        """Pin the transient row / column pass candidates (0..2: two sequences per DFT, 3..5: one
+        sequence per half-length DFT); -1 returns to the tuned or default choice."""
+        self._check(self.lib.varsim_force_transient_variant(self.handle, int(row), int(col)))
 
     def autotune_report(self) -> str:
         buf = ctypes.create_string_buffer(8192)

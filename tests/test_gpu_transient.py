@@ -69,6 +69,21 @@ def _run_gpu(ctx, inp, dtype, out_every=1, tau="moment", leak="exp", cap=1000.0,
     return st, rec, item["dT_out"].cpu().numpy().astype(np.float64)
 
 
+class _variants:
+    """Pin the transient row / column pass candidates for the duration of a block (None: the
+    library's own choice)."""
+
+    def __init__(self, ctx, rv_cv):
+        self.ctx, self.rv_cv = ctx, rv_cv
+
+    def __enter__(self):
+        if self.rv_cv is not None:
+            self.ctx.force_transient_variant(*self.rv_cv)
+
+    def __exit__(self, *exc):
+        self.ctx.force_transient_variant(-1, -1)
+
+
 def _oracle(inp, out_every=1, tau="moment", leak="exp"):
     g = S.geometry_from_die(inp.die, inp.n)
     model = T.TransientModel(g, inp.die.rho_c, tau)
@@ -127,9 +142,44 @@ def test_transient_fp32_matches_oracle(ctx, n, steps, dt, variation, leak, tau, 
     assert np.max(np.abs(last - ref_last)) <= FP32_GATE_K
 
 
+# (row, column) pass candidates: two sequences per DFT (0) and one per half-length DFT (3..5)
+ONE_ROW = [(3, 3), (4, 4), (5, 5), (3, 0), (0, 3)]
+
+
+@pytest.mark.parametrize("rv_cv", ONE_ROW, ids=lambda v: f"row{v[0]}-col{v[1]}")
+@pytest.mark.parametrize("case", [CASES[4], CASES[5], CASES[6]], ids=["64", "64-noleak-lumped", "128"])
+def test_transient_one_row_passes_fp64_match_oracle(ctx, rv_cv, case):
+    import torch
+
+    n, steps, dt, variation, leak, tau, every = case
+    inp = _case_input(n, steps, dt, variation)
+    ref, ref_last = _oracle(inp, every, tau, leak)
+    with _variants(ctx, rv_cv):
+        st, rec, last = _run_gpu(ctx, inp, torch.float64, every, tau, leak)
+    assert st["status"] == 0 and st["iterations"] == steps
+    scale = max(np.max(np.abs(ref)), np.max(np.abs(ref_last)))
+    assert np.max(np.abs(rec - ref)) <= FP64_GATE_REL * scale
+    assert np.max(np.abs(last - ref_last)) <= FP64_GATE_REL * scale
+    assert st["hotspot_index"] == int(np.argmax(ref_last))
+
+
+def test_transient_one_row_passes_fp32_match_oracle(ctx):
+    import torch
+
+    n, steps, dt, variation, leak, tau, every = CASES[6]
+    inp = _case_input(n, steps, dt, variation, seed=1)
+    ref, ref_last = _oracle(inp, every, tau, leak)
+    with _variants(ctx, (3, 3)):
+        st, rec, last = _run_gpu(ctx, inp, torch.float32, every, tau, leak)
+    assert st["status"] == 0
+    assert np.max(np.abs(rec - ref)) <= FP32_GATE_K
+    assert np.max(np.abs(last - ref_last)) <= FP32_GATE_K
+
+
+@pytest.mark.parametrize("rv_cv", [(0, 0), (3, 3)], ids=["pair", "one-row"])
 @pytest.mark.parametrize("dtype_name", ["float64", "float32"])
 @pytest.mark.parametrize("eta", [0.0, 1.3])
-def test_transient_uniform_power_closed_form_1024(ctx, dtype_name, eta):
+def test_transient_uniform_power_closed_form_1024(ctx, dtype_name, eta, rv_cv):
     """Uniform power excites only the uniform mode: theta_n = q t / k_ref (1 - exp(-n dt / tau(0))),
     tau(0) = t^2 rho c / (3 k_ref), and dT_n = Phi^-1(theta_n) in every cell."""
     import torch
@@ -139,7 +189,8 @@ def test_transient_uniform_power_closed_form_1024(ctx, dtype_name, eta):
     die = W.Die(eta=eta)
     inp = W.TransientInputs(die, n, dt, steps, np.array([[0, 0, n, n]], np.int32), np.full((steps, 1), q), None,
                             None, None)
-    st, rec, last = _run_gpu(ctx, inp, dtype, out_every=1, leak="none")
+    with _variants(ctx, rv_cv):
+        st, rec, last = _run_gpu(ctx, inp, dtype, out_every=1, leak="none")
     assert st["status"] == 0
     k_ref = die.k0 * (die.t_amb / 300.0) ** (-eta)
     tau0 = die.t_m ** 2 * die.rho_c / (3.0 * k_ref)
@@ -169,14 +220,16 @@ def test_transient_long_time_reaches_steady_fixed_point(ctx):
     assert np.max(np.abs(last - ref)) <= 1e-9 * np.max(ref)
 
 
-def test_transient_full_size_sampled(ctx):
+@pytest.mark.parametrize("rv_cv", [(0, 0), (3, 3), (4, 5)], ids=["pair", "one-row", "one-row-narrow"])
+def test_transient_full_size_sampled(ctx, rv_cv):
     """1024 x 1024, FP32, leakage + variation: at sampled cells the recorded rise of the last step
     equals the oracle's superposition of the power history rebuilt from the recorded rises."""
     import torch
 
     n, steps, dt = 1024, 10, 50e-6
     inp = W.transient_problem(n=n, n_steps=steps, dt_s=dt, n_blocks=64, hold_s=2 * dt, seed=2)
-    st, rec, last = _run_gpu(ctx, inp, torch.float32, out_every=1)
+    with _variants(ctx, rv_cv):
+        st, rec, last = _run_gpu(ctx, inp, torch.float32, out_every=1)
     assert st["status"] == 0
     assert np.array_equal(rec[-1], last)
     g = S.geometry_from_die(inp.die, n)
@@ -234,18 +287,36 @@ def test_transient_statuses_and_edges(ctx):
 
 @pytest.mark.parametrize("n", [32, 256])
 def test_transient_launch_shapes_give_identical_results(ctx, n):
-    """Every row / column launch shape of the transient passes computes the same arithmetic."""
+    """Launch shapes of one transform family compute the same arithmetic (identical FP32 bits);
+    the two families (two sequences per DFT, one per half-length DFT) agree to FP64 rounding and
+    may be mixed between the row and column passes."""
     import torch
 
     inp = _case_input(n, 6, 100e-6, True)
-    got = []
+
+    def run(rv_cv, dtype):
+        with _variants(ctx, rv_cv):
+            st, rec, last = _run_gpu(ctx, inp, dtype, out_every=2)
+        assert st["status"] == 0
+        return rec, last
+
+    pair = [run((v, v), torch.float32) for v in range(3)]
+    for rec, last in pair[1:]:
+        assert np.array_equal(rec, pair[0][0]) and np.array_equal(last, pair[0][1])
+    # the force_col_variant switch also pins the transient candidates 0..2
     try:
-        for v in range(3):
-            ctx.force_col_variant(v)
-            st, rec, last = _run_gpu(ctx, inp, torch.float32, out_every=2)
-            assert st["status"] == 0
-            got.append((rec, last))
+        ctx.force_col_variant(2)
+        st, rec, last = _run_gpu(ctx, inp, torch.float32, out_every=2)
     finally:
         ctx.force_col_variant(-1)
-    for rec, last in got[1:]:
-        assert np.array_equal(rec, got[0][0]) and np.array_equal(last, got[0][1])
+    assert np.array_equal(last, pair[0][1])
+    one = [run((v, w), torch.float32) for v, w in ((3, 3), (4, 4), (5, 5), (3, 5))]
+    for rec, last in one[1:]:
+        assert np.array_equal(rec, one[0][0]) and np.array_equal(last, one[0][1])
+    if n < 64:  # no one-row passes below 64: the request falls back to candidate 0
+        assert np.array_equal(one[0][1], pair[0][1])
+    f64 = [run(v, torch.float64)[1] for v in ((0, 0), (3, 3), (3, 0), (0, 3))]
+    scale = np.max(np.abs(f64[0]))
+    for last in f64[1:]:
+        assert np.max(np.abs(last - f64[0])) <= 1e-12 * scale
+    assert np.max(np.abs(one[0][1] - pair[0][1])) <= 1e-4 * scale
