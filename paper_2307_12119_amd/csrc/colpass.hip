@@ -82,11 +82,7 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
       const int p = t + TPF * m;
       const bool hi = m >= E / 2;  // p >= N/2: stored at N - p with beta negated
       const int pi = hi ? N - p : p;
-      const Vec<Tc, 4> ka = ca[pi], kb = cb[pi];
-      const Tc ba = hi ? -ka.v[1] : ka.v[1], bb = hi ? -kb.v[1] : kb.v[1];
-      const Tc u = zr[q][m] + pr[m], v = zi[q][m] - pim[m], w = zi[q][m] + pim[m], x = pr[m] - zr[q][m];
-      zr[q][m] = ka.v[0] * u + ba * v - bb * w - kb.v[2] * x;
-      zi[q][m] = ba * u + ka.v[2] * v + kb.v[0] * w + bb * x;
+      lambda_pair<Tc>(ca[pi], cb[pi], hi, zr[q][m], zi[q][m], pr[m], pim[m]);
     }
     wave_sync();
     fft_reg<Tc, N, +1>(zr[q], zi[q], re, im, tw, t);

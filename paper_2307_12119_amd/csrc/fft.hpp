@@ -92,6 +92,14 @@ __device__ __forceinline__ void partner(const T* own, T* out, int t) {
   if (!PERIODIC && head) out[0] = (T)0;
 }
 
+// a b + c d with one fixed rounding order (the product c d rounded, then fused with a b), so
+// that every kernel computing the same expression gets the same bits whatever the compiler's
+// contraction choices around it
+template <typename T>
+__device__ __forceinline__ T dot2(T a, T b, T c, T d) {
+  return fma(a, b, c * d);
+}
+
 // multiply by DIR * i
 template <typename T, int DIR>
 __device__ __forceinline__ void mul_i(T& r, T& i) {
@@ -149,25 +157,27 @@ __device__ __forceinline__ void dft8(T* r, T* i) {
   T orr[4] = {r[1], r[3], r[5], r[7]}, oi[4] = {i[1], i[3], i[5], i[7]};
   dft4<T, DIR>(er, ei);
   dft4<T, DIR>(orr, oi);
-  const T c = (T)0.70710678118654752440084436210485;
-  {
-    const T a = orr[1], b = oi[1];
-    orr[1] = c * (a - (T)DIR * b);
-    oi[1] = c * (b + (T)DIR * a);
-  }
   mul_i<T, DIR>(orr[2], oi[2]);
-  {
-    const T a = orr[3], b = oi[3];
-    orr[3] = c * (-a - (T)DIR * b);
-    oi[3] = c * (-b + (T)DIR * a);
-  }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 4; k += 2) {
     r[k] = er[k] + orr[k];
     i[k] = ei[k] + oi[k];
     r[k + 4] = er[k] - orr[k];
     i[k + 4] = ei[k] - oi[k];
   }
+  // odd terms 1 and 3 carry W8^k = c (+-1 +- i): the factor c is applied in fused
+  // multiply-adds with the even terms (fixed rounding, independent of the compiler's choices)
+  const T c = (T)0.70710678118654752440084436210485;
+  const T x1 = orr[1] - (T)DIR * oi[1], y1 = oi[1] + (T)DIR * orr[1];
+  const T x3 = -orr[3] - (T)DIR * oi[3], y3 = -oi[3] + (T)DIR * orr[3];
+  r[1] = fma(c, x1, er[1]);
+  i[1] = fma(c, y1, ei[1]);
+  r[5] = fma(-c, x1, er[1]);
+  i[5] = fma(-c, y1, ei[1]);
+  r[3] = fma(c, x3, er[3]);
+  i[3] = fma(c, y3, ei[3]);
+  r[7] = fma(-c, x3, er[3]);
+  i[7] = fma(-c, y3, ei[3]);
 }
 
 // radix 16 as 4 x 4: inner DFT-4 over n1 of x[4 n1 + n2], twiddle W16^(n2 k1), outer DFT-4 over n2
@@ -186,8 +196,8 @@ __device__ __forceinline__ void dft16(T* r, T* i) {
       const T wr = cs[j], wi = (T)DIR * sn[j];
       const int e = n2 + 4 * k1;
       const T a = r[e], b = i[e];
-      r[e] = a * wr - b * wi;
-      i[e] = a * wi + b * wr;
+      r[e] = dot2(a, wr, -b, wi);
+      i[e] = dot2(a, wi, b, wr);
     }
   T yr[16], yi[16];
 #pragma unroll
@@ -245,8 +255,8 @@ __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx
       const Cx<T> w = tw[TS * j * r * (N / (NS * R))];
       const T wi = DIR < 0 ? w.i : -w.i;
       const T a = yr[u * R + r], c = yi[u * R + r];
-      yr[u * R + r] = a * w.r - c * wi;
-      yi[u * R + r] = a * wi + c * w.r;
+      yr[u * R + r] = dot2(a, w.r, -c, wi);
+      yi[u * R + r] = dot2(a, wi, c, w.r);
     }
     dft_r<T, R, DIR>(yr + u * R, yi + u * R);
     if constexpr (LAST) {
@@ -293,18 +303,18 @@ __device__ __forceinline__ void fft_reg(T* xr, T* xi, T* re, T* im, const Cx<T>*
 // two packed sequences at p (and at N - p).  (c, s) = (cos, sin)(pi p / 2N).
 template <typename T>
 __device__ __forceinline__ void split_pair(T A, T B, T C, T D, T c, T s, T& xa, T& xb, T& xa2, T& xb2) {
-  xa = (T)0.5 * (c * (A + C) + s * (B - D));
-  xb = (T)0.5 * (c * (B + D) + s * (C - A));
-  xa2 = (T)0.5 * (s * (C + A) + c * (D - B));
-  xb2 = (T)0.5 * (s * (D + B) + c * (A - C));
+  xa = (T)0.5 * dot2(c, A + C, s, B - D);
+  xb = (T)0.5 * dot2(c, B + D, s, C - A);
+  xa2 = (T)0.5 * dot2(s, C + A, c, D - B);
+  xb2 = (T)0.5 * dot2(s, D + B, c, A - C);
 }
 
 // Merge before the inverse DFT: cosine coefficients of the two sequences at p and N - p give
 // Z[p] of the packed inverse.
 template <typename T>
 __device__ __forceinline__ void merge_pair(T ya, T yb, T ya2, T yb2, T c, T s, T& zr, T& zi) {
-  zr = c * ya + s * ya2 - (s * yb - c * yb2);
-  zi = s * ya - c * ya2 + c * yb + s * yb2;
+  zr = dot2(c, ya, s, ya2) - dot2(s, yb, -c, yb2);
+  zi = dot2(s, ya, -c, ya2) + dot2(c, yb, s, yb2);
 }
 
 }  // namespace vs

@@ -102,6 +102,20 @@ __device__ __forceinline__ void store_slots(Tio* __restrict__ row, const Tc* val
   }
 }
 
+// Column-pass step between the forward and inverse column DFTs of a packed column pair: split
+// into the two columns' cosine coefficients at (p, N - p), multiply by lambda, merge back.  ka, kb:
+// the columns' (alpha, beta, gamma) at min(p, N - p); hi: p >= N / 2 (beta negated).  (zr, zi):
+// Z[p] of the forward DFT, (pr, pim): Z[N - p]; (zr, zi) is overwritten with the merged Z[p] of
+// the inverse.
+template <typename Tc>
+__device__ __forceinline__ void lambda_pair(const Vec<Tc, 4>& ka, const Vec<Tc, 4>& kb, bool hi, Tc& zr, Tc& zi,
+                                            Tc pr, Tc pim) {
+  const Tc ba = hi ? -ka.v[1] : ka.v[1], bb = hi ? -kb.v[1] : kb.v[1];
+  const Tc u = zr + pr, v = zi - pim, w = zi + pim, x = pr - zr;
+  zr = dot2(ka.v[0], u, ba, v) - dot2(bb, w, kb.v[2], x);
+  zi = dot2(ba, u, ka.v[2], v) + dot2(kb.v[0], w, bb, x);
+}
+
 template <typename T>
 __device__ __forceinline__ T ldm(const void* p, long i) {
   return ((const T*)p)[i];

@@ -62,11 +62,11 @@ __device__ __forceinline__ void dct2_single(T* zr, T* zi, T* re, T* im, const Cx
     const T evr = (T)0.5 * (zr[m] + cr[m]), evi = (T)0.5 * (zi[m] - ci[m]);
     const T odr = (T)0.5 * (zi[m] + ci[m]), odi = (T)0.5 * (cr[m] - zr[m]);
     const Cx<T> w = tw[p];  // exp(-2 pi i p / N)
-    const T vr = evr + w.r * odr - w.i * odi;
-    const T vi = evi + w.r * odi + w.i * odr;
+    const T vr = evr + dot2(w.r, odr, -w.i, odi);
+    const T vi = evi + dot2(w.r, odi, w.i, odr);
     const Cx<T> q = qw[p];  // (cos, sin)(pi p / 2N)
-    zr[m] = q.r * vr + q.i * vi;
-    T hi = q.i * vr - q.r * vi;
+    zr[m] = dot2(q.r, vr, q.i, vi);
+    T hi = dot2(q.i, vr, -q.r, vi);
     if (m == 0) hi = head ? (evr - odr) * (T)0.70710678118654752440 : hi;  // X[N/2] = V[M] / sqrt 2
     zi[m] = hi;
   }
@@ -85,8 +85,8 @@ __device__ __forceinline__ void dct3_single(T* zr, T* zi, T* re, T* im, const Cx
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const Cx<T> q = qw[t + TPF * m];
-    vr[m] = q.r * zr[m] + q.i * zi[m];
-    vi[m] = q.i * zr[m] - q.r * zi[m];
+    vr[m] = dot2(q.r, zr[m], q.i, zi[m]);
+    vi[m] = dot2(q.i, zr[m], -q.r, zi[m]);
   }
   vi[0] = head ? (T)0 : vi[0];
   T cr[E], ci[E];
@@ -104,8 +104,8 @@ __device__ __forceinline__ void dct3_single(T* zr, T* zi, T* re, T* im, const Cx
     const T sr = vr[m] + gr, si = vi[m] + gi;
     const T dr = vr[m] - gr, di = vi[m] - gi;
     const Cx<T> w = tw[p];  // conj(w) (V[p] - V[p + M]) = 2 x DFT of the odd elements
-    zr[m] = sr - (w.r * di - w.i * dr);
-    zi[m] = si + (w.r * dr + w.i * di);
+    zr[m] = sr - dot2(w.r, di, -w.i, dr);
+    zi[m] = si + dot2(w.r, dr, w.i, di);
   }
   wave_sync();
   fft_reg<T, M, +1, 2>(zr, zi, re, im, tw, t);

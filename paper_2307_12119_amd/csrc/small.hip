@@ -127,11 +127,7 @@ __global__ void __launch_bounds__((SmallCfg<Tc, N>::THREADS))
         const int p = t + TPF * m;
         const bool hi = m >= E / 2;
         const int pi = hi ? N - p : p;
-        const Vec<Tc, 4> ka = ca[pi], kb = cb[pi];
-        const Tc ba = hi ? -ka.v[1] : ka.v[1], bb = hi ? -kb.v[1] : kb.v[1];
-        const Tc u = zr[m] + pr[m], v = zi[m] - pim[m], w = zi[m] + pim[m], x = pr[m] - zr[m];
-        zr[m] = ka.v[0] * u + ba * v - bb * w - kb.v[2] * x;
-        zi[m] = ba * u + ka.v[2] * v + kb.v[0] * w + bb * x;
+        lambda_pair<Tc>(ca[pi], cb[pi], hi, zr[m], zi[m], pr[m], pim[m]);
       }
       wave_sync();
       fft_reg<Tc, N, +1>(zr, zi, re, im, tw, t);

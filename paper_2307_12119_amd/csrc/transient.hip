@@ -252,8 +252,8 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
     Tc xa, xb, xa2, xb2;
     split_pair<Tc>(zr[m], zi[m], pr[m], pim[m], q.r, q.i, xa, xb, xa2, xb2);
     const Vec<Tc, 2> ka = aba[p], kb = abb[p];
-    na[m] = ka.v[0] * sta[p] + ka.v[1] * xa;
-    nb[m] = kb.v[0] * stb[p] + kb.v[1] * xb;
+    na[m] = dot2(ka.v[0], sta[p], ka.v[1], xa);
+    nb[m] = dot2(kb.v[0], stb[p], kb.v[1], xb);
     sta[p] = na[m];
     stb[p] = nb[m];
   }

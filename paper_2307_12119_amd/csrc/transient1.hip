@@ -317,8 +317,8 @@ __global__ void __launch_bounds__((TrCol1Cfg<Tc, N, COLS>::THREADS))
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int p = t + TPF * m, h = spec_hi<N>(p);
-    const Tc n0 = k0[m].v[0] * s0[m] + k0[m].v[1] * zr[m];
-    const Tc n1 = k1[m].v[0] * s1[m] + k1[m].v[1] * zi[m];
+    const Tc n0 = dot2(k0[m].v[0], s0[m], k0[m].v[1], zr[m]);
+    const Tc n1 = dot2(k1[m].v[0], s1[m], k1[m].v[1], zi[m]);
     st[p] = n0;
     st[h] = n1;
     zr[m] = n0;
