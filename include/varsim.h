@@ -321,7 +321,9 @@ VARSIM_API varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t varia
  * transform one row (column) per DFT of half the length (row: 1 / 2 / 4 wavefronts per
  * workgroup; column: widest strip / half / quarter), available for N >= 64 (an N below that
  * falls back to candidate 0).  Results agree to rounding.  -1 returns to the tuned, forced
- * (varsim_force_col_variant) or default choice.  VARSIM_ERR_INVALID outside [-1, 6). */
+ * (varsim_force_col_variant) or default choice (candidate 3 for both passes where N >= 64, else
+ * 0; with autotuning on, the candidates are timed over whole steps on the first solve of each
+ * (N, precision)).  VARSIM_ERR_INVALID outside [-1, 6). */
 VARSIM_API varsim_status varsim_force_transient_variant(varsim_ctx* ctx, int32_t row_variant,
                                                         int32_t col_variant);
 

@@ -818,7 +818,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   // launch shapes: tuned once per (n, precision) when autotuning is on.  The candidates run on
   // this call's workspace (no snapshots), after which the spectral state and flags are reset.
   const int nv = transient_variants(g->nx);
-  int rv = 0, cv = 0;
+  int rv = nv > 3 ? 3 : 0, cv = rv;  // untuned default: one-sequence passes where available
   const auto key = std::make_pair(g->nx, io);
   auto it = ctx->tr_choice.find(key);
   if (ctx->force_col >= 0) {
@@ -832,28 +832,38 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    // the GPU may have idled before this call: a short untimed burst first, then two rounds
-    // over the candidates keeping each one's faster round
-    for (int r = 0; r < 40; ++r) HIP_TRY(launch_transient_col(io, t, s, 0));
+    // Candidates are timed inside whole steps (column pass + row pass, as the solve runs them):
+    // first the row candidates with column candidate 0, then the column candidates with the
+    // chosen row candidate; each over 10 steps, two rounds, the faster round kept.  A short
+    // untimed burst first brings an idle GPU up to speed.
+    auto steps = [&](int r, int c, int count) -> hipError_t {
+      for (int q = 0; q < count; ++q) {
+        hipError_t e = launch_transient_col(io, t, s, c);
+        if (e == hipSuccess) e = launch_transient_row(TR_MERGED, io, t, 1, s, r);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    auto time_steps = [&](int r, int c, float* out) -> hipError_t {
+      hipError_t e = steps(r, c, 1);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      if (e == hipSuccess) e = steps(r, c, 10);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float el = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
+      *out = std::min(*out, el / 10.f);
+      return e;
+    };
+    HIP_TRY(steps(0, 0, 40));
     std::vector<float> ms(2 * nv, 1e30f);
     for (int round = 0; round < 2; ++round)
-      for (int k = 0; k < 2 * nv; ++k) {
-        const int v = k % nv;
-        auto run = [&] {
-          return k < nv ? launch_transient_row(TR_MERGED, io, t, 1, s, v) : launch_transient_col(io, t, s, v);
-        };
-        HIP_TRY(run());
-        HIP_TRY(hipEventRecord(e0, s));
-        for (int r = 0; r < 5; ++r) HIP_TRY(run());
-        HIP_TRY(hipEventRecord(e1, s));
-        HIP_TRY(hipEventSynchronize(e1));
-        float el = 0.f;
-        HIP_TRY(hipEventElapsedTime(&el, e0, e1));
-        ms[k] = std::min(ms[k], el / 5.f);
-      }
+      for (int v = 0; v < nv; ++v) HIP_TRY(time_steps(v, 0, &ms[v]));
+    rv = (int)(std::min_element(ms.begin(), ms.begin() + nv) - ms.begin());
+    for (int round = 0; round < 2; ++round)
+      for (int v = 0; v < nv; ++v) HIP_TRY(time_steps(rv, v, &ms[nv + v]));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    rv = (int)(std::min_element(ms.begin(), ms.begin() + nv) - ms.begin());
     cv = (int)(std::min_element(ms.begin() + nv, ms.end()) - (ms.begin() + nv));
     ctx->tr_choice[key] = {rv, cv};
     ctx->tr_ms[key] = ms;
@@ -930,14 +940,14 @@ varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
   for (const auto& kv : ctx->tr_choice) {
     const auto& ms = ctx->tr_ms[kv.first];
     const int nv = (int)ms.size() / 2;
-    snprintf(line, sizeof line, "transient n=%d %s ms per pass: row", kv.first.first,
+    snprintf(line, sizeof line, "transient n=%d %s ms per step: row candidates", kv.first.first,
              kv.first.second == VARSIM_F32 ? "f32" : "f64");
     out += line;
     for (int v = 0; v < nv; ++v) {
       snprintf(line, sizeof line, " %.4f%s", ms[v], v == kv.second.first ? "*" : "");
       out += line;
     }
-    out += "; col";
+    out += "; column candidates";
     for (int v = 0; v < nv; ++v) {
       snprintf(line, sizeof line, " %.4f%s", ms[nv + v], v == kv.second.second ? "*" : "");
       out += line;

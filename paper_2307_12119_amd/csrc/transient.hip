@@ -18,6 +18,7 @@
 #include "fft.hpp"
 #include "internal.hpp"
 #include "passes.hpp"
+#include "trpoint.hpp"
 
 namespace vs {
 
@@ -146,8 +147,11 @@ __global__ void __launch_bounds__((TrRowCfg<N, FFTS_>::THREADS))
         for (int m = 0; m < E; ++m) z[m] *= mv[m];
       }
 #pragma unroll
+      for (int m = 0; m < E; ++m) x[m] = z[m];
+      kirchhoff_inv_n<Tc, E>(x, pp);
+#pragma unroll
       for (int m = 0; m < E; ++m) {
-        x[m] = (Tc)(Tio)kirchhoff_inv<Tc>(z[m], pp);
+        x[m] = (Tc)(Tio)x[m];
         bad = bad || !(x[m] <= (Tc)pp.cap) || !(x[m] == x[m]);
       }
       if (snap)
@@ -164,12 +168,14 @@ __global__ void __launch_bounds__((TrRowCfg<N, FFTS_>::THREADS))
       const Tio* tr = (const Tio*)a.trace + (long)step * a.n_blocks;
       Tc q[E];
 #pragma unroll
-      for (int m = 0; m < E; ++m) q[m] = id[m] >= 0 ? (Tc)tr[id[m]] : (Tc)0;
+      for (int m = 0; m < E; ++m) {
+        const Tc v = (Tc)tr[id[m] < 0 ? 0 : id[m]];
+        q[m] = id[m] < 0 ? (Tc)0 : v;
+      }
       if (a.ql) {
         Tc ql[E];
         load_slots<Tio, Tc, N>((const Tio*)a.ql + off, ql, t, mirror);
-#pragma unroll
-        for (int m = 0; m < E; ++m) q[m] += ql[m] * leak_factor<Tc>(x[m], pp);
+        add_leakage_n<Tc, E>(q, ql, x, pp);
       }
 #pragma unroll
       for (int m = 0; m < E; ++m) z[m] = (Tc)pp.hxhy * q[m];

@@ -18,6 +18,7 @@
 #include "fft.hpp"
 #include "internal.hpp"
 #include "passes.hpp"
+#include "trpoint.hpp"
 #include "single.hpp"
 
 namespace vs {
@@ -33,50 +34,6 @@ __global__ void __launch_bounds__(256) zorder_kernel(const T* __restrict__ src, 
   const int j = i >> 1, k = i & 1;
   const int y = j < n / 4 ? 4 * j + 2 * k : 2 * n - 4 * j - 1 - 2 * k;
   dst[(long)row * n + i] = src[(long)row * n + y];
-}
-
-// theta -> dT (Kirchhoff inverse of k = k_ref (T / T_amb)^-eta) for K values in place; the same
-// arithmetic as kirchhoff_inv, with the mode tests taken once for all K values and the FP32
-// exp / log fallback entered only when some lane of the wavefront needs it.
-template <typename Tc, int K>
-__device__ __forceinline__ void kirchhoff_inv_n(Tc* v, const PointParams& pp) {
-  if (pp.eta_mode == 0) return;
-  if constexpr (sizeof(Tc) == 4) {
-    const float us = (float)pp.u_scale, umax = (float)pp.poly_umax, ta = (float)pp.t_amb;
-    float u[K];
-    bool far = false;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      u[k] = us * v[k];
-      far = far || !(fabsf(u[k]) <= umax);
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      float acc = pp.polyf[kPoly - 1];
-#pragma unroll
-      for (int c = kPoly - 2; c >= 0; --c) acc = fmaf(acc, u[k], pp.polyf[c]);
-      v[k] = ta * u[k] * acc;
-    }
-    if (__any(far)) {
-      if (pp.eta_mode == 1) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float fb = ta * (__expf(u[k]) - 1.f);
-          v[k] = fabsf(u[k]) <= umax ? v[k] : fb;
-        }
-      } else {
-        const float ie = (float)pp.inv_1m_eta;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float fb = u[k] > -1.f ? ta * (__expf(ie * __logf(1.f + u[k])) - 1.f) : NAN;
-          v[k] = fabsf(u[k]) <= umax ? v[k] : fb;
-        }
-      }
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = kirchhoff_inv<Tc>(v[k], pp);
-  }
 }
 
 template <int N, int W>
@@ -204,15 +161,7 @@ __global__ void __launch_bounds__((TrRow1Cfg<N, W>::THREADS))
 
   if constexpr (FWD) {
     // P_{n+1} = hx hy (q_dyn + QL L(dT_n)), then its row spectrum
-    if (has_ql) {
-      if (pp.leak == VARSIM_LEAK_EXP) {
-#pragma unroll
-        for (int k = 0; k < 2 * E; ++k) qd[k] += ql[k] * exp_leak((Tc)pp.beta * x[k]);
-      } else if (pp.leak == VARSIM_LEAK_LINEAR) {
-#pragma unroll
-        for (int k = 0; k < 2 * E; ++k) qd[k] += ql[k] * ((Tc)1 + (Tc)pp.beta * x[k]);
-      }
-    }
+    if (has_ql) add_leakage_n<Tc, 2 * E>(qd, ql, x, pp);
     const Tc hh = (Tc)pp.hxhy;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
