@@ -372,8 +372,8 @@ varsim_status varsim_create(int device, varsim_ctx** out) {
   if (hipSetDevice(device) != hipSuccess) return VARSIM_ERR_DEVICE;
   varsim_ctx* c = new varsim_ctx();
   c->device = device;
-  if (hipMalloc(&c->active_dev, 2 * sizeof(int)) != hipSuccess ||
-      hipHostMalloc(&c->active_host, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc(&c->active_host, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->active_map, c->active_host, 0) != hipSuccess ||
       hipEventCreateWithFlags(&c->active_ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->active_ev[1], hipEventDisableTiming) != hipSuccess) {
     delete c;
@@ -405,7 +405,6 @@ void varsim_destroy(varsim_ctx* c) {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
-  (void)hipFree(c->active_dev);
   (void)hipHostFree(c->active_host);
   for (hipEvent_t e : c->active_ev)
     if (e) (void)hipEventDestroy(e);
@@ -655,15 +654,13 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
                     [&] { return launch_row_pass(mode, io, io, a, s); }));
     }
     iters_run = k;
-    // Convergence is read one iteration late so that the device never idles: the count of
-    // maps still iterating after iteration k is copied to pinned memory behind iteration k,
-    // and the host waits for iteration k-1's count only after launching iteration k.
+    // Convergence is read one iteration late so that the device never idles: one small kernel
+    // behind iteration k writes the count of maps still iterating into pinned host memory, and
+    // the host waits for iteration k-1's count only after launching iteration k.
     // Launches past a map's convergence return at once (the map is marked finished).
     if (k >= 1) {
       const int slot = k & 1;
-      HIP_TRY(launch_zero_words(ctx->active_dev + slot, sizeof(int), s));
-      HIP_TRY(launch_count_active(base, n, k, opts->tol_K, ctx->active_dev + slot, s));
-      HIP_TRY(hipMemcpyAsync(ctx->active_host + slot, ctx->active_dev + slot, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(launch_count_active(base, n, k, opts->tol_K, ctx->active_map + slot, s));
       HIP_TRY(hipEventRecord(ctx->active_ev[slot], s));
     }
     if (k >= 2) {

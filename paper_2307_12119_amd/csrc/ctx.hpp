@@ -55,8 +55,8 @@ struct varsim_ctx {
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<long long, double>> times;
   std::vector<const char*> class_names;
-  int* active_dev = nullptr;   // [2] device counters of maps still iterating
-  int* active_host = nullptr;  // [2] pinned host copies
+  int* active_host = nullptr;  // [2] pinned host words: counts of maps still iterating
+  int* active_map = nullptr;   // the same words as the device addresses them
   hipEvent_t active_ev[2] = {nullptr, nullptr};
   // host staging of per-call descriptor arrays (kept alive until the call returns)
   std::vector<MapPtrs> h_maps;

@@ -78,6 +78,7 @@ hipError_t launch_init_copy(int io, const PrepArgs* args, int n_maps, long count
 hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t stream);
 
 // Convergence count: number of maps not yet finished after iteration `iter`.
+// out: one int the kernel overwrites with the count (device or mapped pinned host memory)
 hipError_t launch_count_active(const IterState& st, int n_maps, int iter, double tol, int* out, hipStream_t stream);
 
 // The whole fixed point of every map of a group by one LDS-resident workgroup per map

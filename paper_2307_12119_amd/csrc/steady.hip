@@ -187,12 +187,26 @@ __global__ void zero_words_kernel(unsigned* p, size_t words) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
 
-__global__ void count_active_kernel(IterState st, int n_maps, int iter, double tol, int* out) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n_maps) return;
-  if (st.flags[m] & (kFlagSkip | kFlagOwnLoop)) return;
-  const double r = __longlong_as_double((long long)st.resid[(long)m * st.stride + iter]);
-  if (!(r <= tol)) atomicAdd(out, 1);
+// Number of maps still iterating after iteration `iter`, stored to *out by one workgroup (out
+// may be pinned host memory: the host reads it once an event behind this kernel has completed).
+__global__ void __launch_bounds__(1024) count_active_kernel(IterState st, int n_maps, int iter, double tol, int* out) {
+  __shared__ int s_cnt[16];
+  int c = 0;
+  for (int m = threadIdx.x; m < n_maps; m += blockDim.x) {
+    if (st.flags[m] & (kFlagSkip | kFlagOwnLoop)) continue;
+    const double r = __longlong_as_double((long long)st.resid[(long)m * st.stride + iter]);
+    if (!(r <= tol)) ++c;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int total = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += s_cnt[w];
+    *out = total;
+    __threadfence_system();
+  }
 }
 
 template <typename Tio>
@@ -321,7 +335,7 @@ hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t stream) {
 }
 
 hipError_t launch_count_active(const IterState& st, int n_maps, int iter, double tol, int* out, hipStream_t stream) {
-  hipLaunchKernelGGL(count_active_kernel, dim3((n_maps + 255) / 256), dim3(256), 0, stream, st, n_maps, iter, tol, out);
+  hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(1024), 0, stream, st, n_maps, iter, tol, out);
   return hipGetLastError();
 }
 
