@@ -28,6 +28,78 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((unsi
 __device__ __forceinline__ unsigned pack2(float a, float b) { return (unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16); }
 
 // ------------------------------------------------------------------------------ convolution
+// Bias, ReLU and the store of a wavefront's MW x NW accumulator tiles: tile (i, j) holds output
+// channels co0 + 16 i + 4 lg + r (r = 0..3) of pixel (pb[j], py[j], px[j]) in lane (lr, lg).
+template <int MW, int NW, int EPI, bool RELU>
+__device__ __forceinline__ void conv_epilogue(const NnConv& a, const f32x4 (&acc)[MW][NW], const int (&pb)[NW],
+                                              const int (&py)[NW], const int (&px)[NW], const bool (&pv)[NW], int lr,
+                                              int lg, int co0) {
+  if constexpr (EPI == NN_EPI_HEAD) {
+    // this layer's 32 channels -> BF16 -> B operand of the 16-output layer.  Lane (lr, lg) holds
+    // channels 4 lg + r (tile 0) and 16 + 4 lg + r (tile 1) of pixel lr: that is its K group, and
+    // the head's A operand is loaded in the same channel order.
+    static_assert(MW == 2, "head epilogue needs the 32 channels in two tiles");
+    float b1[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      b1[r] = a.bias[4 * lg + r];
+      b1[4 + r] = a.bias[16 + 4 * lg + r];
+    }
+    const uint2 wl = *reinterpret_cast<const uint2*>(a.w2 + lr * 32 + 4 * lg);
+    const uint2 wh = *reinterpret_cast<const uint2*>(a.w2 + lr * 32 + 16 + 4 * lg);
+    const bf16x8 hw = as_bf(make_uint4(wl.x, wl.y, wh.x, wh.y));
+    float hb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hb[r] = a.bias2[4 * lg + r];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      float v[8];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = fmaxf(acc[0][j][r] + b1[r], 0.f);
+        v[4 + r] = fmaxf(acc[1][j][r] + b1[4 + r], 0.f);
+      }
+      const uint4 d = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7]));
+      f32x4 h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hw, as_bf(d), f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      if (!pv[j]) continue;
+      float* out = (float*)a.y + ((long)pb[j] * (4 * a.H) + 4 * py[j] + lg) * (4L * a.W) + 4 * px[j];
+      const float sc = a.out_scale;
+      *reinterpret_cast<float4*>(out) =
+          make_float4(sc * (h[0] + hb[0]), sc * (h[1] + hb[1]), sc * (h[2] + hb[2]), sc * (h[3] + hb[3]));
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < MW; ++i) {
+    const int co = co0 + i * 16 + 4 * lg;
+    float bias[4] = {0.f, 0.f, 0.f, 0.f};
+    if (a.bias)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bias[r] = a.bias[co + r];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      if (!pv[j]) continue;
+      const long p = ((long)pb[j] * a.H + py[j]) * a.W + px[j];
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = acc[i][j][r] + bias[r];
+        if (RELU) v[r] = fmaxf(v[r], 0.f);
+      }
+      if constexpr (EPI == NN_EPI_BF16) {
+        *reinterpret_cast<uint2*>((uint16_t*)a.y + p * a.cout + co) = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+      } else if constexpr (EPI == NN_EPI_F32) {
+        *reinterpret_cast<float4*>((float*)a.y + p * a.cout + co) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        // cout = 16: output channel co + r = 4 lg + r is sub-pixel (lg, r) of the 4x4 patch
+        float* out = (float*)a.y + ((long)pb[j] * (4 * a.H) + 4 * py[j] + lg) * (4L * a.W) + 4 * px[j];
+        const float s = a.out_scale;
+        *reinterpret_cast<float4*>(out) = make_float4(s * v[0], s * v[1], s * v[2], s * v[3]);
+      }
+    }
+  }
+}
+
 template <int KS, int MW, int NW, int EPI, bool RELU>
 __global__ void __launch_bounds__(256) conv_kernel(NnConv a) {
   constexpr int TAPS = KS * KS, R = KS / 2;
@@ -85,70 +157,121 @@ __global__ void __launch_bounds__(256) conv_kernel(NnConv a) {
     }
   }
 
-  if constexpr (EPI == NN_EPI_HEAD) {
-    // this layer's 32 channels -> BF16 -> B operand of the 16-output layer.  Lane (lr, lg) holds
-    // channels 4 lg + r (tile 0) and 16 + 4 lg + r (tile 1) of pixel lr: that is its K group, and
-    // the head's A operand is loaded in the same channel order.
-    static_assert(MW == 2, "head epilogue needs the 32 channels in two tiles");
-    float b1[8];
+  conv_epilogue<MW, NW, EPI, RELU>(a, acc, pb, py, px, pv, lr, lg, co0);
+}
+
+// 3x3 convolution of wide maps with the input staged in LDS.  A workgroup computes 4 rows x 64
+// columns of one image (wavefront w: row w, 4 x 16 consecutive pixels).  The input channels are
+// taken in phases of at most 64 channels of one source (the upsampled coarser level or the skip
+// input, as in conv_kernel); per phase the workgroup copies the 6 x 66 input pixels around its
+// tile -- zero outside the image and beyond the phase's channels up to the next multiple of 32 --
+// into LDS with a pixel pitch of that multiple + 8 elements (an odd multiple of 16 bytes, so 8
+// lanes reading 16 bytes at consecutive pixels use distinct banks), then runs the phase's part
+// of the K loop reading B from LDS.  Each input pixel leaves L2 once per tile instead of once per
+// tap and output pixel.  Requires H % 4 == 0 and W % 64 == 0.
+constexpr int kLdsRows = 4, kLdsCols = 64, kLdsPhase = 64;
+__host__ __device__ constexpr int conv_lds_pitch(int channels) { return ((channels + 31) & ~31) + 8; }
+inline long conv_lds_bytes(int cu, int cx) {
+  const int widest = cu > cx ? cu : cx;
+  return (long)(kLdsRows + 2) * (kLdsCols + 2) * conv_lds_pitch(widest < kLdsPhase ? widest : kLdsPhase) * 2;
+}
+
+template <int MW, int EPI, bool RELU>
+__global__ void __launch_bounds__(256) conv3_lds_kernel(NnConv a) {
+  constexpr int TR = kLdsRows, NW = kLdsRows, TW = kLdsCols + 2;
+  extern __shared__ __attribute__((aligned(16))) uint16_t tile[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int H = a.H, W = a.W, cu = a.cu, cx = a.cx, cin = cu + cx;
+  const int tiles_x = W / kLdsCols, tiles_y = H / TR;
+  const int tb = blockIdx.x / (tiles_x * tiles_y);
+  const int trem = blockIdx.x - tb * tiles_x * tiles_y;
+  const int y0 = (trem / tiles_x) * TR, x0 = (trem % tiles_x) * kLdsCols;
+  const int co0 = blockIdx.y * (16 * MW);
+
+  int pb[NW], py[NW], px[NW];
+  bool pv[NW];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      b1[r] = a.bias[4 * lg + r];
-      b1[4 + r] = a.bias[16 + 4 * lg + r];
-    }
-    const uint2 wl = *reinterpret_cast<const uint2*>(a.w2 + lr * 32 + 4 * lg);
-    const uint2 wh = *reinterpret_cast<const uint2*>(a.w2 + lr * 32 + 16 + 4 * lg);
-    const bf16x8 hw = as_bf(make_uint4(wl.x, wl.y, wh.x, wh.y));
-    float hb[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) hb[r] = a.bias2[4 * lg + r];
-#pragma unroll
-    for (int j = 0; j < NW; ++j) {
-      float v[8];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        v[r] = fmaxf(acc[0][j][r] + b1[r], 0.f);
-        v[4 + r] = fmaxf(acc[1][j][r] + b1[4 + r], 0.f);
-      }
-      const uint4 d = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7]));
-      f32x4 h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hw, as_bf(d), f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      if (!pv[j]) continue;
-      float* out = (float*)a.y + ((long)pb[j] * (4 * H) + 4 * py[j] + lg) * (4L * W) + 4 * px[j];
-      const float sc = a.out_scale;
-      *reinterpret_cast<float4*>(out) =
-          make_float4(sc * (h[0] + hb[0]), sc * (h[1] + hb[1]), sc * (h[2] + hb[2]), sc * (h[3] + hb[3]));
-    }
-    return;
+  for (int j = 0; j < NW; ++j) {
+    pb[j] = tb;
+    py[j] = y0 + wave;
+    px[j] = x0 + 16 * j + lr;
+    pv[j] = true;
   }
+  f32x4 acc[MW][NW];
 #pragma unroll
-  for (int i = 0; i < MW; ++i) {
-    const int co = co0 + i * 16 + 4 * lg;
-    float bias[4] = {0.f, 0.f, 0.f, 0.f};
-    if (a.bias)
+  for (int i = 0; i < MW; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) bias[r] = a.bias[co + r];
+    for (int j = 0; j < NW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+
+  for (int cs = 0; cs < cin;) {
+    const int send = cs < cu ? cu : cin;
+    const int len = send - cs < kLdsPhase ? send - cs : kLdsPhase;
+    const int pitch = conv_lds_pitch(len);
+    // stage the phase's halo, (pitch - 8) / 8 chunks of 8 channels per pixel; each thread issues
+    // a batch of SB loads before storing them, so their latencies overlap
+    constexpr int SB = 4;
+    const int chunks = (pitch - 8) >> 3;
+    const int total = (TR + 2) * TW * chunks;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * SB) {
+      uint4 v[SB];
 #pragma unroll
-    for (int j = 0; j < NW; ++j) {
-      if (!pv[j]) continue;
-      const long p = p0 + j * 16 + lr;
-      float v[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        v[r] = acc[i][j][r] + bias[r];
-        if (RELU) v[r] = fmaxf(v[r], 0.f);
+      for (int u = 0; u < SB; ++u) {
+        const int e = e0 + 256 * u;
+        const int k = e % chunks, pix = e / chunks;
+        const int r = pix / TW, c = pix - r * TW;
+        const int yy = y0 - 1 + r, xx = x0 - 1 + c, ch = cs + 8 * k;
+        v[u] = z4;
+        if (e < total && 8 * k < len && yy >= 0 && yy < H && xx >= 0 && xx < W)
+          v[u] = ch < cu ? ld16(a.xu + (((long)tb * (H >> 1) + (yy >> 1)) * (W >> 1) + (xx >> 1)) * cu + ch)
+                         : ld16(a.x + (((long)tb * H + yy) * W + xx) * cx + (ch - cu));
       }
-      if constexpr (EPI == NN_EPI_BF16) {
-        *reinterpret_cast<uint2*>((uint16_t*)a.y + p * a.cout + co) = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
-      } else if constexpr (EPI == NN_EPI_F32) {
-        *reinterpret_cast<float4*>((float*)a.y + p * a.cout + co) = make_float4(v[0], v[1], v[2], v[3]);
-      } else {
-        // cout = 16: output channel co + r = 4 lg + r is sub-pixel (lg, r) of the 4x4 patch
-        float* out = (float*)a.y + ((long)pb[j] * (4 * H) + 4 * py[j] + lg) * (4L * W) + 4 * px[j];
-        const float s = a.out_scale;
-        *reinterpret_cast<float4*>(out) = make_float4(s * v[0], s * v[1], s * v[2], s * v[3]);
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < total) *reinterpret_cast<uint4*>(tile + (e / chunks) * pitch + 8 * (e % chunks)) = v[u];
       }
     }
+    __syncthreads();
+
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const uint16_t* brow = tile + ((wave + 1 + dy) * TW + 1 + dx) * pitch;
+      for (int c0 = 0; c0 < len; c0 += 32) {
+        const int cl = c0 + 8 * lg;  // channel within the phase
+        const bool kv = cl < len;
+        uint4 av[MW], bv[NW];
+#pragma unroll
+        for (int i = 0; i < MW; ++i) {
+          const int co = co0 + i * 16 + lr;
+          av[i] = kv ? ld16(a.w + ((long)co * 9 + tap) * cin + cs + cl) : z4;
+        }
+#pragma unroll
+        for (int j = 0; j < NW; ++j)  // zero past the phase's channels
+          bv[j] = *reinterpret_cast<const uint4*>(brow + (16 * j + lr) * pitch + cl);
+#pragma unroll
+        for (int i = 0; i < MW; ++i)
+#pragma unroll
+          for (int j = 0; j < NW; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av[i]), as_bf(bv[j]), acc[i][j], 0, 0, 0);
+      }
+    }
+    cs += len;
+    if (cs < cin) __syncthreads();  // the next phase overwrites the tile
   }
+  conv_epilogue<MW, NW, EPI, RELU>(a, acc, pb, py, px, pv, lr, lg, co0);
+}
+
+inline bool conv_lds_ok(const NnConv& a) {
+  return a.W % kLdsCols == 0 && a.H % kLdsRows == 0 && conv_lds_bytes(a.cu, a.cx) <= 65536;
+}
+
+template <int MW, int EPI, bool RELU>
+hipError_t conv_lds(const NnConv& a, hipStream_t s) {
+  const dim3 grid((unsigned)((long)a.B * (a.H / kLdsRows) * (a.W / kLdsCols)), a.cout / (16 * MW));
+  hipLaunchKernelGGL((conv3_lds_kernel<MW, EPI, RELU>), grid, dim3(256), (size_t)conv_lds_bytes(a.cu, a.cx), s, a);
+  return hipGetLastError();
 }
 
 template <int KS, int MW, int NW, int EPI, bool RELU>
@@ -161,6 +284,14 @@ hipError_t conv_launch(const NnConv& a, hipStream_t s) {
 
 template <int KS, int EPI, bool RELU>
 hipError_t conv_tile(const NnConv& a, hipStream_t s) {
+  if constexpr (KS == 3) {
+    if (conv_lds_ok(a)) {
+      if (a.cout % 64 == 0) return conv_lds<4, EPI, RELU>(a, s);
+      if (a.cout % 48 == 0) return conv_lds<3, EPI, RELU>(a, s);
+      if (a.cout % 32 == 0) return conv_lds<2, EPI, RELU>(a, s);
+      return conv_lds<1, EPI, RELU>(a, s);
+    }
+  }
   if (a.cout % 64 == 0) return conv_launch<KS, 4, 2, EPI, RELU>(a, s);
   if (a.cout % 48 == 0) return conv_launch<KS, 3, 2, EPI, RELU>(a, s);
   if (a.cout % 32 == 0) return conv_launch<KS, 2, 4, EPI, RELU>(a, s);
@@ -174,9 +305,11 @@ hipError_t conv_ks(int epi, bool relu, const NnConv& a, hipStream_t s) {
     case NN_EPI_F32: return conv_tile<KS, NN_EPI_F32, false>(a, s);
     case NN_EPI_SHUFFLE:
       if (a.cout != 16) return hipErrorInvalidValue;
+      if (KS == 3 && conv_lds_ok(a)) return conv_lds<1, NN_EPI_SHUFFLE, false>(a, s);
       return conv_launch<KS, 1, 8, NN_EPI_SHUFFLE, false>(a, s);
     case NN_EPI_HEAD:
       if (a.cout != 32 || !a.w2 || !a.bias2) return hipErrorInvalidValue;
+      if (KS == 3 && conv_lds_ok(a)) return conv_lds<2, NN_EPI_HEAD, true>(a, s);
       return conv_launch<KS, 2, 4, NN_EPI_HEAD, true>(a, s);
     default: return hipErrorInvalidValue;
   }

@@ -44,6 +44,14 @@ def _conv1x1(x, w, b=None):
 
 
 CONV_CASES = [  # k, batch, h, w, cin, cout
+    # W % 64 == 0 and H % 4 == 0 take the LDS-staged 3x3 path (input channels staged in phases of
+    # at most 64: cin 80 and 112 take two; cin 16 pads the K chunk with staged zeros)
+    (3, 2, 8, 64, 32, 32),
+    (3, 1, 4, 128, 48, 48),
+    (3, 2, 8, 64, 80, 64),
+    (3, 1, 4, 64, 112, 48),
+    (3, 1, 4, 64, 16, 16),
+    (3, 2, 6, 64, 32, 32),
     (3, 2, 12, 12, 32, 32),
     (3, 1, 8, 8, 48, 48),
     (3, 2, 16, 16, 64, 96),
@@ -130,12 +138,15 @@ def _bf16_weights(spec, p):
     return {k: (_bf16(v) if k.endswith(".w") else v) for k, v in p.items()}
 
 
-def test_net_forward_matches_oracle(ctx):
+@pytest.mark.parametrize("n", [64, 256])
+def test_net_forward_matches_oracle(ctx, n):
+    """n = 256 puts level 0 (64 x 64) on the LDS-staged convolutions, the decoder's fused
+    upsample + concatenation gather and the fused head included."""
     import torch
 
-    net, spec, p = _net(ctx, {"n": 64})
-    q, v, m, _ = _inputs(64, 3)
-    out = torch.empty((3, 64, 64), dtype=torch.float32, device="cuda")
+    net, spec, p = _net(ctx, {"n": n})
+    q, v, m, _ = _inputs(n, 3)
+    out = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
     net.forward(*(torch.from_numpy(a).cuda() for a in (q, v, m)), out)
     got = out.cpu().numpy().astype(np.float64)
     ref, _ = NN.forward(spec, _bf16_weights(spec, p), q.astype(np.float64), v.astype(np.float64),
@@ -144,11 +155,12 @@ def test_net_forward_matches_oracle(ctx):
     assert np.corrcoef(got.ravel(), ref.ravel())[0, 1] > 0.999
 
 
-def test_net_gradient_matches_oracle(ctx):
+@pytest.mark.parametrize("n", [64, 256])
+def test_net_gradient_matches_oracle(ctx, n):
     import torch
 
-    net, spec, p = _net(ctx, {"n": 64}, seed=1)
-    q, v, m, t = _inputs(64, 2, seed=1)
+    net, spec, p = _net(ctx, {"n": n}, seed=1)
+    q, v, m, t = _inputs(n, 2, seed=1)
     grad = torch.empty(net.param_count, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     dq, dv, dm, dt = (torch.from_numpy(a).cuda() for a in (q, v, m, t))
