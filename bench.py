@@ -457,6 +457,7 @@ def surrogate_bench(ctx, items, qd, lv, cm, out_plain, opts, ws, args, plain_map
     achieved = flops / (conv_ms * 1e-3) / 1e12 if conv_ms else None
     maps_per_s = args.batch * args.steps / elapsed
     pred_err = (init - out_plain).abs()
+    training = surrogate_training(ctx, spec, qd, lv, cm, out_plain, args)
     return ({"value": round(maps_per_s, 2), "unit": "maps/s", "speedup_vs_plain": round(maps_per_s / plain_maps_per_s, 4),
              "ms_per_step": round(elapsed / args.steps * 1e3, 4), "iterations_mean": float(np.mean(iters)),
              "plain_iterations_mean": plain_iters, "statuses": sorted({int(x) for x in stats["status"]}),
@@ -467,7 +468,64 @@ def surrogate_bench(ctx, items, qd, lv, cm, out_plain, opts, ws, args, plain_map
                           round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                           "frac": None if achieved is None else round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
                           "flops_per_launch_batch": flops, "conv_ms_per_batch": conv_ms},
-             "weights": os.path.relpath(SURROGATE_WEIGHTS, ROOT)}, out_w)
+             "weights": os.path.relpath(SURROGATE_WEIGHTS, ROOT), "training": training}, out_w)
+
+
+def surrogate_training(ctx, spec, qd, lv, cm, target, args, batch: int = 64, steps: int = 10) -> dict:
+    """Training steps of the network (forward, MSE gradient through every layer, Adam) on batches
+    of 64 of this batch's maps against the plain solve's converged rises, from a fresh He
+    initialisation (the trained weights are not touched).  MFMA figure: dense convolution flops
+    of forward + input gradient + weight gradient over the summed time of those kernels."""
+    import numpy as np
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    dev = qd.device
+    net = V.Net(ctx, spec)
+    net.set_params(torch.from_numpy(spec.he_init(0)).to(dev))
+    grad = torch.empty(net.param_count, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    wst = torch.empty(net.workspace_bytes(batch, True), dtype=torch.uint8, device=dev)
+    n_maps = qd.shape[0]
+    idx = [torch.arange(k * batch, (k + 1) * batch, dtype=torch.int32, device=dev) % n_maps for k in range(steps)]
+
+    def step(k):
+        net.gradient(qd, lv, cm, target, grad, loss, batch, sample_idx=idx[k % steps], workspace=wst)
+        net.adam(grad, 1e-3)
+
+    for k in range(2):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    ctx.set_timing(False)
+    kt = ctx.kernel_times()
+    conv_ms = sum(v["total_ms"] for k, v in kt.items()
+                  if k.startswith("fwd:conv:") or k in ("nn_conv_dgrad", "nn_wgrad")) / steps
+    # forward, input gradient (every layer but the stem, whose inputs are features) and weight
+    # gradient
+    m = spec.n // 4
+    flops = (3.0 * conv_flops_per_map(spec) - 2.0 * 48 * spec.width[0] * m * m) * batch
+    achieved = flops / (conv_ms * 1e-3) / 1e12 if conv_ms else None
+    classes = {}
+    for k, v in kt.items():
+        c = "fwd:conv" if k.startswith("fwd:conv:") else ("fwd:elem" if k.startswith("fwd:") else k)
+        classes[c] = round(classes.get(c, 0.0) + v["total_ms"] / steps, 4)
+    return {"batch": batch, "ms_per_step": round(wall * 1e3, 4), "samples_per_s": round(batch / wall, 1),
+            "last_loss_K2": float(loss.item()), "conv_ms_per_step": round(conv_ms, 4), "class_ms_per_step": classes,
+            "roofline": {"bound": "mfma", "kernel": "conv_kernel / wgrad_kernel (forward, input and weight gradients)",
+                         "achieved": None if achieved is None else round(achieved, 1),
+                         "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": None if achieved is None else round(achieved / MFMA_BF16_PEAK_TFLOPS, 4)}}
 
 
 TRANSIENT_BYTES_PER_CELL = {"tr_row": 20, "tr_col": 24}  # FP32: see transient_bench

@@ -387,68 +387,102 @@ __global__ void __launch_bounds__(256) wgrad_kernel(NnConv a, const uint16_t* __
       }
 }
 
+// 64 outputs per workgroup, four threads per output (chunks g, g + 4, ...), added in a fixed order
 __global__ void __launch_bounds__(256) reduce_parts_kernel(const float* __restrict__ part, int ns, int cout, int taps,
                                                            int cin_src, int cin_dst, float* __restrict__ out) {
+  __shared__ float s[4][64];
   const long n = (long)cout * taps * cin_dst, len = (long)cout * taps * cin_src;
-  for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const long j = (long)blockIdx.x * 64 + o;
+  float acc = 0.f;
+  if (j < n) {
     const long rt = j / cin_dst;
     const long src = rt * cin_src + (j - rt * cin_dst);
-    float s = 0.f;
-    for (int k = 0; k < ns; ++k) s += part[k * len + src];
-    out[j] = s;
+    float a4[4] = {0.f, 0.f, 0.f, 0.f};
+    int k = g;
+    for (; k + 12 < ns; k += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] += part[(long)(k + 4 * u) * len + src];
+    }
+    for (; k < ns; k += 4) a4[0] += part[(long)k * len + src];
+    acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   }
+  s[g][o] = acc;
+  __syncthreads();
+  if (g == 0 && j < n) out[j] = (s[0][o] + s[1][o]) + (s[2][o] + s[3][o]);
 }
 
 // ------------------------------------------------------------------------------ elementwise
+// Thread t owns channel group cg = t % G (8 channels, G = C / 8) of pixels slot, slot + T, ...
+// (T = 256 / G threads per group); its channel sums stay in registers and the workgroup adds the
+// T partials of each channel in a fixed order: no atomics, the same bits on every run.
 __global__ void __launch_bounds__(256) relu_bwd_kernel(const float* __restrict__ da, const float* __restrict__ dpool,
                                                        const uint16_t* __restrict__ act, uint16_t* __restrict__ dz,
                                                        int B, int H, int W, int C, float* __restrict__ part) {
-  __shared__ float s[256];
-  for (int i = threadIdx.x; i < C; i += 256) s[i] = 0.f;
-  __syncthreads();
-  const long n = (long)B * H * W * C;
-  for (long e = ((long)blockIdx.x * 256 + threadIdx.x) * 8; e < n; e += (long)gridDim.x * 256 * 8) {
-    const long p = e / C;
-    const int c = (int)(e - p * C);
-    float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (da) {
-      const float4 lo = *reinterpret_cast<const float4*>(da + e), hi = *reinterpret_cast<const float4*>(da + e + 4);
-      g[0] = lo.x, g[1] = lo.y, g[2] = lo.z, g[3] = lo.w, g[4] = hi.x, g[5] = hi.y, g[6] = hi.z, g[7] = hi.w;
-    }
-    if (dpool) {
-      const long HW = (long)H * W;
-      const int b = (int)(p / HW);
-      const int rem = (int)(p - (long)b * HW);
-      const int y = rem / W, x = rem % W;
-      const float* d = dpool + (((long)b * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1)) * C + c;
-      const float4 lo = *reinterpret_cast<const float4*>(d), hi = *reinterpret_cast<const float4*>(d + 4);
-      g[0] += 0.25f * lo.x, g[1] += 0.25f * lo.y, g[2] += 0.25f * lo.z, g[3] += 0.25f * lo.w;
-      g[4] += 0.25f * hi.x, g[5] += 0.25f * hi.y, g[6] += 0.25f * hi.z, g[7] += 0.25f * hi.w;
-    }
-    if (act) {
-      const uint4 u = ld16(act + e);
-      const uint16_t* h = reinterpret_cast<const uint16_t*>(&u);
+  __shared__ float s[256 * 8];
+  const int G = C >> 3, T = 256 / G;
+  const int cg = threadIdx.x % G, slot = threadIdx.x / G;
+  const int c = 8 * cg;
+  const long P = (long)B * H * W, HW = (long)H * W;
+  float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (slot < T) {
+    for (long p = (long)blockIdx.x * T + slot; p < P; p += (long)gridDim.x * T) {
+      const long e = p * C + c;
+      float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (da) {
+        const float4 lo = *reinterpret_cast<const float4*>(da + e), hi = *reinterpret_cast<const float4*>(da + e + 4);
+        g[0] = lo.x, g[1] = lo.y, g[2] = lo.z, g[3] = lo.w, g[4] = hi.x, g[5] = hi.y, g[6] = hi.z, g[7] = hi.w;
+      }
+      if (dpool) {
+        const int b = (int)(p / HW);
+        const int rem = (int)(p - (long)b * HW);
+        const int y = rem / W, x = rem % W;
+        const float* d = dpool + (((long)b * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1)) * C + c;
+        const float4 lo = *reinterpret_cast<const float4*>(d), hi = *reinterpret_cast<const float4*>(d + 4);
+        g[0] += 0.25f * lo.x, g[1] += 0.25f * lo.y, g[2] += 0.25f * lo.z, g[3] += 0.25f * lo.w;
+        g[4] += 0.25f * hi.x, g[5] += 0.25f * hi.y, g[6] += 0.25f * hi.z, g[7] += 0.25f * hi.w;
+      }
+      if (act) {
+        const uint4 u = ld16(act + e);
+        const uint16_t* h = reinterpret_cast<const uint16_t*>(&u);
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (!(bf2f(h[k]) > 0.f)) g[k] = 0.f;
-    }
+        for (int k = 0; k < 8; ++k) g[k] = bf2f(h[k]) > 0.f ? g[k] : 0.f;
+      }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) atomicAdd(&s[c + k], g[k]);
-    if (dz)
-      *reinterpret_cast<uint4*>(dz + e) = make_uint4(pack2(g[0], g[1]), pack2(g[2], g[3]), pack2(g[4], g[5]),
-                                                     pack2(g[6], g[7]));
+      for (int k = 0; k < 8; ++k) sum[k] += g[k];
+      if (dz)
+        *reinterpret_cast<uint4*>(dz + e) = make_uint4(pack2(g[0], g[1]), pack2(g[2], g[3]), pack2(g[4], g[5]),
+                                                       pack2(g[6], g[7]));
+    }
+  }
+  // s[slot][c + k]: the T partials of every channel
+  if (slot < T) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[slot * C + c + k] = sum[k];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < C; i += 256) part[(long)blockIdx.x * C + i] = s[i];
+  for (int ch = threadIdx.x; ch < C; ch += 256) {
+    float acc = 0.f;
+    for (int q = 0; q < T; ++q) acc += s[q * C + ch];
+    part[(long)blockIdx.x * C + ch] = acc;
+  }
 }
 
-__global__ void colsum_kernel(const float* __restrict__ part, int nb, int stride, int C, float scale,
-                              float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  float s = 0.f;
-  for (int b = 0; b < nb; ++b) s += part[(long)b * stride + c];
-  out[c] = scale * s;
+// one workgroup per column c: thread t adds rows t, t + 256, ...; then a fixed-order tree
+__global__ void __launch_bounds__(256) colsum_kernel(const float* __restrict__ part, int nb, int stride, int C,
+                                                     float scale, float* __restrict__ out) {
+  __shared__ float s[256];
+  const int c = blockIdx.x;
+  float acc = 0.f;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[(long)b * stride + c];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+#pragma unroll
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = scale * s[0];
 }
 
 // y = 2x2 mean of x; one thread per (coarse pixel, 8 channels)
@@ -696,8 +730,8 @@ hipError_t nn_wgrad(int ks, const NnConv& a, const uint16_t* dz, float* part, in
 hipError_t nn_reduce_parts(const float* part, int n_split, int cout, int taps, int cin_src, int cin_dst, float* out,
                            hipStream_t s) {
   const long n = (long)cout * taps * cin_dst;
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(n)), dim3(256), 0, s, part, n_split, cout, taps, cin_src,
-                     cin_dst, out);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, part, n_split, cout, taps,
+                     cin_src, cin_dst, out);
   return hipGetLastError();
 }
 
@@ -709,7 +743,7 @@ hipError_t nn_relu_bwd(const float* da, const float* dpool, const uint16_t* act,
 }
 
 hipError_t nn_colsum(const float* part, int nb, int stride, int C, float scale, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3((C + 63) / 64), dim3(64), 0, s, part, nb, stride, C, scale, out);
+  hipLaunchKernelGGL(colsum_kernel, dim3(C), dim3(256), 0, s, part, nb, stride, C, scale, out);
   return hipGetLastError();
 }
 
