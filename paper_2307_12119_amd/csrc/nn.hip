@@ -316,8 +316,30 @@ hipError_t conv_ks(int epi, bool relu, const NnConv& a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------------ weight gradient
-constexpr int kWgPitch = 40;  // LDS row pitch (elements): 32 pixels + pad, rows 16-byte aligned
+// Pixels per staging step and LDS row pitch (elements): rows 272 bytes apart, so the 16-byte
+// operand reads of 8 consecutive rows fall on distinct banks.
+constexpr int kWgK = 128;
+constexpr int kWgPitch = kWgK + 8;
 
+// Row c of the transpose of an 8 x 8 block of 16-bit values: element e of the result is element c
+// of v[e].
+__device__ __forceinline__ uint4 transpose8_row(const uint4 (&v)[8], int c) {
+  unsigned w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const unsigned lo = reinterpret_cast<const unsigned*>(&v[2 * k])[c >> 1];
+    const unsigned hi = reinterpret_cast<const unsigned*>(&v[2 * k + 1])[c >> 1];
+    w[k] = (c & 1) ? ((lo >> 16) | (hi & 0xffff0000u)) : ((lo & 0xffffu) | (hi << 16));
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Weight gradient of one tap (blockIdx.y) for a 64 x 64 block of (output, input) channels over
+// one chunk of pixels (blockIdx.x).  Each step stages 128 pixels of dz and of the shifted input,
+// transposed so that pixels (the contraction) are contiguous: thread t takes an 8-pixel x
+// 8-channel block of one operand (eight 16-byte loads, one per pixel), transposes it in registers
+// and writes eight 16-byte rows.  Four K steps of 32 pixels follow per staging, while the next
+// step's operands load.
 template <int KS>
 __global__ void __launch_bounds__(256) wgrad_kernel(NnConv a, const uint16_t* __restrict__ dz, float* __restrict__ part,
                                                     long chunk) {
@@ -333,47 +355,87 @@ __global__ void __launch_bounds__(256) wgrad_kernel(NnConv a, const uint16_t* __
   const int wco = (wave >> 1) * 32, wci = (wave & 1) * 32;
   const long pbeg = (long)blockIdx.x * chunk;
   const long pend = P < pbeg + chunk ? P : pbeg + chunk;
-  const int sp = t >> 3, c8 = (t & 7) * 8;  // staging: pixel sp of the step, channels c8..c8+7
+  // staging role: threads 0..127 take dz, 128..255 the input; pixel group pg (8 pixels), channel
+  // group cg (8 channels) of the 64-channel block
+  const bool stage_x = t >= 128;
+  const int pg = t & 15, cg = (t >> 4) & 7;
+  const int co = cob + cg * 8, ci = cib + cg * 8;
+  uint16_t* const dst = (stage_x ? sx : sz) + (cg * 8) * kWgPitch + pg * 8;
+  // W % 8 == 0: the 8 pixels of a group lie in one image row (chunks start at multiples of 128)
+  const bool row8 = (W & 7) == 0;
   const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  uint4 v[8];
+  auto load = [&](long p) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = z4;
+    const long q0 = p + pg * 8;
+    if (!stage_x) {
+      if (co < cout)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (q0 + e < pend) v[e] = ld16(dz + (q0 + e) * cout + co);
+    } else if (ci < cin) {
+      const uint16_t* src = ci < cu ? a.xu + ci : a.x + (ci - cu);
+      const int cs = ci < cu ? cu : cx;
+      if (row8) {
+        if (q0 < pend) {
+          const unsigned b = (unsigned)q0 / (unsigned)HW;
+          const unsigned rem = (unsigned)q0 - b * (unsigned)HW;
+          const int y = (int)(rem / (unsigned)W), x0 = (int)(rem - (unsigned)y * W);
+          const int yy = y + dy;
+          if (yy >= 0 && yy < H) {
+            const long rowbase = ci < cu ? ((long)b * (H >> 1) + (yy >> 1)) * (W >> 1) : ((long)b * H + yy) * W;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int xx = x0 + e + dx;
+              if (xx >= 0 && xx < W) v[e] = ld16(src + (rowbase + (ci < cu ? xx >> 1 : xx)) * cs);
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const long q = q0 + e;
+          if (q < pend) {
+            const unsigned b = (unsigned)q / (unsigned)HW;
+            const unsigned rem = (unsigned)q - b * (unsigned)HW;
+            const int yy = (int)(rem / (unsigned)W) + dy, xx = (int)(rem % (unsigned)W) + dx;
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+              v[e] = ld16(src + (ci < cu ? ((long)b * (H >> 1) + (yy >> 1)) * (W >> 1) + (xx >> 1)
+                                         : ((long)b * H + yy) * W + xx) * cs);
+          }
+        }
+      }
+    }
+  };
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (long p = pbeg; p < pend; p += 32) {
-    const long q = p + sp;
-    const bool pv = q < pend;
-    const int co = cob + c8, ci = cib + c8;
-    const uint4 vz = (pv && co < cout) ? ld16(dz + q * cout + co) : z4;
-    uint4 vx = z4;
-    if (pv && ci < cin) {
-      const int b = (int)(q / HW);
-      const int rem = (int)(q - (long)b * HW);
-      const int yy = rem / W + dy, xx = rem % W + dx;
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-        vx = ci < cu ? ld16(a.xu + (((long)b * (H >> 1) + (yy >> 1)) * (W >> 1) + (xx >> 1)) * cu + ci)
-                     : ld16(a.x + (((long)b * H + yy) * W + xx) * cx + (ci - cu));
-    }
+  if (pbeg < pend) load(pbeg);
+  for (long p = pbeg; p < pend; p += kWgK) {
     __syncthreads();  // the previous step's operand reads are done
-    const uint16_t* ez = reinterpret_cast<const uint16_t*>(&vz);
-    const uint16_t* ex = reinterpret_cast<const uint16_t*>(&vx);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      sz[(c8 + e) * kWgPitch + sp] = ez[e];
-      sx[(c8 + e) * kWgPitch + sp] = ex[e];
-    }
+    for (int c = 0; c < 8; ++c) *reinterpret_cast<uint4*>(dst + c * kWgPitch) = transpose8_row(v, c);
     __syncthreads();
-    uint4 av[2], bv[2];
+    if (p + kWgK < pend) load(p + kWgK);  // next step's operands, in flight during the products
 #pragma unroll
-    for (int i = 0; i < 2; ++i) av[i] = *reinterpret_cast<const uint4*>(sz + (wco + i * 16 + lr) * kWgPitch + 8 * lg);
+    for (int ks = 0; ks < kWgK / 32; ++ks) {
+      uint4 av[2], bv[2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const uint4*>(sx + (wci + j * 16 + lr) * kWgPitch + 8 * lg);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
+        av[i] = *reinterpret_cast<const uint4*>(sz + (wco + i * 16 + lr) * kWgPitch + ks * 32 + 8 * lg);
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av[i]), as_bf(bv[j]), acc[i][j], 0, 0, 0);
+        bv[j] = *reinterpret_cast<const uint4*>(sx + (wci + j * 16 + lr) * kWgPitch + ks * 32 + 8 * lg);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av[i]), as_bf(bv[j]), acc[i][j], 0, 0, 0);
+    }
   }
 
 #pragma unroll
@@ -714,8 +776,9 @@ int nn_wgrad_splits(long pixels) {
 hipError_t nn_wgrad(int ks, const NnConv& a, const uint16_t* dz, float* part, int n_split, hipStream_t s) {
   if ((a.cu % 16) || (a.cx % 16) || (a.cout % 16) || n_split < 1 || n_split > kNnMaxSplit) return hipErrorInvalidValue;
   const long P = (long)a.B * a.H * a.W;
+  if (P > 0x7fffffffL) return hipErrorInvalidValue;  // pixel indices are divided in 32 bits
   long chunk = (P + n_split - 1) / n_split;
-  chunk = (chunk + 31) / 32 * 32;
+  chunk = (chunk + kWgK - 1) / kWgK * kWgK;
   const int cin = a.cu + a.cx;
   const dim3 grid(n_split, ks * ks, ((a.cout + 63) / 64) * ((cin + 63) / 64));
   if (ks == 1)
