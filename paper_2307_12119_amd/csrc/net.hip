@@ -43,7 +43,7 @@ struct NetBufs {
   uint16_t *feat, *stem, *ea[5], *eb[5], *pool[5], *d[4];
   float* y;
   uint16_t *dh, *dz;
-  float *mse_part, *dD, *dcat, *dskip[4], *bufA, *bufX, *wpart, *rpart, *tmp;
+  float *mse_part, *dD, *dcat[4], *bufA, *bufX, *wpart, *rpart, *tmp;
   size_t total;
 };
 
@@ -69,18 +69,17 @@ NetBufs plan(const varsim_net* net, int B, bool training, char* base) {
     const size_t n = net->cfg.n;
     b.y = (float*)take((size_t)B * n * n * 4);
     b.dh = (uint16_t*)take(P(0) * 16 * 2);
-    size_t zmax = P(0) * 16, dmax = 0, catmax = 0, xmax = 0;
+    size_t zmax = P(0) * 16, dmax = 0, xmax = 0;
     for (int l = 0; l < 5; ++l) {
       zmax = std::max(zmax, P(l) * w[l]);
       dmax = std::max(dmax, P(l) * w[l]);
       xmax = std::max(xmax, P(l) * (l ? w[l - 1] : w[0]));
-      if (l < 4) catmax = std::max(catmax, P(l) * (w[l + 1] + w[l]));
     }
     b.dz = (uint16_t*)take(zmax * 2);
     b.mse_part = (float*)take(kNnMseBlocks * 17 * 4);
     b.dD = (float*)take(dmax * 4);
-    b.dcat = (float*)take(catmax * 4);
-    for (int l = 0; l < 4; ++l) b.dskip[l] = (float*)take(P(l) * w[l] * 4);
+    // input gradient of each decoder layer, kept until the encoder has read its skip part
+    for (int l = 0; l < 4; ++l) b.dcat[l] = (float*)take(P(l) * (w[l + 1] + w[l]) * 4);
     b.bufA = (float*)take(dmax * 4);
     b.bufX = (float*)take(xmax * 4);
     // largest weight-gradient partial buffer over the layers
@@ -253,11 +252,25 @@ varsim_status layer_wgrad(varsim_net* net, const NetLayer& L, const uint16_t* x,
   return VARSIM_OK;
 }
 
-varsim_status relu_back(varsim_net* net, const float* da, const float* dpool, const uint16_t* act, int B, int l, int C,
-                        float* bias_grad, const NetBufs& b, hipStream_t s) {
+// Gradient sources of a ReLU output at level l (C channels): da on the same grid (lda floats per
+// pixel), dfine on the grid of level l - 1 (ldf floats per pixel; the gradient through the
+// upsampling into the finer decoder), dpool on level l + 1 (the gradient through the pooling into
+// the coarser encoder).
+struct GradIn {
+  const float* da = nullptr;
+  int lda = 0;
+  const float* dfine = nullptr;
+  int ldf = 0;
+  const float* dpool = nullptr;
+};
+
+varsim_status relu_back(varsim_net* net, const GradIn& g, const uint16_t* act, int B, int l, int C, float* bias_grad,
+                        const NetBufs& b, hipStream_t s) {
   varsim_ctx* ctx = net->ctx;
   const int ml = level_size(net, l);
-  HIP_TRY(timed(ctx, "nn_elementwise", s, [&] { return nn_relu_bwd(da, dpool, act, b.dz, B, ml, ml, C, b.rpart, s); }));
+  HIP_TRY(timed(ctx, "nn_elementwise", s, [&] {
+    return nn_relu_bwd(g.da, g.lda, g.dfine, g.ldf, g.dpool, act, b.dz, B, ml, ml, C, b.rpart, s);
+  }));
   HIP_TRY(timed(ctx, "nn_reduce", s, [&] { return nn_colsum(b.rpart, kNnReluBlocks, C, C, 1.f, bias_grad, s); }));
   return VARSIM_OK;
 }
@@ -279,29 +292,39 @@ varsim_status run_gradient(varsim_net* net, int B, const int* idx, const float* 
   if ((st = layer_wgrad(net, net->head, b.d[0], w[0], nullptr, 0, b.dh, B, 0, grad, b, s)) != VARSIM_OK) return st;
   HIP_TRY(timed(ctx, "nn_conv_dgrad", s,
                 [&] { return nn_conv(1, NN_EPI_F32, false, dgrad_args(net, net->head, b.dh, b.dD, B, 0), s); }));
-  // decoder: dD holds the gradient of d_l (level 0 first); d_4 is e_4
+  // decoder, level 0 first.  dcat[l] = gradient of dec l's input [upsampled d_{l+1} | e_l]; the
+  // gradient of d_l is dD (from the head) at level 0, else the sum over 2 x 2 blocks of the
+  // upsampled part of dcat[l - 1]; d_4 is e_4
   for (int l = 0; l < 4; ++l) {
     const NetLayer& L = net->dec[l];
-    if ((st = relu_back(net, b.dD, nullptr, b.d[l], B, l, w[l], grad + L.b_off, b, s)) != VARSIM_OK) return st;
+    GradIn g;
+    if (l == 0)
+      g.da = b.dD, g.lda = w[0];
+    else
+      g.dfine = b.dcat[l - 1], g.ldf = w[l] + w[l - 1];
+    if ((st = relu_back(net, g, b.d[l], B, l, w[l], grad + L.b_off, b, s)) != VARSIM_OK) return st;
     const uint16_t* up = l == 3 ? b.eb[4] : b.d[l + 1];
     if ((st = layer_wgrad(net, L, b.eb[l], w[l], up, w[l + 1], b.dz, B, l, grad, b, s)) != VARSIM_OK) return st;
     HIP_TRY(timed(ctx, "nn_conv_dgrad", s,
-                  [&] { return nn_conv(3, NN_EPI_F32, false, dgrad_args(net, L, b.dz, b.dcat, B, l), s); }));
-    const int ml = level_size(net, l);
-    HIP_TRY(timed(ctx, "nn_elementwise", s,
-                  [&] { return nn_split_cat_grad(b.dcat, w[l + 1], w[l], b.dD, b.dskip[l], B, ml, ml, s); }));
+                  [&] { return nn_conv(3, NN_EPI_F32, false, dgrad_args(net, L, b.dz, b.dcat[l], B, l), s); }));
   }
-  // encoder, deepest level first: gradient of e_l = skip part + pooled part from level l + 1
+  // encoder, deepest level first: gradient of e_l = skip part of dcat[l] + pooled part from level
+  // l + 1 (level 4: the upsampled part of dcat[3])
   for (int l = 4; l >= 0; --l) {
     const NetLayer& La = net->enc[l][0];
     const NetLayer& Lb = net->enc[l][1];
-    const float* da = l == 4 ? b.dD : b.dskip[l];
-    const float* dpool = l == 4 ? nullptr : b.bufX;
-    if ((st = relu_back(net, da, dpool, b.eb[l], B, l, w[l], grad + Lb.b_off, b, s)) != VARSIM_OK) return st;
+    GradIn g;
+    if (l == 4)
+      g.dfine = b.dcat[3], g.ldf = w[4] + w[3];
+    else
+      g.da = b.dcat[l] + w[l + 1], g.lda = w[l + 1] + w[l], g.dpool = b.bufX;
+    if ((st = relu_back(net, g, b.eb[l], B, l, w[l], grad + Lb.b_off, b, s)) != VARSIM_OK) return st;
     if ((st = layer_wgrad(net, Lb, b.ea[l], w[l], nullptr, 0, b.dz, B, l, grad, b, s)) != VARSIM_OK) return st;
     HIP_TRY(timed(ctx, "nn_conv_dgrad", s,
                   [&] { return nn_conv(3, NN_EPI_F32, false, dgrad_args(net, Lb, b.dz, b.bufA, B, l), s); }));
-    if ((st = relu_back(net, b.bufA, nullptr, b.ea[l], B, l, w[l], grad + La.b_off, b, s)) != VARSIM_OK) return st;
+    GradIn ga;
+    ga.da = b.bufA, ga.lda = w[l];
+    if ((st = relu_back(net, ga, b.ea[l], B, l, w[l], grad + La.b_off, b, s)) != VARSIM_OK) return st;
     const uint16_t* in = l == 0 ? b.stem : b.pool[l];
     const int cin = l == 0 ? w[0] : w[l - 1];
     if ((st = layer_wgrad(net, La, in, cin, nullptr, 0, b.dz, B, l, grad, b, s)) != VARSIM_OK) return st;
@@ -309,7 +332,9 @@ varsim_status run_gradient(varsim_net* net, int B, const int* idx, const float* 
                   [&] { return nn_conv(3, NN_EPI_F32, false, dgrad_args(net, La, b.dz, b.bufX, B, l), s); }));
   }
   // stem (bufX: gradient of the stem output)
-  if ((st = relu_back(net, b.bufX, nullptr, b.stem, B, 0, w[0], grad + net->stem.b_off, b, s)) != VARSIM_OK) return st;
+  GradIn gs;
+  gs.da = b.bufX, gs.lda = w[0];
+  if ((st = relu_back(net, gs, b.stem, B, 0, w[0], grad + net->stem.b_off, b, s)) != VARSIM_OK) return st;
   if ((st = layer_wgrad(net, net->stem, b.feat, 64, nullptr, 0, b.dz, B, 0, grad, b, s)) != VARSIM_OK) return st;
   return VARSIM_OK;
 }

@@ -478,34 +478,45 @@ __global__ void __launch_bounds__(256) reduce_parts_kernel(const float* __restri
 // Thread t owns channel group cg = t % G (8 channels, G = C / 8) of pixels slot, slot + T, ...
 // (T = 256 / G threads per group); its channel sums stay in registers and the workgroup adds the
 // T partials of each channel in a fixed order: no atomics, the same bits on every run.
-__global__ void __launch_bounds__(256) relu_bwd_kernel(const float* __restrict__ da, const float* __restrict__ dpool,
-                                                       const uint16_t* __restrict__ act, uint16_t* __restrict__ dz,
-                                                       int B, int H, int W, int C, float* __restrict__ part) {
+__device__ __forceinline__ void add8(float (&g)[8], const float* __restrict__ p, float w) {
+  const float4 lo = *reinterpret_cast<const float4*>(p), hi = *reinterpret_cast<const float4*>(p + 4);
+  g[0] += w * lo.x, g[1] += w * lo.y, g[2] += w * lo.z, g[3] += w * lo.w;
+  g[4] += w * hi.x, g[5] += w * hi.y, g[6] += w * hi.z, g[7] += w * hi.w;
+}
+
+__global__ void __launch_bounds__(256) relu_bwd_kernel(const float* __restrict__ da, int lda,
+                                                       const float* __restrict__ dfine, int ldf,
+                                                       const float* __restrict__ dpool, const uint16_t* __restrict__ act,
+                                                       uint16_t* __restrict__ dz, int B, int H, int W, int C,
+                                                       float* __restrict__ part) {
   __shared__ float s[256 * 8];
   const int G = C >> 3, T = 256 / G;
   const int cg = threadIdx.x % G, slot = threadIdx.x / G;
   const int c = 8 * cg;
-  const long P = (long)B * H * W, HW = (long)H * W;
+  const long P = (long)B * H * W;
+  const unsigned HW = (unsigned)H * W;
   float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (slot < T) {
     for (long p = (long)blockIdx.x * T + slot; p < P; p += (long)gridDim.x * T) {
-      const long e = p * C + c;
       float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       if (da) {
-        const float4 lo = *reinterpret_cast<const float4*>(da + e), hi = *reinterpret_cast<const float4*>(da + e + 4);
+        const float4 lo = *reinterpret_cast<const float4*>(da + p * lda + c);
+        const float4 hi = *reinterpret_cast<const float4*>(da + p * lda + c + 4);
         g[0] = lo.x, g[1] = lo.y, g[2] = lo.z, g[3] = lo.w, g[4] = hi.x, g[5] = hi.y, g[6] = hi.z, g[7] = hi.w;
       }
-      if (dpool) {
-        const int b = (int)(p / HW);
-        const int rem = (int)(p - (long)b * HW);
-        const int y = rem / W, x = rem % W;
-        const float* d = dpool + (((long)b * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1)) * C + c;
-        const float4 lo = *reinterpret_cast<const float4*>(d), hi = *reinterpret_cast<const float4*>(d + 4);
-        g[0] += 0.25f * lo.x, g[1] += 0.25f * lo.y, g[2] += 0.25f * lo.z, g[3] += 0.25f * lo.w;
-        g[4] += 0.25f * hi.x, g[5] += 0.25f * hi.y, g[6] += 0.25f * hi.z, g[7] += 0.25f * hi.w;
+      if (dfine || dpool) {
+        const unsigned b = (unsigned)p / HW;
+        const unsigned rem = (unsigned)p - b * HW;
+        const int yq = (int)(rem / (unsigned)W), xq = (int)(rem - (unsigned)yq * W);
+        if (dfine)  // nearest-neighbour upsampling: the sum over the 2 x 2 fine block
+#pragma unroll
+          for (int d = 0; d < 4; ++d)
+            add8(g, dfine + (((long)b * 2 * H + 2 * yq + (d >> 1)) * (2L * W) + 2 * xq + (d & 1)) * ldf + c, 1.f);
+        if (dpool)  // 2 x 2 average pool: a quarter of the coarse value
+          add8(g, dpool + (((long)b * (H >> 1) + (yq >> 1)) * (W >> 1) + (xq >> 1)) * C + c, 0.25f);
       }
       if (act) {
-        const uint4 u = ld16(act + e);
+        const uint4 u = ld16(act + p * C + c);
         const uint16_t* h = reinterpret_cast<const uint16_t*>(&u);
 #pragma unroll
         for (int k = 0; k < 8; ++k) g[k] = bf2f(h[k]) > 0.f ? g[k] : 0.f;
@@ -513,8 +524,8 @@ __global__ void __launch_bounds__(256) relu_bwd_kernel(const float* __restrict__
 #pragma unroll
       for (int k = 0; k < 8; ++k) sum[k] += g[k];
       if (dz)
-        *reinterpret_cast<uint4*>(dz + e) = make_uint4(pack2(g[0], g[1]), pack2(g[2], g[3]), pack2(g[4], g[5]),
-                                                       pack2(g[6], g[7]));
+        *reinterpret_cast<uint4*>(dz + p * C + c) = make_uint4(pack2(g[0], g[1]), pack2(g[2], g[3]),
+                                                               pack2(g[4], g[5]), pack2(g[6], g[7]));
     }
   }
   // s[slot][c + k]: the T partials of every channel
@@ -570,39 +581,6 @@ __global__ void __launch_bounds__(256) avgpool_kernel(const uint16_t* __restrict
     *reinterpret_cast<uint4*>(y + pc * C + c) =
         make_uint4(pack2(0.25f * acc[0], 0.25f * acc[1]), pack2(0.25f * acc[2], 0.25f * acc[3]),
                    pack2(0.25f * acc[4], 0.25f * acc[5]), pack2(0.25f * acc[6], 0.25f * acc[7]));
-  }
-}
-
-// dcoarse[pc][c] = sum of the 2x2 fine dcat[.][c], c < cu
-__global__ void __launch_bounds__(256) upsample_grad_kernel(const float* __restrict__ dcat, int C, int cu,
-                                                            float* __restrict__ dcoarse, int B, int Hc, int Wc) {
-  const int g4 = cu / 4;
-  const long n = (long)B * Hc * Wc * g4;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const long pc = i / g4;
-    const int c = (int)(i - pc * g4) * 4;
-    const int b = (int)(pc / ((long)Hc * Wc));
-    const int rem = (int)(pc - (long)b * Hc * Wc);
-    const int Y = rem / Wc, X = rem % Wc;
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const long pf = ((long)b * 2 * Hc + 2 * Y + (d >> 1)) * (2L * Wc) + 2 * X + (d & 1);
-      const float4 v = *reinterpret_cast<const float4*>(dcat + pf * C + c);
-      s.x += v.x, s.y += v.y, s.z += v.z, s.w += v.w;
-    }
-    *reinterpret_cast<float4*>(dcoarse + pc * cu + c) = s;
-  }
-}
-
-__global__ void __launch_bounds__(256) slice_kernel(const float* __restrict__ dcat, int C, int cu, int cx,
-                                                    float* __restrict__ dskip, long P) {
-  const int g4 = cx / 4;
-  const long n = P * g4;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const long p = i / g4;
-    const int c = (int)(i - p * g4) * 4;
-    *reinterpret_cast<float4*>(dskip + p * cx + c) = *reinterpret_cast<const float4*>(dcat + p * C + cu + c);
   }
 }
 
@@ -686,19 +664,22 @@ __global__ void __launch_bounds__(256) stem_kernel(const float* __restrict__ q, 
 __global__ void __launch_bounds__(256) mse_grad_kernel(const float* __restrict__ y, const float* __restrict__ t,
                                                        const int* __restrict__ idx, int n, int B, float out_scale,
                                                        uint16_t* __restrict__ dh, float* __restrict__ part) {
-  __shared__ float s[17];
-  if (threadIdx.x < 17) s[threadIdx.x] = 0.f;
-  __syncthreads();
+  __shared__ float s[4][17];
   const int mc = n / 4;
   const long total = (long)B * mc * mc;
   const float k = 2.f / ((float)B * (float)n * (float)n);
+  // per-thread sums in registers, then a butterfly over the wave and the four waves in a fixed
+  // order: no atomics, the same bits on every run
+  float acc[17];
+#pragma unroll
+  for (int j = 0; j < 17; ++j) acc[j] = 0.f;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
-    const int b = (int)(i / ((long)mc * mc));
-    const int rem = (int)(i - (long)b * mc * mc);
+    const unsigned per = (unsigned)mc * mc;
+    const int b = (int)((unsigned long)i / per);
+    const int rem = (int)(i - (long)b * per);
     const int Y = rem / mc, X = rem % mc;
     const long st = idx ? idx[b] : b;
     float g[16];
-    float sq = 0.f;
 #pragma unroll
     for (int py = 0; py < 4; ++py) {
       const float4 yy = *reinterpret_cast<const float4*>(y + ((long)b * n + 4 * Y + py) * n + 4 * X);
@@ -706,19 +687,28 @@ __global__ void __launch_bounds__(256) mse_grad_kernel(const float* __restrict__
       const float d[4] = {yy.x - tt.x, yy.y - tt.y, yy.z - tt.z, yy.w - tt.w};
 #pragma unroll
       for (int px = 0; px < 4; ++px) {
-        sq += d[px] * d[px];
+        acc[16] += d[px] * d[px];
         g[py * 4 + px] = out_scale * k * d[px];
+        acc[py * 4 + px] += g[py * 4 + px];
       }
     }
     uint4* o = reinterpret_cast<uint4*>(dh + i * 16);
     o[0] = make_uint4(pack2(g[0], g[1]), pack2(g[2], g[3]), pack2(g[4], g[5]), pack2(g[6], g[7]));
     o[1] = make_uint4(pack2(g[8], g[9]), pack2(g[10], g[11]), pack2(g[12], g[13]), pack2(g[14], g[15]));
-#pragma unroll
-    for (int j = 0; j < 16; ++j) atomicAdd(&s[j], g[j]);
-    atomicAdd(&s[16], sq);
   }
+#pragma unroll
+  for (int j = 0; j < 17; ++j)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < 17; ++j) s[wave][j] = acc[j];
   __syncthreads();
-  if (threadIdx.x < 17) part[(long)blockIdx.x * 17 + threadIdx.x] = s[threadIdx.x];
+  if (threadIdx.x < 17) {
+    const int j = threadIdx.x;
+    part[(long)blockIdx.x * 17 + j] = (s[0][j] + s[1][j]) + (s[2][j] + s[3][j]);
+  }
 }
 
 __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
@@ -798,10 +788,13 @@ hipError_t nn_reduce_parts(const float* part, int n_split, int cout, int taps, i
   return hipGetLastError();
 }
 
-hipError_t nn_relu_bwd(const float* da, const float* dpool, const uint16_t* act, uint16_t* dz, int B, int H, int W,
-                       int C, float* part, hipStream_t s) {
-  if (C % 8 || C > 256 || (dpool && ((H | W) & 1))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(relu_bwd_kernel, dim3(kNnReluBlocks), dim3(256), 0, s, da, dpool, act, dz, B, H, W, C, part);
+hipError_t nn_relu_bwd(const float* da, int lda, const float* dfine, int ldf, const float* dpool, const uint16_t* act,
+                       uint16_t* dz, int B, int H, int W, int C, float* part, hipStream_t s) {
+  if (C % 8 || C > 256 || (da && (lda < C || lda % 4)) || (dfine && (ldf < C || ldf % 4)) ||
+      (dpool && ((H | W) & 1)) || (long)B * H * W > 0x7fffffffL)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(relu_bwd_kernel, dim3(kNnReluBlocks), dim3(256), 0, s, da, lda, dfine, ldf, dpool, act, dz, B, H,
+                     W, C, part);
   return hipGetLastError();
 }
 
@@ -814,23 +807,6 @@ hipError_t nn_avgpool(const uint16_t* x, uint16_t* y, int B, int Hc, int Wc, int
   if (C % 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL(avgpool_kernel, dim3(blocks_for((long)B * Hc * Wc * (C / 8))), dim3(256), 0, s, x, y, B, Hc, Wc,
                      C);
-  return hipGetLastError();
-}
-
-hipError_t nn_split_cat_grad(const float* dcat, int cu, int cx, float* dcoarse, float* dskip, int B, int H, int W,
-                             hipStream_t s) {
-  if ((cu % 4) || (cx % 4) || ((H | W) & 1)) return hipErrorInvalidValue;
-  const int C = cu + cx;
-  if (dcoarse && cu) {
-    hipLaunchKernelGGL(upsample_grad_kernel, dim3(blocks_for((long)B * (H / 2) * (W / 2) * (cu / 4))), dim3(256), 0, s,
-                       dcat, C, cu, dcoarse, B, H / 2, W / 2);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (dskip && cx) {
-    const long P = (long)B * H * W;
-    hipLaunchKernelGGL(slice_kernel, dim3(blocks_for(P * (cx / 4))), dim3(256), 0, s, dcat, C, cu, cx, dskip, P);
-  }
   return hipGetLastError();
 }
 

@@ -43,18 +43,18 @@ hipError_t nn_wgrad(int ks, const NnConv& a, const uint16_t* dz, float* part, in
 hipError_t nn_reduce_parts(const float* part, int n_split, int cout, int taps, int cin_src, int cin_dst, float* out,
                            hipStream_t s);
 
-// dz = BF16 of g * [act > 0] (act may be null: no mask), g = da[p][c] + 0.25 dpool[coarse(p)][c]
-// (either may be null); per-channel sums of g into part[block][C].
-constexpr int kNnReluBlocks = 512;
-hipError_t nn_relu_bwd(const float* da, const float* dpool, const uint16_t* act, uint16_t* dz, int B, int H, int W,
-                       int C, float* part, hipStream_t s);
+// dz = BF16 of g * [act > 0] (act may be null: no mask), where g at pixel p of the H x W grid is
+// the sum of the sources that are given: da[p * lda + c] (same grid), the four values
+// dfine[q * ldf + c] of the 2 x 2 block of p on the 2H x 2W grid (gradient of a nearest-neighbour
+// upsampling) and 0.25 dpool[coarse(p) * C + c] (gradient of a 2 x 2 average pool); per-channel
+// sums of g into part[block][C].  Strides in floats, multiples of 4.
+constexpr int kNnReluBlocks = 2048;
+hipError_t nn_relu_bwd(const float* da, int lda, const float* dfine, int ldf, const float* dpool, const uint16_t* act,
+                       uint16_t* dz, int B, int H, int W, int C, float* part, hipStream_t s);
 // out[c] = scale * sum_b part[b * stride + c], b < nb, c < C
 hipError_t nn_colsum(const float* part, int nb, int stride, int C, float scale, float* out, hipStream_t s);
 
 hipError_t nn_avgpool(const uint16_t* x, uint16_t* y, int B, int Hc, int Wc, int C, hipStream_t s);
-// dcoarse[b][Y][X][c] = sum of the 2x2 fine values of dcat[.][c] (c < cu); dskip[p][c] = dcat[p][cu + c]
-hipError_t nn_split_cat_grad(const float* dcat, int cu, int cx, float* dcoarse, float* dskip, int B, int H, int W,
-                             hipStream_t s);
 
 struct NnFeat {
   float shift[3], scale[3];
@@ -69,7 +69,7 @@ hipError_t nn_stem(const float* q, const float* v, const float* m, const int* id
                    const uint16_t* w, const float* bias, int cout, uint16_t* y, uint16_t* feat_out, hipStream_t s);
 // dh[b][Y][X][j] = BF16 of out_scale * 2 (y - t) / (B n^2) at fine pixel (4Y + j/4, 4X + j%4);
 // part[block][17] = per-block sums of the 16 FP32 dh values and of (y - t)^2
-constexpr int kNnMseBlocks = 256;
+constexpr int kNnMseBlocks = 1024;
 hipError_t nn_mse_grad(const float* y, const float* t, const int* idx, int n, int B, float out_scale, uint16_t* dh,
                        float* part, hipStream_t s);
 
