@@ -85,7 +85,8 @@ NetBufs plan(const varsim_net* net, int B, bool training, char* base) {
     // largest weight-gradient partial buffer over the layers
     size_t wp = 0;
     auto wpl = [&](const NetLayer& L, int l) {
-      wp = std::max(wp, (size_t)nn_wgrad_splits((long)P(l)) * L.cout * L.ks * L.ks * L.cin);
+      const int m = level_size(net, l);
+      wp = std::max(wp, (size_t)nn_wgrad_splits(L.ks, B, m, m, L.cin, L.cout) * L.cout * L.ks * L.ks * L.cin);
     };
     wpl(net->stem, 0);
     wpl(net->head, 0);
@@ -244,7 +245,8 @@ varsim_status layer_wgrad(varsim_net* net, const NetLayer& L, const uint16_t* x,
                           const uint16_t* dz, int B, int l, float* grad, const NetBufs& b, hipStream_t s) {
   varsim_ctx* ctx = net->ctx;
   NnConv a = conv_args(net, L, x, cx, xu, cu, nullptr, B, l, false);
-  const int ns = nn_wgrad_splits((long)B * level_size(net, l) * level_size(net, l));
+  const int m = level_size(net, l);
+  const int ns = nn_wgrad_splits(L.ks, B, m, m, a.cu + a.cx, L.cout);
   HIP_TRY(timed(ctx, "nn_wgrad", s, [&] { return nn_wgrad(L.ks, a, dz, b.wpart, ns, s); }));
   HIP_TRY(timed(ctx, "nn_reduce", s, [&] {
     return nn_reduce_parts(b.wpart, ns, L.cout, L.ks * L.ks, L.cin, L.cin_src, grad + L.w_off, s);
@@ -487,7 +489,7 @@ varsim_status varsim_nn_conv_workspace(int32_t op, int32_t k, int32_t batch, int
   if (!bytes || (k != 1 && k != 3) || batch < 1 || h < 1 || w < 1 || cin < 16 || cout < 16) return VARSIM_ERR_INVALID;
   size_t b = 0;
   if (op == VARSIM_NN_DGRAD) b = up256((size_t)cout * k * k * cin * 2);
-  else if (op == VARSIM_NN_WGRAD) b = up256((size_t)nn_wgrad_splits((long)batch * h * w) * cout * k * k * cin * 4);
+  else if (op == VARSIM_NN_WGRAD) b = up256((size_t)nn_wgrad_splits(k, batch, h, w, cin, cout) * cout * k * k * cin * 4);
   else if (op != VARSIM_NN_FWD) return VARSIM_ERR_INVALID;
   *bytes = b;
   return VARSIM_OK;
@@ -519,7 +521,7 @@ varsim_status varsim_nn_conv(varsim_ctx* ctx, int32_t op, int32_t k, int32_t bat
     HIP_TRY(nn_conv(k, NN_EPI_F32, false, c, s));
   } else {
     c.x = a, c.cx = cin, c.cout = cout;
-    const int ns = nn_wgrad_splits((long)batch * h * w);
+    const int ns = nn_wgrad_splits(k, batch, h, w, cin, cout);
     float* part = (float*)workspace;
     HIP_TRY(nn_wgrad(k, c, bw, part, ns, s));
     HIP_TRY(nn_reduce_parts(part, ns, cout, k * k, cin, cin, (float*)out, s));

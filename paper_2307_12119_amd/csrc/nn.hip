@@ -449,6 +449,153 @@ __global__ void __launch_bounds__(256) wgrad_kernel(NnConv a, const uint16_t* __
       }
 }
 
+// Weight gradient of a 3 x 3 layer with the nine taps in one workgroup.  A step covers R = 128 / W
+// whole image rows (128 pixels).  dz of the step is staged once (16 MT channels x 128 pixels,
+// pixels contiguous), and the input once as a halo of R + 2 rows by W + 2 columns (zero outside
+// the image; 16 NT channels, columns contiguous, halo column h holding image column h - 1).  For
+// the 8 pixels of a lane's K slice and a tap (dy, dx), the input operand is the halo run starting at
+// column c + dx + 1: two aligned 16-byte reads per row serve all three dx (byte shifts of 0, 2
+// and 4).  Wave w owns the (output block, input block) pairs w, w + 4, ... of the tile, each with
+// nine accumulators; there is no cross-wave sum.  The input is staged once per step instead of
+// once per tap.
+template <int MT, int NT>
+struct WgFused {
+  static constexpr int PAIRS = MT * NT;
+  static constexpr int PW = (PAIRS + 3) / 4;  // pairs per wave, at most
+  static constexpr int ZP = 136;              // dz row pitch (elements): 272 bytes
+  static constexpr int XPMAX = 456;           // largest halo pitch per channel
+  static constexpr int LDS = 16 * MT * ZP + 16 * NT * XPMAX;
+};
+
+// halo geometry per image width: row pitch W + 16, channel pitch >= (R + 2) (W + 16) with
+// pitch = 8 (mod 64) elements, so 8 consecutive channel rows start 16 bytes apart modulo 128
+__host__ __device__ inline int wg3_hp(int W) { return W + 16; }
+__host__ __device__ inline int wg3_xp(int W) {
+  const int need = (128 / W + 2) * (W + 16);
+  return (need + 55) / 64 * 64 + 8;
+}
+
+__device__ __forceinline__ uint4 shift_elems1(const uint4& a, const uint4& b) {
+  return make_uint4(__builtin_amdgcn_alignbyte(a.y, a.x, 2), __builtin_amdgcn_alignbyte(a.z, a.y, 2),
+                    __builtin_amdgcn_alignbyte(a.w, a.z, 2), __builtin_amdgcn_alignbyte(b.x, a.w, 2));
+}
+
+template <int MT, int NT>
+__global__ void __launch_bounds__(256) wgrad3_kernel(NnConv a, const uint16_t* __restrict__ dz, float* __restrict__ part,
+                                                     int steps_per_wg) {
+  using F = WgFused<MT, NT>;
+  __shared__ __attribute__((aligned(16))) uint16_t lds[F::LDS];
+  uint16_t* const sz = lds;
+  uint16_t* const sx = lds + 16 * MT * F::ZP;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lg = lane >> 4;
+  const int H = a.H, W = a.W, cu = a.cu, cx = a.cx, cin = cu + cx, cout = a.cout;
+  const int R = 128 / W, HP = wg3_hp(W), XP = wg3_xp(W), HB = W / 8 + 1;
+  const int spi = H / R;  // steps per image
+  const int nsteps = a.B * spi;
+  const int nco = (cout + 16 * MT - 1) / (16 * MT);
+  const int cob = (int)(blockIdx.y % nco) * 16 * MT, cib = (int)(blockIdx.y / nco) * 16 * NT;
+  const int s0 = blockIdx.x * steps_per_wg;
+  const int s1 = nsteps < s0 + steps_per_wg ? nsteps : s0 + steps_per_wg;
+  const int nzb = 2 * MT * 16, nblk = nzb + 2 * NT * (R + 2) * HB;
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  f32x4 acc[F::PW][9];
+#pragma unroll
+  for (int q = 0; q < F::PW; ++q)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[q][k] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // one 8-pixel x 8-channel staging block: its loads, and where its transpose goes
+  auto fetch = [&](int blk, int b, int y0, long p0, uint4 (&v)[8], uint16_t*& dst, int& pitch) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = z4;
+    dst = nullptr;
+    if (blk >= nblk) return;
+    if (blk < nzb) {
+      const int cg = blk >> 4, pg = blk & 15;
+      const int co = cob + cg * 8;
+      if (co < cout)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = ld16(dz + (p0 + pg * 8 + e) * cout + co);
+      dst = sz + (cg * 8) * F::ZP + pg * 8;
+      pitch = F::ZP;
+    } else {
+      const int xb = blk - nzb;
+      const int hcb = xb % HB, rest = xb / HB;
+      const int hr = rest % (R + 2), cg = rest / (R + 2);
+      const int ci = cib + cg * 8, y = y0 - 1 + hr;
+      if (ci < cin && y >= 0 && y < H) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int xc = hcb * 8 + e - 1;
+          if (xc >= 0 && xc < W)
+            v[e] = ci < cu ? ld16(a.xu + (((long)b * (H >> 1) + (y >> 1)) * (W >> 1) + (xc >> 1)) * cu + ci)
+                           : ld16(a.x + (((long)b * H + y) * W + xc) * cx + (ci - cu));
+        }
+      }
+      dst = sx + (cg * 8) * XP + hr * HP + hcb * 8;
+      pitch = XP;
+    }
+  };
+
+  for (int st = s0; st < s1; ++st) {
+    const int b = st / spi, y0 = (st - b * spi) * R;
+    const long p0 = (long)st * 128;
+    // at most two staging blocks per thread: both loads in flight before the writes
+    uint4 v0[8], v1[8];
+    uint16_t *d0, *d1;
+    int pt0 = 0, pt1 = 0;
+    fetch(t, b, y0, p0, v0, d0, pt0);
+    fetch(t + 256, b, y0, p0, v1, d1, pt1);
+    __syncthreads();  // the previous step's operand reads are done
+    if (d0)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) *reinterpret_cast<uint4*>(d0 + c * pt0) = transpose8_row(v0, c);
+    if (d1)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) *reinterpret_cast<uint4*>(d1 + c * pt1) = transpose8_row(v1, c);
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int k0 = ks * 32 + 8 * lg;
+      const int r = k0 / W, c = k0 - r * W;
+#pragma unroll
+      for (int q = 0; q < F::PW; ++q) {
+        const int pair = wave + 4 * q;
+        if (pair < F::PAIRS) {
+          const int i = pair / NT, j = pair % NT;
+          const uint4 av = *reinterpret_cast<const uint4*>(sz + (i * 16 + lr) * F::ZP + k0);
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy) {
+            const uint16_t* bx = sx + (j * 16 + lr) * XP + (r + dy) * HP + c;
+            const uint4 c0 = *reinterpret_cast<const uint4*>(bx);
+            const uint4 c1 = *reinterpret_cast<const uint4*>(bx + 8);
+            const uint4 b1 = shift_elems1(c0, c1);
+            const uint4 b2 = make_uint4(c0.y, c0.z, c0.w, c1.x);
+            acc[q][dy * 3 + 0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(c0), acc[q][dy * 3 + 0], 0, 0, 0);
+            acc[q][dy * 3 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(b1), acc[q][dy * 3 + 1], 0, 0, 0);
+            acc[q][dy * 3 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(b2), acc[q][dy * 3 + 2], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int q = 0; q < F::PW; ++q) {
+    const int pair = wave + 4 * q;
+    if (pair < F::PAIRS) {
+      const int i = pair / NT, j = pair % NT;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          const int co = cob + i * 16 + 4 * lg + r4, ci = cib + j * 16 + lr;
+          if (co < cout && ci < cin) part[(((long)blockIdx.x * cout + co) * 9 + tap) * cin + ci] = acc[q][tap][r4];
+        }
+    }
+  }
+}
+
 // 64 outputs per workgroup, four threads per output (chunks g, g + 4, ...), added in a fixed order
 __global__ void __launch_bounds__(256) reduce_parts_kernel(const float* __restrict__ part, int ns, int cout, int taps,
                                                            int cin_src, int cin_dst, float* __restrict__ out) {
@@ -758,15 +905,79 @@ hipError_t nn_conv(int ks, int epi, bool relu, const NnConv& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-int nn_wgrad_splits(long pixels) {
-  const long s = (pixels + 2047) / 2048;
-  return (int)(s < 1 ? 1 : (s > kNnMaxSplit ? kNnMaxSplit : s));
+namespace {
+
+// Tile of the nine-tap kernel for a layer: output blocks MT (<= 4, a divisor of cout / 16 when one
+// exists), input blocks NT chosen for the least padded input channels plus a per-tile cost, within
+// 12 pairs and 72 KB of LDS.  Returns false when the layer does not suit the kernel.
+bool wgrad3_tile(int W, int H, int cout, int cin, int& mt, int& nt) {
+  if (W < 8 || W > 128 || (W & (W - 1)) || H % (128 / W)) return false;
+  const int cm = cout / 16;
+  mt = cm % 4 == 0 ? 4 : (cm % 3 == 0 ? 3 : (cm % 2 == 0 ? 2 : 1));
+  if (mt == 1 && cm > 1) mt = cm >= 4 ? 4 : cm;
+  long best = -1;
+  for (int n = 1; n <= 5; ++n) {
+    if (mt * n > 12 || mt * n < 4) continue;
+    const long lds = 2L * (16 * mt * 136 + 16 * n * 456);
+    if (lds > 72 * 1024) continue;
+    const long cost = (long)((cin + 16 * n - 1) / (16 * n)) * (n + 2);
+    if (best < 0 || cost < best) best = cost, nt = n;
+  }
+  return best >= 0;
+}
+
+int wgrad3_steps_per_wg(int B, int H, int W, int tiles) {
+  const long nsteps = (long)B * H * W / 128;
+  long per = (nsteps * tiles + 767) / 768;
+  if (per < 8) per = 8;
+  return (int)per;
+}
+
+template <int MT, int NT>
+hipError_t wgrad3_launch(const NnConv& a, const uint16_t* dz, float* part, int n_split, int per, hipStream_t s) {
+  const int cin = a.cu + a.cx;
+  const dim3 grid(n_split, ((a.cout + 16 * MT - 1) / (16 * MT)) * ((cin + 16 * NT - 1) / (16 * NT)));
+  hipLaunchKernelGGL((wgrad3_kernel<MT, NT>), grid, dim3(256), 0, s, a, dz, part, per);
+  return hipGetLastError();
+}
+
+hipError_t wgrad3_dispatch(int mt, int nt, const NnConv& a, const uint16_t* dz, float* part, int n_split, int per,
+                           hipStream_t s) {
+  switch (mt * 8 + nt) {
+#define VS_WG3(M, N) \
+  case M * 8 + N: return wgrad3_launch<M, N>(a, dz, part, n_split, per, s);
+    VS_WG3(1, 4) VS_WG3(1, 5) VS_WG3(2, 2) VS_WG3(2, 3) VS_WG3(2, 4) VS_WG3(2, 5) VS_WG3(3, 2) VS_WG3(3, 3)
+    VS_WG3(3, 4) VS_WG3(4, 1) VS_WG3(4, 2) VS_WG3(4, 3)
+#undef VS_WG3
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int nn_wgrad_splits(int ks, int B, int H, int W, int cin, int cout) {
+  int mt, nt;
+  if (ks == 3 && wgrad3_tile(W, H, cout, cin, mt, nt)) {
+    const int tiles = ((cout + 16 * mt - 1) / (16 * mt)) * ((cin + 16 * nt - 1) / (16 * nt));
+    const long nsteps = (long)B * H * W / 128;
+    const int per = wgrad3_steps_per_wg(B, H, W, tiles);
+    return (int)((nsteps + per - 1) / per);
+  }
+  const long s = ((long)B * H * W + 2047) / 2048;
+  return (int)(s < 1 ? 1 : (s > 256 ? 256 : s));
 }
 
 hipError_t nn_wgrad(int ks, const NnConv& a, const uint16_t* dz, float* part, int n_split, hipStream_t s) {
-  if ((a.cu % 16) || (a.cx % 16) || (a.cout % 16) || n_split < 1 || n_split > kNnMaxSplit) return hipErrorInvalidValue;
+  if ((a.cu % 16) || (a.cx % 16) || (a.cout % 16) || (a.cu && ((a.H | a.W) & 1))) return hipErrorInvalidValue;
+  if (n_split != nn_wgrad_splits(ks, a.B, a.H, a.W, a.cu + a.cx, a.cout)) return hipErrorInvalidValue;
   const long P = (long)a.B * a.H * a.W;
   if (P > 0x7fffffffL) return hipErrorInvalidValue;  // pixel indices are divided in 32 bits
+  int mt, nt;
+  if (ks == 3 && wgrad3_tile(a.W, a.H, a.cout, a.cu + a.cx, mt, nt)) {
+    const int cin = a.cu + a.cx;
+    const int tiles = ((a.cout + 16 * mt - 1) / (16 * mt)) * ((cin + 16 * nt - 1) / (16 * nt));
+    return wgrad3_dispatch(mt, nt, a, dz, part, n_split, wgrad3_steps_per_wg(a.B, a.H, a.W, tiles), s);
+  }
   long chunk = (P + n_split - 1) / n_split;
   chunk = (chunk + kWgK - 1) / kWgK * kWgK;
   const int cin = a.cu + a.cx;
