@@ -286,6 +286,10 @@ template <int KS, int EPI, bool RELU>
 hipError_t conv_tile(const NnConv& a, hipStream_t s) {
   if constexpr (KS == 3) {
     if (conv_lds_ok(a)) {
+      // decoder input gradients (80 and 112 channels at the default widths) in one tile, so the
+      // staged halo serves every output channel
+      if (a.cout == 80) return conv_lds<5, EPI, RELU>(a, s);
+      if (a.cout == 112) return conv_lds<7, EPI, RELU>(a, s);
       if (a.cout % 64 == 0) return conv_lds<4, EPI, RELU>(a, s);
       if (a.cout % 48 == 0) return conv_lds<3, EPI, RELU>(a, s);
       if (a.cout % 32 == 0) return conv_lds<2, EPI, RELU>(a, s);

@@ -53,6 +53,11 @@ CONV_CASES = [  # k, batch, h, w, cin, cout
     (3, 1, 4, 64, 16, 16),
     (3, 2, 6, 64, 32, 32),
     (3, 2, 12, 12, 32, 32),
+    # weight gradient: widths 8..128 (powers of two) whose rows fill 128-pixel steps take the
+    # nine-tap kernel (here W = 32 with 16 outputs: one output block, four input blocks); H = 6
+    # does not fill the steps and takes the per-tap kernel
+    (3, 1, 8, 32, 64, 16),
+    (3, 1, 6, 32, 32, 32),
     (3, 1, 8, 8, 48, 48),
     (3, 2, 16, 16, 64, 96),
     (3, 3, 5, 7, 16, 128),
