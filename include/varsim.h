@@ -310,8 +310,8 @@ VARSIM_API varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size
  * path off.  Both paths compute the same iterates. */
 VARSIM_API varsim_status varsim_set_small_path(varsim_ctx* ctx, int32_t max_n);
 /* Testing / manual tuning: every later column pass (solves and varsim_conv) uses strip-width
- * candidate `variant` (0 = default, 1 = double width with two column pairs per transform group,
- * 2 = half width), and transient solves use row-pass candidate `variant` (rows per workgroup:
+ * candidate `variant` (0 = default strip width, 1 = default width with two column pairs per
+ * transform group, 2 = half width), and transient solves use row-pass candidate `variant` (rows per workgroup:
  * default, half, one pair) and column candidate `variant` (default, half, quarter width);
  * -1 returns to the default or tuned choices. */
 VARSIM_API varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t variant);

@@ -335,7 +335,9 @@ varsim_status col_variant_for(varsim_ctx* ctx, const PassArgs& group, int comput
   for (int v = 0; v < kColVariants; ++v) {
     int dup = -1;
     for (int u = 0; u < v; ++u)
-      if (col_pass_columns(compute, a.n, u) == col_pass_columns(compute, a.n, v)) dup = u;
+      if (col_pass_columns(compute, a.n, u) == col_pass_columns(compute, a.n, v) &&
+          col_pass_pairs(compute, a.n, u) == col_pass_pairs(compute, a.n, v))
+        dup = u;
     if (dup >= 0) {
       ms[v] = ms[dup];
       continue;
@@ -929,7 +931,8 @@ varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
     out += line;
     const auto& ms = ctx->col_ms[kv.first];
     for (int v = 0; v < (int)ms.size(); ++v) {
-      snprintf(line, sizeof line, " %d cols %.4f ms%s", col_pass_columns(c, n, v), ms[v], v == kv.second ? "*" : "");
+      snprintf(line, sizeof line, " %d cols x%d %.4f ms%s", col_pass_columns(c, n, v), col_pass_pairs(c, n, v), ms[v],
+               v == kv.second ? "*" : "");
       out += line;
     }
     out += "\n";

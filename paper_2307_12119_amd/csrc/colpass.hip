@@ -53,28 +53,12 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
   int f = threadIdx.x / TPF;
   if constexpr (TPF == 64) f = __builtin_amdgcn_readfirstlane(f);
   const int t = threadIdx.x % TPF;
-  Tc zr[NP][E], zi[NP][E];
-#pragma unroll
-  for (int q = 0; q < NP; ++q)
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int y = tile_slot<Cfg, N>(t + TPF * m);
-      const int c = 2 * (f + Cfg::FFTS * q);
-      zr[q][m] = lds[y * P + c];
-      zi[q][m] = lds[y * P + c + 1];
-    }
-  __syncthreads();
-
-  Tc* re = lds + f * ST;  // all real parts first, then all imaginary parts
-  Tc* im = lds + Cfg::FFTS * ST + f * ST;
-#pragma unroll
-  for (int q = 0; q < NP; ++q) {
-    if (q > 0) wave_sync();
-    fft_reg<Tc, N, -1>(zr[q], zi[q], re, im, tw, t);
+  // split, multiply by lambda and merge in one step (coefficients alpha, beta, gamma per column)
+  auto spectral = [&](Tc* zr, Tc* zi, int q, Tc* re, Tc* im) {
+    fft_reg<Tc, N, -1>(zr, zi, re, im, tw, t);
     Tc pr[E], pim[E];
-    partner<Tc, N, true>(zr[q], pr, t);
-    partner<Tc, N, true>(zi[q], pim, t);
-    // split, multiply by lambda and merge in one step (coefficients alpha, beta, gamma per column)
+    partner<Tc, N, true>(zr, pr, t);
+    partner<Tc, N, true>(zi, pim, t);
     const Vec<Tc, 4>* ca = reinterpret_cast<const Vec<Tc, 4>*>(coef) + (long)(c0 + 2 * (f + Cfg::FFTS * q)) * (N / 2 + 1);
     const Vec<Tc, 4>* cb = ca + (N / 2 + 1);
 #pragma unroll
@@ -82,23 +66,67 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
       const int p = t + TPF * m;
       const bool hi = m >= E / 2;  // p >= N/2: stored at N - p with beta negated
       const int pi = hi ? N - p : p;
-      lambda_pair<Tc>(ca[pi], cb[pi], hi, zr[q][m], zi[q][m], pr[m], pim[m]);
+      lambda_pair<Tc>(ca[pi], cb[pi], hi, zr[m], zi[m], pr[m], pim[m]);
     }
     wave_sync();
-    fft_reg<Tc, N, +1>(zr[q], zi[q], re, im, tw, t);
-  }
-  __syncthreads();
+    fft_reg<Tc, N, +1>(zr, zi, re, im, tw, t);
+  };
+  if constexpr (Cfg::LAZY) {
+    Tc* re = lds + Cfg::TILE + f * ST;  // scratch after the tile: real parts, then imaginary parts
+    Tc* im = lds + Cfg::TILE + Cfg::FFTS * ST + f * ST;
+#pragma unroll 1
+    for (int q = 0; q < NP; ++q) {
+      const int c = 2 * (f + Cfg::FFTS * q);
+      Tc zr[E], zi[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int y = tile_slot<Cfg, N>(t + TPF * m);
+        zr[m] = lds[y * P + c];
+        zi[m] = lds[y * P + c + 1];
+      }
+      if (q > 0) wave_sync();  // the previous pair's scratch reads are done
+      spectral(zr, zi, q, re, im);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int y = tile_slot<Cfg, N>(t + TPF * m);
+        lds[y * P + c] = zr[m];
+        lds[y * P + c + 1] = zi[m];
+      }
+    }
+    __syncthreads();
+  } else {
+    Tc zr[NP][E], zi[NP][E];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int y = tile_slot<Cfg, N>(t + TPF * m);
+        const int c = 2 * (f + Cfg::FFTS * q);
+        zr[q][m] = lds[y * P + c];
+        zi[q][m] = lds[y * P + c + 1];
+      }
+    __syncthreads();
+
+    Tc* re = lds + f * ST;  // all real parts first, then all imaginary parts
+    Tc* im = lds + Cfg::FFTS * ST + f * ST;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      if (q > 0) wave_sync();
+      spectral(zr[q], zi[q], q, re, im);
+    }
+    __syncthreads();
 
 #pragma unroll
-  for (int q = 0; q < NP; ++q)
+    for (int q = 0; q < NP; ++q)
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int y = tile_slot<Cfg, N>(t + TPF * m);
-      const int c = 2 * (f + Cfg::FFTS * q);
-      lds[y * P + c] = zr[q][m];
-      lds[y * P + c + 1] = zi[q][m];
-    }
-  __syncthreads();
+      for (int m = 0; m < E; ++m) {
+        const int y = tile_slot<Cfg, N>(t + TPF * m);
+        const int c = 2 * (f + Cfg::FFTS * q);
+        lds[y * P + c] = zr[q][m];
+        lds[y * P + c + 1] = zi[q][m];
+      }
+    __syncthreads();
+  }
 
 #pragma unroll
   for (int k = 0; k < Cfg::LOADS; ++k) {
@@ -111,12 +139,13 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
   }
 }
 
-// Strip-width candidates: 0 = the default width, 1 = twice as wide with two column pairs per
-// transform group (128-byte row segments at N >= 512), 2 = half the default width.
+// Strip-width candidates: 0 = the default width, 1 = the default width with two column pairs
+// per transform group (half the wavefronts, each taking its pairs from the tile in turn), 2 =
+// half the default width.
 template <typename Tc, int N, int V>
 constexpr int col_candidate() {
   constexpr int c0 = ColCfg<Tc, N>::COLS;
-  constexpr int c = V == 0 ? c0 : (V == 1 ? 2 * c0 : c0 / 2);
+  constexpr int c = V == 2 ? c0 / 2 : c0;
   return c < 2 ? 2 : (c > N ? N : c);
 }
 template <int V>
@@ -161,12 +190,34 @@ template <typename Tc, int N>
 int col_cols_of(int v) {
   return v == 0 ? col_candidate<Tc, N, 0>() : (v == 1 ? col_candidate<Tc, N, 1>() : col_candidate<Tc, N, 2>());
 }
+template <typename Tc, int N, int V>
+constexpr int col_pairs_eff() {
+  return ColCfg<Tc, N, col_candidate<Tc, N, V>(), col_pairs<V>()>::PAIRS;
+}
+template <typename Tc, int N>
+int col_pairs_of(int v) {
+  return v == 0 ? col_pairs_eff<Tc, N, 0>() : (v == 1 ? col_pairs_eff<Tc, N, 1>() : col_pairs_eff<Tc, N, 2>());
+}
 
 }  // namespace
 
 hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream, int variant) {
   if (compute == VARSIM_F32) return col_dispatch_n<float>(variant, a, (const float*)coef, a.tw.tw32, a.tw.qw32, stream);
   return col_dispatch_n<double>(variant, a, (const double*)coef, a.tw.tw64, a.tw.qw64, stream);
+}
+
+int col_pass_pairs(int compute, int n, int variant) {
+  const bool f = compute == VARSIM_F32;
+  switch (n) {
+    case 16: return f ? col_pairs_of<float, 16>(variant) : col_pairs_of<double, 16>(variant);
+    case 32: return f ? col_pairs_of<float, 32>(variant) : col_pairs_of<double, 32>(variant);
+    case 64: return f ? col_pairs_of<float, 64>(variant) : col_pairs_of<double, 64>(variant);
+    case 128: return f ? col_pairs_of<float, 128>(variant) : col_pairs_of<double, 128>(variant);
+    case 256: return f ? col_pairs_of<float, 256>(variant) : col_pairs_of<double, 256>(variant);
+    case 512: return f ? col_pairs_of<float, 512>(variant) : col_pairs_of<double, 512>(variant);
+    case 1024: return f ? col_pairs_of<float, 1024>(variant) : col_pairs_of<double, 1024>(variant);
+    default: return 0;
+  }
 }
 
 int col_pass_columns(int compute, int n, int variant) {

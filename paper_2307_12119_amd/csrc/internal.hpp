@@ -53,12 +53,13 @@ struct PassArgs {
 
 // io: element type of the maps (VARSIM_F32 / VARSIM_F64); compute: type of the transforms.
 hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hipStream_t stream);
-// coef: the column-pass coefficient table of the compute type; variant: strip-width candidate
-// 0 (default), 1 (double width, two column pairs per transform group), 2 (half), see
-// col_pass_columns
+// coef: the column-pass coefficient table of the compute type; variant: launch-shape candidate
+// 0 (default strip width), 1 (default width, two column pairs per transform group), 2 (half
+// width); col_pass_columns / col_pass_pairs give a candidate's strip width and pairs per group
 constexpr int kColVariants = 3;
 hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream, int variant = 0);
 int col_pass_columns(int compute, int n, int variant);
+int col_pass_pairs(int compute, int n, int variant);
 
 // Static inputs: QL = q_leak0 * v, MINV = 1 / m (per map), warm-start screening and copy.
 struct PrepArgs {

@@ -56,7 +56,10 @@ struct ColCfg {
   static constexpr int PITCH = SLOT ? COLS + 1 : (sizeof(Tc) == 4 ? COLS + 3 : COLS + 1);
   static constexpr int TILE = N * PITCH;
   static constexpr int SCRATCH = FFTS * 2 * Shape<N>::STRIDE;
-  static constexpr int LDS = TILE > SCRATCH ? TILE : SCRATCH;
+  // several column pairs per transform group: the transform scratch follows the tile, so each
+  // pair is read from the tile only when its turn comes (one pair's values in registers)
+  static constexpr bool LAZY = PAIRS > 1;
+  static constexpr int LDS = LAZY ? TILE + SCRATCH : (TILE > SCRATCH ? TILE : SCRATCH);
   // row-segment vectors each thread moves per tile
   static constexpr int LOADS = N * (COLS / VEC) / THREADS;
 };
