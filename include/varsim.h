@@ -330,8 +330,10 @@ VARSIM_API varsim_status varsim_force_transient_variant(varsim_ctx* ctx, int32_t
 /* ----------------------------------------------------------------------------------------
  * Kernel timing.  When enabled, every kernel launch of the solves is bracketed by HIP events
  * on the launch stream; varsim_kernel_times reports, per kernel class, the launch count and
- * the summed durations (ms) since the last reset.  Class names are returned in names[i]
- * (static strings).  n_io: in = capacity, out = number of classes written.
+ * the summed durations (ms) since the last reset.  The events are read when varsim_kernel_times
+ * or varsim_reset_timing is called (both wait for the launches recorded so far), not at the end
+ * of each solve, so timing adds no host time between calls.  Class names are returned in
+ * names[i] (static strings).  n_io: in = capacity, out = number of classes written.
  */
 VARSIM_API varsim_status varsim_set_timing(varsim_ctx* ctx, int32_t enable);
 VARSIM_API varsim_status varsim_kernel_times(varsim_ctx* ctx, const char** names, int64_t* counts,

@@ -443,7 +443,7 @@ varsim_status varsim_green_table(varsim_ctx* ctx, const varsim_geometry* geom, v
     HIP_TRY(hipMemcpyAsync(kernel_out, e.kper, (size_t)(geom->nx + 1) * (geom->ny + 1) * sizeof(double),
                            hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  flush_timing(ctx);
+  settle_timing(ctx);
   return VARSIM_OK;
 }
 
@@ -489,7 +489,7 @@ varsim_status varsim_conv(varsim_ctx* ctx, const varsim_geometry* geom, int32_t 
   }));
   HIP_TRY(timed(ctx, "row_conv_tail", s, [&] { return launch_row_pass(ROW_CONV_TAIL, precision, precision, a, s); }));
   HIP_TRY(hipStreamSynchronize(s));
-  flush_timing(ctx);
+  settle_timing(ctx);
   return VARSIM_OK;
 }
 
@@ -692,7 +692,7 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
   ctx->h_stats.resize(n);
   HIP_TRY(hipMemcpyAsync(ctx->h_stats.data(), d_stats, n * sizeof(varsim_stats), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  flush_timing(ctx);
+  settle_timing(ctx);
   int worst = VARSIM_OK;
   for (int i = 0; i < n; ++i) {
     stats[order[i]] = ctx->h_stats[i];
@@ -804,7 +804,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   unsigned h_flags = 0;
   HIP_TRY(hipMemcpyAsync(&h_flags, d_flags, sizeof h_flags, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  flush_timing(ctx);
+  settle_timing(ctx);
   if (h_flags & kFlagInvalid) {
     varsim_stats bad{};
     bad.status = VARSIM_ERR_INVALID;
@@ -883,7 +883,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   HIP_TRY(launch_map_stats(io, problem->dT_out, cells, d_flags, tr->n_steps, d_stats, s));
   HIP_TRY(hipMemcpyAsync(stats, d_stats, sizeof(varsim_stats), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  flush_timing(ctx);
+  settle_timing(ctx);
   if (stats->status != VARSIM_OK)
     return fail(ctx, (varsim_status)stats->status, "transient: %s", varsim_status_string((varsim_status)stats->status));
   return VARSIM_OK;
@@ -966,6 +966,7 @@ varsim_status varsim_set_timing(varsim_ctx* ctx, int32_t enable) {
 
 varsim_status varsim_reset_timing(varsim_ctx* ctx) {
   if (!ctx) return VARSIM_ERR_INVALID;
+  flush_timing(ctx);  // launches recorded before the reset do not count after it
   ctx->times.clear();
   ctx->class_names.clear();
   return VARSIM_OK;
@@ -974,6 +975,7 @@ varsim_status varsim_reset_timing(varsim_ctx* ctx) {
 varsim_status varsim_kernel_times(varsim_ctx* ctx, const char** names, int64_t* counts, double* total_ms,
                                   int32_t* n_io) {
   if (!ctx || !n_io) return VARSIM_ERR_INVALID;
+  flush_timing(ctx);  // waits for the recorded launches
   const int cap = *n_io;
   int k = 0;
   for (const char* nm : ctx->class_names) {

@@ -439,10 +439,7 @@ varsim_status varsim_net_forward(varsim_net* net, int32_t batch, const float* q_
   hipStream_t s = (hipStream_t)stream;
   const NetBufs b = plan(net, batch, false, (char*)workspace);
   st = run_forward(net, batch, q_dyn, leak_var, cond_map, sample_idx, dT_out, b, false, s);
-  if (ctx->timing && st == VARSIM_OK) {
-    HIP_TRY(hipStreamSynchronize(s));
-    flush_timing(ctx);
-  }
+  settle_timing(ctx);
   return st;
 }
 
@@ -459,10 +456,7 @@ varsim_status varsim_net_gradient(varsim_net* net, int32_t batch, const float* q
   const NetBufs b = plan(net, batch, true, (char*)workspace);
   if ((st = run_forward(net, batch, q_dyn, leak_var, cond_map, sample_idx, b.y, b, true, s)) != VARSIM_OK) return st;
   if ((st = run_gradient(net, batch, sample_idx, target, grad, loss, b, s)) != VARSIM_OK) return st;
-  if (ctx->timing) {
-    HIP_TRY(hipStreamSynchronize(s));
-    flush_timing(ctx);
-  }
+  settle_timing(ctx);
   return VARSIM_OK;
 }
 
