@@ -191,16 +191,23 @@ PointParams point_params(const varsim_geometry* g, const varsim_options* o) {
   //   (1 + u)^a - 1 = sum_k C(a, k) u^k, a = 1/(1 - eta);  exp(u) - 1 = sum_k u^k / k! (eta = 1).
   // The FP32 path uses it where the first dropped term is below 1e-9 of the leading one.
   pp.u_scale = eta == 1.0 ? 1.0 / g->t_amb_K : (1.0 - eta) / g->t_amb_K;
-  double c[kPoly + 1];
+  // The FP64 steady path uses it (more terms) where the first dropped term is below 1e-17.
+  double c[kPoly64 + 1];
   double ck = 1.0;
-  for (int k = 1; k <= kPoly + 1; ++k) {
+  for (int k = 1; k <= kPoly64 + 1; ++k) {
     ck = eta == 1.0 ? ck / k : ck * (pp.inv_1m_eta - (k - 1)) / k;
     c[k - 1] = ck;
   }
   for (int k = 0; k < kPoly; ++k) pp.polyf[k] = (float)c[k];
-  const double lead = std::fabs(c[0]), drop = std::fabs(c[kPoly]);
-  pp.poly_umax = drop > 0.0 ? std::min(0.1, std::pow(1e-9 * lead / drop, 1.0 / kPoly)) : 0.1;
-  if (eta == 0.0) pp.poly_umax = 0.0;
+  for (int k = 0; k < kPoly64; ++k) pp.polyd[k] = c[k];
+  const double lead = std::fabs(c[0]);
+  auto umax = [&](int K, double rel) {
+    const double drop = std::fabs(c[K]);
+    return drop > 0.0 ? std::min(0.1, std::pow(rel * lead / drop, 1.0 / K)) : 0.1;
+  };
+  pp.poly_umax = umax(kPoly, 1e-9);
+  pp.poly_umax64 = umax(kPoly64, 1e-17);
+  if (eta == 0.0) pp.poly_umax = pp.poly_umax64 = 0.0;
   return pp;
 }
 

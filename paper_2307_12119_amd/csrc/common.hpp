@@ -50,12 +50,17 @@ struct PointParams {
   int leak;           // VARSIM_LEAK_*
   int eta_mode;       // 0: eta == 0, 1: eta == 1, 2: general
   // Taylor coefficients of (1 + u)^(1/(1-eta)) - 1 = sum_k poly[k-1] u^k (k = 1..kPoly), used
-  // by the FP32 path for |u| <= poly_umax, u = (1 - eta) theta / T_amb; 0 disables it.
+  // by the FP32 path for |u| <= poly_umax, u = (1 - eta) theta / T_amb; 0 disables it.  The FP64
+  // steady path uses the first kPoly64 coefficients for |u| <= poly_umax64 (first dropped term
+  // below 1e-17 of the leading one).
   double u_scale;     // u = u_scale * theta: (1 - eta) / T_amb, or 1 / T_amb when eta == 1
   double poly_umax;
   float polyf[10];
+  double poly_umax64;
+  double polyd[20];
 };
 constexpr int kPoly = 10;
+constexpr int kPoly64 = 20;
 
 // Per-map iteration state in the workspace.
 struct IterState {

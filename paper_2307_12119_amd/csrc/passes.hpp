@@ -163,6 +163,14 @@ __device__ __forceinline__ Tc kirchhoff_inv(Tc theta, const PointParams& pp) {
     if (!(u > -1.f)) return NAN;
     return (float)pp.t_amb * (__expf((float)pp.inv_1m_eta * __logf(1.f + u)) - 1.f);
   } else {
+    // FP64: the same series to degree kPoly64 inside its range (about a tenth of the cost of
+    // log1p + expm1, which the compiler inlines per element), the library forms beyond it
+    if (fabs(u) <= pp.poly_umax64) {
+      double acc = pp.polyd[kPoly64 - 1];
+#pragma unroll
+      for (int k = kPoly64 - 2; k >= 0; --k) acc = fma(acc, u, pp.polyd[k]);
+      return pp.t_amb * u * acc;
+    }
     if (pp.eta_mode == 1) return (Tc)pp.t_amb * expm1(u);
     if (!(u > (Tc)-1)) return (Tc)NAN;
     return (Tc)pp.t_amb * expm1((Tc)pp.inv_1m_eta * log1p(u));
