@@ -210,8 +210,42 @@ def main() -> int:
     torch.cuda.synchronize()
     print(f"[bench] warm-up done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
-    ctx.reset_timing()
-    ctx.set_timing(not args.no_kernel_timing)
+    per_map = algorithmic_bytes(args.n)
+
+    def passes_of(it):
+        """map-passes per kernel class over steps with iteration counts `it` (steps x maps)"""
+        steps = it.shape[0]
+        return {"prep": args.batch * steps, "row_head": args.batch * steps,
+                "col": int(it.sum()), "row_merged": int(it.sum()), "row_last": 0,
+                "resid_head": args.batch * steps, "resid_col": args.batch * steps,
+                "resid_tail": args.batch * steps}
+
+    def kernel_table(ktimes, passes):
+        out = {}
+        for name, v in ktimes.items():
+            if name not in per_map:
+                continue
+            b = per_map[name] * passes[name]
+            out[name] = {"launches": v["count"], "avg_ms": v["total_ms"] / max(v["count"], 1),
+                         "total_ms": v["total_ms"],
+                         "GB/s": b / (v["total_ms"] * 1e-3) / 1e9 if v["total_ms"] else None}
+        return out
+
+    # one untimed-region step with every kernel class bracketed by events: the per-class table
+    # and the dominant class, which alone carries events during the timed steps
+    kernels, dom = {}, None
+    if not args.no_kernel_timing:
+        ctx.reset_timing()
+        ctx.set_timing_only(None)
+        ctx.set_timing(True)
+        st_all = ctx.solve_batch(batch, opts, ws)
+        torch.cuda.synchronize()
+        ctx.set_timing(False)
+        kernels = kernel_table(ctx.kernel_times(), passes_of(np.array([st_all["iterations"]])))
+        dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+        ctx.reset_timing()
+        ctx.set_timing_only(dom)
+        ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = []
@@ -222,30 +256,20 @@ def main() -> int:
     elapsed = time.perf_counter() - t0
     ctx.set_timing(False)
     ktimes = ctx.kernel_times()
+    ctx.set_timing_only(None)
     print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
     statuses = sorted({int(x) for x in stats["status"]})
     it = np.array(iters)
     maps_per_s = args.batch * args.steps / elapsed
-    per_map = algorithmic_bytes(args.n)
-    # map-passes per kernel class over the timed region
-    passes = {"prep": args.batch * args.steps, "row_head": args.batch * args.steps,
-              "col": int(it.sum()), "row_merged": int(it.sum()), "row_last": 0,
-              "resid_head": args.batch * args.steps, "resid_col": args.batch * args.steps,
-              "resid_tail": args.batch * args.steps}
+    passes = passes_of(it)
     if args.no_kernel_timing:
         print(json.dumps({"metric": METRIC, "value": round(maps_per_s, 2), "unit": "maps/s",
                           "ms_per_step": round(elapsed / args.steps * 1e3, 4), "kernel_timing": False,
                           "iterations_mean": float(it.mean())}))
         return 0
-    kernels = {}
-    for name, v in ktimes.items():
-        if name not in per_map:
-            continue
-        b = per_map[name] * passes[name]
-        kernels[name] = {"launches": v["count"], "avg_ms": v["total_ms"] / max(v["count"], 1),
-                         "total_ms": v["total_ms"], "GB/s": b / (v["total_ms"] * 1e-3) / 1e9 if v["total_ms"] else None}
-    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    # the dominant class over the timed steps (its events only)
+    kernels[dom] = kernel_table({dom: ktimes[dom]}, passes)[dom]
     dom_bytes_per_launch = per_map[dom] * passes[dom] / kernels[dom]["launches"]
     per_pass = measured_traffic(dom, args.n, args.batch)
     traffic = None if per_pass is None else int(per_pass * passes[dom] / kernels[dom]["launches"])
@@ -274,7 +298,10 @@ def main() -> int:
                      "bytes_per_launch": int(dom_bytes_per_launch), "avg_launch_ms": kernels[dom]["avg_ms"]},
         "solve": {"iterations_mean": float(it.mean()), "iterations_max": int(it.max()), "statuses": statuses,
                   "residual_f64_max_K": float(np.max(resid)),
-                  "effective_GBps_all_kernels": round(total_alg / elapsed / 1e9, 1), "kernels": kernels,
+                  "effective_GBps_all_kernels": round(total_alg / elapsed / 1e9, 1),
+                  "kernels_note": f"{dom}: timed steps; other classes: one step timed with every class "
+                                  "before the timed region",
+                  "kernels": kernels,
                   "autotune": ctx.autotune_report().strip().split("\n")},
         "surrogate": None,
     }

@@ -339,6 +339,10 @@ VARSIM_API varsim_status varsim_set_timing(varsim_ctx* ctx, int32_t enable);
 VARSIM_API varsim_status varsim_kernel_times(varsim_ctx* ctx, const char** names, int64_t* counts,
                                   double* total_ms, int32_t* n_io);
 VARSIM_API varsim_status varsim_reset_timing(varsim_ctx* ctx);
+/* Restricts timing to one kernel class (a name varsim_kernel_times reports, e.g. "row_merged"),
+ * so that a measurement of that class records two events per launch of it only; NULL or ""
+ * times every class again. */
+VARSIM_API varsim_status varsim_set_timing_only(varsim_ctx* ctx, const char* kernel_class);
 
 #ifdef __cplusplus
 }

@@ -968,6 +968,20 @@ varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
 varsim_status varsim_set_timing(varsim_ctx* ctx, int32_t enable) {
   if (!ctx) return VARSIM_ERR_INVALID;
   ctx->timing = enable != 0;
+  HIP_TRY(hipSetDevice(ctx->device));
+  // events for the launches to come are created now, not between a call's launches
+  constexpr size_t kEventStock = 4096;
+  while (ctx->timing && ctx->pool.size() + 2 * ctx->pending.size() < kEventStock) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return fail(ctx, VARSIM_ERR_DEVICE, "hipEventCreate failed");
+    ctx->pool.push_back(e);
+  }
+  return VARSIM_OK;
+}
+
+varsim_status varsim_set_timing_only(varsim_ctx* ctx, const char* kernel_class) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  ctx->timing_only = kernel_class ? kernel_class : "";
   return VARSIM_OK;
 }
 

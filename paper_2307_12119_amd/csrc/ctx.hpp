@@ -51,6 +51,7 @@ struct varsim_ctx {
   std::map<TableKey, TableEntry> tables;
   std::map<int, TwEntry> twiddles;
   bool timing = false;
+  std::string timing_only;  // non-empty: only this kernel class is timed
   std::vector<TimedEvent> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<long long, double>> times;
@@ -109,7 +110,7 @@ inline hipEvent_t take_event(varsim_ctx* c) {
 
 template <class F>
 hipError_t timed(varsim_ctx* c, const char* cls, hipStream_t s, F&& f) {
-  if (!c->timing) return f();
+  if (!c->timing || (!c->timing_only.empty() && c->timing_only != cls)) return f();
   hipEvent_t a = take_event(c), b = take_event(c);
   if (!a || !b) return hipErrorOutOfMemory;
   (void)hipEventRecord(a, s);

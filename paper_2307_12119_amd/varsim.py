@@ -109,6 +109,7 @@ EXPORTS = {
     "varsim_kernel_times": (c_int, [c_void_p, POINTER(c_char_p), POINTER(c_int64), POINTER(c_double),
                                     POINTER(c_int32)]),
     "varsim_reset_timing": (c_int, [c_void_p]),
+    "varsim_set_timing_only": (c_int, [c_void_p, c_char_p]),
 }
 
 
@@ -356,6 +357,10 @@ class Context:
 
     def reset_timing(self):
         self._check(self.lib.varsim_reset_timing(self.handle))
+
+    def set_timing_only(self, kernel_class: str | None):
+        """Time only `kernel_class` (None: every class)."""
+        self._check(self.lib.varsim_set_timing_only(self.handle, kernel_class.encode() if kernel_class else None))
 
     def kernel_times(self) -> dict:
         cap = 256
