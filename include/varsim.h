@@ -189,8 +189,12 @@ VARSIM_API varsim_status varsim_solve_steady(varsim_ctx* ctx, const varsim_probl
 /* ----------------------------------------------------------------------------------------
  * Batched steady solve (Monte Carlo over variation samples, Sec. I): n problems, possibly of
  * different grid sizes and possibly sharing input pointers, solved together; each problem
- * stops at its own convergence.  stats: host array of n entries.  Returns the worst status.
- * Synchronises `stream`.
+ * stops at its own convergence.  stats: an array of n entries, in host or device memory.
+ *   - Host memory: the call synchronises `stream`, fills stats and returns the worst status.
+ *   - Device memory (hipMalloc): the call returns once the last kernels are enqueued (it still
+ *     follows the convergence loop on the host); stats is written on `stream`, in the caller's
+ *     order, and the return value reports only argument and device errors, not the per-problem
+ *     statuses.  The workspace must not be reused by another stream before that point.
  */
 VARSIM_API varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
                                  const varsim_options* opts, void* workspace, size_t ws_bytes,

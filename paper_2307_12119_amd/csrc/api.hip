@@ -118,12 +118,22 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 struct Layout {
   int stride = 0;
   size_t resid = 0, sum = 0, maxpack = 0, flags = 0, resid64 = 0, state_end = 0;
-  size_t stats = 0, maps = 0, prep = 0;
+  size_t stats = 0, maps = 0, prep = 0, order = 0;
   std::vector<size_t> S, QL, MINV, S64;
   size_t total = 0;
 };
 
 size_t esize(int precision) { return precision == VARSIM_F64 ? 8 : 4; }
+
+// true for memory the device owns (hipMalloc / torch tensors), false for host memory
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();  // plain host memory is reported as an error; do not leave it behind
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice;
+}
 
 Layout make_layout(const std::vector<const varsim_problem*>& probs, const varsim_options* o) {
   Layout L;
@@ -147,6 +157,8 @@ Layout make_layout(const std::vector<const varsim_problem*>& probs, const varsim
   off = align_up(off + n * sizeof(MapPtrs));
   L.prep = off;
   off = align_up(off + n * sizeof(PrepArgs));
+  L.order = off;
+  off = align_up(off + n * sizeof(int));
   const size_t es = esize(o->precision);
   for (const varsim_problem* p : probs) {
     const size_t cells = (size_t)p->geom->nx * p->geom->ny;
@@ -549,6 +561,8 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
   base.stride = L.stride;
   MapPtrs* d_maps = (MapPtrs*)(ws + L.maps);
   PrepArgs* d_prep = (PrepArgs*)(ws + L.prep);
+  int* d_order = (int*)(ws + L.order);
+  const bool dev_stats = is_device_ptr(stats);
   varsim_stats* d_stats = (varsim_stats*)(ws + L.stats);
   const int io = opts->precision;
   const bool want_res = opts->final_f64_residual != 0;
@@ -582,6 +596,10 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
   HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(ws, L.state_end, s); }));
   HIP_TRY(hipMemcpyAsync(d_maps, ctx->h_maps.data(), n * sizeof(MapPtrs), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(d_prep, ctx->h_prep.data(), n * sizeof(PrepArgs), hipMemcpyHostToDevice, s));
+  if (dev_stats) {
+    ctx->h_order = order;
+    HIP_TRY(hipMemcpyAsync(d_order, ctx->h_order.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  }
 
   auto group_args = [&](const Group& g, int iter) {
     PassArgs a{};
@@ -695,6 +713,11 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
     PassArgs a = group_args(g, 0);
     HIP_TRY(launch_finalize(a.st, d_maps + g.first, g.count, io, (long)g.geom->nx * g.geom->ny, opts->max_iter,
                             iters_run, opts->tol_K, want_res ? 1 : 0, d_stats + g.first, s));
+  }
+  if (dev_stats) {  // statistics stay on the device, in the caller's order; no synchronisation
+    HIP_TRY(launch_scatter_stats(d_stats, d_order, n, stats, s));
+    settle_timing(ctx);
+    return VARSIM_OK;
   }
   ctx->h_stats.resize(n);
   HIP_TRY(hipMemcpyAsync(ctx->h_stats.data(), d_stats, n * sizeof(varsim_stats), hipMemcpyDeviceToHost, s));

@@ -63,6 +63,7 @@ struct varsim_ctx {
   std::vector<MapPtrs> h_maps;
   std::vector<PrepArgs> h_prep;
   std::vector<varsim_stats> h_stats;
+  std::vector<int> h_order;  // caller index of each sorted problem (device-side statistics)
   MapPtrs* conv_maps = nullptr;
   size_t conv_maps_cap = 0;
   // column-pass strip width chosen by timing, per (n, compute type, log2 of the group size)

@@ -339,6 +339,19 @@ hipError_t launch_count_active(const IterState& st, int n_maps, int iter, double
   return hipGetLastError();
 }
 
+namespace {
+__global__ void scatter_stats_kernel(const varsim_stats* __restrict__ src, const int* __restrict__ order, int n,
+                                     varsim_stats* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[order[i]] = src[i];
+}
+}  // namespace
+
+hipError_t launch_scatter_stats(const varsim_stats* src, const int* order, int n, varsim_stats* dst, hipStream_t s) {
+  hipLaunchKernelGGL(scatter_stats_kernel, dim3((n + 127) / 128), dim3(128), 0, s, src, order, n, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, long cells, int max_iter,
                            int iters_run, double tol, int residual_done, varsim_stats* out, hipStream_t stream) {
   if (io == VARSIM_F32)

@@ -261,10 +261,13 @@ class Context:
         return self._ws_query(probs, len(items), opts)
 
     def solve_batch(self, items, opts: Options, workspace=None, raise_on=(ERR_INVALID,
-                    ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY)):
+                    ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY), stats_out=None):
         """Solve every problem (dicts of device tensors: die, q_dyn, dT_out, optional q_leak0,
         leak_var, cond_map, dT_init); returns per-problem stats dicts.  Given a PreparedBatch,
-        returns the stats as a numpy structured array (one record per problem)."""
+        returns the stats as a numpy structured array (one record per problem).  With stats_out
+        (a device tensor of at least n * sizeof(Stats) bytes) the statistics are written there on
+        the current stream and the call returns without synchronising (None); read them with
+        stats_from_bytes."""
         import numpy as np
         import torch
 
@@ -279,6 +282,14 @@ class Context:
             need = self._ws_query(probs, n, opts)
         if workspace is None or workspace.numel() < need:
             workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=torch.device("cuda", self.device))
+        if stats_out is not None:
+            if not stats_out.is_cuda or stats_out.numel() * stats_out.element_size() < n * ctypes.sizeof(Stats):
+                raise ValueError("stats_out must be a device tensor of n * sizeof(Stats) bytes")
+            st = self.lib.varsim_solve_batch(self.handle, probs, n, ctypes.byref(opts), _ptr(workspace),
+                                             workspace.numel(), ctypes.cast(_ptr(stats_out), POINTER(Stats)),
+                                             _stream())
+            self._check(st)
+            return None
         arr = np.ctypeslib.as_array(stats)
         arr["status"] = -1
         st = self.lib.varsim_solve_batch(self.handle, probs, n, ctypes.byref(opts), _ptr(workspace),
@@ -370,6 +381,16 @@ class Context:
         n = c_int32(cap)
         self._check(self.lib.varsim_kernel_times(self.handle, names, counts, tot, ctypes.byref(n)))
         return {names[i].decode(): {"count": counts[i], "total_ms": tot[i]} for i in range(n.value)}
+
+
+def stats_from_bytes(buf, n: int):
+    """Per-problem statistics written by solve_batch(stats_out=...) (a tensor or bytes) as a
+    numpy structured array."""
+    import numpy as np
+
+    raw = bytes(buf.cpu().numpy().tobytes()) if hasattr(buf, "cpu") else bytes(buf)
+    arr = (Stats * n).from_buffer_copy(raw[:n * ctypes.sizeof(Stats)])
+    return np.ctypeslib.as_array(arr).copy()
 
 
 class PreparedBatch:

@@ -226,6 +226,30 @@ def test_batch_mixed_sizes_equal_single_solves(ctx):
         assert torch.equal(item["dT_out"], single["dT_out"])
 
 
+def test_batch_device_stats_equal_host_stats(ctx):
+    """Statistics written to a device array (the call returns after enqueue) equal the host
+    array's, in the caller's order, with bitwise equal maps; sizes above the small-grid limit
+    take the two-pass loop with the FP64 residual."""
+    import ctypes
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    inps = [W.steady_problem(3, n, 16, floorplan=i, sample=i) for i, n in enumerate([256, 16, 128, 256, 64])]
+    opts = _opts(V.F32, inps[0], 50, 1e-3, res=True)
+    host_items = [gpu_item(i, torch.float32) for i in inps]
+    host = ctx.solve_batch(host_items, opts)
+    dev_items = [gpu_item(i, torch.float32) for i in inps]
+    buf = torch.full((len(inps) * ctypes.sizeof(V.Stats),), 255, dtype=torch.uint8, device="cuda")
+    assert ctx.solve_batch(dev_items, opts, stats_out=buf) is None
+    torch.cuda.synchronize()
+    got = V.stats_from_bytes(buf, len(inps))
+    for h, g, a, b in zip(host, got, host_items, dev_items):
+        assert h["status"] == V.OK
+        for k, v in h.items():
+            assert g[k] == v or (v != v and g[k] != g[k]), k
+        assert torch.equal(a["dT_out"], b["dT_out"])
+
+
 # ----------------------------------------------------------------------------- statuses
 def test_not_converged_invalid_and_runaway(ctx):
     import torch
