@@ -15,6 +15,7 @@ struct NetLayer {
   int ks = 1, cin_src = 0, cin = 0, cout = 0;  // cin: padded input channels the kernels use
   long w_off = 0, b_off = 0;                   // offsets in the flat FP32 parameters
   size_t wb = 0, wt = 0;                       // element offsets of the BF16 copies (forward, transposed)
+  int wblk = 0;                                // BF16 copies in the blocked layout (see w_index)
 };
 
 size_t up256(size_t b) { return (b + 255) / 256 * 256; }
@@ -117,7 +118,12 @@ void build_layers(varsim_net* net) {
   const int* w = net->cfg.width;
   long off = 0;
   size_t bo = 0;
-  auto add = [&](NetLayer& L, int ks, int cin_src, int cin, int cout) {
+  // 3x3 layers whose convolutions gather their operands from global memory (maps narrower than
+  // the LDS-staged kernel's 64 columns) keep their weights blocked: the A operands of a step are
+  // then one contiguous kilobyte.  The LDS-staged kernel measured faster with rows.
+  auto add = [&](NetLayer& L, int ks, int cin_src, int cin, int cout, int level) {
+    const int m = (net->cfg.n / 4) >> level;
+    L.wblk = ks == 3 && !nn_conv_staged(ks, m, m) ? 1 : 0;
     L.ks = ks, L.cin_src = cin_src, L.cin = cin, L.cout = cout;
     L.w_off = off;
     off += (long)cout * ks * ks * cin_src;
@@ -129,14 +135,14 @@ void build_layers(varsim_net* net) {
     L.wt = bo;
     bo += (e + 127) / 128 * 128;
   };
-  add(net->stem, 1, 48, 64, w[0]);
+  add(net->stem, 1, 48, 64, w[0], 0);
   for (int l = 0; l < 5; ++l) {
     const int cin = l == 0 ? w[0] : w[l - 1];
-    add(net->enc[l][0], 3, cin, cin, w[l]);
-    add(net->enc[l][1], 3, w[l], w[l], w[l]);
+    add(net->enc[l][0], 3, cin, cin, w[l], l);
+    add(net->enc[l][1], 3, w[l], w[l], w[l], l);
   }
-  for (int l = 3; l >= 0; --l) add(net->dec[l], 3, w[l + 1] + w[l], w[l + 1] + w[l], w[l]);
-  add(net->head, 1, w[0], w[0], 16);
+  for (int l = 3; l >= 0; --l) add(net->dec[l], 3, w[l + 1] + w[l], w[l + 1] + w[l], w[l], l);
+  add(net->head, 1, w[0], w[0], 16, 0);
   net->count = off;
   net->wbf_elems = bo;
 }
@@ -153,7 +159,8 @@ hipError_t refresh_bf16(varsim_net* net, hipStream_t s) {
   hipError_t e = hipSuccess;
   for_layers(net, [&](const NetLayer& L) {
     if (e != hipSuccess) return;
-    e = nn_weight_cast(net->p + L.w_off, L.cout, L.ks * L.ks, L.cin_src, L.cin, net->wbf + L.wb, net->wbf + L.wt, s);
+    e = nn_weight_cast(net->p + L.w_off, L.cout, L.ks * L.ks, L.cin_src, L.cin, net->wbf + L.wb, net->wbf + L.wt, s,
+                       L.wblk);
   });
   return e;
 }
@@ -163,6 +170,7 @@ NnConv conv_args(const varsim_net* net, const NetLayer& L, const uint16_t* x, in
   NnConv a{};
   a.x = x, a.cx = cx, a.xu = xu, a.cu = cu;
   a.w = net->wbf + L.wb;
+  a.wblk = L.wblk;
   a.bias = with_bias ? net->p + L.b_off : nullptr;
   a.y = y;
   a.B = B, a.H = a.W = level_size(net, l);
@@ -176,6 +184,7 @@ NnConv dgrad_args(const varsim_net* net, const NetLayer& L, const uint16_t* dz, 
   NnConv a{};
   a.x = dz, a.cx = L.cout;
   a.w = net->wbf + L.wt;
+  a.wblk = L.wblk;
   a.y = out;
   a.B = B, a.H = a.W = level_size(net, l);
   a.cout = L.cin;

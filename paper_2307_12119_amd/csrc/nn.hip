@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(256) conv_kernel(NnConv a) {
 #pragma unroll
       for (int i = 0; i < MW; ++i) {
         const int co = co0 + i * 16 + lr;
-        av[i] = kv ? ld16(a.w + ((long)co * TAPS + tap) * cin + ci) : z4;
+        av[i] = kv ? ld16(a.w + w_index(a.wblk, co, tap, ci, TAPS, cin)) : z4;
       }
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
@@ -263,8 +263,9 @@ __global__ void __launch_bounds__(256) conv3_lds_kernel(NnConv a) {
   conv_epilogue<MW, NW, EPI, RELU>(a, acc, pb, py, px, pv, lr, lg, co0);
 }
 
+// (the staged kernel reads weights in rows)
 inline bool conv_lds_ok(const NnConv& a) {
-  return a.W % kLdsCols == 0 && a.H % kLdsRows == 0 && conv_lds_bytes(a.cu, a.cx) <= 65536;
+  return !a.wblk && a.W % kLdsCols == 0 && a.H % kLdsRows == 0 && conv_lds_bytes(a.cu, a.cx) <= 65536;
 }
 
 template <int MW, int EPI, bool RELU>
@@ -881,15 +882,15 @@ __device__ __forceinline__ uint16_t to_bf(uint16_t x) { return x; }
 template <typename S>
 __global__ void __launch_bounds__(256) weight_cast_kernel(const S* __restrict__ src, int cout, int taps, int cin_src,
                                                           int cin_pad, uint16_t* __restrict__ dst,
-                                                          uint16_t* __restrict__ dstT) {
+                                                          uint16_t* __restrict__ dstT, int blocked) {
   const long n = (long)cout * taps * cin_pad;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const int ci = (int)(i % cin_pad);
     const long rt = i / cin_pad;
     const int tap = (int)(rt % taps), co = (int)(rt / taps);
     const uint16_t h = ci < cin_src ? to_bf(src[rt * cin_src + ci]) : (uint16_t)0;
-    if (dst) dst[i] = h;
-    if (dstT) dstT[((long)ci * taps + (taps - 1 - tap)) * cout + co] = h;
+    if (dst) dst[w_index(blocked, co, tap, ci, taps, cin_pad)] = h;
+    if (dstT) dstT[w_index(blocked, ci, taps - 1 - tap, co, taps, cout)] = h;
   }
 }
 
@@ -899,6 +900,11 @@ unsigned blocks_for(long n, int per_thread = 1, unsigned cap = 4096) {
 }
 
 }  // namespace
+
+bool nn_conv_staged(int ks, int H, int W) {
+  // phases of at most 64 channels keep the staged halo within 64 KB for any channel count
+  return ks == 3 && W % kLdsCols == 0 && H % kLdsRows == 0;
+}
 
 hipError_t nn_conv(int ks, int epi, bool relu, const NnConv& a, hipStream_t s) {
   if ((a.cu % 16) || (a.cx % 16) || a.cu + a.cx <= 0 || (a.cout % 16) || a.cout <= 0 || a.B <= 0 || a.H <= 0 ||
@@ -1053,10 +1059,11 @@ hipError_t nn_adam(float* p, float* m, float* v, const float* g, long n, float l
 }
 
 hipError_t nn_weight_cast(const float* src, int cout, int taps, int cin_src, int cin_pad, uint16_t* dst,
-                          uint16_t* dstT, hipStream_t s) {
+                          uint16_t* dstT, hipStream_t s, int blocked) {
+  if (blocked && ((cout % 16) || (cin_pad % 16))) return hipErrorInvalidValue;
   const long n = (long)cout * taps * cin_pad;
   hipLaunchKernelGGL(weight_cast_kernel<float>, dim3(blocks_for(n)), dim3(256), 0, s, src, cout, taps, cin_src, cin_pad,
-                     dst, dstT);
+                     dst, dstT, blocked);
   return hipGetLastError();
 }
 
@@ -1064,7 +1071,7 @@ hipError_t nn_weight_cast_bf16(const uint16_t* src, int cout, int taps, int cin_
                                uint16_t* dstT, hipStream_t s) {
   const long n = (long)cout * taps * cin_pad;
   hipLaunchKernelGGL(weight_cast_kernel<uint16_t>, dim3(blocks_for(n)), dim3(256), 0, s, src, cout, taps, cin_src,
-                     cin_pad, dst, dstT);
+                     cin_pad, dst, dstT, 0);
   return hipGetLastError();
 }
 

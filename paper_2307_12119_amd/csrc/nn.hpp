@@ -14,7 +14,8 @@ struct NnConv {
   const uint16_t* x;
   const uint16_t* xu;
   int cu, cx;
-  const uint16_t* w;
+  const uint16_t* w;  // [cout][k*k][cin] rows, or the blocked layout when wblk (see w_index)
+  int wblk;           // 1: w is blocked (cout and cin multiples of 16 and 8)
   const float* bias;  // [cout] or null
   void* y;            // output, see NnEpi
   int B, H, W, cout;
@@ -33,6 +34,8 @@ enum NnEpi : int {
 
 
 hipError_t nn_conv(int ks, int epi, bool relu, const NnConv& a, hipStream_t s);
+// true when a ks x ks convolution on H x W maps takes the LDS-staged kernel
+bool nn_conv_staged(int ks, int H, int W);
 
 // Weight gradient: part[s][cout][ks*ks][cin] = sum over pixel chunk s of dz (x) shifted input.
 // n_split must be nn_wgrad_splits(ks, B, H, W, cu + cx, cout), the number of chunks of the
@@ -76,11 +79,20 @@ hipError_t nn_mse_grad(const float* y, const float* t, const int* idx, int n, in
 
 hipError_t nn_adam(float* p, float* m, float* v, const float* g, long n, float lr, float b1, float b2, float eps,
                    float bc1, float bc2, hipStream_t s);
+// Blocked weight layout: element (co, tap, ci) of a [C_out][taps][C_in] weight sits at
+// ((co / 16 * taps + tap) * C_in / 8 + ci / 8) * 128 + (co % 16) * 8 + ci % 8, so the 16-byte A
+// operands of one matrix-core step (16 output channels x 32 input channels of one tap) are one
+// contiguous kilobyte.
+__host__ __device__ inline long w_index(int blocked, int co, int tap, int ci, int taps, int c_in) {
+  if (!blocked) return ((long)co * taps + tap) * c_in + ci;
+  return (((long)(co >> 4) * taps + tap) * (c_in >> 3) + (ci >> 3)) * 128 + (co & 15) * 8 + (ci & 7);
+}
 // BF16 copies of one layer's weights src[cout][taps][cin_src] (FP32, or BF16 bit patterns):
-// dst[cout][taps][cin_pad] (zero padded) and dstT[cin_pad][taps][cout] with the taps reversed
-// (the input-gradient weights); either output may be null
+// dst = [cout][taps][cin_pad] (zero padded) and dstT = [cin_pad][taps][cout] with the taps
+// reversed (the input-gradient weights), both in rows or, with blocked, in the blocked layout;
+// either output may be null
 hipError_t nn_weight_cast(const float* src, int cout, int taps, int cin_src, int cin_pad, uint16_t* dst,
-                          uint16_t* dstT, hipStream_t s);
+                          uint16_t* dstT, hipStream_t s, int blocked = 0);
 hipError_t nn_weight_cast_bf16(const uint16_t* src, int cout, int taps, int cin_src, int cin_pad, uint16_t* dst,
                                uint16_t* dstT, hipStream_t s);
 
