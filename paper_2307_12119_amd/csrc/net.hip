@@ -118,12 +118,10 @@ void build_layers(varsim_net* net) {
   const int* w = net->cfg.width;
   long off = 0;
   size_t bo = 0;
-  // 3x3 layers whose convolutions gather their operands from global memory (maps narrower than
-  // the LDS-staged kernel's 64 columns) keep their weights blocked: the A operands of a step are
-  // then one contiguous kilobyte.  The LDS-staged kernel measured faster with rows.
-  auto add = [&](NetLayer& L, int ks, int cin_src, int cin, int cout, int level) {
-    const int m = (net->cfg.n / 4) >> level;
-    L.wblk = ks == 3 && !nn_conv_staged(ks, m, m) ? 1 : 0;
+  // 3x3 layers keep their weights blocked: the A operands of a matrix-core step are then one
+  // contiguous kilobyte
+  auto add = [&](NetLayer& L, int ks, int cin_src, int cin, int cout) {
+    L.wblk = ks == 3 ? 1 : 0;
     L.ks = ks, L.cin_src = cin_src, L.cin = cin, L.cout = cout;
     L.w_off = off;
     off += (long)cout * ks * ks * cin_src;
@@ -135,14 +133,14 @@ void build_layers(varsim_net* net) {
     L.wt = bo;
     bo += (e + 127) / 128 * 128;
   };
-  add(net->stem, 1, 48, 64, w[0], 0);
+  add(net->stem, 1, 48, 64, w[0]);
   for (int l = 0; l < 5; ++l) {
     const int cin = l == 0 ? w[0] : w[l - 1];
-    add(net->enc[l][0], 3, cin, cin, w[l], l);
-    add(net->enc[l][1], 3, w[l], w[l], w[l], l);
+    add(net->enc[l][0], 3, cin, cin, w[l]);
+    add(net->enc[l][1], 3, w[l], w[l], w[l]);
   }
-  for (int l = 3; l >= 0; --l) add(net->dec[l], 3, w[l + 1] + w[l], w[l + 1] + w[l], w[l], l);
-  add(net->head, 1, w[0], w[0], 16, 0);
+  for (int l = 3; l >= 0; --l) add(net->dec[l], 3, w[l + 1] + w[l], w[l + 1] + w[l], w[l]);
+  add(net->head, 1, w[0], w[0], 16);
   net->count = off;
   net->wbf_elems = bo;
 }

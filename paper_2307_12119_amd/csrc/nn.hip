@@ -176,7 +176,7 @@ inline long conv_lds_bytes(int cu, int cx) {
   return (long)(kLdsRows + 2) * (kLdsCols + 2) * conv_lds_pitch(widest < kLdsPhase ? widest : kLdsPhase) * 2;
 }
 
-template <int MW, int EPI, bool RELU>
+template <int MW, int EPI, bool RELU, bool BLK>
 __global__ void __launch_bounds__(256) conv3_lds_kernel(NnConv a) {
   constexpr int TR = kLdsRows, NW = kLdsRows, TW = kLdsCols + 2;
   extern __shared__ __attribute__((aligned(16))) uint16_t tile[];
@@ -245,7 +245,9 @@ __global__ void __launch_bounds__(256) conv3_lds_kernel(NnConv a) {
 #pragma unroll
         for (int i = 0; i < MW; ++i) {
           const int co = co0 + i * 16 + lr;
-          av[i] = kv ? ld16(a.w + ((long)co * 9 + tap) * cin + cs + cl) : z4;
+          const long wi = BLK ? (((long)((co0 >> 4) + i) * 9 + tap) * (cin >> 3) + ((cs + cl) >> 3)) * 128 + lr * 8
+                              : ((long)co * 9 + tap) * cin + cs + cl;
+          av[i] = kv ? ld16(a.w + wi) : z4;
         }
 #pragma unroll
         for (int j = 0; j < NW; ++j)  // zero past the phase's channels
@@ -263,15 +265,19 @@ __global__ void __launch_bounds__(256) conv3_lds_kernel(NnConv a) {
   conv_epilogue<MW, NW, EPI, RELU>(a, acc, pb, py, px, pv, lr, lg, co0);
 }
 
-// (the staged kernel reads weights in rows)
 inline bool conv_lds_ok(const NnConv& a) {
-  return !a.wblk && a.W % kLdsCols == 0 && a.H % kLdsRows == 0 && conv_lds_bytes(a.cu, a.cx) <= 65536;
+  return a.W % kLdsCols == 0 && a.H % kLdsRows == 0 && conv_lds_bytes(a.cu, a.cx) <= 65536;
 }
 
 template <int MW, int EPI, bool RELU>
 hipError_t conv_lds(const NnConv& a, hipStream_t s) {
   const dim3 grid((unsigned)((long)a.B * (a.H / kLdsRows) * (a.W / kLdsCols)), a.cout / (16 * MW));
-  hipLaunchKernelGGL((conv3_lds_kernel<MW, EPI, RELU>), grid, dim3(256), (size_t)conv_lds_bytes(a.cu, a.cx), s, a);
+  if (a.wblk)
+    hipLaunchKernelGGL((conv3_lds_kernel<MW, EPI, RELU, true>), grid, dim3(256), (size_t)conv_lds_bytes(a.cu, a.cx), s,
+                       a);
+  else
+    hipLaunchKernelGGL((conv3_lds_kernel<MW, EPI, RELU, false>), grid, dim3(256), (size_t)conv_lds_bytes(a.cu, a.cx),
+                       s, a);
   return hipGetLastError();
 }
 
@@ -900,11 +906,6 @@ unsigned blocks_for(long n, int per_thread = 1, unsigned cap = 4096) {
 }
 
 }  // namespace
-
-bool nn_conv_staged(int ks, int H, int W) {
-  // phases of at most 64 channels keep the staged halo within 64 KB for any channel count
-  return ks == 3 && W % kLdsCols == 0 && H % kLdsRows == 0;
-}
 
 hipError_t nn_conv(int ks, int epi, bool relu, const NnConv& a, hipStream_t s) {
   if ((a.cu % 16) || (a.cx % 16) || a.cu + a.cx <= 0 || (a.cout % 16) || a.cout <= 0 || a.B <= 0 || a.H <= 0 ||

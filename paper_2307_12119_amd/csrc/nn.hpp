@@ -34,8 +34,6 @@ enum NnEpi : int {
 
 
 hipError_t nn_conv(int ks, int epi, bool relu, const NnConv& a, hipStream_t s);
-// true when a ks x ks convolution on H x W maps takes the LDS-staged kernel
-bool nn_conv_staged(int ks, int H, int W);
 
 // Weight gradient: part[s][cout][ks*ks][cin] = sum over pixel chunk s of dz (x) shifted input.
 // n_split must be nn_wgrad_splits(ks, B, H, W, cu + cx, cout), the number of chunks of the
