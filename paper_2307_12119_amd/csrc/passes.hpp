@@ -82,14 +82,18 @@ __device__ __forceinline__ int tile_slot(int k) {
 // Row values at the sample positions of this lane's slots (slot m <-> reordered index
 // t + TPF m).  Each lane loads the adjacent pair (2k, 2k+1) of its even slot k = t + TPF m;
 // the odd sample 2k+1 belongs to slot E-1-m of the mirror lane TPF-1-t and is swapped over.
-template <typename Tio, typename Tc, int N>
+// NT: non-temporal loads, for maps streamed once per pass (a batch's inputs outgrow the caches
+// between passes); callers that re-read a map while it is still cached keep the default.
+template <typename Tio, typename Tc, int N, bool NT = false>
 __device__ __forceinline__ void load_slots(const Tio* __restrict__ row, Tc* out, int t, int mirror) {
   constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
+  typedef Tio pair_t __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int m = 0; m < E / 2; ++m) {
-    const Vec<Tio, 2> v = *reinterpret_cast<const Vec<Tio, 2>*>(row + 2 * (t + TPF * m));
-    out[m] = (Tc)v.v[0];
-    out[E - 1 - m] = (Tc)lane_get(v.v[1], mirror);
+    const pair_t* p = reinterpret_cast<const pair_t*>(row + 2 * (t + TPF * m));
+    const pair_t v = NT ? __builtin_nontemporal_load(p) : *p;
+    out[m] = (Tc)v.x;
+    out[E - 1 - m] = (Tc)lane_get(v.y, mirror);
   }
 }
 

@@ -30,7 +30,7 @@ struct LaneStats {
 };
 
 // one map's pointwise update of one row: theta slots -> dT (stored) -> total power slots
-template <typename Tio, typename Tc, int N, int MODE>
+template <typename Tio, typename Tc, int N, int MODE, bool NT = false>
 __device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off, int t, int mirror, bool zero_old,
                                               const PointParams& pp, LaneStats<Tc>& ls) {
   constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
@@ -40,13 +40,13 @@ __device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off
 #pragma unroll
       for (int m = 0; m < E; ++m) x[m] = (Tc)0;
     } else {
-      load_slots<Tio, Tc, N>((const Tio*)mp.dT + off, x, t, mirror);
+      load_slots<Tio, Tc, N, NT>((const Tio*)mp.dT + off, x, t, mirror);
     }
   } else {
     Tc old[E];
     if (mp.minv) {
       Tc mv[E];
-      load_slots<Tio, Tc, N>((const Tio*)mp.minv + off, mv, t, mirror);
+      load_slots<Tio, Tc, N, NT>((const Tio*)mp.minv + off, mv, t, mirror);
 #pragma unroll
       for (int m = 0; m < E; ++m) z[m] *= mv[m];
     }
@@ -56,7 +56,7 @@ __device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off
 #pragma unroll
       for (int m = 0; m < E; ++m) old[m] = (Tc)0;
     } else {
-      load_slots<Tio, Tc, N>((const Tio*)mp.dT + off, old, t, mirror);
+      load_slots<Tio, Tc, N, NT>((const Tio*)mp.dT + off, old, t, mirror);
     }
     if constexpr (MODE == ROW_RESID) {
 #pragma unroll
@@ -75,10 +75,10 @@ __device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off
   }
   if constexpr (MODE == ROW_HEAD || MODE == ROW_MERGED) {
     Tc q[E];
-    load_slots<Tio, Tc, N>((const Tio*)mp.qd + off, q, t, mirror);
+    load_slots<Tio, Tc, N, NT>((const Tio*)mp.qd + off, q, t, mirror);
     if (mp.ql) {
       Tc ql[E];
-      load_slots<Tio, Tc, N>((const Tio*)mp.ql + off, ql, t, mirror);
+      load_slots<Tio, Tc, N, NT>((const Tio*)mp.ql + off, ql, t, mirror);
 #pragma unroll
       for (int m = 0; m < E; ++m) q[m] += ql[m] * leak_factor<Tc>(x[m], pp);
     }

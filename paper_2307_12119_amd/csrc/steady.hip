@@ -84,11 +84,11 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
     store_slots<Tio, Tc, N>((Tio*)mp.dT + oa, zr, t, mirror);
     store_slots<Tio, Tc, N>((Tio*)mp.dT + ob, zi, t, mirror);
   } else if constexpr (MODE == ROW_CONV_HEAD) {
-    load_slots<Tio, Tc, N>((const Tio*)mp.qd + oa, zr, t, mirror);
-    load_slots<Tio, Tc, N>((const Tio*)mp.qd + ob, zi, t, mirror);
+    load_slots<Tio, Tc, N, true>((const Tio*)mp.qd + oa, zr, t, mirror);
+    load_slots<Tio, Tc, N, true>((const Tio*)mp.qd + ob, zi, t, mirror);
   } else {
-    row_pointwise<Tio, Tc, N, MODE>(zr, mp, oa, t, mirror, zero_old, pp, ls);
-    row_pointwise<Tio, Tc, N, MODE>(zi, mp, ob, t, mirror, zero_old, pp, ls);
+    row_pointwise<Tio, Tc, N, MODE, true>(zr, mp, oa, t, mirror, zero_old, pp, ls);
+    row_pointwise<Tio, Tc, N, MODE, true>(zi, mp, ob, t, mirror, zero_old, pp, ls);
   }
 
   if constexpr (STATS) {
