@@ -155,20 +155,35 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
 // ---------------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) prep_kernel(const PrepArgs* __restrict__ args, long count) {
+  // 16 bytes per lane and step; the inputs are read once (non-temporal), QL and 1/m are read
+  // again by the first row pass
+  constexpr int V = 16 / (int)sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(V)));
   const PrepArgs pa = args[blockIdx.y];
   bool invalid = false, warm_bad = false;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
+  const long nv = count / V;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (long)gridDim.x * blockDim.x) {
     if (pa.ql_out) {
-      T v = ((const T*)pa.q_leak0)[i];
-      if (pa.leak_var) v *= ((const T*)pa.leak_var)[i];
-      ((T*)pa.ql_out)[i] = v;
+      vec_t v = __builtin_nontemporal_load((const vec_t*)pa.q_leak0 + i);
+      if (pa.leak_var) v *= __builtin_nontemporal_load((const vec_t*)pa.leak_var + i);
+      ((vec_t*)pa.ql_out)[i] = v;
     }
     if (pa.minv_out) {
-      const T m = ((const T*)pa.cond_map)[i];
-      if (!(m > (T)0) || !isfinite(m)) invalid = true;
-      ((T*)pa.minv_out)[i] = (T)1 / m;
+      const vec_t m = __builtin_nontemporal_load((const vec_t*)pa.cond_map + i);
+      vec_t r;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        if (!(m[e] > (T)0) || !isfinite(m[e])) invalid = true;
+        r[e] = (T)1 / m[e];
+      }
+      ((vec_t*)pa.minv_out)[i] = r;
     }
-    if (pa.init && !isfinite(((const T*)pa.init)[i])) warm_bad = true;
+    if (pa.init) {
+      const vec_t w = ((const vec_t*)pa.init)[i];
+#pragma unroll
+      for (int e = 0; e < V; ++e)
+        if (!isfinite(w[e])) warm_bad = true;
+    }
   }
   if (invalid) atomicOr(pa.flags, kFlagInvalid);
   if (warm_bad) atomicOr(pa.flags, kFlagWarmRejected);
@@ -309,7 +324,9 @@ hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hip
 }
 
 hipError_t launch_prep(int io, const PrepArgs* args, int n_maps, long count, hipStream_t stream) {
-  const int bx = (int)((count + 255) / 256 < 64 ? (count + 255) / 256 : 64);
+  if (count % 4) return hipErrorInvalidValue;  // whole 16-byte vectors (grids are 16 x 16 or larger)
+  const long nv = count / (io == VARSIM_F32 ? 4 : 2);
+  const int bx = (int)((nv + 255) / 256 < 64 ? (nv + 255) / 256 : 64);
   if (io == VARSIM_F32)
     hipLaunchKernelGGL(prep_kernel<float>, dim3(bx, n_maps), dim3(256), 0, stream, args, count);
   else
