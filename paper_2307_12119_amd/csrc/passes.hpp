@@ -97,15 +97,20 @@ __device__ __forceinline__ void load_slots(const Tio* __restrict__ row, Tc* out,
   }
 }
 
-template <typename Tio, typename Tc, int N>
+template <typename Tio, typename Tc, int N, bool NT = false>
 __device__ __forceinline__ void store_slots(Tio* __restrict__ row, const Tc* val, int t, int mirror) {
   constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
+  typedef Tio pair_t __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int m = 0; m < E / 2; ++m) {
-    Vec<Tio, 2> v;
-    v.v[0] = (Tio)val[m];
-    v.v[1] = lane_get((Tio)val[E - 1 - m], mirror);
-    *reinterpret_cast<Vec<Tio, 2>*>(row + 2 * (t + TPF * m)) = v;
+    pair_t v;
+    v.x = (Tio)val[m];
+    v.y = lane_get((Tio)val[E - 1 - m], mirror);
+    pair_t* p = reinterpret_cast<pair_t*>(row + 2 * (t + TPF * m));
+    if (NT)
+      __builtin_nontemporal_store(v, p);
+    else
+      *p = v;
   }
 }
 

@@ -70,7 +70,7 @@ __device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off
         x[m] = (Tc)(Tio)x[m];  // the iterate as stored
         ls.add(x[m], old[m], (int)off + unperm<N>(t + TPF * m));
       }
-      store_slots<Tio, Tc, N>((Tio*)mp.dT + off, x, t, mirror);
+      store_slots<Tio, Tc, N, NT>((Tio*)mp.dT + off, x, t, mirror);
     }
   }
   if constexpr (MODE == ROW_HEAD || MODE == ROW_MERGED) {
