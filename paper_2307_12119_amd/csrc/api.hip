@@ -426,6 +426,7 @@ void varsim_destroy(varsim_ctx* c) {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  if (c->desc_ev) (void)hipEventDestroy(c->desc_ev);
   (void)hipHostFree(c->active_host);
   for (hipEvent_t e : c->active_ev)
     if (e) (void)hipEventDestroy(e);
@@ -488,6 +489,7 @@ varsim_status varsim_conv(varsim_ctx* ctx, const varsim_geometry* geom, int32_t 
       return fail(ctx, VARSIM_ERR_NO_MEMORY, "descriptor allocation failed");
     ctx->conv_maps_cap = n_maps;
   }
+  wait_descriptors(ctx);
   ctx->h_maps.assign(n_maps, MapPtrs{});
   for (int i = 0; i < n_maps; ++i) {
     ctx->h_maps[i].qd = (const char*)power + i * cells * es;
@@ -567,6 +569,7 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
   const int io = opts->precision;
   const bool want_res = opts->final_f64_residual != 0;
 
+  wait_descriptors(ctx);
   ctx->h_maps.assign(n, MapPtrs{});
   ctx->h_prep.assign(n, PrepArgs{});
   bool any_init = false;
@@ -600,6 +603,7 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
     ctx->h_order = order;
     HIP_TRY(hipMemcpyAsync(d_order, ctx->h_order.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
   }
+  HIP_TRY(descriptors_sent(ctx, s));
 
   auto group_args = [&](const Group& g, int iter) {
     PassArgs a{};
@@ -800,6 +804,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   a.qlz = a.ql ? ws + L.QLZ : nullptr;
   a.minvz = a.minv ? ws + L.MINVZ : nullptr;
 
+  wait_descriptors(ctx);
   ctx->h_prep.assign(1, PrepArgs{});
   PrepArgs& q = ctx->h_prep[0];
   q.q_leak0 = problem->q_leak0;

@@ -64,6 +64,11 @@ struct varsim_ctx {
   std::vector<PrepArgs> h_prep;
   std::vector<varsim_stats> h_stats;
   std::vector<int> h_order;  // caller index of each sorted problem (device-side statistics)
+  // recorded after the host descriptor arrays above are copied to the device; a call that
+  // returns before its stream finishes (device-side statistics) leaves it pending, and the next
+  // call waits on it before refilling the arrays
+  hipEvent_t desc_ev = nullptr;
+  bool desc_pending = false;
   MapPtrs* conv_maps = nullptr;
   size_t conv_maps_cap = 0;
   // column-pass strip width chosen by timing, per (n, compute type, log2 of the group size)
@@ -97,6 +102,23 @@ inline varsim_status fail(varsim_ctx* c, varsim_status s, const char* fmt, ...) 
     hipError_t e_ = (expr);                                                                      \
     if (e_ != hipSuccess) return fail(ctx, VARSIM_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+
+inline void wait_descriptors(varsim_ctx* c) {
+  if (c->desc_pending) {
+    (void)hipEventSynchronize(c->desc_ev);
+    c->desc_pending = false;
+  }
+}
+
+inline hipError_t descriptors_sent(varsim_ctx* c, hipStream_t s) {
+  if (!c->desc_ev) {
+    const hipError_t e = hipEventCreateWithFlags(&c->desc_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  const hipError_t e = hipEventRecord(c->desc_ev, s);
+  c->desc_pending = e == hipSuccess;
+  return e;
+}
 
 inline hipEvent_t take_event(varsim_ctx* c) {
   if (!c->pool.empty()) {

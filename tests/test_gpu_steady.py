@@ -250,6 +250,32 @@ def test_batch_device_stats_equal_host_stats(ctx):
         assert torch.equal(a["dT_out"], b["dT_out"])
 
 
+def test_batch_device_stats_back_to_back(ctx):
+    """Calls with device-side statistics return before their work finishes; two such calls in a
+    row (small maps only: no host wait inside either) give the host-statistics results."""
+    import ctypes
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    sets = [[W.steady_problem(3, n, 16, floorplan=i + k, sample=i + k) for i, n in enumerate([64, 16, 128, 32])]
+            for k in (0, 7)]
+    opts = _opts(V.F32, sets[0][0], 50, 1e-3)
+    host = [ctx.solve_batch([gpu_item(i, torch.float32) for i in inps], opts) for inps in sets]
+    dev_items = [[gpu_item(i, torch.float32) for i in inps] for inps in sets]
+    bufs = [torch.zeros((4 * ctypes.sizeof(V.Stats),), dtype=torch.uint8, device="cuda") for _ in sets]
+    for items, buf in zip(dev_items, bufs):
+        assert ctx.solve_batch(items, opts, stats_out=buf) is None
+    torch.cuda.synchronize()
+    for h, items, buf, inps in zip(host, dev_items, bufs, sets):
+        got = V.stats_from_bytes(buf, len(inps))
+        for hs, g in zip(h, got):
+            assert hs["status"] == V.OK and g["status"] == V.OK and g["iterations"] == hs["iterations"]
+        for item, inp in zip(items, inps):
+            single = gpu_item(inp, torch.float32)
+            ctx.solve_steady(single, opts)
+            assert torch.equal(item["dT_out"], single["dT_out"])
+
+
 # ----------------------------------------------------------------------------- statuses
 def test_not_converged_invalid_and_runaway(ctx):
     import torch
