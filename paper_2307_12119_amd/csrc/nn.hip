@@ -460,7 +460,8 @@ __global__ void __launch_bounds__(256) wgrad_kernel(NnConv a, const uint16_t* __
       }
 }
 
-// Weight gradient of a 3 x 3 layer with the nine taps in one workgroup.  A step covers R = 128 / W
+// Weight gradient of a 3 x 3 layer with the nine taps in one workgroup (a 1 x 1 layer: the same
+// steps without the halo and with one tap).  A step covers R = 128 / W
 // whole image rows (128 pixels).  dz of the step is staged once (16 MT channels x 128 pixels,
 // pixels contiguous), and the input once as a halo of R + 2 rows by W + 2 columns (zero outside
 // the image; 16 NT channels, columns contiguous, halo column h holding image column h - 1).  For
@@ -491,29 +492,30 @@ __device__ __forceinline__ uint4 shift_elems1(const uint4& a, const uint4& b) {
                     __builtin_amdgcn_alignbyte(a.w, a.z, 2), __builtin_amdgcn_alignbyte(b.x, a.w, 2));
 }
 
-template <int MT, int NT>
+template <int KS, int MT, int NT>
 __global__ void __launch_bounds__(256) wgrad3_kernel(NnConv a, const uint16_t* __restrict__ dz, float* __restrict__ part,
                                                      int steps_per_wg) {
   using F = WgFused<MT, NT>;
+  constexpr int TAPS = KS * KS, PAD = KS / 2;  // a 1x1 layer stages no halo: one tap
   __shared__ __attribute__((aligned(16))) uint16_t lds[F::LDS];
   uint16_t* const sz = lds;
   uint16_t* const sx = lds + 16 * MT * F::ZP;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lg = lane >> 4;
   const int H = a.H, W = a.W, cu = a.cu, cx = a.cx, cin = cu + cx, cout = a.cout;
-  const int R = 128 / W, HP = wg3_hp(W), XP = wg3_xp(W), HB = W / 8 + 1;
+  const int R = 128 / W, HP = wg3_hp(W), XP = wg3_xp(W), HB = W / 8 + PAD, HR = R + 2 * PAD;
   const int spi = H / R;  // steps per image
   const int nsteps = a.B * spi;
   const int nco = (cout + 16 * MT - 1) / (16 * MT);
   const int cob = (int)(blockIdx.y % nco) * 16 * MT, cib = (int)(blockIdx.y / nco) * 16 * NT;
   const int s0 = blockIdx.x * steps_per_wg;
   const int s1 = nsteps < s0 + steps_per_wg ? nsteps : s0 + steps_per_wg;
-  const int nzb = 2 * MT * 16, nblk = nzb + 2 * NT * (R + 2) * HB;
+  const int nzb = 2 * MT * 16, nblk = nzb + 2 * NT * HR * HB;
   const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-  f32x4 acc[F::PW][9];
+  f32x4 acc[F::PW][TAPS];
 #pragma unroll
   for (int q = 0; q < F::PW; ++q)
 #pragma unroll
-    for (int k = 0; k < 9; ++k) acc[q][k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < TAPS; ++k) acc[q][k] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   // one 8-pixel x 8-channel staging block: its loads, and where its transpose goes
   auto fetch = [&](int blk, int b, int y0, long p0, uint4 (&v)[8], uint16_t*& dst, int& pitch) {
@@ -532,12 +534,12 @@ __global__ void __launch_bounds__(256) wgrad3_kernel(NnConv a, const uint16_t* _
     } else {
       const int xb = blk - nzb;
       const int hcb = xb % HB, rest = xb / HB;
-      const int hr = rest % (R + 2), cg = rest / (R + 2);
-      const int ci = cib + cg * 8, y = y0 - 1 + hr;
+      const int hr = rest % HR, cg = rest / HR;
+      const int ci = cib + cg * 8, y = y0 - PAD + hr;
       if (ci < cin && y >= 0 && y < H) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const int xc = hcb * 8 + e - 1;
+          const int xc = hcb * 8 + e - PAD;
           if (xc >= 0 && xc < W)
             v[e] = ci < cu ? ld16(a.xu + (((long)b * (H >> 1) + (y >> 1)) * (W >> 1) + (xc >> 1)) * cu + ci)
                            : ld16(a.x + (((long)b * H + y) * W + xc) * cx + (ci - cu));
@@ -575,16 +577,24 @@ __global__ void __launch_bounds__(256) wgrad3_kernel(NnConv a, const uint16_t* _
         if (pair < F::PAIRS) {
           const int i = pair / NT, j = pair % NT;
           const uint4 av = *reinterpret_cast<const uint4*>(sz + (i * 16 + lr) * F::ZP + k0);
+          if constexpr (KS == 1) {
+            const uint4 c0 = *reinterpret_cast<const uint4*>(sx + (j * 16 + lr) * XP + r * HP + c);
+            acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(c0), acc[q][0], 0, 0, 0);
+          } else {
 #pragma unroll
-          for (int dy = 0; dy < 3; ++dy) {
-            const uint16_t* bx = sx + (j * 16 + lr) * XP + (r + dy) * HP + c;
-            const uint4 c0 = *reinterpret_cast<const uint4*>(bx);
-            const uint4 c1 = *reinterpret_cast<const uint4*>(bx + 8);
-            const uint4 b1 = shift_elems1(c0, c1);
-            const uint4 b2 = make_uint4(c0.y, c0.z, c0.w, c1.x);
-            acc[q][dy * 3 + 0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(c0), acc[q][dy * 3 + 0], 0, 0, 0);
-            acc[q][dy * 3 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(b1), acc[q][dy * 3 + 1], 0, 0, 0);
-            acc[q][dy * 3 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(b2), acc[q][dy * 3 + 2], 0, 0, 0);
+            for (int dy = 0; dy < 3; ++dy) {
+              const uint16_t* bx = sx + (j * 16 + lr) * XP + (r + dy) * HP + c;
+              const uint4 c0 = *reinterpret_cast<const uint4*>(bx);
+              const uint4 c1 = *reinterpret_cast<const uint4*>(bx + 8);
+              const uint4 b1 = shift_elems1(c0, c1);
+              const uint4 b2 = make_uint4(c0.y, c0.z, c0.w, c1.x);
+              acc[q][dy * 3 + 0] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(c0), acc[q][dy * 3 + 0], 0, 0, 0);
+              acc[q][dy * 3 + 1] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(b1), acc[q][dy * 3 + 1], 0, 0, 0);
+              acc[q][dy * 3 + 2] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(b2), acc[q][dy * 3 + 2], 0, 0, 0);
+            }
           }
         }
       }
@@ -597,11 +607,11 @@ __global__ void __launch_bounds__(256) wgrad3_kernel(NnConv a, const uint16_t* _
     if (pair < F::PAIRS) {
       const int i = pair / NT, j = pair % NT;
 #pragma unroll
-      for (int tap = 0; tap < 9; ++tap)
+      for (int tap = 0; tap < TAPS; ++tap)
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
           const int co = cob + i * 16 + 4 * lg + r4, ci = cib + j * 16 + lr;
-          if (co < cout && ci < cin) part[(((long)blockIdx.x * cout + co) * 9 + tap) * cin + ci] = acc[q][tap][r4];
+          if (co < cout && ci < cin) part[(((long)blockIdx.x * cout + co) * TAPS + tap) * cin + ci] = acc[q][tap][r4];
         }
     }
   }
@@ -944,19 +954,20 @@ int wgrad3_steps_per_wg(int B, int H, int W, int tiles) {
   return (int)per;
 }
 
-template <int MT, int NT>
+template <int KS, int MT, int NT>
 hipError_t wgrad3_launch(const NnConv& a, const uint16_t* dz, float* part, int n_split, int per, hipStream_t s) {
   const int cin = a.cu + a.cx;
   const dim3 grid(n_split, ((a.cout + 16 * MT - 1) / (16 * MT)) * ((cin + 16 * NT - 1) / (16 * NT)));
-  hipLaunchKernelGGL((wgrad3_kernel<MT, NT>), grid, dim3(256), 0, s, a, dz, part, per);
+  hipLaunchKernelGGL((wgrad3_kernel<KS, MT, NT>), grid, dim3(256), 0, s, a, dz, part, per);
   return hipGetLastError();
 }
 
+template <int KS>
 hipError_t wgrad3_dispatch(int mt, int nt, const NnConv& a, const uint16_t* dz, float* part, int n_split, int per,
                            hipStream_t s) {
   switch (mt * 8 + nt) {
 #define VS_WG3(M, N) \
-  case M * 8 + N: return wgrad3_launch<M, N>(a, dz, part, n_split, per, s);
+  case M * 8 + N: return wgrad3_launch<KS, M, N>(a, dz, part, n_split, per, s);
     VS_WG3(1, 4) VS_WG3(1, 5) VS_WG3(2, 2) VS_WG3(2, 3) VS_WG3(2, 4) VS_WG3(2, 5) VS_WG3(3, 2) VS_WG3(3, 3)
     VS_WG3(3, 4) VS_WG3(4, 1) VS_WG3(4, 2) VS_WG3(4, 3)
 #undef VS_WG3
@@ -968,7 +979,7 @@ hipError_t wgrad3_dispatch(int mt, int nt, const NnConv& a, const uint16_t* dz, 
 
 int nn_wgrad_splits(int ks, int B, int H, int W, int cin, int cout) {
   int mt, nt;
-  if (ks == 3 && wgrad3_tile(W, H, cout, cin, mt, nt)) {
+  if ((ks == 1 || ks == 3) && wgrad3_tile(W, H, cout, cin, mt, nt)) {
     const int tiles = ((cout + 16 * mt - 1) / (16 * mt)) * ((cin + 16 * nt - 1) / (16 * nt));
     const long nsteps = (long)B * H * W / 128;
     const int per = wgrad3_steps_per_wg(B, H, W, tiles);
@@ -984,10 +995,12 @@ hipError_t nn_wgrad(int ks, const NnConv& a, const uint16_t* dz, float* part, in
   const long P = (long)a.B * a.H * a.W;
   if (P > 0x7fffffffL) return hipErrorInvalidValue;  // pixel indices are divided in 32 bits
   int mt, nt;
-  if (ks == 3 && wgrad3_tile(a.W, a.H, a.cout, a.cu + a.cx, mt, nt)) {
+  if ((ks == 1 || ks == 3) && wgrad3_tile(a.W, a.H, a.cout, a.cu + a.cx, mt, nt)) {
     const int cin = a.cu + a.cx;
     const int tiles = ((a.cout + 16 * mt - 1) / (16 * mt)) * ((cin + 16 * nt - 1) / (16 * nt));
-    return wgrad3_dispatch(mt, nt, a, dz, part, n_split, wgrad3_steps_per_wg(a.B, a.H, a.W, tiles), s);
+    const int per = wgrad3_steps_per_wg(a.B, a.H, a.W, tiles);
+    return ks == 1 ? wgrad3_dispatch<1>(mt, nt, a, dz, part, n_split, per, s)
+                   : wgrad3_dispatch<3>(mt, nt, a, dz, part, n_split, per, s);
   }
   long chunk = (P + n_split - 1) / n_split;
   chunk = (chunk + kWgK - 1) / kWgK * kWgK;

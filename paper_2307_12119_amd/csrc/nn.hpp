@@ -37,8 +37,8 @@ hipError_t nn_conv(int ks, int epi, bool relu, const NnConv& a, hipStream_t s);
 
 // Weight gradient: part[s][cout][ks*ks][cin] = sum over pixel chunk s of dz (x) shifted input.
 // n_split must be nn_wgrad_splits(ks, B, H, W, cu + cx, cout), the number of chunks of the
-// kernel the shape selects (3 x 3 layers whose image width is a power of two up to 128 and whose
-// rows come in whole 128-pixel steps: all nine taps per workgroup; otherwise one tap each).
+// kernel the shape selects (1 x 1 and 3 x 3 layers whose image width is a power of two up to 128
+// and whose rows come in whole 128-pixel steps: every tap per workgroup; otherwise one tap each).
 int nn_wgrad_splits(int ks, int B, int H, int W, int cin, int cout);
 hipError_t nn_wgrad(int ks, const NnConv& a, const uint16_t* dz, float* part, int n_split, hipStream_t s);
 // out[co][t][ci] (ci < cin_dst) = sum_s part[s][co][t][ci] (part has cin_src columns)
