@@ -161,8 +161,8 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-2, help="fixed-point tolerance (max increment, K)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sample sharding is described in "
-                                   "DESIGN.md but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "one GPU only: sharding the samples over several GPUs is not built",
+                          "n_gpus": args.gpus}))
         return 2
 
     t_gen = time.perf_counter()

@@ -5,7 +5,7 @@ FP64 NumPy reference of every layer of the learned warm start and of its trainin
 nearest 2x upsampling, channel concatenation, the 4x4 patch stem and pixel-shuffle head, the
 mean-squared error and one Adam step.  The network maps the solver's own inputs (dynamic power,
 leakage variation, conductivity) to a predicted converged rise, used as the fixed point's
-starting iterate; the fixed-point solve stays the judge of the result.  The paper has no learned
+starting iterate; the fixed-point solve still decides the result.  The paper has no learned
 part: the architecture is this project's (a five-level encoder-decoder), described by
 ``NetSpec``.
 

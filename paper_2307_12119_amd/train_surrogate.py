@@ -59,7 +59,7 @@ def main() -> int:
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
-    ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "surrogate_512"))
+    ap.add_argument("--out", default="surrogate_512", help="output path stem (.npy weights, .json record)")
     args = ap.parse_args()
 
     import multiprocessing as mp

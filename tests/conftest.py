@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def gpu_lib():
-    """The loaded C-ABI library on a GPU machine; tests marked gpu fail loudly without it."""
+    """The loaded C-ABI library on a machine with a GPU; tests marked gpu fail loudly without it."""
     import torch
 
     if not torch.cuda.is_available():
