@@ -159,6 +159,8 @@ def main() -> int:
     ap.add_argument("--mixed-batch", type=int, default=256, help="samples per size class")
     ap.add_argument("--transient-runs", type=int, default=3)
     ap.add_argument("--tol", type=float, default=1e-2, help="fixed-point tolerance (max increment, K)")
+    ap.add_argument("--graph-iterations", type=int, default=2,
+                    help="iterations per captured HIP graph in the launch-mode comparison (0: skip it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: sharding the samples over several GPUs is not built",
@@ -264,6 +266,24 @@ def main() -> int:
     ctx.set_timing_only(None)
     print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
+    # the same steps with no events at all: direct launches, then the fixed-point loop as
+    # captured graphs of --graph-iterations iterations (same results, bitwise)
+    launch_modes = None
+    if args.graph_iterations > 0:
+        launch_modes = {"graph_iterations": args.graph_iterations}
+        lstats = torch.empty_like(dstats)
+        for name, k_graph in (("direct_ms_per_step", 0), ("graph_ms_per_step", args.graph_iterations)):
+            ctx.set_graph_iterations(k_graph)
+            ctx.solve_batch(batch, opts, ws, stats_out=lstats[0])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for k in range(args.steps):
+                ctx.solve_batch(batch, opts, ws, stats_out=lstats[k])
+            torch.cuda.synchronize()
+            launch_modes[name] = round((time.perf_counter() - t1) / args.steps * 1e3, 4)
+        ctx.set_graph_iterations(0)
+        print(f"[bench] launch modes {launch_modes}", file=sys.stderr, flush=True)
+
     per_step = [V.stats_from_bytes(dstats[k], args.batch) for k in range(args.steps)]
     stats = per_step[-1]
     statuses = sorted({int(x) for s_ in per_step for x in s_["status"]})
@@ -309,6 +329,7 @@ def main() -> int:
                   "kernels_note": f"{dom}: timed steps; other classes: one step timed with every class "
                                   "before the timed region",
                   "kernels": kernels,
+                  "launch_modes": launch_modes,
                   "autotune": ctx.autotune_report().strip().split("\n")},
         "surrogate": None,
     }

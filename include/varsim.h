@@ -111,7 +111,8 @@ typedef struct varsim_stats {
   double last_increment_K;      /* max |dT_k - dT_{k-1}| of the last iteration */
   double residual_f64_K;        /* max |G64(dT) - dT| in FP64 (NaN when not requested) */
   double dT_max_K;              /* max of dT */
-  double dT_mean_K;             /* mean of dT (FP64 accumulation) */
+  double dT_mean_K;             /* mean of dT (FP64 accumulation; per-workgroup partial sums are
+                                   added in arrival order, so the last bits may vary by run) */
   int64_t hotspot_index;        /* row-major index of the max (lowest index on ties) */
   int32_t warm_start_rejected;  /* 1 when dT_init held a non-finite value and 0 was used */
   int32_t reserved;
@@ -313,6 +314,19 @@ VARSIM_API varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size
  * the sizes whose working set fits one CU's LDS; max_n = -1 restores that default, 0 turns the
  * path off.  Both paths compute the same iterates. */
 VARSIM_API varsim_status varsim_set_small_path(varsim_ctx* ctx, int32_t max_n);
+/* Batching (the scope table's persistent-scheduling row; the paper's Monte Carlo use case,
+ * Sec. I and Sec. V): with iterations = K > 0 the fixed-point loop of varsim_solve_batch /
+ * varsim_solve_steady is launched as HIP graphs of K iterations each (column and row pass of
+ * every looping group, then the count of maps still iterating), captured on a private stream and
+ * replayed on the caller's stream.  Executable graph j (the j-th chunk of a call) is kept by the
+ * context and rewritten for the next call with hipGraphExecUpdate, after its previous launch
+ * has finished (re-instantiated when the launch structure differs); the host reads convergence
+ * once per chunk, so a chunk may run up to K - 1 iterations past the last needed one, which
+ * return at once for maps already converged.  Results are bitwise those of direct launches.
+ * iterations = 0 (the default) launches every pass directly; per-kernel timing
+ * (varsim_set_timing) also uses direct launches.  VARSIM_ERR_INVALID outside [0, 16];
+ * VARSIM_ERR_DEVICE if the capture stream cannot be created. */
+VARSIM_API varsim_status varsim_set_graph_iterations(varsim_ctx* ctx, int32_t iterations);
 /* Testing / manual tuning: every later column pass (solves and varsim_conv) uses strip-width
  * candidate `variant` (0 = default strip width, 1 = default width with two column pairs per
  * transform group, 2 = half width), and transient solves use row-pass candidate `variant` (rows per workgroup:

@@ -427,6 +427,11 @@ void varsim_destroy(varsim_ctx* c) {
   }
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   if (c->desc_ev) (void)hipEventDestroy(c->desc_ev);
+  for (hipGraphExec_t g : c->graph_exec)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (hipEvent_t e : c->graph_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   (void)hipHostFree(c->active_host);
   for (hipEvent_t e : c->active_ev)
     if (e) (void)hipEventDestroy(e);
@@ -669,8 +674,9 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
     }
   }
 
-  int iters_run = 0;
-  for (int k = 1; any_loop && k <= opts->max_iter; ++k) {
+  // Fixed-point iteration k over every looping group on stream q; slot >= 0 adds the count of
+  // maps still iterating after it, written into that pinned host word.
+  auto iteration = [&](int k, int slot, hipStream_t q) -> hipError_t {
     for (size_t gi = 0; gi < groups.size(); ++gi) {
       if (own[gi]) continue;
       const Group& g = groups[gi];
@@ -679,25 +685,85 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
       for (int i = g.first; i < g.first + g.count; ++i) all_zero = all_zero && !sorted[i]->dT_init;
       a.zero_start = all_zero ? 1 : 0;
       const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
-      HIP_TRY(timed(ctx, "col", s, [&] { return launch_col_pass(io, a, lam, s, col_var[gi]); }));
+      hipError_t e = timed(ctx, "col", q, [&] { return launch_col_pass(io, a, lam, q, col_var[gi]); });
+      if (e != hipSuccess) return e;
       const int mode = k < opts->max_iter ? ROW_MERGED : ROW_LAST;
-      HIP_TRY(timed(ctx, mode == ROW_MERGED ? "row_merged" : "row_last", s,
-                    [&] { return launch_row_pass(mode, io, io, a, s); }));
+      e = timed(ctx, mode == ROW_MERGED ? "row_merged" : "row_last", q,
+                [&] { return launch_row_pass(mode, io, io, a, q); });
+      if (e != hipSuccess) return e;
     }
-    iters_run = k;
-    // Convergence is read one iteration late so that the device never idles: one small kernel
-    // behind iteration k writes the count of maps still iterating into pinned host memory, and
-    // the host waits for iteration k-1's count only after launching iteration k.
-    // Launches past a map's convergence return at once (the map is marked finished).
-    if (k >= 1) {
+    return slot >= 0 ? launch_count_active(base, n, k, opts->tol_K, ctx->active_map + slot, q) : hipSuccess;
+  };
+
+  // Convergence is read one step late so that the device never idles: a small kernel behind
+  // iteration k (or behind the last iteration of a captured chunk) writes the count of maps still
+  // iterating into pinned host memory, and the host waits for the previous step's count only
+  // after launching the next step.  Launches past a map's convergence return at once (the map
+  // reads its own finished increment), so a chunk may run past the last needed iteration.
+  int iters_run = 0;
+  const bool graphs = ctx->graph_chunk > 0 && !ctx->timing && any_loop;
+  if (!graphs) {
+    for (int k = 1; any_loop && k <= opts->max_iter; ++k) {
       const int slot = k & 1;
-      HIP_TRY(launch_count_active(base, n, k, opts->tol_K, ctx->active_map + slot, s));
+      HIP_TRY(iteration(k, slot, s));
       HIP_TRY(hipEventRecord(ctx->active_ev[slot], s));
+      iters_run = k;
+      if (k >= 2) {
+        const int prev = (k - 1) & 1;
+        HIP_TRY(hipEventSynchronize(ctx->active_ev[prev]));
+        if (ctx->active_host[prev] == 0) break;
+      }
     }
-    if (k >= 2) {
-      const int prev = (k - 1) & 1;
-      HIP_TRY(hipEventSynchronize(ctx->active_ev[prev]));
-      if (ctx->active_host[prev] == 0) break;
+  } else {
+    const int C = ctx->graph_chunk;
+    for (int j = 0, k0 = 1; k0 <= opts->max_iter; ++j, k0 += C) {
+      const int k1 = std::min(k0 + C - 1, opts->max_iter);
+      const int slot = j & 1;
+      if ((int)ctx->graph_exec.size() <= j) {
+        ctx->graph_exec.push_back(nullptr);
+        ctx->graph_ev.push_back(nullptr);
+        ctx->graph_live.push_back(0);
+        HIP_TRY(hipEventCreateWithFlags(&ctx->graph_ev[j], hipEventDisableTiming));
+      }
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (int k = k0; k <= k1 && e == hipSuccess; ++k) e = iteration(k, k == k1 ? slot : -1, ctx->cap_stream);
+      const hipError_t e_end = hipStreamEndCapture(ctx->cap_stream, &graph);
+      if (e != hipSuccess || e_end != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        HIP_TRY(e);
+        HIP_TRY(e_end);
+      }
+      // the executable graph may still be running from the previous call: its kernel arguments
+      // are rewritten only after that launch has finished
+      if (ctx->graph_live[j]) HIP_TRY(hipEventSynchronize(ctx->graph_ev[j]));
+      bool updated = false;
+      if (ctx->graph_exec[j]) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res;
+        updated = hipGraphExecUpdate(ctx->graph_exec[j], graph, &bad, &res) == hipSuccess &&
+                  res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+          (void)hipGetLastError();
+          (void)hipGraphExecDestroy(ctx->graph_exec[j]);
+          ctx->graph_exec[j] = nullptr;
+        }
+      }
+      if (!updated) e = hipGraphInstantiate(&ctx->graph_exec[j], graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) ctx->graph_exec[j] = nullptr;
+      HIP_TRY(e);
+      HIP_TRY(hipGraphLaunch(ctx->graph_exec[j], s));
+      HIP_TRY(hipEventRecord(ctx->graph_ev[j], s));
+      ctx->graph_live[j] = 1;
+      HIP_TRY(hipEventRecord(ctx->active_ev[slot], s));
+      iters_run = k1;
+      if (j >= 1) {
+        const int prev = (j - 1) & 1;
+        HIP_TRY(hipEventSynchronize(ctx->active_ev[prev]));
+        if (ctx->active_host[prev] == 0) break;
+      }
     }
   }
 
@@ -944,6 +1010,21 @@ varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t variant) {
   if (!ctx) return VARSIM_ERR_INVALID;
   if (variant < -1 || variant >= kColVariants) return fail(ctx, VARSIM_ERR_INVALID, "variant must be in [-1, %d]", kColVariants - 1);
   ctx->force_col = variant;
+  return VARSIM_OK;
+}
+
+varsim_status varsim_set_graph_iterations(varsim_ctx* ctx, int32_t iterations) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  if (iterations < 0 || iterations > kMaxGraphIterations)
+    return fail(ctx, VARSIM_ERR_INVALID, "iterations per graph must be in [0, %d]", kMaxGraphIterations);
+  if (iterations > 0 && !ctx->cap_stream) {
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      ctx->cap_stream = nullptr;
+      return fail(ctx, VARSIM_ERR_DEVICE, "capture stream: %s", hipGetErrorString(hipGetLastError()));
+    }
+  }
+  ctx->graph_chunk = iterations;
   return VARSIM_OK;
 }
 

@@ -56,6 +56,15 @@ struct varsim_ctx {
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<long long, double>> times;
   std::vector<const char*> class_names;
+  // fixed-point iterations per captured graph (0: direct launches).  Chunk j of a call is
+  // captured on the private stream cap_stream and written into executable graph j with
+  // hipGraphExecUpdate (instantiated anew when the launch structure changed); graph_ev[j] is
+  // recorded after its last launch, and the next update of that graph waits for it
+  int graph_chunk = 0;
+  hipStream_t cap_stream = nullptr;
+  std::vector<hipGraphExec_t> graph_exec;
+  std::vector<hipEvent_t> graph_ev;
+  std::vector<char> graph_live;  // graph_ev[j] has been recorded
   int* active_host = nullptr;  // [2] pinned host words: counts of maps still iterating
   int* active_map = nullptr;   // the same words as the device addresses them
   hipEvent_t active_ev[2] = {nullptr, nullptr};

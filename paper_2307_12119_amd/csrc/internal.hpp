@@ -57,6 +57,7 @@ hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hip
 // 0 (default strip width), 1 (default width, two column pairs per transform group), 2 (half
 // width); col_pass_columns / col_pass_pairs give a candidate's strip width and pairs per group
 constexpr int kColVariants = 3;
+constexpr int kMaxGraphIterations = 16;  // fixed-point iterations one captured graph may hold
 hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream, int variant = 0);
 int col_pass_columns(int compute, int n, int variant);
 int col_pass_pairs(int compute, int n, int variant);

@@ -105,6 +105,7 @@ EXPORTS = {
     "varsim_force_col_variant": (c_int, [c_void_p, c_int32]),
     "varsim_force_transient_variant": (c_int, [c_void_p, c_int32, c_int32]),
     "varsim_set_small_path": (c_int, [c_void_p, c_int32]),
+    "varsim_set_graph_iterations": (c_int, [c_void_p, c_int32]),
     "varsim_set_timing": (c_int, [c_void_p, c_int32]),
     "varsim_kernel_times": (c_int, [c_void_p, POINTER(c_char_p), POINTER(c_int64), POINTER(c_double),
                                     POINTER(c_int32)]),
@@ -348,6 +349,10 @@ class Context:
     def set_small_path(self, max_n: int):
         """Largest N solved by one LDS-resident workgroup per map (-1 default, 0 off)."""
         self._check(self.lib.varsim_set_small_path(self.handle, int(max_n)))
+
+    def set_graph_iterations(self, iterations: int):
+        """Fixed-point iterations per captured HIP graph (0: direct launches)."""
+        self._check(self.lib.varsim_set_graph_iterations(self.handle, int(iterations)))
 
     def force_col_variant(self, variant: int):
         self._check(self.lib.varsim_force_col_variant(self.handle, int(variant)))
