@@ -30,7 +30,7 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
   __shared__ Tc lds[Cfg::LDS];
 
   int strip, map;
-  xcd_tile(strip, map);
+  xcd_strip_tile(strip, map);
   if (a.iter >= 0) {  // iter < 0: plain convolution, no solver state
     if (a.st.flags[map] & kFlagSkip) return;
     if (!a.resid_pass && finished_before(a.st, map, a.iter, a.pp.tol)) return;
