@@ -14,6 +14,23 @@ namespace vs {
 
 namespace {
 
+// When the strips split evenly over the eight XCDs (workgroups are handed to them round-robin
+// in launch order), XCD x takes strips [x gx/8, (x+1) gx/8) of every map, so its L2 holds one
+// eighth of the column coefficient table (the whole FP64 table at N = 512 is 4.2 MB, as large as
+// one XCD's L2) while each XCD still reads whole 128-byte lines of a map's rows; otherwise the
+// map-major split of the row passes.
+__device__ __forceinline__ void xcd_strip_tile(int& strip, int& map) {
+  const int gx = gridDim.x;
+  if (gx & 7) {
+    xcd_tile(strip, map);
+    return;
+  }
+  const int w = blockIdx.x + gx * blockIdx.y;
+  const int per = gx >> 3, i = w >> 3;
+  strip = (w & 7) * per + i % per;
+  map = i / per;
+}
+
 template <typename Tc, int N, int COLS, int PAIRS>
 __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
     col_pass_kernel(PassArgs a, const Tc* __restrict__ coef, const Cx<Tc>* __restrict__ tw,

@@ -38,22 +38,6 @@ __device__ __forceinline__ void xcd_tile(int& strip, int& map) {
   map = l / gx;
 }
 
-// Column passes: when the strips split evenly over the eight XCDs, XCD x takes strips
-// [x gx/8, (x+1) gx/8) of every map, so its L2 holds one eighth of the column coefficient table
-// (the whole FP64 table at N = 512 is 4.2 MB, as large as one XCD's L2) while each XCD still
-// reads whole 128-byte lines of a map's rows; otherwise the map-major split above.
-__device__ __forceinline__ void xcd_strip_tile(int& strip, int& map) {
-  const int gx = gridDim.x;
-  if (gx & 7) {
-    xcd_tile(strip, map);
-    return;
-  }
-  const int w = blockIdx.x + gx * blockIdx.y;
-  const int per = gx >> 3, i = w >> 3;
-  strip = (w & 7) * per + i % per;
-  map = i / per;
-}
-
 // COLS_ = 0: the default strip width (col_count); otherwise an explicit even width.  Each
 // transform group (one wavefront at N >= 512) handles PAIRS column pairs one after the other,
 // so a strip can be wider (longer contiguous row segments) without more threads.
