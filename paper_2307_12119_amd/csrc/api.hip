@@ -702,11 +702,16 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
   // reads its own finished increment), so a chunk may run past the last needed iteration.
   int iters_run = 0;
   const bool graphs = ctx->graph_chunk > 0 && !ctx->timing && any_loop;
+  // A previous call's last counts (possibly queued on another stream, behind iterations the
+  // host no longer waited for) land before this call reuses the two words.
+  for (int i = 0; any_loop && i < 2; ++i)
+    if (ctx->active_live[i]) HIP_TRY(hipEventSynchronize(ctx->active_ev[i]));
   if (!graphs) {
     for (int k = 1; any_loop && k <= opts->max_iter; ++k) {
       const int slot = k & 1;
       HIP_TRY(iteration(k, slot, s));
       HIP_TRY(hipEventRecord(ctx->active_ev[slot], s));
+      ctx->active_live[slot] = true;
       iters_run = k;
       if (k >= 2) {
         const int prev = (k - 1) & 1;
@@ -758,6 +763,7 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
       HIP_TRY(hipEventRecord(ctx->graph_ev[j], s));
       ctx->graph_live[j] = 1;
       HIP_TRY(hipEventRecord(ctx->active_ev[slot], s));
+      ctx->active_live[slot] = true;
       iters_run = k1;
       if (j >= 1) {
         const int prev = (j - 1) & 1;

@@ -68,6 +68,7 @@ struct varsim_ctx {
   int* active_host = nullptr;  // [2] pinned host words: counts of maps still iterating
   int* active_map = nullptr;   // the same words as the device addresses them
   hipEvent_t active_ev[2] = {nullptr, nullptr};
+  bool active_live[2] = {false, false};  // active_ev[i] has been recorded
   // host staging of per-call descriptor arrays (kept alive until the call returns)
   std::vector<MapPtrs> h_maps;
   std::vector<PrepArgs> h_prep;

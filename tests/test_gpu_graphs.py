@@ -140,3 +140,31 @@ def test_graph_iterations_out_of_range(ctx):
             ctx.set_graph_iterations(bad)
     ctx.set_graph_iterations(16)
     ctx.set_graph_iterations(0)
+
+
+def test_two_streams_back_to_back(ctx):
+    """Batches alternating between two streams with device-side statistics: each call returns
+    once its iterations are read, so its residual passes overlap the next call on the other
+    stream, which reuses the context's convergence words.  Every result equals the
+    single-stream one."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    sets = [[W.steady_problem(3, n, 16, floorplan=i + k, sample=i + k) for i, n in enumerate([512, 256, 512])]
+            for k in (0, 4, 8, 12)]
+    opts = _opts(V.F32, sets[0][0], 50, 1e-3, res=True)
+    host = [_solve(ctx, inps, opts, torch.float32) for inps in sets]
+    streams = (torch.cuda.current_stream(), torch.cuda.Stream())
+    dev_items = [[gpu_item(i, torch.float32) for i in inps] for inps in sets]
+    bufs = [torch.zeros((len(inps) * ctypes.sizeof(V.Stats),), dtype=torch.uint8, device="cuda") for inps in sets]
+    torch.cuda.synchronize()
+    for k, (items, buf) in enumerate(zip(dev_items, bufs)):
+        with torch.cuda.stream(streams[k & 1]):
+            assert ctx.solve_batch(items, opts, stats_out=buf) is None
+    torch.cuda.synchronize()
+    for (h_items, h), items, buf, inps in zip(host, dev_items, bufs, sets):
+        got = V.stats_from_bytes(buf, len(inps))
+        for hs, g, a, b in zip(h, got, h_items, items):
+            assert hs["status"] == V.OK
+            _same_stats(hs, g)
+            assert torch.equal(a["dT_out"], b["dT_out"])
