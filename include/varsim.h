@@ -196,6 +196,9 @@ VARSIM_API varsim_status varsim_solve_steady(varsim_ctx* ctx, const varsim_probl
  *     follows the convergence loop on the host); stats is written on `stream`, in the caller's
  *     order, and the return value reports only argument and device errors, not the per-problem
  *     statuses.  The workspace must not be reused by another stream before that point.
+ * Consecutive calls of one context may use different streams (calls are made from one host
+ * thread at a time); each call in flight needs its own workspace and outputs.  A call waits
+ * for the previous call's last convergence counts before reusing the context's count words.
  */
 VARSIM_API varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
                                  const varsim_options* opts, void* workspace, size_t ws_bytes,
