@@ -168,3 +168,32 @@ def test_two_streams_back_to_back(ctx):
             assert hs["status"] == V.OK
             _same_stats(hs, g)
             assert torch.equal(a["dT_out"], b["dT_out"])
+
+
+def test_two_streams_with_graphs(ctx):
+    """Graph-launched calls alternating between two streams: executable graph j is rewritten by
+    each call after the previous call's launch of it (on the other stream) has finished."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    sets = [[W.steady_problem(3, n, 16, floorplan=i + k, sample=i + k) for i, n in enumerate([256, 512, 256])]
+            for k in (1, 6, 10, 15)]
+    opts = _opts(V.F32, sets[0][0], 50, 1e-3, res=True)
+    ctx.set_graph_iterations(0)
+    host = [_solve(ctx, inps, opts, torch.float32) for inps in sets]
+    streams = (torch.cuda.current_stream(), torch.cuda.Stream())
+    dev_items = [[gpu_item(i, torch.float32) for i in inps] for inps in sets]
+    bufs = [torch.zeros((len(inps) * ctypes.sizeof(V.Stats),), dtype=torch.uint8, device="cuda") for inps in sets]
+    torch.cuda.synchronize()
+    ctx.set_graph_iterations(2)
+    for k, (items, buf) in enumerate(zip(dev_items, bufs)):
+        with torch.cuda.stream(streams[k & 1]):
+            assert ctx.solve_batch(items, opts, stats_out=buf) is None
+    torch.cuda.synchronize()
+    ctx.set_graph_iterations(0)
+    for (h_items, h), items, buf, inps in zip(host, dev_items, bufs, sets):
+        got = V.stats_from_bytes(buf, len(inps))
+        for hs, g, a, b in zip(h, got, h_items, items):
+            assert hs["status"] == V.OK
+            _same_stats(hs, g)
+            assert torch.equal(a["dT_out"], b["dT_out"])
