@@ -59,3 +59,16 @@ def test_struct_layouts_match_c(tmp_path):
             assert ctypes.sizeof(py) == int(val), cname
         else:
             assert getattr(py, field).offset == int(val), (cname, field)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for several it prints one JSON error line and exits 2
+    before generating inputs or touching a device."""
+    import json
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
