@@ -13,7 +13,14 @@ Two solvers of the *same* linear system:
     system in depth per lateral cosine mode (large grids).
 Richardson extrapolation in the refinement removes the leading O(h^2) error.
 
-Parity: pinned (``solve_modes`` against ``solve_sparse`` to rounding; convergence order checked).
+A spatially varying conductivity k(x, y) = k m(x, y) (the conductivity-variation map of
+Sec. II-E, constant through the depth, piecewise constant on the coarse cells) couples the
+cosine modes; ``solve_lateral_k`` then solves the same finite-volume system (harmonic-mean face
+conductances) by conjugate gradients preconditioned with the exact constant-conductivity
+solve, and ``solve_sparse`` takes the same map for a direct check on tiny grids.
+
+Parity: pinned (``solve_modes`` and ``solve_lateral_k`` against ``solve_sparse`` to rounding;
+convergence order checked).
 """
 from __future__ import annotations
 
@@ -75,12 +82,15 @@ def solve_modes(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float, 
     return _coarse_centres(_surface_from_top_cells(t_top, q_fine, dz, k), r)
 
 
-def solve_sparse(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float, r: int, nz: int) -> np.ndarray:
-    """Same discretisation as ``solve_modes``, assembled as one sparse 3-D system (small grids)."""
+def solve_sparse(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float, r: int, nz: int,
+                 m_coarse: np.ndarray | None = None) -> np.ndarray:
+    """Same discretisation as ``solve_modes`` (or ``solve_lateral_k`` when a conductivity map
+    ``m_coarse`` is given), assembled as one sparse 3-D system with explicit loops (small grids)."""
     ny, nx = q_coarse.shape
     mfx, mfy = nx * r, ny * r
     hx, hy, dz = lx / mfx, ly / mfy, t / nz
     q_fine = _fine_flux(q_coarse, r)
+    kc = k * (_fine_flux(m_coarse, r) if m_coarse is not None else np.ones((mfy, mfx)))
     n = mfx * mfy * nz
 
     def idx(z, y, x):
@@ -88,21 +98,22 @@ def solve_sparse(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float,
 
     rows, cols, vals = [], [], []
     rhs = np.zeros(n)
-    gx, gy, gz = k / (hx * hx), k / (hy * hy), k / (dz * dz)
     for z in range(nz):
         for y in range(mfy):
             for x in range(mfx):
                 i = idx(z, y, x)
                 dsum = 0.0
-                for (zz, yy, xx, g) in ((z, y, x - 1, gx), (z, y, x + 1, gx), (z, y - 1, x, gy),
-                                        (z, y + 1, x, gy), (z - 1, y, x, gz), (z + 1, y, x, gz)):
+                for (zz, yy, xx, h2) in ((z, y, x - 1, hx * hx), (z, y, x + 1, hx * hx), (z, y - 1, x, hy * hy),
+                                         (z, y + 1, x, hy * hy), (z - 1, y, x, dz * dz), (z + 1, y, x, dz * dz)):
                     if 0 <= xx < mfx and 0 <= yy < mfy and 0 <= zz < nz:
+                        a_, b_ = kc[y, x], kc[yy, xx]
+                        g = 2.0 * a_ * b_ / (a_ + b_) / h2  # harmonic mean of the two cells
                         rows.append(i)
                         cols.append(idx(zz, yy, xx))
                         vals.append(-g)
                         dsum += g
                     elif zz == nz:  # bottom face held at ambient, half a cell away
-                        dsum += 2.0 * g
+                        dsum += 2.0 * kc[y, x] / h2
                 rows.append(i)
                 cols.append(i)
                 vals.append(dsum)
@@ -111,7 +122,7 @@ def solve_sparse(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float,
     a = sp.csc_matrix((vals, (rows, cols)), shape=(n, n))
     sol = spla.spsolve(a, rhs)
     t_top = sol[:mfx * mfy].reshape(mfy, mfx)
-    return _coarse_centres(_surface_from_top_cells(t_top, q_fine, dz, k), r)
+    return _coarse_centres(t_top + q_fine * 0.5 * dz / kc, r)
 
 
 def richardson(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float, r0: int = 9,
@@ -121,6 +132,110 @@ def richardson(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float, r
     r, nz = r0, nz0
     for _ in range(levels + 1):
         sols.append(solve_modes(q_coarse, lx, ly, t, k, r, nz))
+        r *= 3
+        nz *= 3
+    cur = sols
+    order = 2
+    for _ in range(levels):
+        f = 3.0 ** order
+        cur = [(f * cur[i + 1] - cur[i]) / (f - 1.0) for i in range(len(cur) - 1)]
+        order += 2
+    return cur[-1]
+
+
+# ----------------------------------------------------------------------------- lateral k(x, y)
+def _apply_operator(temp: np.ndarray, kc: np.ndarray, hx: float, hy: float, dz: float) -> np.ndarray:
+    """A T for the finite-volume system of ``solve_sparse`` with column conductivities kc[y][x]
+    (temp: [nz][ny][nx], top layer first)."""
+    out = np.zeros_like(temp)
+    gx = 2.0 * kc[:, :-1] * kc[:, 1:] / (kc[:, :-1] + kc[:, 1:]) / (hx * hx)
+    flux = gx * (temp[:, :, 1:] - temp[:, :, :-1])
+    out[:, :, :-1] -= flux
+    out[:, :, 1:] += flux
+    gy = 2.0 * kc[:-1, :] * kc[1:, :] / (kc[:-1, :] + kc[1:, :]) / (hy * hy)
+    flux = gy * (temp[:, 1:, :] - temp[:, :-1, :])
+    out[:, :-1, :] -= flux
+    out[:, 1:, :] += flux
+    gz = kc / (dz * dz)
+    flux = gz * (temp[1:] - temp[:-1])
+    out[:-1] -= flux
+    out[1:] += flux
+    out[-1] += 2.0 * gz * temp[-1]
+    return out
+
+
+def _constant_k_solve(rhs: np.ndarray, k: float, hx: float, hy: float, dz: float) -> np.ndarray:
+    """Exact inverse of the operator with a uniform conductivity k (cosine modes laterally, one
+    tridiagonal system in depth per mode), for a right-hand side in every layer."""
+    nz, mfy, mfx = rhs.shape
+    lam_x = (2.0 - 2.0 * np.cos(np.pi * np.arange(mfx) / mfx)) / (hx * hx)
+    lam_y = (2.0 - 2.0 * np.cos(np.pi * np.arange(mfy) / mfy)) / (hy * hy)
+    lam = lam_y[:, None] + lam_x[None, :]
+    b = sfft.dctn(rhs, type=2, norm="ortho", axes=(1, 2)) * (dz * dz / k)
+    off = -1.0
+    diag = [np.full(lam.shape, 2.0) + lam * dz * dz for _ in range(nz)]
+    diag[0] = diag[0] - 1.0
+    diag[-1] = diag[-1] + 1.0
+    cp = [None] * nz
+    dp = [None] * nz
+    cp[0] = off / diag[0]
+    dp[0] = b[0] / diag[0]
+    for z in range(1, nz):
+        den = diag[z] - off * cp[z - 1]
+        cp[z] = off / den
+        dp[z] = (b[z] - off * dp[z - 1]) / den
+    x = np.empty_like(b)
+    x[-1] = dp[-1]
+    for z in range(nz - 2, -1, -1):
+        x[z] = dp[z] - cp[z] * x[z + 1]
+    return sfft.idctn(x, type=2, norm="ortho", axes=(1, 2))
+
+
+def solve_lateral_k(q_coarse: np.ndarray, m_coarse: np.ndarray, lx: float, ly: float, t: float, k: float, r: int,
+                    nz: int, rtol: float = 1e-14, max_iter: int = 500) -> np.ndarray:
+    """Top-surface rise at the coarse cell centres [K] with conductivity k m(x, y) (m piecewise
+    constant on the coarse cells, constant through the depth): preconditioned conjugate
+    gradients on the finite-volume system, the preconditioner the exact solve at the mean
+    conductivity."""
+    if r % 2 == 0:
+        raise ValueError("refinement must be odd")
+    ny, nx = q_coarse.shape
+    mfx, mfy = nx * r, ny * r
+    hx, hy, dz = lx / mfx, ly / mfy, t / nz
+    q_fine = _fine_flux(q_coarse, r)
+    kc = k * _fine_flux(np.asarray(m_coarse, dtype=np.float64), r)
+    kbar = float(np.mean(kc))
+    rhs = np.zeros((nz, mfy, mfx))
+    rhs[0] = q_fine / dz
+    x = _constant_k_solve(rhs, kbar, hx, hy, dz)
+    res = rhs - _apply_operator(x, kc, hx, hy, dz)
+    zv = _constant_k_solve(res, kbar, hx, hy, dz)
+    p = zv.copy()
+    rz = float(np.vdot(res, zv))
+    bnorm = float(np.linalg.norm(rhs))
+    for _ in range(max_iter):
+        if float(np.linalg.norm(res)) <= rtol * bnorm:
+            break
+        ap = _apply_operator(p, kc, hx, hy, dz)
+        alpha = rz / float(np.vdot(p, ap))
+        x += alpha * p
+        res -= alpha * ap
+        zv = _constant_k_solve(res, kbar, hx, hy, dz)
+        rz_new = float(np.vdot(res, zv))
+        p = zv + (rz_new / rz) * p
+        rz = rz_new
+    else:
+        raise RuntimeError("conjugate gradients did not converge")
+    return _coarse_centres(x[0] + q_fine * 0.5 * dz / kc, r)
+
+
+def richardson_lateral_k(q_coarse: np.ndarray, m_coarse: np.ndarray, lx: float, ly: float, t: float, k: float,
+                         r0: int = 3, nz0: int = 6, levels: int = 2) -> np.ndarray:
+    """``richardson`` for a conductivity map: refine by 3 per level, extrapolate the h^2, h^4 terms."""
+    sols = []
+    r, nz = r0, nz0
+    for _ in range(levels + 1):
+        sols.append(solve_lateral_k(q_coarse, m_coarse, lx, ly, t, k, r, nz))
         r *= 3
         nz *= 3
     cur = sols

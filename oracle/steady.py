@@ -12,7 +12,14 @@ temperature values converge"):
          theta_SI(i, j) = sum_{k, l} P(k, l) [K(i-k, j-l) + K(i+k+1, j-l) + K(i-k, j+l+1) + K(i+k+1, j+l+1)]
      with K the periodised cell kernel of ``oracle.kernel`` at k_ref = k(T_amb);
   3. conductivity variation map m (Sec. II-E): the Green's function scales as 1/k (Eq. fspvsk
-     with c' = 1/k0'), applied as a Hadamard factor:  theta = theta_SI / m;
+     with c' = 1/k0'), applied as a Hadamard factor.  The paper does not say at which end of
+     the source -> target path the local conductivity acts; two placements are offered:
+         source (default):  theta = K (*) (P / m)    (each source's spreading uses its own k)
+         target:            theta = (K (*) P) / m    (the target cell's k scales its rise)
+     Both are exact for a uniform m.  Against a finite-volume solve of Eq. fourier with the
+     conductivity k m(x, y) (``oracle.fd.solve_lateral_k``), the source placement's error is
+     about a quarter of the target placement's (0.47 % vs 2.0 % of the max rise for a +-5 %
+     map), so it is the default;
   4. temperature-dependent conductivity k = k0 (T/300)^-eta (Eq. condsi): theta is the Kirchhoff
      transform  Phi(dT) = int_{T_amb}^{T_amb + dT} k(T)/k_ref dT,  inverted in closed form
          dT' = T_amb [ (1 + (1 - eta) theta / T_amb)^(1/(1 - eta)) - 1 ]   (dT' = theta if eta = 0,
@@ -24,9 +31,11 @@ non-finite iterate, dT above the cap, or a non-positive Kirchhoff base.
 
 Parity: pinned -- the blocked direct sum against a literal quadruple loop, uniform power
 against q t / k, linear and exponential leakage against their closed forms (Lambert W), the
-leakage-aware spectral form of Eq. detsol at alpha = 0, Phi(Phi^-1) against quadrature of k(T),
-and the whole operator against a finite-volume solve of Eq. fourier.  The Hadamard treatment of a
-non-uniform m is the paper's reading (exact for uniform m); beyond that it is "parity unpinned".
+leakage-aware spectral form of Eq. detsol at alpha = 0, Phi(Phi^-1) against quadrature of k(T)
+(eta = 1.3 and eta = 1), and the whole operator against a finite-volume solve of Eq. fourier.
+A non-uniform m is pinned only to the accuracy of the Hadamard model itself: the finite-volume
+solve with k m(x, y) bounds the source placement's error and separates it from the target
+placement's; the model error (linear in the amplitude of m) is the paper's approximation.
 """
 from __future__ import annotations
 
@@ -80,6 +89,7 @@ class Options:
     max_iter: int = 50
     tol: float = 1e-6
     dT_cap: float = 1000.0
+    cond: str = "source"  # placement of the conductivity factor 1/m: "source" or "target"
 
 
 @dataclass
@@ -221,9 +231,15 @@ class SteadyProblem:
 
     def map(self, dT: np.ndarray, opts: Options):
         """One application of G; returns (dT', domain_ok)."""
-        theta = self.op.apply(self.power(dT, opts))
-        if self.m is not None:
-            theta = theta / self.m
+        p = self.power(dT, opts)
+        if self.m is None:
+            theta = self.op.apply(p)
+        elif opts.cond == "source":
+            theta = self.op.apply(p / self.m)
+        elif opts.cond == "target":
+            theta = self.op.apply(p) / self.m
+        else:
+            raise ValueError(opts.cond)
         return kirchhoff_inverse(theta, self.geom.t_amb, self.geom.eta)
 
 

@@ -20,7 +20,9 @@ Definition followed:
     truncates it after 5 ms).
   * Leakage and k(T) (Sec. IV-E: "substitute the leakage-aware Green's function"): step n uses
     the previous step's rise, P_n = hx hy [q_dyn(t_n) + q_leak0 v L(dT_{n-1})], and
-    dT_n = Phi^-1(theta_n / m) pointwise.
+    dT_n = Phi^-1(theta_n) pointwise; the conductivity map enters as in the steady oracle, on the
+    source side (P_n / m enters the superposition, the default) or on the target side
+    (theta_n / m).
 
 The step kernels come from lambda (an (N+1)-point cosine transform of the periodised steady
 kernel) by the inverse transform; the superposition itself is a plain direct sum.
@@ -86,7 +88,7 @@ class TransientModel:
 
 def solve_transient(model: TransientModel, q_dyn_steps: np.ndarray, dt: float, q_leak: np.ndarray | None = None,
                     cond_map: np.ndarray | None = None, leak: str = "exp", beta: float = 0.017,
-                    record_every: int = 1):
+                    record_every: int = 1, cond: str = "source"):
     """Full-history superposition (Eq. tranapprox) with the one-step-lagged leakage loop.
 
     q_dyn_steps: [n_steps][ny][nx] dynamic power density held over each step.  Returns the rises
@@ -103,13 +105,18 @@ def solve_transient(model: TransientModel, q_dyn_steps: np.ndarray, dt: float, q
         if q_leak is not None and leak != "none":
             lf = np.exp(beta * dT) if leak == "exp" else 1.0 + beta * dT
             q = q + q_leak * lf
-        p_hist.append(g.hx * g.hy * q)
+        if cond not in ("source", "target"):
+            raise ValueError(cond)
+        p_new = g.hx * g.hy * q
+        if cond_map is not None and cond == "source":
+            p_new = p_new / cond_map
+        p_hist.append(p_new)
         theta = np.zeros((g.ny, g.nx))
         for j in range(1, n + 1):  # S_j applied to P_{n-j+1} - P_{n-j}
             newer = p_hist[n - j]
             older = p_hist[n - j - 1] if n - j - 1 >= 0 else 0.0
             theta += kernels[j - 1].apply(newer - older)
-        if cond_map is not None:
+        if cond_map is not None and cond == "target":
             theta = theta / cond_map
         dT, ok = S.kirchhoff_inverse(theta, g.t_amb, g.eta)
         if n % record_every == 0:

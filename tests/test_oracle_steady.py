@@ -159,6 +159,36 @@ def test_kirchhoff_roundtrip_and_quadrature():
     assert np.allclose(S.kirchhoff(dT, t_amb, eta), theta, rtol=1e-13, atol=1e-13)
 
 
+def test_kirchhoff_eta_one_against_quadrature():
+    # eta = 1 is its own branch: Phi(dT) = T_amb ln(1 + dT / T_amb), Phi^-1 = T_amb expm1(theta / T_amb)
+    t_amb = 318.0
+    theta = np.array([0.0, 0.3, 4.0, 40.0, 200.0])
+    dT, ok = S.kirchhoff_inverse(theta, t_amb, 1.0)
+    assert np.all(ok)
+    for th, d in zip(theta, dT):
+        quad, _ = integrate.quad(lambda tt: t_amb / tt, t_amb, t_amb + d, epsabs=1e-13, epsrel=1e-14)
+        assert quad == pytest.approx(th, rel=1e-12, abs=1e-13)
+    assert np.allclose(S.kirchhoff(dT, t_amb, 1.0), theta, rtol=1e-13, atol=1e-13)
+    # the general-eta formula approaches the eta = 1 branch continuously
+    for eps in (1e-6, -1e-6):
+        near, _ = S.kirchhoff_inverse(theta, t_amb, 1.0 + eps)
+        assert np.allclose(near, dT, rtol=1e-5)
+
+
+def test_uniform_with_k_of_t_eta_one_against_ode():
+    # the same ODE check as below at eta = 1 (k = k0 300 / T), no leakage: dT/dz = q T / (k0 300)
+    n, eta, t_amb = 8, 1.0, 318.0
+    q = 3.0e6
+    g = _geom(n, eta=eta)
+    dT, st = S.solve_steady(S.SteadyProblem(g, np.full((n, n), q)), S.Options(leak="none", tol=1e-13))
+    sol = integrate.solve_ivp(lambda z, y: [q * (t_amb + y[0]) / (KC * 300.0)], (0.0, T), [0.0],
+                              rtol=1e-12, atol=1e-14, method="DOP853")
+    assert st.status == S.Status.OK
+    # closed form of the same ODE: T_top = T_amb exp(q t / (300 k0))
+    assert sol.y[0, -1] == pytest.approx(t_amb * math.expm1(q * T / (KC * 300.0)), rel=1e-10)
+    assert np.allclose(dT, sol.y[0, -1], rtol=1e-10)
+
+
 def test_uniform_with_k_of_t_against_ode():
     # uniform flux through a slab with k = k0 (T/300)^-eta: integrate dT/dz = q / k(T) upward
     # from the isothermal bottom (independent of the closed-form Kirchhoff inverse), and find
@@ -180,13 +210,60 @@ def test_uniform_with_k_of_t_against_ode():
     assert np.allclose(dT, root, rtol=1e-9)
 
 
-def test_uniform_conductivity_multiplier_is_exact():
+@pytest.mark.parametrize("cond", ["source", "target"])
+def test_uniform_conductivity_multiplier_is_exact(cond):
     # m = c uniform is a homogeneous slab with conductivity c k: dT = q t / (c k)
     n = 8
     g = _geom(n)
     prob = S.SteadyProblem(g, np.full((n, n), 1e6), cond_map=np.full((n, n), 1.04))
-    dT, st = S.solve_steady(prob, S.Options(leak="none"))
+    dT, st = S.solve_steady(prob, S.Options(leak="none", cond=cond))
     assert np.allclose(dT, 1e6 * T / (1.04 * KC), rtol=1e-12)
+
+
+def _conductivity_case(amp=0.05):
+    """8 x 8 random powers on a 2 mm die with a +-amp conductivity map (l = 0.5 mm)."""
+    from scipy.special import ndtr
+
+    n, lx = 8, 2e-3
+    g = _geom(n, lx, lx)
+    qd = W.make_rng(77, n, 0, 0).uniform(0.1e6, 2e6, (n, n))
+    zk = W.gaussian_field(n, lx / n, 0.5e-3, W.make_rng(77, n, 0, 2))
+    m = 1.0 + amp * (2.0 * ndtr(zk) - 1.0)
+    return g, qd, m
+
+
+def test_conductivity_map_placement_against_finite_volume():
+    # Eq. fspvsk read as a Hadamard factor 1/m: a finite-volume solve of Eq. fourier with the
+    # conductivity k m(x, y) (two Richardson levels, converged to ~1e-5 of the max rise) fixes
+    # how well each placement models it.  The oracle's default (source side) must be within
+    # 0.6 % of the max rise; the target side is about 4x worse.  A placement swapped by mistake,
+    # or a dropped factor, fails one of the bounds.
+    g, qd, m = _conductivity_case()
+    ref = fd.richardson_lateral_k(qd, m, g.lx, g.ly, T, KC, r0=3, nz0=6, levels=1)
+    mx = float(np.max(ref))
+    errs = {}
+    for cond in ("source", "target"):
+        prob = S.SteadyProblem(g, qd, cond_map=m)
+        dT, st = S.solve_steady(prob, S.Options(leak="none", cond=cond))
+        errs[cond] = float(np.max(np.abs(dT - ref))) / mx
+    plain = S.SteadyProblem(g, qd)
+    d0, _ = S.solve_steady(plain, S.Options(leak="none"))
+    err_ignore = float(np.max(np.abs(d0 - ref))) / mx
+    assert errs["source"] < 0.006
+    assert errs["target"] > 3.0 * errs["source"]
+    assert err_ignore > 5.0 * errs["source"]  # the map matters: ignoring it is far worse
+
+
+def test_lateral_conductivity_solvers_agree():
+    rng = np.random.default_rng(21)
+    q = rng.uniform(0.0, 1e6, (3, 4))
+    m = rng.uniform(0.9, 1.1, (3, 4))
+    a = fd.solve_lateral_k(q, m, 1e-3, 0.8e-3, T, KC, 3, 5)
+    b = fd.solve_sparse(q, 1e-3, 0.8e-3, T, KC, 3, 5, m_coarse=m)
+    assert np.allclose(a, b, rtol=1e-12)
+    # a uniform map is a homogeneous slab of conductivity c k
+    c = fd.solve_lateral_k(q, np.full((3, 4), 1.04), 1e-3, 0.8e-3, T, KC, 3, 5)
+    assert np.allclose(c * 1.04, fd.solve_modes(q, 1e-3, 0.8e-3, T, KC, 3, 5), rtol=1e-12)
 
 
 def test_leakage_aware_green_function_alpha_zero():

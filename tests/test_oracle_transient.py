@@ -60,17 +60,18 @@ def test_lumped_tau_matches_moment_at_dc():
     assert np.all(b.tau[1:, 1:] < a.tau[1:, 1:] * 10)
 
 
-def test_superposition_equals_single_pole_recursion():
+@pytest.mark.parametrize("cond", ["source", "target"])
+def test_superposition_equals_single_pole_recursion(cond):
     """Eq. tranapprox (full history, real-space step kernels, direct sums) against an independent
     per-mode recursion theta_hat_n = a theta_hat_{n-1} + b P_hat_n, with the lagged leakage, the
-    conductivity map and k(T)."""
+    conductivity map (either placement) and k(T)."""
     n, steps, dt = 16, 25, 20e-6
     g = _geom(n, eta=1.3)
     model = T.TransientModel(g, RHOC)
     tr = W.transient_problem(n=n, n_steps=steps, dt_s=dt, n_blocks=6, hold_s=5 * dt)
     qd = np.stack([W.raster_trace_step(tr.block_rects, tr.trace[i], n) for i in range(steps)])
     ql = tr.q_leak0 * tr.leak_var
-    rec, last = T.solve_transient(model, qd, dt, q_leak=ql, cond_map=tr.cond_map)
+    rec, last = T.solve_transient(model, qd, dt, q_leak=ql, cond_map=tr.cond_map, cond=cond)
     lam = model.lam_full[:n, :n]
     tau = model.tau[:n, :n]
     a = np.exp(-dt / tau)
@@ -79,8 +80,29 @@ def test_superposition_equals_single_pole_recursion():
     dT = np.zeros((n, n))
     for i in range(steps):
         p = g.hx * g.hy * (qd[i] + ql * np.exp(0.017 * dT))
+        if cond == "source":
+            p = p / tr.cond_map
         th_hat = a * th_hat + b * sfft.dctn(p, type=2)
-        theta = sfft.idctn(th_hat, type=2) / tr.cond_map
+        theta = sfft.idctn(th_hat, type=2)
+        if cond == "target":
+            theta = theta / tr.cond_map
         dT, ok = S.kirchhoff_inverse(theta, g.t_amb, g.eta)
         assert np.allclose(rec[i], dT, rtol=1e-11, atol=1e-12 * np.max(np.abs(dT)))
     assert np.max(last) > 0.5
+
+
+@pytest.mark.parametrize("cond", ["source", "target"])
+def test_long_time_limit_with_conductivity_map_is_steady(cond):
+    """Constant power held far longer than every tau reaches the steady fixed point of the same
+    conductivity placement (no leakage, eta = 0: the steady map is linear)."""
+    n, steps, dt = 8, 3, 0.05
+    g = _geom(n)
+    model = T.TransientModel(g, RHOC)
+    rng = np.random.default_rng(4)
+    q = rng.uniform(0.1e6, 2e6, (n, n))
+    m = rng.uniform(0.95, 1.05, (n, n))
+    _, last = T.solve_transient(model, np.stack([q] * steps), dt, cond_map=m, leak="none", cond=cond)
+    steady, st = S.solve_steady(S.SteadyProblem(g, q, cond_map=m, operator=model.op),
+                                S.Options(leak="none", cond=cond, tol=1e-14))
+    assert st.status == S.Status.OK
+    assert np.allclose(last, steady, rtol=1e-12)
