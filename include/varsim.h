@@ -59,6 +59,12 @@ typedef enum varsim_status {
 enum { VARSIM_LEAK_NONE = 0, VARSIM_LEAK_EXP = 1, VARSIM_LEAK_LINEAR = 2 };
 enum { VARSIM_F32 = 0, VARSIM_F64 = 1 };
 enum { VARSIM_TAU_MOMENT = 0, VARSIM_TAU_LUMPED = 1 };
+/* Where the conductivity-variation factor 1/m acts (Eq. fspvsk read as a Hadamard factor):
+ *   SOURCE: theta = K (*) (P / m) -- each source's heat spreads with its own cell's conductivity;
+ *   TARGET: theta = (K (*) P) / m -- the target cell's conductivity scales its rise.
+ * Both are exact for a uniform m.  Against a finite-volume solve of the heat equation with a
+ * +-5 % conductivity map the source placement's error is about a quarter of the target's. */
+enum { VARSIM_COND_SOURCE = 0, VARSIM_COND_TARGET = 1 };
 
 typedef struct varsim_ctx varsim_ctx;
 
@@ -91,6 +97,7 @@ typedef struct varsim_options {
   double tol_K;                 /* stop at the first iterate with max |dT_k - dT_{k-1}| <= tol, > 0 */
   double dT_cap_K;              /* RUNAWAY when any dT exceeds it, > 0 (1000 K is a sane value) */
   int32_t final_f64_residual;   /* 1: report max |G64(dT) - dT| from one FP64 application */
+  int32_t cond_model;           /* VARSIM_COND_SOURCE or VARSIM_COND_TARGET (placement of 1/m) */
 } varsim_options;
 
 /* One steady problem (all maps device pointers [ny][nx]; see conventions above). */
@@ -111,8 +118,8 @@ typedef struct varsim_stats {
   double last_increment_K;      /* max |dT_k - dT_{k-1}| of the last iteration */
   double residual_f64_K;        /* max |G64(dT) - dT| in FP64 (NaN when not requested) */
   double dT_max_K;              /* max of dT */
-  double dT_mean_K;             /* mean of dT (FP64 accumulation; per-workgroup partial sums are
-                                   added in arrival order, so the last bits may vary by run) */
+  double dT_mean_K;             /* mean of dT (FP64 accumulation in a fixed order: the same bits
+                                   on every run) */
   int64_t hotspot_index;        /* row-major index of the max (lowest index on ties) */
   int32_t warm_start_rejected;  /* 1 when dT_init held a non-finite value and 0 was used */
   int32_t reserved;
@@ -177,7 +184,7 @@ VARSIM_API varsim_status varsim_workspace_size(varsim_ctx* ctx, const varsim_pro
 /* ----------------------------------------------------------------------------------------
  * Steady solve of one problem: the fixed point dT = G(dT) of
  *   P     = hx hy [q_dyn + q_leak0 v L(dT)]                  (Eqs. Pt, Pleak)
- *   theta = (K_per (*) P) / m                                (Eqs. Green, fspvsk)
+ *   theta = K_per (*) (P / m)  or  (K_per (*) P) / m         (Eqs. Green, fspvsk; cond_model)
  *   G(dT) = Phi^-1(theta), Phi the Kirchhoff transform of k(T) (Eq. condsi)
  * by Picard iteration from dT_init (or 0) to the first increment <= tol_K.
  * Writes dT_out and *stats (host pointer).  Synchronises `stream`; returns stats->status.

@@ -47,6 +47,8 @@ varsim_status check_options(varsim_ctx* ctx, const varsim_options* o) {
   if (!(o->dT_cap_K > 0)) return fail(ctx, VARSIM_ERR_INVALID, "dT_cap_K must be positive");
   if (!std::isfinite(o->beta_per_K)) return fail(ctx, VARSIM_ERR_INVALID, "beta must be finite");
   if (o->sv_radius != 0) return fail(ctx, VARSIM_ERR_UNSUPPORTED, "only sv_radius = 0 is supported");
+  if (o->cond_model != VARSIM_COND_SOURCE && o->cond_model != VARSIM_COND_TARGET)
+    return fail(ctx, VARSIM_ERR_INVALID, "bad cond_model");
   return VARSIM_OK;
 }
 
@@ -117,7 +119,7 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 // Workspace layout of a batch (problems in group-sorted order).
 struct Layout {
   int stride = 0;
-  size_t resid = 0, sum = 0, maxpack = 0, flags = 0, resid64 = 0, state_end = 0;
+  size_t resid = 0, sum = 0, maxpack = 0, flags = 0, resid64 = 0, part = 0, state_end = 0;
   size_t stats = 0, maps = 0, prep = 0, order = 0;
   std::vector<size_t> S, QL, MINV, S64;
   size_t total = 0;
@@ -150,7 +152,9 @@ Layout make_layout(const std::vector<const varsim_problem*>& probs, const varsim
   off = align_up(off + n * 4);
   L.resid64 = off;
   off = align_up(off + n * 8);
-  L.state_end = off;
+  L.state_end = off;  // the words above are zeroed at the start of a call; the partial sums need not be
+  L.part = off;
+  off = align_up(off + n * kRowGroupsMax * 8);
   L.stats = off;
   off = align_up(off + n * sizeof(varsim_stats));
   L.maps = off;
@@ -199,6 +203,7 @@ PointParams point_params(const varsim_geometry* g, const varsim_options* o) {
   pp.cap = o->dT_cap_K;
   pp.tol = o->tol_K;
   pp.leak = o->leak;
+  pp.cond_src = o->cond_model == VARSIM_COND_SOURCE ? 1 : 0;
   // Taylor series of the Kirchhoff inverse in u = u_scale theta:
   //   (1 + u)^a - 1 = sum_k C(a, k) u^k, a = 1/(1 - eta);  exp(u) - 1 = sum_k u^k / k! (eta = 1).
   // The FP32 path uses it where the first dropped term is below 1e-9 of the leading one.
@@ -566,6 +571,7 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
   base.flags = (unsigned*)(ws + L.flags);
   base.resid64 = (unsigned long long*)(ws + L.resid64);
   base.stride = L.stride;
+  base.part = (double*)(ws + L.part);
   MapPtrs* d_maps = (MapPtrs*)(ws + L.maps);
   PrepArgs* d_prep = (PrepArgs*)(ws + L.prep);
   int* d_order = (int*)(ws + L.order);
@@ -621,6 +627,7 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
     a.st.maxpack += (size_t)g.first * L.stride;
     a.st.flags += g.first;
     a.st.resid64 += g.first;
+    a.st.part += (size_t)g.first * kRowGroupsMax;
     a.pp = point_params(g.geom, opts);
     a.tw = Twiddles{g.tw.tw64, g.tw.tw32, g.tw.qw64, g.tw.qw32};
     a.iter = iter;
@@ -787,8 +794,8 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
   }
   for (const Group& g : groups) {
     PassArgs a = group_args(g, 0);
-    HIP_TRY(launch_finalize(a.st, d_maps + g.first, g.count, io, (long)g.geom->nx * g.geom->ny, opts->max_iter,
-                            iters_run, opts->tol_K, want_res ? 1 : 0, d_stats + g.first, s));
+    HIP_TRY(launch_finalize(a.st, d_maps + g.first, g.count, io, g.geom->nx, opts->max_iter, iters_run, opts->tol_K,
+                            want_res ? 1 : 0, d_stats + g.first, s));
   }
   if (dev_stats) {  // statistics stay on the device, in the caller's order; no synchronisation
     HIP_TRY(launch_scatter_stats(d_stats, d_order, n, stats, s));

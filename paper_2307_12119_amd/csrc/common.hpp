@@ -49,6 +49,7 @@ struct PointParams {
   double tol;         // convergence tolerance, K
   int leak;           // VARSIM_LEAK_*
   int eta_mode;       // 0: eta == 0, 1: eta == 1, 2: general
+  int cond_src;       // 1: the factor 1/m scales the power (source side), 0: the rise (target side)
   // Taylor coefficients of (1 + u)^(1/(1-eta)) - 1 = sum_k poly[k-1] u^k (k = 1..kPoly), used
   // by the FP32 path for |u| <= poly_umax, u = (1 - eta) theta / T_amb; 0 disables it.  The FP64
   // steady path uses the first kPoly64 coefficients for |u| <= poly_umax64 (first dropped term
@@ -70,7 +71,11 @@ struct IterState {
   unsigned* flags;              // [maps]
   unsigned long long* resid64;  // [maps] double bits of the FP64 residual
   int stride;
+  // two-pass row passes: [maps][kRowGroupsMax] sum of dT over each workgroup's rows in the last
+  // iteration that ran (overwritten each iteration, no atomics); added in a fixed order at the end
+  double* part;
 };
+constexpr int kRowGroupsMax = 128;  // row-pass workgroups of one map, at most
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
 

@@ -91,8 +91,10 @@ hipError_t launch_small_solve(int io, const PassArgs& a, int max_iter, const voi
 // Final statistics of every map into a device varsim_stats array.
 // dst[order[i]] = src[i], i < n (per-problem statistics back into the caller's order)
 hipError_t launch_scatter_stats(const varsim_stats* src, const int* order, int n, varsim_stats* dst, hipStream_t s);
-hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, long cells, int max_iter,
+hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, int n, int max_iter,
                            int iters_run, double tol, int residual_done, varsim_stats* out, hipStream_t stream);
+// workgroups of one map's row pass (<= kRowGroupsMax)
+int row_pass_groups(int n);
 
 // Transient solve of one map (element type T = io = compute type).
 struct TransArgs {

@@ -1,6 +1,7 @@
 // Row-pass building blocks shared by the two-pass steady solve and the LDS-resident small-grid
 // solve: per-lane statistics of a new iterate and the pointwise update of one row (theta ->
-// conductivity factor -> Kirchhoff inverse -> increment / statistics -> new total power).
+// [conductivity factor, target side] -> Kirchhoff inverse -> increment / statistics -> new total
+// power -> [conductivity factor, source side]).
 #pragma once
 
 #include <cmath>
@@ -44,7 +45,7 @@ __device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off
     }
   } else {
     Tc old[E];
-    if (mp.minv) {
+    if (mp.minv && !pp.cond_src) {  // target side: the rise is scaled
       Tc mv[E];
       load_slots<Tio, Tc, N, NT>((const Tio*)mp.minv + off, mv, t, mirror);
 #pragma unroll
@@ -84,6 +85,12 @@ __device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) z[m] = (Tc)pp.hxhy * q[m];
+    if (mp.minv && pp.cond_src) {  // source side: the power is scaled
+      Tc mv[E];
+      load_slots<Tio, Tc, N, NT>((const Tio*)mp.minv + off, mv, t, mirror);
+#pragma unroll
+      for (int m = 0; m < E; ++m) z[m] *= mv[m];
+    }
   }
 }
 

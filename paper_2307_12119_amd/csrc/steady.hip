@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
       } else {
         const long slot = (long)map * a.st.stride + a.iter;
         atomicMax(&a.st.resid[slot], (unsigned long long)__double_as_longlong(any_bad ? (double)INFINITY : i0));
-        atomicAdd(&a.st.sum[slot], s0);
+        a.st.part[(long)map * kRowGroupsMax + blockIdx.x] = s0;
         atomicMax(&a.st.maxpack[slot], b0);
         if (any_bad) atomicOr(&a.st.flags[map], kFlagRunaway);
       }
@@ -224,9 +224,12 @@ __global__ void __launch_bounds__(1024) count_active_kernel(IterState st, int n_
   }
 }
 
+// Per-map statistics.  The mean of a map iterated by the two-pass loop adds the row-pass
+// workgroups' sums of its last iteration (row_groups of them) in index order; a map solved by its
+// own LDS-resident workgroup has its sum in the iteration's slot.
 template <typename Tio>
 __global__ void finalize_kernel(IterState st, const MapPtrs* __restrict__ maps, int n_maps, long cells, int max_iter,
-                                int iters_run, double tol, int residual_done, varsim_stats* out) {
+                                int iters_run, double tol, int residual_done, int row_groups, varsim_stats* out) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_maps) return;
   varsim_stats s;
@@ -262,7 +265,14 @@ __global__ void finalize_kernel(IterState st, const MapPtrs* __restrict__ maps, 
   s.iterations = kf;
   if (kf > 0 && !(fl & kFlagSkip)) {
     s.last_increment_K = __longlong_as_double((long long)st.resid[base + kf]);
-    s.dT_mean_K = st.sum[base + kf] / (double)cells;
+    double total = 0.0;
+    if (fl & kFlagOwnLoop) {
+      total = st.sum[base + kf];
+    } else {
+      const double* p = st.part + (long)m * kRowGroupsMax;
+      for (int g = 0; g < row_groups; ++g) total += p[g];
+    }
+    s.dT_mean_K = total / (double)cells;
     const unsigned long long mp = st.maxpack[base + kf];
     const long idx = (long)(0xFFFFFFFFu - (unsigned)(mp & 0xFFFFFFFFull));
     const bool valid = mp != 0ull && idx >= 0 && idx < cells;
@@ -369,15 +379,31 @@ hipError_t launch_scatter_stats(const varsim_stats* src, const int* order, int n
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, long cells, int max_iter,
+hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, int n, int max_iter,
                            int iters_run, double tol, int residual_done, varsim_stats* out, hipStream_t stream) {
+  const long cells = (long)n * n;
+  const int groups = row_pass_groups(n);
+  if (groups < 1 || groups > kRowGroupsMax) return hipErrorInvalidValue;
   if (io == VARSIM_F32)
     hipLaunchKernelGGL(finalize_kernel<float>, dim3((n_maps + 127) / 128), dim3(128), 0, stream, st, maps, n_maps,
-                       cells, max_iter, iters_run, tol, residual_done, out);
+                       cells, max_iter, iters_run, tol, residual_done, groups, out);
   else
     hipLaunchKernelGGL(finalize_kernel<double>, dim3((n_maps + 127) / 128), dim3(128), 0, stream, st, maps, n_maps,
-                       cells, max_iter, iters_run, tol, residual_done, out);
+                       cells, max_iter, iters_run, tol, residual_done, groups, out);
   return hipGetLastError();
+}
+
+int row_pass_groups(int n) {
+  switch (n) {
+    case 16: return (16 / 2) / RowCfg<16>::FFTS;
+    case 32: return (32 / 2) / RowCfg<32>::FFTS;
+    case 64: return (64 / 2) / RowCfg<64>::FFTS;
+    case 128: return (128 / 2) / RowCfg<128>::FFTS;
+    case 256: return (256 / 2) / RowCfg<256>::FFTS;
+    case 512: return (512 / 2) / RowCfg<512>::FFTS;
+    case 1024: return (1024 / 2) / RowCfg<1024>::FFTS;
+    default: return 0;
+  }
 }
 
 }  // namespace vs

@@ -140,7 +140,7 @@ __global__ void __launch_bounds__((TrRowCfg<N, FFTS_>::THREADS))
     const long off = half ? ob : oa;
     Tc x[E];
     if constexpr (INV) {
-      if (a.minv) {
+      if (a.minv && !pp.cond_src) {  // conductivity factor on the target side
         Tc mv[E];
         load_slots<Tio, Tc, N>((const Tio*)a.minv + off, mv, t, mirror);
 #pragma unroll
@@ -179,6 +179,12 @@ __global__ void __launch_bounds__((TrRowCfg<N, FFTS_>::THREADS))
       }
 #pragma unroll
       for (int m = 0; m < E; ++m) z[m] = (Tc)pp.hxhy * q[m];
+      if (a.minv && pp.cond_src) {  // conductivity factor on the source side
+        Tc mv[E];
+        load_slots<Tio, Tc, N>((const Tio*)a.minv + off, mv, t, mirror);
+#pragma unroll
+        for (int m = 0; m < E; ++m) z[m] *= mv[m];
+      }
     }
   }
   if (INV && __any(bad) && (__lane_id() & 63) == 0) atomicOr(a.flags, kFlagRunaway);

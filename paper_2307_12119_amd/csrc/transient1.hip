@@ -102,15 +102,15 @@ __global__ void __launch_bounds__((TrRow1Cfg<N, W>::THREADS))
       }
     }
   }
-  if constexpr (INV) {
-    if (has_mv) {
-      const Vec<Tio, 2>* src = reinterpret_cast<const Vec<Tio, 2>*>((const Tio*)a.minvz + off);
+  // 1/m acts on the rise (target side, inverse half) or on the next power map (source side)
+  const bool mv_inv = INV && has_mv && !pp.cond_src, mv_fwd = FWD && has_mv && pp.cond_src;
+  if (mv_inv || mv_fwd) {
+    const Vec<Tio, 2>* src = reinterpret_cast<const Vec<Tio, 2>*>((const Tio*)a.minvz + off);
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const Vec<Tio, 2> v = src[t + TPF * m];
-        mv[m] = (Tc)v.v[0];
-        mv[E + m] = (Tc)v.v[1];
-      }
+    for (int m = 0; m < E; ++m) {
+      const Vec<Tio, 2> v = src[t + TPF * m];
+      mv[m] = (Tc)v.v[0];
+      mv[E + m] = (Tc)v.v[1];
     }
   }
 
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__((TrRow1Cfg<N, W>::THREADS))
       x[m] = zr[m];
       x[E + m] = zi[m];
     }
-    if (has_mv) {
+    if (mv_inv) {
 #pragma unroll
       for (int k = 0; k < 2 * E; ++k) x[k] *= mv[k];
     }
@@ -167,6 +167,13 @@ __global__ void __launch_bounds__((TrRow1Cfg<N, W>::THREADS))
     for (int m = 0; m < E; ++m) {
       zr[m] = hh * qd[m];
       zi[m] = hh * qd[E + m];
+    }
+    if (mv_fwd) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        zr[m] *= mv[m];
+        zi[m] *= mv[E + m];
+      }
     }
     dct2_single<Tc, N>(zr, zi, re, im, tw, qw, t);
 #pragma unroll

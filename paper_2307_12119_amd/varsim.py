@@ -19,6 +19,7 @@ OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_NOT_CONVERGED, ERR_RUNAWAY, ERR_DEVICE, ER
 LEAK_NONE, LEAK_EXP, LEAK_LINEAR = 0, 1, 2
 F32, F64 = 0, 1
 TAU_MOMENT, TAU_LUMPED = 0, 1
+COND_SOURCE, COND_TARGET = 0, 1
 
 
 class VarsimError(RuntimeError):
@@ -39,7 +40,8 @@ class Geometry(Structure):
 
 class Options(Structure):
     _fields_ = [("leak", c_int32), ("beta_per_K", c_double), ("sv_radius", c_int32), ("precision", c_int32),
-                ("max_iter", c_int32), ("tol_K", c_double), ("dT_cap_K", c_double), ("final_f64_residual", c_int32)]
+                ("max_iter", c_int32), ("tol_K", c_double), ("dT_cap_K", c_double), ("final_f64_residual", c_int32),
+                ("cond_model", c_int32)]
 
 
 class Problem(Structure):
@@ -173,8 +175,9 @@ def make_geometry(die: Die, n: int) -> tuple[Geometry, Layer]:
 
 
 def make_options(precision: int = F32, leak: int = LEAK_EXP, beta: float = 0.017, max_iter: int = 50,
-                 tol: float = 1e-3, cap: float = 1000.0, f64_residual: bool = False) -> Options:
-    return Options(leak, beta, 0, precision, max_iter, tol, cap, 1 if f64_residual else 0)
+                 tol: float = 1e-3, cap: float = 1000.0, f64_residual: bool = False,
+                 cond: int = COND_SOURCE) -> Options:
+    return Options(leak, beta, 0, precision, max_iter, tol, cap, 1 if f64_residual else 0, cond)
 
 
 class Context:

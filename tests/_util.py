@@ -39,9 +39,9 @@ def leak_code(inp):
     return {"exp": V.LEAK_EXP, "linear": V.LEAK_LINEAR, "none": V.LEAK_NONE}[inp.leak]
 
 
-def oracle_solve(inp, tol, max_iter, init=None, operator=None):
+def oracle_solve(inp, tol, max_iter, init=None, operator=None, cond="source"):
     from oracle import steady as S
 
     prob, opts = S.problem_from_inputs(inp, operator)
-    opts.tol, opts.max_iter = tol, max_iter
+    opts.tol, opts.max_iter, opts.cond = tol, max_iter, cond
     return S.solve_steady(prob, opts, init=init), prob

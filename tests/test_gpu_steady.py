@@ -18,6 +18,7 @@ from tests._util import die_of, gpu_item, leak_code, oracle_solve, to_dev
 pytestmark = pytest.mark.gpu
 
 FP32_GATE_K = 0.05
+FP32_ACHIEVED_K = 1e-4
 FP64_GATE_REL = 1e-9
 
 
@@ -30,10 +31,11 @@ def ctx(gpu_lib):
     c.close()
 
 
-def _opts(prec, inp, max_iter, tol, res=False):
+def _opts(prec, inp, max_iter, tol, res=False, cond="source"):
     from paper_2307_12119_amd import varsim as V
 
-    return V.make_options(prec, leak_code(inp), inp.beta, max_iter, tol, f64_residual=res)
+    code = {"source": V.COND_SOURCE, "target": V.COND_TARGET}[cond]
+    return V.make_options(prec, leak_code(inp), inp.beta, max_iter, tol, f64_residual=res, cond=code)
 
 
 # ----------------------------------------------------------------------------- table / conv
@@ -108,7 +110,7 @@ def test_full_size_1024_fixed_point_sampled(ctx):
     hot = np.unravel_index(int(np.argmax(got)), got.shape)
     rows = np.concatenate([[0, 1023, hot[0]], rng.integers(0, 1024, 30)])
     cols = np.concatenate([[0, 1023, hot[1]], rng.integers(0, 1024, 30)])
-    theta = prob.op.apply_at(prob.power(got, opts), rows, cols) / prob.m[rows, cols]
+    theta = prob.op.apply_at(prob.power(got, opts) / prob.m, rows, cols)
     again, ok = S.kirchhoff_inverse(theta, prob.geom.t_amb, prob.geom.eta)
     assert np.all(ok)
     assert np.max(np.abs(again - got[rows, cols])) <= 2e-3
@@ -154,18 +156,103 @@ def test_config1_fp64_converged(ctx, seed):
     assert st["residual_f64_K"] == pytest.approx(float(np.max(np.abs(again - got))), rel=1e-6, abs=1e-12)
 
 
-@pytest.mark.parametrize("n", [16, 32, 128])
-def test_fp64_variation_and_k_of_t(ctx, n):
+@pytest.mark.parametrize("n,cond", [(16, "source"), (32, "source"), (128, "source"), (32, "target"),
+                                    (128, "target")])
+def test_fp64_variation_and_k_of_t(ctx, n, cond):
     import torch
     from paper_2307_12119_amd import varsim as V
 
     inp = W.steady_problem(2, n, 64, variation=True)
+    (ref, rs), _ = oracle_solve(inp, 1e-9, 40, cond=cond)
+    item = gpu_item(inp, torch.float64)
+    st = ctx.solve_steady(item, _opts(V.F64, inp, 40, 1e-9, cond=cond))
+    assert st["status"] == V.OK and st["iterations"] == rs.iterations
+    got = item["dT_out"].cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= FP64_GATE_REL * np.max(ref)
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_fp64_conductivity_exponent_one(ctx, n):
+    """eta = 1 takes its own Kirchhoff branch (T_amb expm1(theta / T_amb)) on both paths."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    inp = W.steady_problem(2, n, 64, variation=True, eta=1.0)
     (ref, rs), _ = oracle_solve(inp, 1e-9, 40)
     item = gpu_item(inp, torch.float64)
     st = ctx.solve_steady(item, _opts(V.F64, inp, 40, 1e-9))
     assert st["status"] == V.OK and st["iterations"] == rs.iterations
     got = item["dT_out"].cpu().numpy()
     assert np.max(np.abs(got - ref)) <= FP64_GATE_REL * np.max(ref)
+    # FP32 on the same problem (the FP32 series / exp2 fallback of the eta = 1 branch)
+    item32 = gpu_item(inp, torch.float32)
+    st32 = ctx.solve_steady(item32, _opts(V.F32, inp, 40, 1e-6))
+    assert st32["status"] == V.OK
+    assert np.max(np.abs(item32["dT_out"].cpu().numpy().astype(np.float64) - ref)) <= FP32_ACHIEVED_K
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_fp64_linear_leakage(ctx, n):
+    """The paper's own leakage law (Eq. Pleak, 1 + beta dT, beta = 0.0275) in the steady loop, with
+    variation and k(T)."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    inp = W.steady_problem(2, n, 64, variation=True, beta=0.0275)
+    inp.leak = "linear"
+    (ref, rs), _ = oracle_solve(inp, 1e-9, 60)
+    item = gpu_item(inp, torch.float64)
+    st = ctx.solve_steady(item, _opts(V.F64, inp, 60, 1e-9))
+    assert st["status"] == V.OK and st["iterations"] == rs.iterations
+    got = item["dT_out"].cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= FP64_GATE_REL * np.max(ref)
+
+
+def test_fp64_leakage_aware_green_function_closed_form(ctx):
+    """Eq. detsol at alpha = 0 (linear leakage with a uniform baseline leakage mu, eta = 0, m = 1):
+    the GPU fixed point equals the one-shot spectral solution DCT-III(lambda g^ / (1 - beta mu
+    hx hy lambda)), g = hx hy (q_dyn + mu), lambda from the oracle's periodised kernel."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    n = 64
+    inp = W.config1(0, n=n)
+    mu = 0.3e6
+    inp.q_leak0 = np.full((n, n), mu)
+    inp.leak, inp.beta = "linear", 0.0275
+    item = gpu_item(inp, torch.float64)
+    st = ctx.solve_steady(item, _opts(V.F64, inp, 200, 1e-12))
+    assert st["status"] == V.OK
+    g = S.geometry_from_die(inp.die, n)
+    table = OK_.periodized_table(n, n, g.lx, g.ly, g.t, g.k_ref)
+    lam = sfft.dct(sfft.dct(table, type=1, axis=0), type=1, axis=1)[:n, :n]
+    h2 = g.hx * g.hy
+    ghat = sfft.dctn(h2 * (inp.q_dyn + mu), type=2)
+    expect = sfft.idctn(lam * ghat / (1.0 - inp.beta * mu * h2 * lam), type=2)
+    got = item["dT_out"].cpu().numpy()
+    assert np.max(np.abs(got - expect)) <= 1e-10 * np.max(expect)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_anisotropic_cells(ctx, prec):
+    """A 10 mm x 6 mm die on a square grid: hx != hy in the kernel table, the eigenvalues and the
+    cell area."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    n = 64
+    inp = W.steady_problem(2, n, 64, variation=True, die=W.Die(lx_m=10e-3, ly_m=6e-3))
+    (ref, rs), _ = oracle_solve(inp, 1e-9, 40)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    item = gpu_item(inp, dt)
+    st = ctx.solve_steady(item, _opts(V.F64 if prec == "f64" else V.F32, inp, 40, 1e-9 if prec == "f64" else 1e-6))
+    assert st["status"] == V.OK
+    got = item["dT_out"].cpu().numpy().astype(np.float64)
+    if prec == "f64":
+        assert st["iterations"] == rs.iterations
+        assert np.max(np.abs(got - ref)) <= FP64_GATE_REL * np.max(ref)
+    else:
+        assert np.max(np.abs(got - ref)) <= FP32_ACHIEVED_K
 
 
 # ----------------------------------------------------------------------------- steady FP32
@@ -208,6 +295,9 @@ def test_config2_full_size_one_map(ctx):
           f"residual_f64 {st['residual_f64_K']:.3e} K")
     assert st["status"] == V.OK and st["iterations"] == rs.iterations
     assert err <= FP32_GATE_K
+    # the error FP32 arithmetic actually reaches at equal iteration counts (about 1e-5 K): a loss
+    # of FP32 accuracy far below the 0.05 K gate (twiddles by recurrence, a dropped FMA) fails here
+    assert err <= FP32_ACHIEVED_K
 
 
 # ----------------------------------------------------------------------------- batch
@@ -224,6 +314,46 @@ def test_batch_mixed_sizes_equal_single_solves(ctx):
         s1 = ctx.solve_steady(single, opts)
         assert st["status"] == V.OK and st["iterations"] == s1["iterations"]
         assert torch.equal(item["dT_out"], single["dT_out"])
+
+
+def test_batch_large_maps_equal_single_solves_and_oracle(ctx):
+    """One batch of four distinct 512 x 512 Monte Carlo samples, two 256 x 256 and one
+    1024 x 1024 map (two-pass loop, three size groups): every map is bitwise its single solve;
+    the 256^2 and 512^2 maps are within the FP32 gate of the oracle's converged map elementwise,
+    the 1024^2 map is a fixed point of the oracle's map at sampled cells."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    inps = [W.config2(sample=s) for s in (0, 85, 170, 255)]
+    inps += [W.config3(1, s) for s in (0, 1)] + [W.config3(3, 0)]
+    order = [4, 0, 6, 1, 2, 5, 3]  # sizes interleaved in the problem array
+    inps = [inps[i] for i in order]
+    opts = _opts(V.F32, inps[0], 50, 1e-3, res=True)
+    items = [gpu_item(i, torch.float32) for i in inps]
+    stats = ctx.solve_batch(items, opts)
+    for inp, item, st in zip(inps, items, stats):
+        single = gpu_item(inp, torch.float32)
+        s1 = ctx.solve_steady(single, opts)
+        assert st["status"] == V.OK and s1 == st, inp.n
+        assert torch.equal(item["dT_out"], single["dT_out"]), inp.n
+    for inp, item, st in zip(inps, items, stats):
+        got = item["dT_out"].cpu().numpy().astype(np.float64)
+        if inp.n <= 512:
+            (ref, rs), _ = oracle_solve(inp, 1e-3, 50)
+            err = float(np.max(np.abs(got - ref)))
+            print(f"{inp.n}^2 sample {inp.meta['sample']}: iterations {st['iterations']} (oracle {rs.iterations}) "
+                  f"max |err| {err:.3e} K")
+            assert err <= FP32_GATE_K
+        else:
+            prob, o = S.problem_from_inputs(inp)
+            rng = np.random.default_rng(9)
+            hot = np.unravel_index(int(np.argmax(got)), got.shape)
+            rows = np.concatenate([[0, inp.n - 1, hot[0]], rng.integers(0, inp.n, 20)])
+            cols = np.concatenate([[inp.n - 1, 0, hot[1]], rng.integers(0, inp.n, 20)])
+            theta = prob.op.apply_at(prob.power(got, o) / prob.m, rows, cols)
+            again, ok = S.kirchhoff_inverse(theta, prob.geom.t_amb, prob.geom.eta)
+            assert np.all(ok)
+            assert np.max(np.abs(again - got[rows, cols])) <= 5e-3
 
 
 def test_batch_device_stats_equal_host_stats(ctx):

@@ -42,7 +42,7 @@ def _leak_code(name):
     return {"exp": V.LEAK_EXP, "linear": V.LEAK_LINEAR, "none": V.LEAK_NONE}[name]
 
 
-def _run_gpu(ctx, inp, dtype, out_every=1, tau="moment", leak="exp", cap=1000.0, snapshots=True):
+def _run_gpu(ctx, inp, dtype, out_every=1, tau="moment", leak="exp", cap=1000.0, snapshots=True, cond="source"):
     import torch
     from paper_2307_12119_amd import varsim as V
 
@@ -60,7 +60,8 @@ def _run_gpu(ctx, inp, dtype, out_every=1, tau="moment", leak="exp", cap=1000.0,
     snaps = None
     if snapshots and inp.n_steps // out_every > 0:
         snaps = torch.full((inp.n_steps // out_every, n, n), float("nan"), dtype=dtype, device="cuda")
-    opts = V.make_options(prec, _leak_code(leak), inp.beta, 1, 1e-3, cap=cap)
+    opts = V.make_options(prec, _leak_code(leak), inp.beta, 1, 1e-3, cap=cap,
+                          cond={"source": V.COND_SOURCE, "target": V.COND_TARGET}[cond])
     st = ctx.solve_transient(item, rects, trace, inp.dt_s, opts, snapshots=snaps, out_every=out_every,
                              tau_model=_tau_code(tau), raise_on=(V.ERR_INVALID, V.ERR_UNSUPPORTED, V.ERR_DEVICE,
                                                                   V.ERR_NO_MEMORY))
@@ -84,7 +85,7 @@ class _variants:
         self.ctx.force_transient_variant(-1, -1)
 
 
-def _oracle(inp, out_every=1, tau="moment", leak="exp"):
+def _oracle(inp, out_every=1, tau="moment", leak="exp", cond="source"):
     g = S.geometry_from_die(inp.die, inp.n)
     model = T.TransientModel(g, inp.die.rho_c, tau)
     steps = np.stack([W.raster_trace_step(inp.block_rects, inp.trace[k], inp.n) for k in range(inp.n_steps)])
@@ -92,7 +93,7 @@ def _oracle(inp, out_every=1, tau="moment", leak="exp"):
     if leak != "none" and inp.q_leak0 is not None:
         q_leak = inp.q_leak0 * (inp.leak_var if inp.leak_var is not None else 1.0)
     return T.solve_transient(model, steps, inp.dt_s, q_leak=q_leak, cond_map=inp.cond_map, leak=leak,
-                             beta=inp.beta, record_every=out_every)
+                             beta=inp.beta, record_every=out_every, cond=cond)
 
 
 CASES = [
@@ -128,6 +129,25 @@ def test_transient_fp64_matches_oracle(ctx, n, steps, dt, variation, leak, tau, 
     assert st["dT_max_K"] == pytest.approx(float(np.max(ref_last)), rel=1e-9)
     assert st["hotspot_index"] == int(np.argmax(ref_last))
     assert st["dT_mean_K"] == pytest.approx(float(np.mean(ref_last)), rel=1e-9)
+
+
+@pytest.mark.parametrize("rv_cv", [(0, 0), (3, 3)], ids=["pair", "one-row"])
+@pytest.mark.parametrize("n,eta,cond", [(32, 1.3, "target"), (64, 1.3, "target"), (32, 1.0, "source"),
+                                        (64, 1.0, "target")])
+def test_transient_fp64_placement_and_eta_one(ctx, n, eta, cond, rv_cv):
+    """The target-side conductivity factor and the eta = 1 Kirchhoff branch in both transient
+    pass families, against the full-history oracle."""
+    import torch
+
+    inp = W.transient_problem(n=n, n_steps=12, dt_s=100e-6, n_blocks=8 if n <= 32 else 24, hold_s=3e-4, seed=5,
+                              variation=True, eta=eta)
+    ref, ref_last = _oracle(inp, 2, cond=cond)
+    with _variants(ctx, rv_cv):
+        st, rec, last = _run_gpu(ctx, inp, torch.float64, 2, cond=cond)
+    assert st["status"] == 0
+    scale = max(np.max(np.abs(ref)), np.max(np.abs(ref_last)))
+    assert np.max(np.abs(rec - ref)) <= FP64_GATE_REL * scale
+    assert np.max(np.abs(last - ref_last)) <= FP64_GATE_REL * scale
 
 
 @pytest.mark.parametrize("n,steps,dt,variation,leak,tau,every", [CASES[0], CASES[2], CASES[4], CASES[6]])
@@ -239,7 +259,7 @@ def test_transient_full_size_sampled(ctx, rv_cv):
     prev = np.zeros((n, n))
     for k in range(steps):
         q = W.raster_trace_step(inp.block_rects, inp.trace[k], n) + ql * np.exp(inp.beta * prev)
-        hist.append(g.hx * g.hy * q)
+        hist.append(g.hx * g.hy * q / inp.cond_map)  # conductivity factor on the source side
         prev = rec[k]
     rng = np.random.default_rng(11)
     hot = np.unravel_index(int(np.argmax(last)), last.shape)
@@ -249,7 +269,7 @@ def test_transient_full_size_sampled(ctx, rv_cv):
     for j in range(1, steps + 1):
         op = S.DirectSum(g, table=model.step_kernel(j * dt))
         theta += op.apply_at(hist[steps - j + 1] - hist[steps - j], rows, cols)
-    expect, ok = S.kirchhoff_inverse(theta / inp.cond_map[rows, cols], g.t_amb, g.eta)
+    expect, ok = S.kirchhoff_inverse(theta, g.t_amb, g.eta)
     assert np.all(ok)
     assert np.max(np.abs(last[rows, cols] - expect)) <= FP32_GATE_K
     assert np.max(expect) > 1.0
