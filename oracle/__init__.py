@@ -11,6 +11,8 @@ kernel     cell-averaged Green's function of the die (Sec. II-B, Appendix Theore
            method of images for the die edges (Sec. IV-F)
 steady     direct spatial summation and the leakage / conductivity fixed point
            (Eqs. Pt, Pleak, condsi, fspvsk; the iterate-to-convergence ground truth of Sec. V-C)
+oneshot    one-shot leakage-aware modified Green's functions, deterministic and random parts
+           (Sec. IV-C: Eqs. detsol, randsol, detrandsol) in a well-posed discrete reading
 transient  single-pole transient Green's function (Eq. tranGreen) and full-history
            superposition of step responses (Eq. tranapprox)
 fd         brute-force finite-volume solve of the heat equation (Eq. fourier), used to pin
