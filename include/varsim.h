@@ -212,6 +212,30 @@ VARSIM_API varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_proble
                                  varsim_stats* stats, void* stream);
 
 /* ----------------------------------------------------------------------------------------
+ * Batched steady solve that allocates nothing, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * problems, options, statistics and results as varsim_solve_batch (the same kernels, bitwise
+ * equal outputs), with the workspace taken from a static device array of
+ * varsim_noalloc_scratch_bytes() bytes (32 MiB) that each GPU holds until the process ends:
+ * one 1024 x 1024 map of any precision with both variation maps and the FP64 residual fits.
+ * The call makes no hipMalloc / hipFree, so:
+ *   - every geometry of the batch must already have its Green's table in the context's cache
+ *     (varsim_green_table, or an earlier allocating solve of the same geometry), else INVALID;
+ *   - the column strip width is the tuned one if the context has it, else the default (no
+ *     timing of candidates); the fixed-point loop is launched directly (no graphs); kernel
+ *     timing is suspended for the call.
+ * The static array is shared by every call on that GPU and keeps the last call's contents (the
+ * call clears what must start at zero).  Calls that overlap on one GPU -- from different streams,
+ * threads or contexts -- race on it; calls on one stream are ordered and safe.  With device-side
+ * stats the call returns before its last kernels run, so the next call must be on the same stream.
+ * Errors: as varsim_solve_batch; NO_MEMORY when the batch's workspace exceeds the static array
+ * (nothing is launched); DEVICE if the array's device address could not be looked up.
+ */
+VARSIM_API varsim_status varsim_solve_batch_noalloc(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
+                                                    const varsim_options* opts, varsim_stats* stats, void* stream);
+VARSIM_API varsim_status varsim_noalloc_scratch_bytes(size_t* bytes);
+
+/* ----------------------------------------------------------------------------------------
  * Transient solve (Eqs. Ttran, tranGreen, tranapprox).  Starting from dT = 0 at t = 0, step n
  * holds the block powers trace[n] over (t_{n-1}, t_n]; each spatial cosine mode responds with
  * a single pole, the leakage and conductivity of step n use dT_{n-1}.  Writes dT every

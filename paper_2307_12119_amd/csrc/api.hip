@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <tuple>
@@ -17,7 +18,32 @@
 
 using namespace vs;
 
+// Workspace of varsim_solve_batch_noalloc: one static device array per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel or copy (on the host the
+// name is only a stand-in for the symbol); it uses the device address that varsim_create looks
+// up once per device with hipGetSymbolAddress.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device -> address of `scratch` there (nullptr: lookup failed)
+
+// Called with `device` current.
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+    (void)hipGetLastError();
+    ptr = nullptr;
+  }
+  g_scratch_addr[device] = ptr;
+  return ptr;
+}
+
 
 bool is_pow2_in_range(int n) { return n >= kMinN && n <= kMaxN && (n & (n - 1)) == 0; }
 
@@ -97,20 +123,35 @@ varsim_status get_table(varsim_ctx* ctx, const varsim_geometry* g, hipStream_t s
         hipMalloc(&e.coef32, coef_entries(sp.nx, sp.ny) * sizeof(float)) != hipSuccess)
       return fail(ctx, VARSIM_ERR_NO_MEMORY, "table allocation failed");
   }
-  double* scratch = nullptr;
-  if (hipMalloc(&scratch, green_table_scratch_doubles(sp.nx, sp.ny) * sizeof(double)) != hipSuccess)
+  double* tab_tmp = nullptr;
+  if (hipMalloc(&tab_tmp, green_table_scratch_doubles(sp.nx, sp.ny) * sizeof(double)) != hipSuccess)
     return fail(ctx, VARSIM_ERR_NO_MEMORY, "table scratch allocation failed");
   hipError_t err = timed(ctx, "green_table", s,
                          [&] {
                            return launch_green_table(sp, e.kper, e.lam64T, e.lam32T, e.coef64, e.coef32, lam_rowmajor,
-                                                     scratch, s);
+                                                     tab_tmp, s);
                          });
   hipError_t err2 = hipStreamSynchronize(s);
-  (void)hipFree(scratch);
+  (void)hipFree(tab_tmp);
   if (err != hipSuccess || err2 != hipSuccess)
     return fail(ctx, VARSIM_ERR_DEVICE, "green table: %s", hipGetErrorString(err != hipSuccess ? err : err2));
   ctx->tables[key] = e;
   *out = e;
+  return VARSIM_OK;
+}
+
+// Lookup only (no allocation, no kernel): the geometry's Green's table and twiddles, which
+// varsim_green_table or an earlier solve of the same geometry put in the context's caches.
+varsim_status find_cached(varsim_ctx* ctx, const varsim_geometry* g, TableEntry* tab, TwEntry* tw) {
+  auto it = ctx->tables.find(key_of(g));
+  auto jt = ctx->twiddles.find(g->nx);
+  if (it == ctx->tables.end() || jt == ctx->twiddles.end())
+    return fail(ctx, VARSIM_ERR_INVALID,
+                "no cached Green's table for this %dx%d geometry: build it first with varsim_green_table "
+                "(which allocates) or an allocating solve",
+                g->nx, g->ny);
+  *tab = it->second;
+  *tw = jt->second;
   return VARSIM_OK;
 }
 
@@ -339,7 +380,7 @@ TransLayout make_transient_layout(const varsim_problem* p, const varsim_options*
 // Column-pass strip width for a group: the tuned choice if the context has one (timing the
 // candidates on this group's own arrays first if autotuning is on), else the default.
 varsim_status col_variant_for(varsim_ctx* ctx, const PassArgs& group, int compute, const void* coef, hipStream_t s,
-                              int* variant) {
+                              int* variant, bool may_tune = true) {
   *variant = ctx->force_col >= 0 ? ctx->force_col : 0;
   if (ctx->force_col >= 0) return VARSIM_OK;
   const auto key = std::make_tuple(group.n, compute, ilog2(group.n_maps));
@@ -348,7 +389,7 @@ varsim_status col_variant_for(varsim_ctx* ctx, const PassArgs& group, int comput
     *variant = it->second;
     return VARSIM_OK;
   }
-  if (!ctx->autotune) return VARSIM_OK;
+  if (!ctx->autotune || !may_tune) return VARSIM_OK;
   PassArgs a = group;
   a.iter = -1;  // plain transform: no solver state is read or written
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -401,10 +442,12 @@ varsim_status varsim_create(int device, varsim_ctx** out) {
   if (hipHostMalloc(&c->active_host, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
       hipHostGetDevicePointer((void**)&c->active_map, c->active_host, 0) != hipSuccess ||
       hipEventCreateWithFlags(&c->active_ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->active_ev[1], hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->active_ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->desc_ev, hipEventDisableTiming) != hipSuccess) {
     delete c;
     return VARSIM_ERR_NO_MEMORY;
   }
+  c->scratch = scratch_address(device);
   *out = c;
   return VARSIM_OK;
 }
@@ -469,6 +512,8 @@ varsim_status varsim_green_table(varsim_ctx* ctx, const varsim_geometry* geom, v
   TableEntry e;
   st = get_table(ctx, geom, s, &e, (double*)lambda_out);
   if (st != VARSIM_OK) return st;
+  TwEntry tw;
+  if ((st = get_twiddles(ctx, geom->nx, s, &tw)) != VARSIM_OK) return st;
   if (kernel_out)
     HIP_TRY(hipMemcpyAsync(kernel_out, e.kper, (size_t)(geom->nx + 1) * (geom->ny + 1) * sizeof(double),
                            hipMemcpyDeviceToDevice, s));
@@ -538,9 +583,12 @@ varsim_status varsim_workspace_size(varsim_ctx* ctx, const varsim_problem* probl
   return VARSIM_OK;
 }
 
-varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
-                                 const varsim_options* opts, void* workspace, size_t ws_bytes, varsim_stats* stats,
-                                 void* stream) {
+// The batch solve.  no_alloc: the workspace is the static scratch array and the call allocates
+// nothing -- tables and twiddles must be cached, column strip widths are not timed, the loop is
+// launched directly (no graphs) and kernel timing is off for the call.
+static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
+                                      const varsim_options* opts, void* workspace, size_t ws_bytes, varsim_stats* stats,
+                                      void* stream, bool no_alloc) {
   if (!ctx) return VARSIM_ERR_INVALID;
   if (!problems || n < 1 || !stats || !workspace) return fail(ctx, VARSIM_ERR_INVALID, "NULL argument or n < 1");
   varsim_status st = check_options(ctx, opts);
@@ -556,12 +604,27 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
   std::vector<const varsim_problem*> sorted(n);
   for (int i = 0; i < n; ++i) sorted[i] = &problems[order[i]];
   const Layout L = make_layout(sorted, opts);
-  if (ws_bytes < L.total)
+  if (ws_bytes < L.total) {
+    if (no_alloc)
+      return fail(ctx, VARSIM_ERR_NO_MEMORY, "batch needs %zu bytes of workspace, more than the %zu-byte static scratch",
+                  L.total, ws_bytes);
     return fail(ctx, VARSIM_ERR_NO_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  }
   for (Group& g : groups) {
+    if (no_alloc) {
+      if ((st = find_cached(ctx, g.geom, &g.table, &g.tw)) != VARSIM_OK) return st;
+      continue;
+    }
     if ((st = get_table(ctx, g.geom, s, &g.table)) != VARSIM_OK) return st;
     if ((st = get_twiddles(ctx, g.geom->nx, s, &g.tw)) != VARSIM_OK) return st;
   }
+  // timing records events from a pool that may grow; a no-allocation call runs untimed
+  struct TimingOff {
+    varsim_ctx* c;
+    bool saved;
+    ~TimingOff() { c->timing = saved; }
+  } timing_off{ctx, ctx->timing};
+  if (no_alloc) ctx->timing = false;
 
   char* ws = (char*)workspace;
   IterState base{};
@@ -642,10 +705,12 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
     PassArgs a = group_args(g, 1);
     const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
     const int lim = ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
-    if (g.geom->nx > lim && (st = col_variant_for(ctx, a, io, lam, s, &col_var[gi])) != VARSIM_OK) return st;
+    if (g.geom->nx > lim && (st = col_variant_for(ctx, a, io, lam, s, &col_var[gi], !no_alloc)) != VARSIM_OK)
+      return st;
     if (want_res) {
       a.use_s64 = io == VARSIM_F32 ? 1 : 0;
-      if ((st = col_variant_for(ctx, a, VARSIM_F64, g.table.coef64, s, &col_var64[gi])) != VARSIM_OK) return st;
+      if ((st = col_variant_for(ctx, a, VARSIM_F64, g.table.coef64, s, &col_var64[gi], !no_alloc)) != VARSIM_OK)
+        return st;
     }
   }
 
@@ -708,7 +773,7 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
   // after launching the next step.  Launches past a map's convergence return at once (the map
   // reads its own finished increment), so a chunk may run past the last needed iteration.
   int iters_run = 0;
-  const bool graphs = ctx->graph_chunk > 0 && !ctx->timing && any_loop;
+  const bool graphs = !no_alloc && ctx->graph_chunk > 0 && !ctx->timing && any_loop;
   // A previous call's last counts (possibly queued on another stream, behind iterations the
   // host no longer waited for) land before this call reuses the two words.
   for (int i = 0; any_loop && i < 2; ++i)
@@ -820,6 +885,26 @@ varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems
       }
   }
   return (varsim_status)worst;
+}
+
+varsim_status varsim_solve_batch(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
+                                 const varsim_options* opts, void* workspace, size_t ws_bytes, varsim_stats* stats,
+                                 void* stream) {
+  return solve_batch_impl(ctx, problems, n, opts, workspace, ws_bytes, stats, stream, false);
+}
+
+varsim_status varsim_solve_batch_noalloc(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
+                                         const varsim_options* opts, varsim_stats* stats, void* stream) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  if (!ctx->scratch)
+    return fail(ctx, VARSIM_ERR_DEVICE, "the static scratch array has no device address on device %d", ctx->device);
+  return solve_batch_impl(ctx, problems, n, opts, ctx->scratch, kScratchBytes, stats, stream, true);
+}
+
+varsim_status varsim_noalloc_scratch_bytes(size_t* bytes) {
+  if (!bytes) return VARSIM_ERR_INVALID;
+  *bytes = kScratchBytes;
+  return VARSIM_OK;
 }
 
 varsim_status varsim_solve_steady(varsim_ctx* ctx, const varsim_problem* problem, const varsim_options* opts,

@@ -47,6 +47,7 @@ struct varsim_ctx {
   using MapPtrs = vs::MapPtrs;
   using PrepArgs = vs::PrepArgs;
   int device = 0;
+  void* scratch = nullptr;  // device address of the static scratch array on `device`
   std::string err;
   std::map<TableKey, TableEntry> tables;
   std::map<int, TwEntry> twiddles;

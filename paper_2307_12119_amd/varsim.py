@@ -82,6 +82,9 @@ EXPORTS = {
                                     POINTER(Stats), c_void_p]),
     "varsim_solve_batch": (c_int, [c_void_p, POINTER(Problem), c_int32, POINTER(Options), c_void_p, c_size_t,
                                    POINTER(Stats), c_void_p]),
+    "varsim_solve_batch_noalloc": (c_int, [c_void_p, POINTER(Problem), c_int32, POINTER(Options), POINTER(Stats),
+                                           c_void_p]),
+    "varsim_noalloc_scratch_bytes": (c_int, [POINTER(c_size_t)]),
     "varsim_solve_transient": (c_int, [c_void_p, POINTER(Problem), POINTER(Transient), POINTER(Options), c_void_p,
                                        c_void_p, c_size_t, POINTER(Stats), c_void_p]),
     "varsim_transient_workspace_size": (c_int, [c_void_p, POINTER(Problem), POINTER(Transient), POINTER(Options),
@@ -305,6 +308,26 @@ class Context:
         if prep is not None:
             return arr.copy()
         return [stats[i].as_dict() for i in range(n)]
+
+    def solve_batch_noalloc(self, items: list[dict], opts: Options) -> list[dict]:
+        """varsim_solve_batch_noalloc: the same solve with the library's static workspace (no
+        device allocation by the library or here); every geometry's table must be cached
+        (green_table).  Returns per-problem stats dicts; raises on argument / device errors."""
+        probs, keep = self._problems(items)
+        n = len(items)
+        stats = (Stats * n)()
+        for i in range(n):
+            stats[i].status = -1
+        st = self.lib.varsim_solve_batch_noalloc(self.handle, probs, n, ctypes.byref(opts), stats, _stream())
+        if st in (ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY) and not all(
+                stats[i].status >= 0 for i in range(n)):
+            self._check(st, allow=())
+        return [stats[i].as_dict() for i in range(n)]
+
+    def noalloc_scratch_bytes(self) -> int:
+        nbytes = c_size_t()
+        self._check(self.lib.varsim_noalloc_scratch_bytes(ctypes.byref(nbytes)))
+        return nbytes.value
 
     def solve_steady(self, item: dict, opts: Options, workspace=None) -> dict:
         return self.solve_batch([item], opts, workspace)[0]
