@@ -236,6 +236,39 @@ VARSIM_API varsim_status varsim_solve_batch_noalloc(varsim_ctx* ctx, const varsi
 VARSIM_API varsim_status varsim_noalloc_scratch_bytes(size_t* bytes);
 
 /* ----------------------------------------------------------------------------------------
+ * One-shot solve with the paper's leakage-aware modified Green's functions (Sec. IV-C), no
+ * iteration.  Leakage is linearised, q_leak0 v (1 + beta theta) (Eq. Pt), and the leakage per
+ * unit conductivity multiplier is split into a uniform density mu and a remainder
+ * r = q_leak0 v / m - mu (Eq. expanded2):
+ *   deterministic part (Eqs. expanded3, detsol with alpha = 0): the operator (I - beta hx hy mu K)
+ *     is diagonal in the cosine basis, so theta_det = DCT-III(lambda / (1 - beta hx hy mu lambda)
+ *     . DCT-II(g)) with g = hx hy (q_dyn + q_leak0 v) / m;
+ *   random part (Eq. randsol, first order in r): theta_rand = the same operator applied to
+ *     beta hx hy r theta_det;
+ *   total (Eq. detrandsol): dT = Phi^-1(theta_det + theta_rand), the Kirchhoff inverse of k(T)
+ *     in place of the paper's empirical alpha (Eq. fspvsT).
+ * The result approximates the fixed point of varsim_solve_steady (exactly equal to it for a
+ * uniform leakage density, linear leakage and eta = 0); with final_f64_residual the stats report
+ * its distance max |G64(dT) - dT| from that fixed point.  It also serves as dT_init of an
+ * iterative solve.  The deterministic operator's table is built once per (geometry, beta mu) and
+ * cached in the context (the paper's once-per-chip deterministic Green's function).
+ *   problems, n, workspace, ws_bytes, stats, stream: as varsim_solve_batch (same workspace size;
+ *     dT_init is not read); opts: as for the steady solve, but max_iter and tol_K are not used,
+ *     leak NONE means beta = 0, and cond_model must be VARSIM_COND_SOURCE;
+ *   stats: iterations = 0, last_increment_K = NaN; max, mean, hotspot and residual as usual.
+ * Errors: INVALID, UNSUPPORTED (target-side conductivity), RUNAWAY (beta mu t / k_ref >= 1: the
+ * linearised problem has no fixed point, or a non-finite / above-cap rise), DEVICE, NO_MEMORY.
+ */
+typedef struct varsim_oneshot {
+  double mu_W_m2;        /* leakage density (W/m^2, per unit m) the deterministic part treats as uniform, >= 0 */
+  int32_t random_part;   /* 1: add the first-order random part; 0: deterministic part only (ignoring f_rand) */
+} varsim_oneshot;
+
+VARSIM_API varsim_status varsim_solve_oneshot(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
+                                              const varsim_options* opts, const varsim_oneshot* oneshot,
+                                              void* workspace, size_t ws_bytes, varsim_stats* stats, void* stream);
+
+/* ----------------------------------------------------------------------------------------
  * Transient solve (Eqs. Ttran, tranGreen, tranapprox).  Starting from dT = 0 at t = 0, step n
  * holds the block powers trace[n] over (t_{n-1}, t_n]; each spatial cosine mode responds with
  * a single pole, the leakage and conductivity of step n use dT_{n-1}.  Writes dT every

@@ -104,8 +104,9 @@ class Stats:
     increments: list = field(default_factory=list)
 
 
-def geometry_from_die(die, n: int) -> Geometry:
-    return Geometry(die.lx_m, die.ly_m, n, n, die.t_m, die.k0, die.eta, die.t_amb, die.rho_c)
+def geometry_from_die(die, n: int, ny: int | None = None) -> Geometry:
+    """Geometry of an n x n grid (n columns by ny rows when ny is given) of a die."""
+    return Geometry(die.lx_m, die.ly_m, n, ny or n, die.t_m, die.k0, die.eta, die.t_amb, die.rho_c)
 
 
 # ----------------------------------------------------------------------------- direct sum
@@ -271,7 +272,7 @@ def solve_steady(prob: SteadyProblem, opts: Options, init: np.ndarray | None = N
 
 def problem_from_inputs(inp, operator: DirectSum | None = None) -> tuple[SteadyProblem, Options]:
     """Build the oracle problem from a ``workloads.SteadyInputs``."""
-    geom = geometry_from_die(inp.die, inp.n)
+    geom = geometry_from_die(inp.die, inp.n, getattr(inp, "ny", None))
     prob = SteadyProblem(geom, inp.q_dyn, inp.q_leak0, inp.leak_var, inp.cond_map, operator)
     opts = Options(leak=inp.leak, beta=inp.beta)
     return prob, opts

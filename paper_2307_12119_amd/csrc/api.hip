@@ -52,8 +52,11 @@ varsim_status check_geometry(varsim_ctx* ctx, const varsim_geometry* g) {
   if (!(g->lx_m > 0) || !(g->ly_m > 0) || !(g->t_amb_K > 0))
     return fail(ctx, VARSIM_ERR_INVALID, "die size and ambient temperature must be positive");
   if (g->nx <= 0 || g->ny <= 0) return fail(ctx, VARSIM_ERR_INVALID, "grid size must be positive");
-  if (g->nx != g->ny || !is_pow2_in_range(g->nx))
-    return fail(ctx, VARSIM_ERR_UNSUPPORTED, "grid %dx%d: need nx == ny, a power of two in [16, 1024]", g->nx, g->ny);
+  if (!is_pow2_in_range(g->nx) || !is_pow2_in_range(g->ny))
+    return fail(ctx, VARSIM_ERR_UNSUPPORTED, "grid %dx%d: nx and ny must be powers of two in [16, 1024]", g->nx, g->ny);
+  if (row_pass_groups(g->nx, g->ny) < 1)
+    return fail(ctx, VARSIM_ERR_UNSUPPORTED, "grid %dx%d: rows of %d cells need ny >= %d", g->nx, g->ny, g->nx,
+                row_pass_rows(g->nx));
   if (g->n_layers != 1 || !g->layers)
     return fail(ctx, g->n_layers < 1 || !g->layers ? VARSIM_ERR_INVALID : VARSIM_ERR_UNSUPPORTED,
                 "exactly one layer is supported");
@@ -142,16 +145,41 @@ varsim_status get_table(varsim_ctx* ctx, const varsim_geometry* g, hipStream_t s
 
 // Lookup only (no allocation, no kernel): the geometry's Green's table and twiddles, which
 // varsim_green_table or an earlier solve of the same geometry put in the context's caches.
-varsim_status find_cached(varsim_ctx* ctx, const varsim_geometry* g, TableEntry* tab, TwEntry* tw) {
+varsim_status find_cached(varsim_ctx* ctx, const varsim_geometry* g, TableEntry* tab, TwEntry* tw, TwEntry* twc) {
   auto it = ctx->tables.find(key_of(g));
   auto jt = ctx->twiddles.find(g->nx);
-  if (it == ctx->tables.end() || jt == ctx->twiddles.end())
+  auto kt = ctx->twiddles.find(g->ny);
+  if (it == ctx->tables.end() || jt == ctx->twiddles.end() || kt == ctx->twiddles.end())
     return fail(ctx, VARSIM_ERR_INVALID,
                 "no cached Green's table for this %dx%d geometry: build it first with varsim_green_table "
                 "(which allocates) or an allocating solve",
                 g->nx, g->ny);
   *tab = it->second;
   *tw = jt->second;
+  *twc = kt->second;
+  return VARSIM_OK;
+}
+
+// Column coefficients of the leakage-aware deterministic operator lambda / (1 - c lambda) of
+// the one-shot solve (Eq. detsol), cached per (geometry, c); tab: the geometry's green table.
+varsim_status get_det_coef(varsim_ctx* ctx, const varsim_geometry* g, const TableEntry& tab, double c, hipStream_t s,
+                           DetEntry* out) {
+  const auto key = std::make_pair(key_of(g), c);
+  auto it = ctx->det_coefs.find(key);
+  if (it != ctx->det_coefs.end()) {
+    *out = it->second;
+    return VARSIM_OK;
+  }
+  DetEntry e;
+  const size_t cnt = coef_entries(g->nx, g->ny);
+  if (hipMalloc(&e.coef64, cnt * sizeof(double)) != hipSuccess || hipMalloc(&e.coef32, cnt * sizeof(float)) != hipSuccess) {
+    (void)hipFree(e.coef64);
+    return fail(ctx, VARSIM_ERR_NO_MEMORY, "deterministic-operator table allocation failed");
+  }
+  const TableSpec sp{g->nx, g->ny, g->lx_m, g->ly_m, g->layers[0].thickness_m, k_ref_of(g)};
+  HIP_TRY(timed(ctx, "det_table", s, [&] { return launch_det_coef(sp, tab.lam64T, c, e.coef64, e.coef32, s); }));
+  ctx->det_coefs[key] = e;
+  *out = e;
   return VARSIM_OK;
 }
 
@@ -273,7 +301,8 @@ struct Group {
   int first, count;  // range in sorted order
   const varsim_geometry* geom;
   TableEntry table;
-  TwEntry tw;
+  TwEntry tw;   // length nx (row passes)
+  TwEntry twc;  // length ny (column passes)
 };
 
 varsim_status validate_problem(varsim_ctx* ctx, const varsim_problem* p) {
@@ -306,7 +335,7 @@ varsim_status sort_into_groups(varsim_ctx* ctx, const varsim_problem* problems, 
         continue;
       }
     }
-    groups.push_back(Group{i, 1, g, {}, {}});
+    groups.push_back(Group{i, 1, g, {}, {}, {}});
   }
   return VARSIM_OK;
 }
@@ -316,6 +345,8 @@ varsim_status check_transient(varsim_ctx* ctx, const varsim_problem* p, const va
   if (!p || !tr) return fail(ctx, VARSIM_ERR_INVALID, "problem or transient is NULL");
   varsim_status s = check_geometry(ctx, p->geom);
   if (s != VARSIM_OK) return s;
+  if (p->geom->nx != p->geom->ny)
+    return fail(ctx, VARSIM_ERR_UNSUPPORTED, "transient solves take square grids (nx == ny)");
   if ((s = check_options(ctx, o)) != VARSIM_OK) return s;
   if (!p->dT_out) return fail(ctx, VARSIM_ERR_INVALID, "dT_out is required");
   if (!(p->geom->layers[0].rho_c_J_m3K > 0) || !std::isfinite(p->geom->layers[0].rho_c_J_m3K))
@@ -383,7 +414,7 @@ varsim_status col_variant_for(varsim_ctx* ctx, const PassArgs& group, int comput
                               int* variant, bool may_tune = true) {
   *variant = ctx->force_col >= 0 ? ctx->force_col : 0;
   if (ctx->force_col >= 0) return VARSIM_OK;
-  const auto key = std::make_tuple(group.n, compute, ilog2(group.n_maps));
+  const auto key = std::make_tuple(group.n, group.ny, compute, ilog2(group.n_maps));
   auto it = ctx->col_choice.find(key);
   if (it != ctx->col_choice.end()) {
     *variant = it->second;
@@ -400,8 +431,8 @@ varsim_status col_variant_for(varsim_ctx* ctx, const PassArgs& group, int comput
   for (int v = 0; v < kColVariants; ++v) {
     int dup = -1;
     for (int u = 0; u < v; ++u)
-      if (col_pass_columns(compute, a.n, u) == col_pass_columns(compute, a.n, v) &&
-          col_pass_pairs(compute, a.n, u) == col_pass_pairs(compute, a.n, v))
+      if (col_pass_columns(compute, a.ny, u) == col_pass_columns(compute, a.ny, v) &&
+          col_pass_pairs(compute, a.ny, u) == col_pass_pairs(compute, a.ny, v))
         dup = u;
     if (dup >= 0) {
       ms[v] = ms[dup];
@@ -463,6 +494,10 @@ void varsim_destroy(varsim_ctx* c) {
     (void)hipFree(kv.second.coef64);
     (void)hipFree(kv.second.coef32);
   }
+  for (auto& kv : c->det_coefs) {
+    (void)hipFree(kv.second.coef64);
+    (void)hipFree(kv.second.coef32);
+  }
   for (auto& kv : c->twiddles) {
     (void)hipFree(kv.second.tw64);
     (void)hipFree(kv.second.tw32);
@@ -514,6 +549,7 @@ varsim_status varsim_green_table(varsim_ctx* ctx, const varsim_geometry* geom, v
   if (st != VARSIM_OK) return st;
   TwEntry tw;
   if ((st = get_twiddles(ctx, geom->nx, s, &tw)) != VARSIM_OK) return st;
+  if ((st = get_twiddles(ctx, geom->ny, s, &tw)) != VARSIM_OK) return st;
   if (kernel_out)
     HIP_TRY(hipMemcpyAsync(kernel_out, e.kper, (size_t)(geom->nx + 1) * (geom->ny + 1) * sizeof(double),
                            hipMemcpyDeviceToDevice, s));
@@ -532,9 +568,10 @@ varsim_status varsim_conv(varsim_ctx* ctx, const varsim_geometry* geom, int32_t 
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(ctx->device));
   TableEntry tab;
-  TwEntry tw;
+  TwEntry tw, twc;
   if ((st = get_table(ctx, geom, s, &tab)) != VARSIM_OK) return st;
   if ((st = get_twiddles(ctx, geom->nx, s, &tw)) != VARSIM_OK) return st;
+  if ((st = get_twiddles(ctx, geom->ny, s, &twc)) != VARSIM_OK) return st;
   const size_t cells = (size_t)geom->nx * geom->ny, es = esize(precision);
   if (ctx->conv_maps_cap < (size_t)n_maps) {
     (void)hipFree(ctx->conv_maps);
@@ -556,7 +593,9 @@ varsim_status varsim_conv(varsim_ctx* ctx, const varsim_geometry* geom, int32_t 
   a.maps = ctx->conv_maps;
   a.n_maps = n_maps;
   a.n = geom->nx;
+  a.ny = geom->ny;
   a.tw = Twiddles{tw.tw64, tw.tw32, tw.qw64, tw.qw32};
+  a.twc = Twiddles{twc.tw64, twc.tw32, twc.qw64, twc.qw32};
   a.iter = -1;
   HIP_TRY(timed(ctx, "row_conv_head", s, [&] { return launch_row_pass(ROW_CONV_HEAD, precision, precision, a, s); }));
   HIP_TRY(timed(ctx, "col", s, [&] {
@@ -612,11 +651,12 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
   }
   for (Group& g : groups) {
     if (no_alloc) {
-      if ((st = find_cached(ctx, g.geom, &g.table, &g.tw)) != VARSIM_OK) return st;
+      if ((st = find_cached(ctx, g.geom, &g.table, &g.tw, &g.twc)) != VARSIM_OK) return st;
       continue;
     }
     if ((st = get_table(ctx, g.geom, s, &g.table)) != VARSIM_OK) return st;
     if ((st = get_twiddles(ctx, g.geom->nx, s, &g.tw)) != VARSIM_OK) return st;
+    if ((st = get_twiddles(ctx, g.geom->ny, s, &g.twc)) != VARSIM_OK) return st;
   }
   // timing records events from a pool that may grow; a no-allocation call runs untimed
   struct TimingOff {
@@ -684,6 +724,7 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
     a.maps = d_maps + g.first;
     a.n_maps = g.count;
     a.n = g.geom->nx;
+    a.ny = g.geom->ny;
     a.st = base;
     a.st.resid += (size_t)g.first * L.stride;
     a.st.sum += (size_t)g.first * L.stride;
@@ -693,6 +734,7 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
     a.st.part += (size_t)g.first * kRowGroupsMax;
     a.pp = point_params(g.geom, opts);
     a.tw = Twiddles{g.tw.tw64, g.tw.tw32, g.tw.qw64, g.tw.qw32};
+    a.twc = Twiddles{g.twc.tw64, g.twc.tw32, g.twc.qw64, g.twc.qw32};
     a.iter = iter;
     a.zero_start = 0;
     return a;
@@ -705,7 +747,8 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
     PassArgs a = group_args(g, 1);
     const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
     const int lim = ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
-    if (g.geom->nx > lim && (st = col_variant_for(ctx, a, io, lam, s, &col_var[gi], !no_alloc)) != VARSIM_OK)
+    if (!(g.geom->nx == g.geom->ny && g.geom->nx <= lim) &&
+        (st = col_variant_for(ctx, a, io, lam, s, &col_var[gi], !no_alloc)) != VARSIM_OK)
       return st;
     if (want_res) {
       a.use_s64 = io == VARSIM_F32 ? 1 : 0;
@@ -736,7 +779,7 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
           HIP_TRY(launch_zero_words(sorted[i]->dT_out, (size_t)g.geom->nx * g.geom->ny * esize(io), s));
     }
     const int lim = ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
-    own[gi] = g.geom->nx <= lim;
+    own[gi] = g.geom->nx == g.geom->ny && g.geom->nx <= lim;  // the LDS-resident solver takes square maps
     if (own[gi]) {
       const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
       HIP_TRY(timed(ctx, "small_solve", s, [&] { return launch_small_solve(io, a, opts->max_iter, lam, s); }));
@@ -859,7 +902,8 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
   }
   for (const Group& g : groups) {
     PassArgs a = group_args(g, 0);
-    HIP_TRY(launch_finalize(a.st, d_maps + g.first, g.count, io, g.geom->nx, opts->max_iter, iters_run, opts->tol_K,
+    HIP_TRY(launch_finalize(a.st, d_maps + g.first, g.count, io, g.geom->nx, g.geom->ny, opts->max_iter, iters_run,
+                            opts->tol_K,
                             want_res ? 1 : 0, d_stats + g.first, s));
   }
   if (dev_stats) {  // statistics stay on the device, in the caller's order; no synchronisation
@@ -910,6 +954,163 @@ varsim_status varsim_noalloc_scratch_bytes(size_t* bytes) {
 varsim_status varsim_solve_steady(varsim_ctx* ctx, const varsim_problem* problem, const varsim_options* opts,
                                   void* workspace, size_t ws_bytes, varsim_stats* stats, void* stream) {
   return varsim_solve_batch(ctx, problem, 1, opts, workspace, ws_bytes, stats, stream);
+}
+
+varsim_status varsim_solve_oneshot(varsim_ctx* ctx, const varsim_problem* problems, int32_t n,
+                                   const varsim_options* opts, const varsim_oneshot* os, void* workspace,
+                                   size_t ws_bytes, varsim_stats* stats, void* stream) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  if (!problems || n < 1 || !stats || !workspace || !os)
+    return fail(ctx, VARSIM_ERR_INVALID, "NULL argument or n < 1");
+  varsim_status st = check_options(ctx, opts);
+  if (st != VARSIM_OK) return st;
+  if (!(os->mu_W_m2 >= 0) || !std::isfinite(os->mu_W_m2) || (os->random_part != 0 && os->random_part != 1))
+    return fail(ctx, VARSIM_ERR_INVALID, "mu_W_m2 must be finite and >= 0, random_part 0 or 1");
+  if (opts->cond_model != VARSIM_COND_SOURCE)
+    return fail(ctx, VARSIM_ERR_UNSUPPORTED, "the one-shot solve takes the conductivity map on the source side only");
+  for (int i = 0; i < n; ++i)
+    if ((st = validate_problem(ctx, &problems[i])) != VARSIM_OK) return st;
+  const bool leak_on = opts->leak != VARSIM_LEAK_NONE;
+  const double beta = leak_on ? opts->beta_per_K : 0.0;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+
+  std::vector<int> order;
+  std::vector<Group> groups;
+  sort_into_groups(ctx, problems, n, order, groups);
+  std::vector<const varsim_problem*> sorted(n);
+  for (int i = 0; i < n; ++i) sorted[i] = &problems[order[i]];
+  const Layout L = make_layout(sorted, opts);
+  if (ws_bytes < L.total) return fail(ctx, VARSIM_ERR_NO_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  std::vector<DetEntry> det(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    Group& g = groups[gi];
+    // the deterministic operator (I - c K) is invertible while c lambda_max = beta mu t / k_ref < 1
+    // (lambda_max = sum of the kernel = t / (k_ref hx hy))
+    const double c = beta * (g.geom->lx_m / g.geom->nx) * (g.geom->ly_m / g.geom->ny) * os->mu_W_m2;
+    if (beta * os->mu_W_m2 * g.geom->layers[0].thickness_m / k_ref_of(g.geom) >= 1.0)
+      return fail(ctx, VARSIM_ERR_RUNAWAY, "beta mu t / k >= 1: the linearised leakage has no fixed point");
+    if ((st = get_table(ctx, g.geom, s, &g.table)) != VARSIM_OK) return st;
+    if ((st = get_twiddles(ctx, g.geom->nx, s, &g.tw)) != VARSIM_OK) return st;
+    if ((st = get_twiddles(ctx, g.geom->ny, s, &g.twc)) != VARSIM_OK) return st;
+    if ((st = get_det_coef(ctx, g.geom, g.table, c, s, &det[gi])) != VARSIM_OK) return st;
+  }
+
+  char* ws = (char*)workspace;
+  IterState base{};
+  base.resid = (unsigned long long*)(ws + L.resid);
+  base.sum = (double*)(ws + L.sum);
+  base.maxpack = (unsigned long long*)(ws + L.maxpack);
+  base.flags = (unsigned*)(ws + L.flags);
+  base.resid64 = (unsigned long long*)(ws + L.resid64);
+  base.stride = L.stride;
+  base.part = (double*)(ws + L.part);
+  MapPtrs* d_maps = (MapPtrs*)(ws + L.maps);
+  PrepArgs* d_prep = (PrepArgs*)(ws + L.prep);
+  int* d_order = (int*)(ws + L.order);
+  varsim_stats* d_stats = (varsim_stats*)(ws + L.stats);
+  const bool dev_stats = is_device_ptr(stats);
+  const int io = opts->precision;
+  const bool want_res = opts->final_f64_residual != 0;
+
+  wait_descriptors(ctx);
+  ctx->h_maps.assign(n, MapPtrs{});
+  ctx->h_prep.assign(n, PrepArgs{});
+  for (int i = 0; i < n; ++i) {
+    const varsim_problem* p = sorted[i];
+    MapPtrs& m = ctx->h_maps[i];
+    PrepArgs& q = ctx->h_prep[i];
+    m.qd = p->q_dyn;
+    m.dT = p->dT_out;
+    m.S = ws + L.S[i];
+    m.S64 = L.S64[i] != (size_t)-1 ? ws + L.S64[i] : nullptr;
+    const bool leak = p->q_leak0 && leak_on;
+    m.ql = leak ? (L.QL[i] != (size_t)-1 ? (const void*)(ws + L.QL[i]) : p->q_leak0) : nullptr;
+    m.minv = L.MINV[i] != (size_t)-1 ? ws + L.MINV[i] : nullptr;
+    q.q_leak0 = p->q_leak0;
+    q.leak_var = p->leak_var;
+    q.cond_map = p->cond_map;
+    q.ql_out = (leak && L.QL[i] != (size_t)-1) ? ws + L.QL[i] : nullptr;
+    q.minv_out = (void*)m.minv;
+    q.dT = p->dT_out;
+    q.flags = base.flags + i;  // dT_init is not used
+  }
+  HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(ws, L.state_end, s); }));
+  HIP_TRY(hipMemcpyAsync(d_maps, ctx->h_maps.data(), n * sizeof(MapPtrs), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_prep, ctx->h_prep.data(), n * sizeof(PrepArgs), hipMemcpyHostToDevice, s));
+  if (dev_stats) {
+    ctx->h_order = order;
+    HIP_TRY(hipMemcpyAsync(d_order, ctx->h_order.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(descriptors_sent(ctx, s));
+
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group& g = groups[gi];
+    const long cells = (long)g.geom->nx * g.geom->ny;
+    HIP_TRY(timed(ctx, "prep", s, [&] { return launch_prep(io, d_prep + g.first, g.count, cells, s); }));
+    PassArgs a{};
+    a.maps = d_maps + g.first;
+    a.n_maps = g.count;
+    a.n = g.geom->nx;
+    a.ny = g.geom->ny;
+    a.st = base;
+    a.st.resid += (size_t)g.first * L.stride;
+    a.st.sum += (size_t)g.first * L.stride;
+    a.st.maxpack += (size_t)g.first * L.stride;
+    a.st.flags += g.first;
+    a.st.resid64 += g.first;
+    a.st.part += (size_t)g.first * kRowGroupsMax;
+    a.pp = point_params(g.geom, opts);
+    a.pp.beta = beta;
+    a.pp.os_mu = os->mu_W_m2;
+    a.pp.os_rand = os->random_part && leak_on ? 1 : 0;
+    a.tw = Twiddles{g.tw.tw64, g.tw.tw32, g.tw.qw64, g.tw.qw32};
+    a.twc = Twiddles{g.twc.tw64, g.twc.tw32, g.twc.qw64, g.twc.qw32};
+    a.iter = 1;
+    a.zero_start = 1;
+    const void* dc = io == VARSIM_F32 ? (const void*)det[gi].coef32 : (const void*)det[gi].coef64;
+    const auto key = std::make_tuple(a.n, a.ny, io, ilog2(a.n_maps));
+    const auto ch = ctx->col_choice.find(key);
+    const int var = ctx->force_col >= 0 ? ctx->force_col : (ch != ctx->col_choice.end() ? ch->second : 0);
+    // g = hx hy (q_dyn + QL) / m (the head from dT = 0) -> theta_det = DCT-III(lambda_det . DCT-II(g))
+    HIP_TRY(timed(ctx, "row_head", s, [&] { return launch_row_pass(ROW_HEAD, io, io, a, s); }));
+    HIP_TRY(timed(ctx, "os_col", s, [&] { return launch_col_pass(io, a, dc, s, var); }));
+    if (a.pp.os_rand) {  // theta_rand = DCT-III(lambda_det . DCT-II(beta hx hy (QL / m - mu) theta_det))
+      HIP_TRY(timed(ctx, "os_mid", s, [&] { return launch_row_pass(ROW_OS_MID, io, io, a, s); }));
+      HIP_TRY(timed(ctx, "os_col", s, [&] { return launch_col_pass(io, a, dc, s, var); }));
+    }
+    HIP_TRY(timed(ctx, "os_tail", s, [&] { return launch_row_pass(ROW_OS_TAIL, io, io, a, s); }));
+    if (want_res) {  // distance of the one-shot rise from the fixed point: max |G64(dT) - dT|
+      PassArgs r = a;
+      r.pp = point_params(g.geom, opts);
+      r.iter = 0;
+      r.zero_start = 0;
+      r.resid_pass = 1;
+      r.use_s64 = io == VARSIM_F32 ? 1 : 0;
+      HIP_TRY(timed(ctx, "resid_head", s, [&] { return launch_row_pass(ROW_HEAD, io, VARSIM_F64, r, s); }));
+      HIP_TRY(timed(ctx, "resid_col", s, [&] { return launch_col_pass(VARSIM_F64, r, g.table.coef64, s, 0); }));
+      HIP_TRY(timed(ctx, "resid_tail", s, [&] { return launch_row_pass(ROW_RESID, io, VARSIM_F64, r, s); }));
+    }
+    HIP_TRY(launch_finalize(a.st, d_maps + g.first, g.count, io, g.geom->nx, g.geom->ny, opts->max_iter, 1, 0.0,
+                            want_res ? 1 : 0, d_stats + g.first, s, 1));
+  }
+  if (dev_stats) {
+    HIP_TRY(launch_scatter_stats(d_stats, d_order, n, stats, s));
+    settle_timing(ctx);
+    return VARSIM_OK;
+  }
+  ctx->h_stats.resize(n);
+  HIP_TRY(hipMemcpyAsync(ctx->h_stats.data(), d_stats, n * sizeof(varsim_stats), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  settle_timing(ctx);
+  int worst = VARSIM_OK;
+  for (int i = 0; i < n; ++i) {
+    stats[order[i]] = ctx->h_stats[i];
+    worst = std::max(worst, (int)ctx->h_stats[i].status);
+  }
+  if (worst != VARSIM_OK)
+    fail(ctx, (varsim_status)worst, "one-shot solve: %s", varsim_status_string((varsim_status)worst));
+  return (varsim_status)worst;
 }
 
 varsim_status varsim_transient_workspace_size(varsim_ctx* ctx, const varsim_problem* problem,
@@ -1140,8 +1341,12 @@ varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
   std::string out;
   char line[256];
   for (const auto& kv : ctx->col_choice) {
-    const int n = std::get<0>(kv.first), c = std::get<1>(kv.first), b = std::get<2>(kv.first);
-    snprintf(line, sizeof line, "col n=%d %s maps>=%d:", n, c == VARSIM_F32 ? "f32" : "f64", 1 << b);
+    const int nx = std::get<0>(kv.first), n = std::get<1>(kv.first), c = std::get<2>(kv.first),
+              b = std::get<3>(kv.first);
+    if (nx == n)
+      snprintf(line, sizeof line, "col n=%d %s maps>=%d:", n, c == VARSIM_F32 ? "f32" : "f64", 1 << b);
+    else
+      snprintf(line, sizeof line, "col nx=%d ny=%d %s maps>=%d:", nx, n, c == VARSIM_F32 ? "f32" : "f64", 1 << b);
     out += line;
     const auto& ms = ctx->col_ms[kv.first];
     for (int v = 0; v < (int)ms.size(); ++v) {

@@ -55,12 +55,13 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
   const MapPtrs mp = a.maps[map];
   Tc* S = (Tc*)(a.use_s64 ? mp.S64 : mp.S);
   const int c0 = strip * Cfg::COLS;
+  const long rs = a.n;  // row stride: the map's row length nx (N = ny is the column length)
 
 #pragma unroll
   for (int k = 0; k < Cfg::LOADS; ++k) {
     const int it = threadIdx.x + k * Cfg::THREADS;
     const int y = it / VPR, j = it % VPR;
-    const Vec<Tc, VEC> v = *reinterpret_cast<const Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC);
+    const Vec<Tc, VEC> v = *reinterpret_cast<const Vec<Tc, VEC>*>(S + y * rs + c0 + j * VEC);
 #pragma unroll
     for (int e = 0; e < VEC; ++e) lds[tile_row<Cfg, N>(y) * P + j * VEC + e] = v.v[e];
   }
@@ -152,7 +153,7 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
     Vec<Tc, VEC> v;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) v.v[e] = lds[tile_row<Cfg, N>(y) * P + j * VEC + e];
-    *reinterpret_cast<Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC) = v;
+    *reinterpret_cast<Vec<Tc, VEC>*>(S + y * rs + c0 + j * VEC) = v;
   }
 }
 
@@ -173,8 +174,10 @@ constexpr int col_pairs() {
 template <typename Tc, int N, int COLS, int PAIRS>
 hipError_t col_launch(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   using Cfg = ColCfg<Tc, N, COLS, PAIRS>;
-  hipLaunchKernelGGL((col_pass_kernel<Tc, N, COLS, PAIRS>), dim3(N / Cfg::COLS, a.n_maps), dim3(Cfg::THREADS), 0, s, a,
-                     coef, tw, qw);
+  // strips of COLS columns across the row length a.n (a power of two >= 16 >= COLS)
+  if (a.n < Cfg::COLS || a.n % Cfg::COLS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((col_pass_kernel<Tc, N, COLS, PAIRS>), dim3(a.n / Cfg::COLS, a.n_maps), dim3(Cfg::THREADS), 0, s,
+                     a, coef, tw, qw);
   return hipGetLastError();
 }
 
@@ -191,7 +194,7 @@ hipError_t col_variant(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>* t
 template <typename Tc>
 hipError_t col_dispatch_n(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw,
                           hipStream_t s) {
-  switch (a.n) {
+  switch (a.ny) {
     case 16: return col_variant<Tc, 16>(v, a, coef, tw, qw, s);
     case 32: return col_variant<Tc, 32>(v, a, coef, tw, qw, s);
     case 64: return col_variant<Tc, 64>(v, a, coef, tw, qw, s);
@@ -219,8 +222,8 @@ int col_pairs_of(int v) {
 }  // namespace
 
 hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream, int variant) {
-  if (compute == VARSIM_F32) return col_dispatch_n<float>(variant, a, (const float*)coef, a.tw.tw32, a.tw.qw32, stream);
-  return col_dispatch_n<double>(variant, a, (const double*)coef, a.tw.tw64, a.tw.qw64, stream);
+  if (compute == VARSIM_F32) return col_dispatch_n<float>(variant, a, (const float*)coef, a.twc.tw32, a.twc.qw32, stream);
+  return col_dispatch_n<double>(variant, a, (const double*)coef, a.twc.tw64, a.twc.qw64, stream);
 }
 
 int col_pass_pairs(int compute, int n, int variant) {

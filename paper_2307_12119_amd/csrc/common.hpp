@@ -59,6 +59,10 @@ struct PointParams {
   float polyf[10];
   double poly_umax64;
   double polyd[20];
+  // one-shot solve (Sec. IV-C): leakage density mu (W/m^2, per unit conductivity multiplier) that
+  // the deterministic operator treats as uniform, and whether the random part is added
+  double os_mu;
+  int os_rand;
 };
 constexpr int kPoly = 10;
 constexpr int kPoly64 = 20;

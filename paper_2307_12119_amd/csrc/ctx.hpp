@@ -32,6 +32,12 @@ struct TwEntry {
 
 using TableKey = std::tuple<int, int, double, double, double, double>;
 
+// Column coefficients of the one-shot solve's deterministic operator, per (geometry, c).
+struct DetEntry {
+  double* coef64 = nullptr;
+  float* coef32 = nullptr;
+};
+
 struct TimedEvent {
   const char* cls;
   hipEvent_t a, b;
@@ -50,6 +56,7 @@ struct varsim_ctx {
   void* scratch = nullptr;  // device address of the static scratch array on `device`
   std::string err;
   std::map<TableKey, TableEntry> tables;
+  std::map<std::pair<TableKey, double>, vs::DetEntry> det_coefs;
   std::map<int, TwEntry> twiddles;
   bool timing = false;
   std::string timing_only;  // non-empty: only this kernel class is timed
@@ -82,13 +89,13 @@ struct varsim_ctx {
   bool desc_pending = false;
   MapPtrs* conv_maps = nullptr;
   size_t conv_maps_cap = 0;
-  // column-pass strip width chosen by timing, per (n, compute type, log2 of the group size)
+  // column-pass strip width chosen by timing, per (nx, ny, compute type, log2 of the group size)
   bool autotune = false;
   int force_col = -1;  // >= 0: every column pass uses this strip-width candidate
   int force_tr_row = -1, force_tr_col = -1;  // >= 0: transient passes use these candidates
   int small_limit = -1;  // largest N solved by one LDS-resident workgroup (-1: library default, 0: off)
-  std::map<std::tuple<int, int, int>, int> col_choice;
-  std::map<std::tuple<int, int, int>, std::vector<float>> col_ms;
+  std::map<std::tuple<int, int, int, int>, int> col_choice;
+  std::map<std::tuple<int, int, int, int>, std::vector<float>> col_ms;
   // transient launch shapes per (n, precision): (row variant, column variant) and their timings
   std::map<std::pair<int, int>, std::pair<int, int>> tr_choice;
   std::map<std::pair<int, int>, std::vector<float>> tr_ms;

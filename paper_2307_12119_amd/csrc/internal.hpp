@@ -15,6 +15,11 @@ struct TableSpec {
 // unscaled.  scratch: green_table_scratch_doubles(nx, ny) doubles.
 hipError_t launch_green_table(const TableSpec& sp, double* kper, double* lam64T, float* lam32T, double* coef64,
                               float* coef32, double* lam_rowmajor, double* scratch, hipStream_t stream);
+// Column-pass coefficients of the leakage-aware deterministic operator of the one-shot solve
+// (Eq. detsol): lambda / (1 - c lambda) per mode, c = beta hx hy mu (lambda in K/W, unscaled),
+// from lam64T of the green table.
+hipError_t launch_det_coef(const TableSpec& sp, const double* lam64T, double c, double* coef64, float* coef32,
+                           hipStream_t stream);
 inline size_t coef_entries(int nx, int ny) { return (size_t)nx * (ny / 2 + 1) * 4; }
 size_t green_table_scratch_doubles(int nx, int ny);
 
@@ -29,6 +34,10 @@ enum RowMode : int {
   ROW_RESID = 3,      // S -> theta -> dT'' ; residual max |dT'' - dT| only (no write)
   ROW_CONV_HEAD = 4,  // power map (W per cell) -> row DCT-II -> S
   ROW_CONV_TAIL = 5,  // S -> row DCT-III -> theta written to the output map
+  // one-shot solve (Sec. IV-C), after a head pass from dT = 0 and a column pass with the
+  // deterministic operator's coefficients:
+  ROW_OS_MID = 6,   // S -> theta_det (stored in dT) -> beta hx hy (QL / m - mu) theta_det -> row DCT-II -> S
+  ROW_OS_TAIL = 7,  // S -> theta_rand (+ theta_det from dT) -> Phi^-1 -> dT, statistics
 };
 
 struct Twiddles {
@@ -41,10 +50,12 @@ struct Twiddles {
 struct PassArgs {
   const MapPtrs* maps;  // device array, one entry per map of the group
   int n_maps;
-  int n;  // grid size (nx == ny)
+  int n;   // row length nx (the row passes' transform length)
+  int ny;  // row count (the column passes' transform length); nx == ny for the LDS-resident solver
   IterState st;
   PointParams pp;
-  Twiddles tw;
+  Twiddles tw;   // twiddles of length nx (row passes)
+  Twiddles twc;  // twiddles of length ny (column passes)
   int iter;        // 1-based iteration index of the pass
   int zero_start;  // iteration 1 starts from dT = 0 (no warm start)
   int use_s64;     // operate on MapPtrs::S64 instead of S
@@ -91,10 +102,14 @@ hipError_t launch_small_solve(int io, const PassArgs& a, int max_iter, const voi
 // Final statistics of every map into a device varsim_stats array.
 // dst[order[i]] = src[i], i < n (per-problem statistics back into the caller's order)
 hipError_t launch_scatter_stats(const varsim_stats* src, const int* order, int n, varsim_stats* dst, hipStream_t s);
-hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, int n, int max_iter,
-                           int iters_run, double tol, int residual_done, varsim_stats* out, hipStream_t stream);
-// workgroups of one map's row pass (<= kRowGroupsMax)
-int row_pass_groups(int n);
+// oneshot = 1: statistics of the one-shot solve (iterations 0, no increment)
+hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, int nx, int ny, int max_iter,
+                           int iters_run, double tol, int residual_done, varsim_stats* out, hipStream_t stream,
+                           int oneshot = 0);
+// rows one row-pass workgroup transforms for rows of length nx; the workgroups of one map's row
+// pass (<= kRowGroupsMax) on an nx x ny grid (0 when ny is not a multiple of row_pass_rows(nx))
+int row_pass_rows(int nx);
+int row_pass_groups(int nx, int ny);
 
 // Transient solve of one map (element type T = io = compute type).
 struct TransArgs {

@@ -94,4 +94,48 @@ __device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off
   }
 }
 
+// One-shot solve (Sec. IV-C, Eqs. detsol, randsol, detrandsol), pointwise part of one row.
+//   ROW_OS_MID : theta_det slots -> stored in dT -> random-part source
+//                beta hx hy (QL / m - mu) theta_det (W per cell) for the forward transform;
+//   ROW_OS_TAIL: theta_rand slots (+ theta_det from dT when the random part is on) -> Phi^-1 ->
+//                dT, statistics (max, sum, argmax; no increment).
+template <typename Tio, typename Tc, int N, int MODE, bool NT = false>
+__device__ __forceinline__ void row_oneshot(Tc* z, const MapPtrs& mp, long off, int t, int mirror, const PointParams& pp,
+                                            LaneStats<Tc>& ls) {
+  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
+  if constexpr (MODE == ROW_OS_MID) {
+    store_slots<Tio, Tc, N, NT>((Tio*)mp.dT + off, z, t, mirror);
+    Tc r[E];
+    if (mp.ql) {
+      load_slots<Tio, Tc, N, NT>((const Tio*)mp.ql + off, r, t, mirror);
+      if (mp.minv) {
+        Tc mv[E];
+        load_slots<Tio, Tc, N, NT>((const Tio*)mp.minv + off, mv, t, mirror);
+#pragma unroll
+        for (int m = 0; m < E; ++m) r[m] *= mv[m];
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) r[m] = (Tc)0;
+    }
+    const Tc bh = (Tc)(pp.beta * pp.hxhy), mu = (Tc)pp.os_mu;
+#pragma unroll
+    for (int m = 0; m < E; ++m) z[m] = bh * (r[m] - mu) * z[m];
+  } else {
+    if (pp.os_rand) {
+      Tc d[E];
+      load_slots<Tio, Tc, N, NT>((const Tio*)mp.dT + off, d, t, mirror);
+#pragma unroll
+      for (int m = 0; m < E; ++m) z[m] += d[m];
+    }
+    Tc x[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      x[m] = (Tc)(Tio)kirchhoff_inv<Tc>(z[m], pp);
+      ls.add(x[m], x[m], (int)off + unperm<N>(t + TPF * m));
+    }
+    store_slots<Tio, Tc, N, NT>((Tio*)mp.dT + off, x, t, mirror);
+  }
+}
+
 }  // namespace vs

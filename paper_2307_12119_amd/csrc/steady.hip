@@ -11,6 +11,7 @@
 //                 colpass.hip).
 // The first row pass of a solve starts from dT_init (or 0), the last one skips the forward part.
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "fft.hpp"
@@ -29,9 +30,10 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
   constexpr int TPF = Cfg::TPF;
   constexpr int E = Shape<N>::E;
   constexpr int ST = Shape<N>::STRIDE;
-  constexpr bool INV = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_CONV_TAIL;
-  constexpr bool FWD = MODE == ROW_HEAD || MODE == ROW_MERGED || MODE == ROW_CONV_HEAD;
-  constexpr bool STATS = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID;
+  constexpr bool OS = MODE == ROW_OS_MID || MODE == ROW_OS_TAIL;
+  constexpr bool INV = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_CONV_TAIL || OS;
+  constexpr bool FWD = MODE == ROW_HEAD || MODE == ROW_MERGED || MODE == ROW_CONV_HEAD || MODE == ROW_OS_MID;
+  constexpr bool STATS = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_OS_TAIL;
   __shared__ Tc s_re[Cfg::FFTS * ST];
   __shared__ Tc s_im[Cfg::FFTS * ST];
   __shared__ double s_red[3][Cfg::WAVES];
@@ -86,6 +88,9 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
   } else if constexpr (MODE == ROW_CONV_HEAD) {
     load_slots<Tio, Tc, N, true>((const Tio*)mp.qd + oa, zr, t, mirror);
     load_slots<Tio, Tc, N, true>((const Tio*)mp.qd + ob, zi, t, mirror);
+  } else if constexpr (OS) {
+    row_oneshot<Tio, Tc, N, MODE>(zr, mp, oa, t, mirror, pp, ls);
+    row_oneshot<Tio, Tc, N, MODE>(zi, mp, ob, t, mirror, pp, ls);
   } else {
     row_pointwise<Tio, Tc, N, MODE, true>(zr, mp, oa, t, mirror, zero_old, pp, ls);
     row_pointwise<Tio, Tc, N, MODE, true>(zi, mp, ob, t, mirror, zero_old, pp, ls);
@@ -229,7 +234,8 @@ __global__ void __launch_bounds__(1024) count_active_kernel(IterState st, int n_
 // own LDS-resident workgroup has its sum in the iteration's slot.
 template <typename Tio>
 __global__ void finalize_kernel(IterState st, const MapPtrs* __restrict__ maps, int n_maps, long cells, int max_iter,
-                                int iters_run, double tol, int residual_done, int row_groups, varsim_stats* out) {
+                                int iters_run, double tol, int residual_done, int row_groups, int oneshot,
+                                varsim_stats* out) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_maps) return;
   varsim_stats s;
@@ -284,6 +290,10 @@ __global__ void finalize_kernel(IterState st, const MapPtrs* __restrict__ maps, 
     s.dT_max_K = NAN;
     s.hotspot_index = -1;
   }
+  if (oneshot) {  // the one-shot solve iterates nothing: no count, no increment
+    s.iterations = 0;
+    s.last_increment_K = NAN;
+  }
   out[m] = s;
 }
 
@@ -291,7 +301,9 @@ __global__ void finalize_kernel(IterState st, const MapPtrs* __restrict__ maps, 
 template <typename Tio, typename Tc, int N>
 hipError_t row_dispatch_mode(int mode, const PassArgs& a, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   using Cfg = RowCfg<N>;
-  const dim3 grid((N / 2) / Cfg::FFTS, a.n_maps), block(Cfg::THREADS);
+  // rows of the map: a.ny, 2 FFTS per workgroup (the host admits only grids where they divide)
+  if (a.ny < 2 * Cfg::FFTS || a.ny % (2 * Cfg::FFTS)) return hipErrorInvalidValue;
+  const dim3 grid((a.ny / 2) / Cfg::FFTS, a.n_maps), block(Cfg::THREADS);
   switch (mode) {
     case ROW_HEAD: hipLaunchKernelGGL((row_pass_kernel<Tio, Tc, N, ROW_HEAD>), grid, block, 0, s, a, tw, qw); break;
     case ROW_MERGED: hipLaunchKernelGGL((row_pass_kernel<Tio, Tc, N, ROW_MERGED>), grid, block, 0, s, a, tw, qw); break;
@@ -302,6 +314,18 @@ hipError_t row_dispatch_mode(int mode, const PassArgs& a, const Cx<Tc>* tw, cons
       break;
     case ROW_CONV_TAIL:
       hipLaunchKernelGGL((row_pass_kernel<Tio, Tc, N, ROW_CONV_TAIL>), grid, block, 0, s, a, tw, qw);
+      break;
+    case ROW_OS_MID:
+      if constexpr (std::is_same<Tio, Tc>::value)
+        hipLaunchKernelGGL((row_pass_kernel<Tio, Tc, N, ROW_OS_MID>), grid, block, 0, s, a, tw, qw);
+      else
+        return hipErrorInvalidValue;
+      break;
+    case ROW_OS_TAIL:
+      if constexpr (std::is_same<Tio, Tc>::value)
+        hipLaunchKernelGGL((row_pass_kernel<Tio, Tc, N, ROW_OS_TAIL>), grid, block, 0, s, a, tw, qw);
+      else
+        return hipErrorInvalidValue;
       break;
     default: return hipErrorInvalidValue;
   }
@@ -379,31 +403,37 @@ hipError_t launch_scatter_stats(const varsim_stats* src, const int* order, int n
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, int n, int max_iter,
-                           int iters_run, double tol, int residual_done, varsim_stats* out, hipStream_t stream) {
-  const long cells = (long)n * n;
-  const int groups = row_pass_groups(n);
+hipError_t launch_finalize(const IterState& st, const MapPtrs* maps, int n_maps, int io, int nx, int ny, int max_iter,
+                           int iters_run, double tol, int residual_done, varsim_stats* out, hipStream_t stream,
+                           int oneshot) {
+  const long cells = (long)nx * ny;
+  const int groups = row_pass_groups(nx, ny);
   if (groups < 1 || groups > kRowGroupsMax) return hipErrorInvalidValue;
   if (io == VARSIM_F32)
     hipLaunchKernelGGL(finalize_kernel<float>, dim3((n_maps + 127) / 128), dim3(128), 0, stream, st, maps, n_maps,
-                       cells, max_iter, iters_run, tol, residual_done, groups, out);
+                       cells, max_iter, iters_run, tol, residual_done, groups, oneshot, out);
   else
     hipLaunchKernelGGL(finalize_kernel<double>, dim3((n_maps + 127) / 128), dim3(128), 0, stream, st, maps, n_maps,
-                       cells, max_iter, iters_run, tol, residual_done, groups, out);
+                       cells, max_iter, iters_run, tol, residual_done, groups, oneshot, out);
   return hipGetLastError();
 }
 
-int row_pass_groups(int n) {
-  switch (n) {
-    case 16: return (16 / 2) / RowCfg<16>::FFTS;
-    case 32: return (32 / 2) / RowCfg<32>::FFTS;
-    case 64: return (64 / 2) / RowCfg<64>::FFTS;
-    case 128: return (128 / 2) / RowCfg<128>::FFTS;
-    case 256: return (256 / 2) / RowCfg<256>::FFTS;
-    case 512: return (512 / 2) / RowCfg<512>::FFTS;
-    case 1024: return (1024 / 2) / RowCfg<1024>::FFTS;
+int row_pass_rows(int nx) {
+  switch (nx) {
+    case 16: return 2 * RowCfg<16>::FFTS;
+    case 32: return 2 * RowCfg<32>::FFTS;
+    case 64: return 2 * RowCfg<64>::FFTS;
+    case 128: return 2 * RowCfg<128>::FFTS;
+    case 256: return 2 * RowCfg<256>::FFTS;
+    case 512: return 2 * RowCfg<512>::FFTS;
+    case 1024: return 2 * RowCfg<1024>::FFTS;
     default: return 0;
   }
+}
+
+int row_pass_groups(int nx, int ny) {
+  const int r = row_pass_rows(nx);
+  return r > 0 && ny % r == 0 ? ny / r : 0;
 }
 
 }  // namespace vs

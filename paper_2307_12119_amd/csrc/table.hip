@@ -266,22 +266,25 @@ __global__ void __launch_bounds__(256) dct1_y_kernel(const double* __restrict__ 
 //     alpha = (c^2 l[p] + s^2 l[n-p]) / 2,  beta = c s (l[p] - l[n-p]) / 2,  gamma = (s^2 l[p] + c^2 l[n-p]) / 2
 // per column (alpha, gamma even and beta odd under p -> n - p, so p in [0, n/2] is stored).
 // out[q][p] = (alpha, beta, gamma, 0) for column q; l = lamT[q][.] (already scaled).
+// c_scaled != 0: the eigenvalues of the leakage-aware deterministic operator, l / (1 - c_scaled l)
+// (c_scaled = 0 leaves l exactly as it is).
 __global__ void __launch_bounds__(256) coef_kernel(const double* __restrict__ lamT, double* __restrict__ c64,
-                                                   float* __restrict__ c32, int nx, int ny) {
+                                                   float* __restrict__ c32, int nx, int ny, double c_scaled) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   const int half = ny / 2;
   if (p > half) return;
   const double* l = lamT + (size_t)q * ny;
+  auto lam = [&](int i) { return l[i] / (1.0 - c_scaled * l[i]); };
   double a, b, g;
   if (p == 0) {
-    a = 0.5 * l[0];
+    a = 0.5 * lam(0);
     b = 0.0;
     g = 0.0;
   } else {
     double sn, cs;
     sincospi(0.5 * p / ny, &sn, &cs);
-    const double lp = l[p], lq = l[ny - p];
+    const double lp = lam(p), lq = lam(ny - p);
     a = 0.5 * (cs * cs * lp + sn * sn * lq);
     b = 0.5 * cs * sn * (lp - lq);
     g = 0.5 * (sn * sn * lp + cs * cs * lq);
@@ -344,7 +347,16 @@ hipError_t launch_green_table(const TableSpec& sp, double* kper, double* lam64T,
   hipLaunchKernelGGL(dct1_y_kernel, dim3((sp.ny + 255) / 256, sp.nx), dim3(256), 0, stream, A, lam64T, lam32T,
                      lam_rowmajor, cosy, sp.nx, sp.ny, 1.0 / ((double)sp.nx * sp.ny));
   hipLaunchKernelGGL(coef_kernel, dim3((sp.ny / 2 + 1 + 255) / 256, sp.nx), dim3(256), 0, stream, lam64T, coef64, coef32,
-                     sp.nx, sp.ny);
+                     sp.nx, sp.ny, 0.0);
+  return hipGetLastError();
+}
+
+hipError_t launch_det_coef(const TableSpec& sp, const double* lam64T, double c, double* coef64, float* coef32,
+                           hipStream_t stream) {
+  // lam64T holds lambda / (nx ny)
+  const double c_scaled = c * (double)sp.nx * (double)sp.ny;
+  hipLaunchKernelGGL(coef_kernel, dim3((sp.ny / 2 + 1 + 255) / 256, sp.nx), dim3(256), 0, stream, lam64T, coef64, coef32,
+                     sp.nx, sp.ny, c_scaled);
   return hipGetLastError();
 }
 

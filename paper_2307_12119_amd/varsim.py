@@ -63,6 +63,10 @@ class Transient(Structure):
                 ("block_rects", c_void_p), ("trace", c_void_p), ("tau_model", c_int32)]
 
 
+class OneShot(Structure):
+    _fields_ = [("mu_W_m2", c_double), ("random_part", c_int32)]
+
+
 class NetConfig(Structure):
     _fields_ = [("n", c_int32), ("width", c_int32 * 5), ("shift", ctypes.c_float * 3), ("scale", ctypes.c_float * 3),
                 ("out_scale", ctypes.c_float), ("k0_W_mK", ctypes.c_float)]
@@ -85,6 +89,8 @@ EXPORTS = {
     "varsim_solve_batch_noalloc": (c_int, [c_void_p, POINTER(Problem), c_int32, POINTER(Options), POINTER(Stats),
                                            c_void_p]),
     "varsim_noalloc_scratch_bytes": (c_int, [POINTER(c_size_t)]),
+    "varsim_solve_oneshot": (c_int, [c_void_p, POINTER(Problem), c_int32, POINTER(Options), POINTER(OneShot),
+                                     c_void_p, c_size_t, POINTER(Stats), c_void_p]),
     "varsim_solve_transient": (c_int, [c_void_p, POINTER(Problem), POINTER(Transient), POINTER(Options), c_void_p,
                                        c_void_p, c_size_t, POINTER(Stats), c_void_p]),
     "varsim_transient_workspace_size": (c_int, [c_void_p, POINTER(Problem), POINTER(Transient), POINTER(Options),
@@ -171,9 +177,10 @@ class Die:
     rho_c: float = 1.66e6
 
 
-def make_geometry(die: Die, n: int) -> tuple[Geometry, Layer]:
+def make_geometry(die: Die, n: int, ny: int | None = None) -> tuple[Geometry, Layer]:
+    """Geometry of an n x n grid (n columns by ny rows when ny is given)."""
     layer = Layer(die.t_m, die.k0, die.eta, die.rho_c)
-    geom = Geometry(die.lx_m, die.ly_m, n, n, 1, None, 0, 0.0, die.t_amb)
+    geom = Geometry(die.lx_m, die.ly_m, n, ny or n, 1, None, 0, 0.0, die.t_amb)
     return geom, layer
 
 
@@ -213,28 +220,29 @@ class Context:
         return st
 
     # -------------------------------------------------------------------------------- table
-    def green_table(self, die: Die, n: int):
-        """(K_per [n+1][n+1], lambda [n][n]) as FP64 device tensors."""
+    def green_table(self, die: Die, n: int, ny: int | None = None):
+        """(K_per [ny+1][n+1], lambda [ny][n]) as FP64 device tensors (ny = n by default)."""
         import torch
 
-        geom, layer = make_geometry(die, n)
+        ny = ny or n
+        geom, layer = make_geometry(die, n, ny)
         geom.layers = ctypes.pointer(layer)
         dev = torch.device("cuda", self.device)
-        kper = torch.empty((n + 1, n + 1), dtype=torch.float64, device=dev)
-        lam = torch.empty((n, n), dtype=torch.float64, device=dev)
+        kper = torch.empty((ny + 1, n + 1), dtype=torch.float64, device=dev)
+        lam = torch.empty((ny, n), dtype=torch.float64, device=dev)
         self._check(self.lib.varsim_green_table(self.handle, ctypes.byref(geom), _ptr(kper), _ptr(lam), _stream()))
         return kper, lam
 
     def conv(self, die: Die, power, out=None):
-        """theta = mirrored Green's convolution of power maps [..., n, n] (W per cell)."""
+        """theta = mirrored Green's convolution of power maps [..., ny, nx] (W per cell)."""
         import torch
 
-        n = power.shape[-1]
-        geom, layer = make_geometry(die, n)
+        ny, n = power.shape[-2], power.shape[-1]
+        geom, layer = make_geometry(die, n, ny)
         geom.layers = ctypes.pointer(layer)
         prec = F64 if power.dtype == torch.float64 else F32
         out = torch.empty_like(power) if out is None else out
-        n_maps = power.numel() // (n * n)
+        n_maps = power.numel() // (n * ny)
         self._check(self.lib.varsim_conv(self.handle, ctypes.byref(geom), prec, _ptr(power), _ptr(out), n_maps,
                                          _stream()))
         return out
@@ -243,7 +251,7 @@ class Context:
     def _problems(self, items: list[dict]):
         geoms, layers, probs = [], [], (Problem * len(items))()
         for i, it in enumerate(items):
-            geom, layer = make_geometry(it["die"], it["dT_out"].shape[-1])
+            geom, layer = make_geometry(it["die"], it["dT_out"].shape[-1], it["dT_out"].shape[-2])
             layers.append(layer)
             geoms.append(geom)
             geom.layers = ctypes.pointer(layer)
@@ -328,6 +336,40 @@ class Context:
         nbytes = c_size_t()
         self._check(self.lib.varsim_noalloc_scratch_bytes(ctypes.byref(nbytes)))
         return nbytes.value
+
+    def solve_oneshot(self, items, opts: Options, mu_W_m2: float, random_part: bool = True, workspace=None,
+                      stats_out=None):
+        """varsim_solve_oneshot: the one-shot modified-Green's-function rise of every problem (same
+        items as solve_batch; dT_init is ignored).  Returns per-problem stats dicts (a numpy
+        structured array for a PreparedBatch); with stats_out, as solve_batch."""
+        import numpy as np
+        import torch
+
+        if isinstance(items, PreparedBatch):
+            probs, n, stats, need = items.probs, items.n, items.stats, items.workspace_bytes(opts)
+        else:
+            probs, keep = self._problems(items)
+            n = len(items)
+            stats = (Stats * n)()
+            need = self._ws_query(probs, n, opts)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=torch.device("cuda", self.device))
+        os_ = OneShot(float(mu_W_m2), 1 if random_part else 0)
+        if stats_out is not None:
+            st = self.lib.varsim_solve_oneshot(self.handle, probs, n, ctypes.byref(opts), ctypes.byref(os_),
+                                               _ptr(workspace), workspace.numel(),
+                                               ctypes.cast(_ptr(stats_out), POINTER(Stats)), _stream())
+            self._check(st)
+            return None
+        arr = np.ctypeslib.as_array(stats)
+        arr["status"] = -1
+        st = self.lib.varsim_solve_oneshot(self.handle, probs, n, ctypes.byref(opts), ctypes.byref(os_),
+                                           _ptr(workspace), workspace.numel(), stats, _stream())
+        if st in (ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY) or not bool((arr["status"] >= 0).all()):
+            self._check(st, allow=(OK, ERR_RUNAWAY) if bool((arr["status"] >= 0).all()) else (OK,))
+        if isinstance(items, PreparedBatch):
+            return arr.copy()
+        return [stats[i].as_dict() for i in range(n)]
 
     def solve_steady(self, item: dict, opts: Options, workspace=None) -> dict:
         return self.solve_batch([item], opts, workspace)[0]

@@ -21,7 +21,7 @@ def gpu_item(inp, dtype, dT_init=None):
     """Dict of device tensors for Context.solve_* from a workloads.SteadyInputs."""
     import torch
 
-    n = inp.n
+    shape = inp.q_dyn.shape
     return {
         "die": die_of(inp),
         "q_dyn": to_dev(inp.q_dyn, dtype),
@@ -29,7 +29,7 @@ def gpu_item(inp, dtype, dT_init=None):
         "leak_var": to_dev(inp.leak_var, dtype),
         "cond_map": to_dev(inp.cond_map, dtype),
         "dT_init": to_dev(dT_init, dtype) if dT_init is not None else None,
-        "dT_out": torch.zeros((n, n), dtype=dtype, device="cuda"),
+        "dT_out": torch.zeros(shape, dtype=dtype, device="cuda"),
     }
 
 

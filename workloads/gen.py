@@ -91,6 +91,11 @@ class SteadyInputs:
     beta: float = 0.017
     leak: str = "exp"  # "exp", "linear" or "none"
     meta: dict = field(default_factory=dict)
+    ny: int | None = None  # rows when the grid is not square (then n is the column count nx)
+
+    @property
+    def shape(self) -> tuple[int, int]:
+        return (self.ny or self.n, self.n)
 
 
 @dataclass
@@ -233,6 +238,41 @@ def config3(size_class: int, sample: int) -> SteadyInputs:
     """Mixed-size Monte Carlo batch: floorplan f is rasterised at N = 128 * 2^f."""
     n = 128 << size_class
     return steady_problem(3, n, 64, floorplan=size_class, sample=sample, variation=True)
+
+
+def rect_problem(nx: int, ny: int, lx_m: float = 10e-3, ly_m: float = 10e-3, seed: int = 0, n_blocks: int = 16,
+                 variation: bool = True, eta: float = 1.3, beta: float = 0.017) -> SteadyInputs:
+    """A block-floorplan problem on an nx x ny grid of an lx x ly die (rectangular grids; cells
+    may be anisotropic).  Blocks, the Vth field and the conductivity field live on a square
+    lattice of the finer cell size, are cropped to the die and area-averaged to the grid."""
+    die = replace(Die(lx_m=lx_m, ly_m=ly_m), eta=eta if variation else 0.0)
+    fine = min(lx_m / nx, ly_m / ny)
+    fx, fy = round(lx_m / fine), round(ly_m / fine)
+    if abs(fx * fine - lx_m) > 1e-9 * lx_m or abs(fy * fine - ly_m) > 1e-9 * ly_m or fx % nx or fy % ny:
+        raise ValueError("die and grid must share a fine lattice")
+    side = max(fx, fy)
+    rng = make_rng(7, seed, nx, ny)
+    # blocks drawn on the square lattice and stretched onto the fy x fx die lattice
+    blocks = random_blocks(n_blocks, rng, lattice=side)
+    lat = np.zeros((fy, fx))
+    q = rng.uniform(0.1, 2.0, size=n_blocks) * W_PER_MM2
+    for b in range(n_blocks):
+        x0, x1 = blocks.x0[b] * fx // side, (blocks.x0[b] + blocks.w[b]) * fx // side
+        y0, y1 = blocks.y0[b] * fy // side, (blocks.y0[b] + blocks.h[b]) * fy // side
+        lat[y0:max(y1, y0 + 1), x0:max(x1, x0 + 1)] = q[b]
+
+    def to_grid(a):
+        return a.reshape(ny, fy // ny, nx, fx // nx).mean(axis=(1, 3))
+
+    q_dyn = to_grid(lat)
+    leak_var = cond_map = None
+    if variation:
+        z_v = gaussian_field(side, fine, 1.0e-3, make_rng(7, seed, nx, ny, 1))[:fy, :fx]
+        z_k = gaussian_field(side, fine, 1.0e-3, make_rng(7, seed, nx, ny, 2))[:fy, :fx]
+        leak_var = to_grid(np.exp(-vth_leak_scale(die.t_amb) * z_v))
+        cond_map = to_grid(1.0 + 0.05 * (2.0 * ndtr(z_k) - 1.0))
+    return SteadyInputs(die, nx, q_dyn, 0.2 * q_dyn, leak_var, cond_map, beta, "exp",
+                        {"seed": seed, "n_blocks": n_blocks}, ny=ny)
 
 
 def uniform_problem(n: int, q_w_mm2: float, leak_w_mm2: float = 0.0, die: Die | None = None,
