@@ -11,6 +11,8 @@ kernel     cell-averaged Green's function of the die (Sec. II-B, Appendix Theore
            method of images for the die edges (Sec. IV-F)
 steady     direct spatial summation and the leakage / conductivity fixed point
            (Eqs. Pt, Pleak, condsi, fspvsk; the iterate-to-convergence ground truth of Sec. V-C)
+anderson   Anderson(1)-accelerated iteration of the same fixed point (a classical baseline,
+           not from the paper)
 oneshot    one-shot leakage-aware modified Green's functions, deterministic and random parts
            (Sec. IV-C: Eqs. detsol, randsol, detrandsol) in a well-posed discrete reading
 transient  single-pole transient Green's function (Eq. tranGreen) and full-history
