@@ -153,6 +153,8 @@ def main() -> int:
                     help="run one plain device-to-device copy of this size first (counter calibration)")
     ap.add_argument("--no-transient", action="store_true", help="skip the 1024^2 x 1000-step transient run")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-warm-started solve")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the compensated-twiddle leg (FP32 error at fixed iterations, time cost)")
     ap.add_argument("--no-oneshot", action="store_true",
                     help="skip the one-shot modified-Green's-function leg (solver, warm start, ablation)")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes (no timing of candidates)")
@@ -394,6 +396,8 @@ def main() -> int:
     if not args.no_surrogate:
         result["surrogate"], out_w = surrogate_bench(ctx, items, qd, lv, cm, out, opts, ws, args, maps_per_s,
                                                      float(it.mean()))
+    if not args.no_precision:
+        result["precision"] = precision_bench(ctx, items, out, opts, ws, args, maps_per_s)
     if not args.no_oneshot:
         ql_all = np.stack([s_[1] * s_[2] / s_[3] for s_ in samples]).astype(np.float64)
         mu = float(ql_all.mean())  # the batch's (one floorplan's) mean leakage per unit m
@@ -544,6 +548,65 @@ def mixed_bench(ctx, samples, args) -> dict:
             "_first_maps": first}
 
 
+def precision_bench(ctx, items, out_plain, opts, ws, args, plain_maps_per_s) -> dict:
+    """FP32 with compensated twiddles (hi + lo pairs for every twiddle and butterfly constant):
+    the headline batch timed with it (no kernel events), and the FP32 arithmetic error with and
+    without it -- iterate 5 of the FP32 solve against iterate 5 of the FP64 solve of the same map
+    (the GPU's FP64 path, within 1e-9 of the oracle) -- at 512^2 (maps 0-3 of the batch) and
+    1024^2 (two samples of the mixed batch's 1024^2 floorplan)."""
+    import numpy as np
+    import torch
+
+    import workloads.gen as W
+    from paper_2307_12119_amd import varsim as V
+
+    dev = out_plain.device
+    ct = V.make_options(V.F32, V.LEAK_EXP, opts.beta_per_K, opts.max_iter, opts.tol_K, f64_residual=True,
+                        compensated_twiddles=True)
+    out_c = torch.zeros_like(out_plain)
+    items_c = ctx.prepare([dict(it, dT_out=out_c[i]) for i, it in enumerate(items)])
+    for _ in range(args.warmup):
+        ctx.solve_batch(items_c, ct, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = ctx.solve_batch(items_c, ct, ws)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    res = {"compensated": {"maps_per_s": round(args.batch / el, 2), "ms_per_step": round(el * 1e3, 4),
+                           "time_vs_plain": round(plain_maps_per_s / (args.batch / el), 4),
+                           "iterations_mean": float(np.mean(st["iterations"])),
+                           "residual_f64_max_K": float(np.max(st["residual_f64_K"])),
+                           "max_diff_vs_plain_K": float((out_c - out_plain).abs().max())},
+           "note": "errors: FP32 iterate 5 against FP64 iterate 5 of the same map (fixed iteration count)"}
+
+    def errs(maps):
+        out = {}
+        for name, prec, dtype, comp in (("rounded", V.F32, torch.float32, False),
+                                        ("compensated", V.F32, torch.float32, True),
+                                        ("fp64", V.F64, torch.float64, False)):
+            its = [dict(m, q_dyn=m["q_dyn"].to(dtype), q_leak0=m["q_leak0"].to(dtype), leak_var=m["leak_var"].to(dtype),
+                        cond_map=m["cond_map"].to(dtype), dT_out=torch.zeros_like(m["q_dyn"], dtype=dtype))
+                   for m in maps]
+            o = V.make_options(prec, V.LEAK_EXP, opts.beta_per_K, 5, 1e-30, compensated_twiddles=comp)
+            ctx.solve_batch(its, o, raise_on=())
+            out[name] = [it["dT_out"].double() for it in its]
+        return {k: float(max((a - b).abs().max().item() for a, b in zip(out[k], out["fp64"])))
+                for k in ("rounded", "compensated")}
+
+    res["error_512_K"] = errs([items[i] for i in range(min(4, len(items)))])
+    d = W.Die(eta=1.3)
+    die = V.Die(d.lx_m, d.ly_m, d.t_m, d.k0, d.eta, d.t_amb, d.rho_c)
+    big = []
+    for smp in range(2):
+        inp = W.config3(3, smp)
+        t = lambda a: torch.from_numpy(a.astype(np.float32)).to(dev)  # FP32 inputs for every precision
+        big.append({"die": die, "q_dyn": t(inp.q_dyn), "q_leak0": t(inp.q_leak0), "leak_var": t(inp.leak_var),
+                    "cond_map": t(inp.cond_map)})
+    res["error_1024_K"] = errs(big)
+    return res
+
+
 def oneshot_bench(ctx, items, out_plain, opts, ws, args, mu, plain_maps_per_s, plain_iters) -> dict:
     """The paper's one-shot modified Green's functions (Sec. IV-C) on the same batch: as a
     zero-iteration solver (deterministic part only -- the paper's "ignoring f_rand" -- and with
@@ -575,19 +638,20 @@ def oneshot_bench(ctx, items, out_plain, opts, ws, args, mu, plain_maps_per_s, p
                      "max_err_pct_of_max_rise": float((err.amax(dim=(1, 2)) / out_plain.amax(dim=(1, 2))).max() * 100),
                      "residual_f64_max_K": float(np.max(st["residual_f64_K"])),
                      "statuses": sorted({int(x) for x in st["status"]})}
-    # warm start: one-shot (with the random part) then the fixed point from it
+    # warm start: one-shot (with the random part, no residual) then the fixed point from it
+    opts_os = V.make_options(V.F32, V.LEAK_EXP, opts.beta_per_K, opts.max_iter, opts.tol_K)
     init = torch.zeros_like(out_plain)
     out_w = torch.zeros_like(out_plain)
     items_i = ctx.prepare([dict(it, dT_out=init[i]) for i, it in enumerate(items)])
     items_w = ctx.prepare([dict(it, dT_init=init[i], dT_out=out_w[i]) for i, it in enumerate(items)])
     for _ in range(args.warmup):
-        ctx.solve_oneshot(items_i, opts, mu, True, ws)
+        ctx.solve_oneshot(items_i, opts_os, mu, True, ws)
         ctx.solve_batch(items_w, opts, ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = []
     for _ in range(args.steps):
-        ctx.solve_oneshot(items_i, opts, mu, True, ws)
+        ctx.solve_oneshot(items_i, opts_os, mu, True, ws)
         st = ctx.solve_batch(items_w, opts, ws)
         iters.append(st["iterations"])
     torch.cuda.synchronize()

@@ -98,6 +98,12 @@ typedef struct varsim_options {
   double dT_cap_K;              /* RUNAWAY when any dT exceeds it, > 0 (1000 K is a sane value) */
   int32_t final_f64_residual;   /* 1: report max |G64(dT) - dT| from one FP64 application */
   int32_t cond_model;           /* VARSIM_COND_SOURCE or VARSIM_COND_TARGET (placement of 1/m) */
+  int32_t compensated_twiddles; /* 0 or 1.  1: the FP32 transforms of the fixed-point passes of
+                                   varsim_solve_steady / _batch / _batch_noalloc hold every
+                                   twiddle and butterfly constant as an FP32 pair hi + lo and add
+                                   the product with lo, removing the constants' own rounding from
+                                   the result (maps of any size then take the two-pass path).
+                                   Ignored by FP64 solves, the one-shot and transient solves. */
 } varsim_options;
 
 /* One steady problem (all maps device pointers [ny][nx]; see conventions above). */
@@ -396,9 +402,11 @@ VARSIM_API varsim_status varsim_set_small_path(varsim_ctx* ctx, int32_t max_n);
 VARSIM_API varsim_status varsim_set_graph_iterations(varsim_ctx* ctx, int32_t iterations);
 /* Testing / manual tuning: every later column pass (solves and varsim_conv) uses strip-width
  * candidate `variant` (0 = default strip width, 1 = default width with two column pairs per
- * transform group, 2 = half width), and transient solves use row-pass candidate `variant` (rows per workgroup:
- * default, half, one pair) and column candidate `variant` (default, half, quarter width);
- * -1 returns to the default or tuned choices. */
+ * transform group, 2 = half width, 3 / 4 = the wide strip of 128-byte row segments whose
+ * transforms use the strip's own tile columns as scratch, one / two pairs per group; square
+ * maps only, rectangular ones keep 0), and transient solves use row-pass candidate `variant`
+ * and column candidate `variant` (see varsim_force_transient_variant); -1 returns to the
+ * default or tuned choices.  VARSIM_ERR_INVALID outside [-1, 4]. */
 VARSIM_API varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t variant);
 /* Testing / manual tuning of transient solves: row-pass candidate `row_variant` and column-pass
  * candidate `col_variant`, each in [0, 6): 0..2 transform two rows (columns) per DFT (row: rows

@@ -78,6 +78,8 @@ varsim_status check_options(varsim_ctx* ctx, const varsim_options* o) {
   if (o->sv_radius != 0) return fail(ctx, VARSIM_ERR_UNSUPPORTED, "only sv_radius = 0 is supported");
   if (o->cond_model != VARSIM_COND_SOURCE && o->cond_model != VARSIM_COND_TARGET)
     return fail(ctx, VARSIM_ERR_INVALID, "bad cond_model");
+  if (o->compensated_twiddles != 0 && o->compensated_twiddles != 1)
+    return fail(ctx, VARSIM_ERR_INVALID, "compensated_twiddles must be 0 or 1");
   return VARSIM_OK;
 }
 
@@ -98,9 +100,10 @@ varsim_status get_twiddles(varsim_ctx* ctx, int n, hipStream_t s, TwEntry* out) 
   }
   TwEntry e;
   if (hipMalloc(&e.tw64, n * sizeof(Cx<double>)) != hipSuccess || hipMalloc(&e.tw32, n * sizeof(Cx<float>)) != hipSuccess ||
-      hipMalloc(&e.qw64, n * sizeof(Cx<double>)) != hipSuccess || hipMalloc(&e.qw32, n * sizeof(Cx<float>)) != hipSuccess)
+      hipMalloc(&e.qw64, n * sizeof(Cx<double>)) != hipSuccess || hipMalloc(&e.qw32, n * sizeof(Cx<float>)) != hipSuccess ||
+      hipMalloc(&e.tw32lo, n * sizeof(Cx<float>)) != hipSuccess || hipMalloc(&e.qw32lo, n * sizeof(Cx<float>)) != hipSuccess)
     return fail(ctx, VARSIM_ERR_NO_MEMORY, "twiddle table allocation failed");
-  HIP_TRY(launch_twiddles(n, e.tw64, e.tw32, e.qw64, e.qw32, s));
+  HIP_TRY(launch_twiddles(n, e.tw64, e.tw32, e.qw64, e.qw32, e.tw32lo, e.qw32lo, s));
   HIP_TRY(hipStreamSynchronize(s));
   ctx->twiddles[n] = e;
   *out = e;
@@ -413,7 +416,7 @@ TransLayout make_transient_layout(const varsim_problem* p, const varsim_options*
 varsim_status col_variant_for(varsim_ctx* ctx, const PassArgs& group, int compute, const void* coef, hipStream_t s,
                               int* variant, bool may_tune = true) {
   *variant = ctx->force_col >= 0 ? ctx->force_col : 0;
-  if (ctx->force_col >= 0) return VARSIM_OK;
+  if (ctx->force_col >= 0 || group.n != group.ny) return VARSIM_OK;  // rectangular maps: default strip
   const auto key = std::make_tuple(group.n, group.ny, compute, ilog2(group.n_maps));
   auto it = ctx->col_choice.find(key);
   if (it != ctx->col_choice.end()) {
@@ -503,6 +506,8 @@ void varsim_destroy(varsim_ctx* c) {
     (void)hipFree(kv.second.tw32);
     (void)hipFree(kv.second.qw64);
     (void)hipFree(kv.second.qw32);
+    (void)hipFree(kv.second.tw32lo);
+    (void)hipFree(kv.second.qw32lo);
   }
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.a);
@@ -594,8 +599,8 @@ varsim_status varsim_conv(varsim_ctx* ctx, const varsim_geometry* geom, int32_t 
   a.n_maps = n_maps;
   a.n = geom->nx;
   a.ny = geom->ny;
-  a.tw = Twiddles{tw.tw64, tw.tw32, tw.qw64, tw.qw32};
-  a.twc = Twiddles{twc.tw64, twc.tw32, twc.qw64, twc.qw32};
+  a.tw = twiddles_of(tw);
+  a.twc = twiddles_of(twc);
   a.iter = -1;
   HIP_TRY(timed(ctx, "row_conv_head", s, [&] { return launch_row_pass(ROW_CONV_HEAD, precision, precision, a, s); }));
   HIP_TRY(timed(ctx, "col", s, [&] {
@@ -733,8 +738,9 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
     a.st.resid64 += g.first;
     a.st.part += (size_t)g.first * kRowGroupsMax;
     a.pp = point_params(g.geom, opts);
-    a.tw = Twiddles{g.tw.tw64, g.tw.tw32, g.tw.qw64, g.tw.qw32};
-    a.twc = Twiddles{g.twc.tw64, g.twc.tw32, g.twc.qw64, g.twc.qw32};
+    a.tw = twiddles_of(g.tw);
+    a.twc = twiddles_of(g.twc);
+    a.ct = opts->compensated_twiddles && io == VARSIM_F32 ? 1 : 0;
     a.iter = iter;
     a.zero_start = 0;
     return a;
@@ -746,7 +752,9 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
     const Group& g = groups[gi];
     PassArgs a = group_args(g, 1);
     const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
-    const int lim = ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
+    // the LDS-resident solver has no compensated-twiddle variant: such solves take the two passes
+    const int lim = opts->compensated_twiddles && io == VARSIM_F32 ? 0
+                    : ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
     if (!(g.geom->nx == g.geom->ny && g.geom->nx <= lim) &&
         (st = col_variant_for(ctx, a, io, lam, s, &col_var[gi], !no_alloc)) != VARSIM_OK)
       return st;
@@ -778,7 +786,9 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
         if (!sorted[i]->dT_init)
           HIP_TRY(launch_zero_words(sorted[i]->dT_out, (size_t)g.geom->nx * g.geom->ny * esize(io), s));
     }
-    const int lim = ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
+    // the LDS-resident solver has no compensated-twiddle variant: such solves take the two passes
+    const int lim = opts->compensated_twiddles && io == VARSIM_F32 ? 0
+                    : ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
     own[gi] = g.geom->nx == g.geom->ny && g.geom->nx <= lim;  // the LDS-resident solver takes square maps
     if (own[gi]) {
       const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
@@ -1064,8 +1074,8 @@ varsim_status varsim_solve_oneshot(varsim_ctx* ctx, const varsim_problem* proble
     a.pp.beta = beta;
     a.pp.os_mu = os->mu_W_m2;
     a.pp.os_rand = os->random_part && leak_on ? 1 : 0;
-    a.tw = Twiddles{g.tw.tw64, g.tw.tw32, g.tw.qw64, g.tw.qw32};
-    a.twc = Twiddles{g.twc.tw64, g.twc.tw32, g.twc.qw64, g.twc.qw32};
+    a.tw = twiddles_of(g.tw);
+    a.twc = twiddles_of(g.twc);
     a.iter = 1;
     a.zero_start = 1;
     const void* dc = io == VARSIM_F32 ? (const void*)det[gi].coef32 : (const void*)det[gi].coef64;
@@ -1164,7 +1174,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   a.out_every = tr->out_every;
   a.flags = d_flags;
   a.pp = point_params(g, opts);
-  a.tw = Twiddles{tw.tw64, tw.tw32, tw.qw64, tw.qw32};
+  a.tw = twiddles_of(tw);
   a.idz = (const int*)(ws + L.IDZ);
   a.qlz = a.ql ? ws + L.QLZ : nullptr;
   a.minvz = a.minv ? ws + L.MINVZ : nullptr;

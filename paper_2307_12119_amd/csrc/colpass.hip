@@ -4,6 +4,7 @@
 // the merge for the inverse), and the column DCT-III, in place.  The strip width is a tuning
 // parameter: the library times the candidates on the actual batch and keeps the fastest.
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "fft.hpp"
@@ -31,11 +32,14 @@ __device__ __forceinline__ void xcd_strip_tile(int& strip, int& map) {
   map = i / per;
 }
 
-template <typename Tc, int N, int COLS, int PAIRS>
-__global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
+// SQ: square map, row stride N known at compile time (otherwise the run-time row length a.n;
+// a run-time stride costs the square maps about 15 % of the pass).  CT: compensated twiddles
+// (twl: low parts of tw; FP32 only).
+template <typename Tc, int N, int COLS, int PAIRS, bool SQ, bool CT = false, bool INPL = false>
+__global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS, INPL>::THREADS))
     col_pass_kernel(PassArgs a, const Tc* __restrict__ coef, const Cx<Tc>* __restrict__ tw,
-                    const Cx<Tc>* __restrict__ qw) {
-  using Cfg = ColCfg<Tc, N, COLS, PAIRS>;
+                    const Cx<Tc>* __restrict__ qw, const Cx<Tc>* __restrict__ twl) {
+  using Cfg = ColCfg<Tc, N, COLS, PAIRS, INPL>;
   constexpr int TPF = Cfg::TPF;
   constexpr int E = Shape<N>::E;
   constexpr int ST = Shape<N>::STRIDE;
@@ -55,7 +59,7 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
   const MapPtrs mp = a.maps[map];
   Tc* S = (Tc*)(a.use_s64 ? mp.S64 : mp.S);
   const int c0 = strip * Cfg::COLS;
-  const long rs = a.n;  // row stride: the map's row length nx (N = ny is the column length)
+  const long rs = SQ ? (long)N : (long)a.n;  // row stride: the row length nx (N = ny is the column length)
 
 #pragma unroll
   for (int k = 0; k < Cfg::LOADS; ++k) {
@@ -72,8 +76,10 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
   if constexpr (TPF == 64) f = __builtin_amdgcn_readfirstlane(f);
   const int t = threadIdx.x % TPF;
   // split, multiply by lambda and merge in one step (coefficients alpha, beta, gamma per column)
+  // LS: element stride of the transform scratch (P when it is the pair's own tile columns)
+  constexpr int LS = Cfg::INPL ? P : 1;
   auto spectral = [&](Tc* zr, Tc* zi, int q, Tc* re, Tc* im) {
-    fft_reg<Tc, N, -1>(zr, zi, re, im, tw, t);
+    fft_reg<Tc, N, -1, 1, CT, LS>(zr, zi, re, im, tw, t, twl);
     Tc pr[E], pim[E];
     partner<Tc, N, true>(zr, pr, t);
     partner<Tc, N, true>(zi, pim, t);
@@ -87,9 +93,32 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
       lambda_pair<Tc>(ca[pi], cb[pi], hi, zr[m], zi[m], pr[m], pim[m]);
     }
     wave_sync();
-    fft_reg<Tc, N, +1>(zr, zi, re, im, tw, t);
+    fft_reg<Tc, N, +1, 1, CT, LS>(zr, zi, re, im, tw, t, twl);
   };
-  if constexpr (Cfg::LAZY) {
+  if constexpr (Cfg::INPL) {
+    // pair q's scratch is its own tile columns c (real) and c + 1 (imaginary): the values are
+    // in registers before the transform first writes there, and other pairs never touch them
+#pragma unroll 1
+    for (int q = 0; q < NP; ++q) {
+      const int c = 2 * (f + Cfg::FFTS * q);
+      Tc zr[E], zi[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int y = tile_slot<Cfg, N>(t + TPF * m);
+        zr[m] = lds[y * P + c];
+        zi[m] = lds[y * P + c + 1];
+      }
+      spectral(zr, zi, q, lds + c, lds + c + 1);
+      wave_sync();  // the transform's last scratch reads are done before the results overwrite rows
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int y = tile_slot<Cfg, N>(t + TPF * m);
+        lds[y * P + c] = zr[m];
+        lds[y * P + c + 1] = zi[m];
+      }
+    }
+    __syncthreads();
+  } else if constexpr (Cfg::LAZY) {
     Tc* re = lds + Cfg::TILE + f * ST;  // scratch after the tile: real parts, then imaginary parts
     Tc* im = lds + Cfg::TILE + Cfg::FFTS * ST + f * ST;
 #pragma unroll 1
@@ -159,36 +188,68 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS>::THREADS))
 
 // Strip-width candidates: 0 = the default width, 1 = the default width with two column pairs
 // per transform group (half the wavefronts, each taking its pairs from the tile in turn), 2 =
-// half the default width.
+// half the default width, 3 / 4 = the wide in-place strip (128-byte row segments where two
+// workgroups' tiles fit one CU's LDS) with one / two pairs per transform group.
+template <typename Tc, int N>
+constexpr int col_wide() {
+  int c = 128 / (int)sizeof(Tc);
+  while (c > 2 && (long)Shape<N>::STRIDE * (c + 1) * (long)sizeof(Tc) > 80000) c /= 2;
+  return c < N ? c : N;
+}
 template <typename Tc, int N, int V>
 constexpr int col_candidate() {
   constexpr int c0 = ColCfg<Tc, N>::COLS;
-  constexpr int c = V == 2 ? c0 / 2 : c0;
+  constexpr int c = V >= 3 ? col_wide<Tc, N>() : (V == 2 ? c0 / 2 : c0);
   return c < 2 ? 2 : (c > N ? N : c);
 }
 template <int V>
 constexpr int col_pairs() {
-  return V == 1 ? 2 : 1;
+  return V == 1 || V == 4 ? 2 : 1;
+}
+template <int V>
+constexpr bool col_inplace() {
+  return V >= 3;
 }
 
-template <typename Tc, int N, int COLS, int PAIRS>
+template <typename Tc, int N, int COLS, int PAIRS, bool SQ = true, bool CT = false, bool INPL = false>
 hipError_t col_launch(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
-  using Cfg = ColCfg<Tc, N, COLS, PAIRS>;
+  using Cfg = ColCfg<Tc, N, COLS, PAIRS, INPL>;
   // strips of COLS columns across the row length a.n (a power of two >= 16 >= COLS)
-  if (a.n < Cfg::COLS || a.n % Cfg::COLS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((col_pass_kernel<Tc, N, COLS, PAIRS>), dim3(a.n / Cfg::COLS, a.n_maps), dim3(Cfg::THREADS), 0, s,
-                     a, coef, tw, qw);
+  if (a.n < Cfg::COLS || a.n % Cfg::COLS || (SQ && a.n != N)) return hipErrorInvalidValue;
+  const Cx<Tc>* twl = nullptr;
+  if constexpr (CT) {
+    twl = (const Cx<Tc>*)a.twc.tw32lo;
+    if (!twl) return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL((col_pass_kernel<Tc, N, COLS, PAIRS, SQ, CT, INPL>), dim3(a.n / Cfg::COLS, a.n_maps),
+                     dim3(Cfg::THREADS), 0, s, a, coef, tw, qw, twl);
   return hipGetLastError();
 }
 
-template <typename Tc, int N>
-hipError_t col_variant(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+// Rectangular maps take the default strip width only (the tuner times square maps); compensated
+// twiddles are an FP32 option of square maps.
+template <typename Tc, int N, int V, bool CT>
+hipError_t col_launch_v(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+  return col_launch<Tc, N, col_candidate<Tc, N, V>(), col_pairs<V>(), true, CT, col_inplace<V>()>(a, coef, tw, qw, s);
+}
+template <typename Tc, int N, bool CT>
+hipError_t col_variant_ct(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   switch (v) {
-    case 0: return col_launch<Tc, N, col_candidate<Tc, N, 0>(), col_pairs<0>()>(a, coef, tw, qw, s);
-    case 1: return col_launch<Tc, N, col_candidate<Tc, N, 1>(), col_pairs<1>()>(a, coef, tw, qw, s);
-    case 2: return col_launch<Tc, N, col_candidate<Tc, N, 2>(), col_pairs<2>()>(a, coef, tw, qw, s);
+    case 0: return col_launch_v<Tc, N, 0, CT>(a, coef, tw, qw, s);
+    case 1: return col_launch_v<Tc, N, 1, CT>(a, coef, tw, qw, s);
+    case 2: return col_launch_v<Tc, N, 2, CT>(a, coef, tw, qw, s);
+    case 3: return col_launch_v<Tc, N, 3, CT>(a, coef, tw, qw, s);
+    case 4: return col_launch_v<Tc, N, 4, CT>(a, coef, tw, qw, s);
     default: return hipErrorInvalidValue;
   }
+}
+template <typename Tc, int N>
+hipError_t col_variant(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+  if (a.n != N) return col_launch<Tc, N, col_candidate<Tc, N, 0>(), col_pairs<0>(), false>(a, coef, tw, qw, s);
+  if constexpr (std::is_same<Tc, float>::value) {
+    if (a.ct) return col_variant_ct<Tc, N, true>(v, a, coef, tw, qw, s);
+  }
+  return col_variant_ct<Tc, N, false>(v, a, coef, tw, qw, s);
 }
 
 template <typename Tc>
@@ -208,15 +269,29 @@ hipError_t col_dispatch_n(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>
 
 template <typename Tc, int N>
 int col_cols_of(int v) {
-  return v == 0 ? col_candidate<Tc, N, 0>() : (v == 1 ? col_candidate<Tc, N, 1>() : col_candidate<Tc, N, 2>());
+  switch (v) {
+    case 0: return col_candidate<Tc, N, 0>();
+    case 1: return col_candidate<Tc, N, 1>();
+    case 2: return col_candidate<Tc, N, 2>();
+    case 3: return col_candidate<Tc, N, 3>();
+    case 4: return col_candidate<Tc, N, 4>();
+    default: return 0;
+  }
 }
 template <typename Tc, int N, int V>
 constexpr int col_pairs_eff() {
-  return ColCfg<Tc, N, col_candidate<Tc, N, V>(), col_pairs<V>()>::PAIRS;
+  return ColCfg<Tc, N, col_candidate<Tc, N, V>(), col_pairs<V>(), col_inplace<V>()>::PAIRS;
 }
 template <typename Tc, int N>
 int col_pairs_of(int v) {
-  return v == 0 ? col_pairs_eff<Tc, N, 0>() : (v == 1 ? col_pairs_eff<Tc, N, 1>() : col_pairs_eff<Tc, N, 2>());
+  switch (v) {
+    case 0: return col_pairs_eff<Tc, N, 0>();
+    case 1: return col_pairs_eff<Tc, N, 1>();
+    case 2: return col_pairs_eff<Tc, N, 2>();
+    case 3: return col_pairs_eff<Tc, N, 3>();
+    case 4: return col_pairs_eff<Tc, N, 4>();
+    default: return 0;
+  }
 }
 
 }  // namespace

@@ -28,7 +28,11 @@ struct TwEntry {
   Cx<float>* tw32 = nullptr;
   Cx<double>* qw64 = nullptr;
   Cx<float>* qw32 = nullptr;
+  Cx<float>* tw32lo = nullptr;  // low parts of tw32 / qw32 (compensated twiddles)
+  Cx<float>* qw32lo = nullptr;
 };
+
+inline Twiddles twiddles_of(const TwEntry& e) { return Twiddles{e.tw64, e.tw32, e.qw64, e.qw32, e.tw32lo, e.qw32lo}; }
 
 using TableKey = std::tuple<int, int, double, double, double, double>;
 

@@ -100,6 +100,19 @@ __device__ __forceinline__ T dot2(T a, T b, T c, T d) {
   return fma(a, b, c * d);
 }
 
+// Compensated twiddles (CT): a constant w held as w_hi + w_lo, w_hi = w rounded to T and
+// w_lo = (w - w_hi) rounded, so a product x w is x w_hi plus the correction x w_lo, which
+// removes the rounding of the constant itself from the result (an option of the FP32
+// transforms; FP64 never uses it).
+template <typename T>
+struct Split {
+  T hi, lo;
+};
+template <typename T>
+__host__ __device__ constexpr Split<T> split_const(double w) {
+  return {(T)w, (T)(w - (double)(T)w)};
+}
+
 // multiply by DIR * i
 template <typename T, int DIR>
 __device__ __forceinline__ void mul_i(T& r, T& i) {
@@ -151,7 +164,7 @@ __device__ __forceinline__ void dft4s(T* r, T* i, int b, int s) {
   }
 }
 
-template <typename T, int DIR>
+template <typename T, int DIR, bool CT = false>
 __device__ __forceinline__ void dft8(T* r, T* i) {
   T er[4] = {r[0], r[2], r[4], r[6]}, ei[4] = {i[0], i[2], i[4], i[6]};
   T orr[4] = {r[1], r[3], r[5], r[7]}, oi[4] = {i[1], i[3], i[5], i[7]};
@@ -170,6 +183,18 @@ __device__ __forceinline__ void dft8(T* r, T* i) {
   const T c = (T)0.70710678118654752440084436210485;
   const T x1 = orr[1] - (T)DIR * oi[1], y1 = oi[1] + (T)DIR * orr[1];
   const T x3 = -orr[3] - (T)DIR * oi[3], y3 = -oi[3] + (T)DIR * orr[3];
+  if constexpr (CT) {
+    constexpr T cl = split_const<T>(0.70710678118654752440084436210485).lo;
+    r[1] = fma(cl, x1, fma(c, x1, er[1]));
+    i[1] = fma(cl, y1, fma(c, y1, ei[1]));
+    r[5] = fma(-cl, x1, fma(-c, x1, er[1]));
+    i[5] = fma(-cl, y1, fma(-c, y1, ei[1]));
+    r[3] = fma(cl, x3, fma(c, x3, er[3]));
+    i[3] = fma(cl, y3, fma(c, y3, ei[3]));
+    r[7] = fma(-cl, x3, fma(-c, x3, er[3]));
+    i[7] = fma(-cl, y3, fma(-c, y3, ei[3]));
+    return;
+  }
   r[1] = fma(c, x1, er[1]);
   i[1] = fma(c, y1, ei[1]);
   r[5] = fma(-c, x1, er[1]);
@@ -181,13 +206,18 @@ __device__ __forceinline__ void dft8(T* r, T* i) {
 }
 
 // radix 16 as 4 x 4: inner DFT-4 over n1 of x[4 n1 + n2], twiddle W16^(n2 k1), outer DFT-4 over n2
-template <typename T, int DIR>
+template <typename T, int DIR, bool CT = false>
 __device__ __forceinline__ void dft16(T* r, T* i) {
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2) dft4s<T, DIR>(r, i, n2, 4);  // a[n2 + 4 k1]
-  const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, h = (T)0.70710678118654752440;
+  constexpr double C1 = 0.92387953251128675613, S1 = 0.38268343236508977173, H = 0.70710678118654752440;
+  const T c1 = (T)C1, s1 = (T)S1, h = (T)H;
   const T cs[10] = {(T)1, c1, h, s1, (T)0, -s1, -h, -c1, (T)-1, -c1};  // cos(2 pi j / 16), j = 0..9
   const T sn[10] = {(T)0, s1, h, c1, (T)1, c1, h, s1, (T)0, -s1};      // sin(2 pi j / 16)
+  // low parts of the same constants (compensated twiddles)
+  constexpr T c1l = split_const<T>(C1).lo, s1l = split_const<T>(S1).lo, hl = split_const<T>(H).lo;
+  const T csl[10] = {(T)0, c1l, hl, s1l, (T)0, -s1l, -hl, -c1l, (T)0, -c1l};
+  const T snl[10] = {(T)0, s1l, hl, c1l, (T)0, c1l, hl, s1l, (T)0, -s1l};
 #pragma unroll
   for (int n2 = 1; n2 < 4; ++n2)
 #pragma unroll
@@ -198,6 +228,11 @@ __device__ __forceinline__ void dft16(T* r, T* i) {
       const T a = r[e], b = i[e];
       r[e] = dot2(a, wr, -b, wi);
       i[e] = dot2(a, wi, b, wr);
+      if constexpr (CT) {
+        const T wrl = csl[j], wil = (T)DIR * snl[j];
+        r[e] = fma(a, wrl, fma(-b, wil, r[e]));
+        i[e] = fma(a, wil, fma(b, wrl, i[e]));
+      }
     }
   T yr[16], yi[16];
 #pragma unroll
@@ -218,18 +253,21 @@ __device__ __forceinline__ void dft16(T* r, T* i) {
   }
 }
 
-template <typename T, int R, int DIR>
+template <typename T, int R, int DIR, bool CT = false>
 __device__ __forceinline__ void dft_r(T* r, T* i) {
-  if constexpr (R == 16) dft16<T, DIR>(r, i);
-  else if constexpr (R == 8) dft8<T, DIR>(r, i);
+  if constexpr (R == 16) dft16<T, DIR, CT>(r, i);
+  else if constexpr (R == 8) dft8<T, DIR, CT>(r, i);
   else if constexpr (R == 4) dft4<T, DIR>(r, i);
   else dft2<T, DIR>(r, i);
 }
 
 // Stockham stages of span NS onwards: LDS in, LDS out (middle) or registers out (last).
 // tw[TS k] = exp(-2 pi i k / N): TS = 1 with the table of N, TS = 2 with the table of 2N.
-template <typename T, int N, int NS, int DIR, int TS = 1>
-__device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx<T>* __restrict__ tw, int t) {
+// CT: twl holds the low parts of the same twiddles (compensated twiddles).  LS: element stride
+// of the LDS buffer (1: re / im contiguous; > 1: a column of a row-major tile of pitch LS).
+template <typename T, int N, int NS, int DIR, int TS = 1, bool CT = false, int LS = 1>
+__device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx<T>* __restrict__ tw, int t,
+                                            const Cx<T>* __restrict__ twl = nullptr) {
   constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
   constexpr int R = (N / NS >= 8) ? 8 : (N / NS);
   constexpr int NB = N / R, PER = E / R;
@@ -241,8 +279,8 @@ __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int s = lds_at<N>(b + r * NB);
-      yr[u * R + r] = re[s];
-      yi[u * R + r] = im[s];
+      yr[u * R + r] = re[s * LS];
+      yi[u * R + r] = im[s * LS];
     }
   }
   wave_sync();
@@ -257,8 +295,14 @@ __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx
       const T a = yr[u * R + r], c = yi[u * R + r];
       yr[u * R + r] = dot2(a, w.r, -c, wi);
       yi[u * R + r] = dot2(a, wi, c, w.r);
+      if constexpr (CT) {
+        const Cx<T> wl = twl[TS * j * r * (N / (NS * R))];
+        const T wli = DIR < 0 ? wl.i : -wl.i;
+        yr[u * R + r] = fma(a, wl.r, fma(-c, wli, yr[u * R + r]));
+        yi[u * R + r] = fma(a, wli, fma(c, wl.r, yi[u * R + r]));
+      }
     }
-    dft_r<T, R, DIR>(yr + u * R, yi + u * R);
+    dft_r<T, R, DIR, CT>(yr + u * R, yi + u * R);
     if constexpr (LAST) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -270,32 +314,33 @@ __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int s = lds_at<N>(base + r * NS);
-        re[s] = yr[u * R + r];
-        im[s] = yi[u * R + r];
+        re[s * LS] = yr[u * R + r];
+        im[s * LS] = yi[u * R + r];
       }
     }
   }
   if constexpr (!LAST) {
     wave_sync();
-    stages_from<T, N, NS * R, DIR, TS>(xr, xi, re, im, tw, t);
+    stages_from<T, N, NS * R, DIR, TS, CT, LS>(xr, xi, re, im, tw, t, twl);
   }
 }
 
 // Unnormalised DFT (DIR = -1) or inverse DFT (DIR = +1) of the group's sequence, slot m of lane
 // t holding element t + TPF m on entry and on exit.  (re, im): this group's LDS buffer; the
 // caller must have finished its own reads of that buffer (wave_sync) before the call.
-template <typename T, int N, int DIR, int TS = 1>
-__device__ __forceinline__ void fft_reg(T* xr, T* xi, T* re, T* im, const Cx<T>* __restrict__ tw, int t) {
+template <typename T, int N, int DIR, int TS = 1, bool CT = false, int LS = 1>
+__device__ __forceinline__ void fft_reg(T* xr, T* xi, T* re, T* im, const Cx<T>* __restrict__ tw, int t,
+                                        const Cx<T>* __restrict__ twl = nullptr) {
   constexpr int E = Shape<N>::E;
-  dft_r<T, E, DIR>(xr, xi);
+  dft_r<T, E, DIR, CT>(xr, xi);
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int s = lds_at<N>(t * E + r);
-    re[s] = xr[r];
-    im[s] = xi[r];
+    re[s * LS] = xr[r];
+    im[s * LS] = xi[r];
   }
   wave_sync();
-  stages_from<T, N, E, DIR, TS>(xr, xi, re, im, tw, t);
+  stages_from<T, N, E, DIR, TS, CT, LS>(xr, xi, re, im, tw, t, twl);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -308,6 +353,15 @@ __device__ __forceinline__ void split_pair(T A, T B, T C, T D, T c, T s, T& xa, 
   xa2 = (T)0.5 * dot2(s, C + A, c, D - B);
   xb2 = (T)0.5 * dot2(s, D + B, c, A - C);
 }
+// the same with compensated (c, s) = (c + cl, s + sl)
+template <typename T>
+__device__ __forceinline__ void split_pair_ct(T A, T B, T C, T D, T c, T s, T cl, T sl, T& xa, T& xb, T& xa2,
+                                              T& xb2) {
+  xa = (T)0.5 * fma(cl, A + C, fma(sl, B - D, dot2(c, A + C, s, B - D)));
+  xb = (T)0.5 * fma(cl, B + D, fma(sl, C - A, dot2(c, B + D, s, C - A)));
+  xa2 = (T)0.5 * fma(sl, C + A, fma(cl, D - B, dot2(s, C + A, c, D - B)));
+  xb2 = (T)0.5 * fma(sl, D + B, fma(cl, A - C, dot2(s, D + B, c, A - C)));
+}
 
 // Merge before the inverse DFT: cosine coefficients of the two sequences at p and N - p give
 // Z[p] of the packed inverse.
@@ -315,6 +369,13 @@ template <typename T>
 __device__ __forceinline__ void merge_pair(T ya, T yb, T ya2, T yb2, T c, T s, T& zr, T& zi) {
   zr = dot2(c, ya, s, ya2) - dot2(s, yb, -c, yb2);
   zi = dot2(s, ya, -c, ya2) + dot2(c, yb, s, yb2);
+}
+// the same with compensated (c, s) = (c + cl, s + sl)
+template <typename T>
+__device__ __forceinline__ void merge_pair_ct(T ya, T yb, T ya2, T yb2, T c, T s, T cl, T sl, T& zr, T& zi) {
+  merge_pair<T>(ya, yb, ya2, yb2, c, s, zr, zi);
+  zr = fma(cl, ya, fma(sl, ya2, fma(-sl, yb, fma(cl, yb2, zr))));
+  zi = fma(sl, ya, fma(-cl, ya2, fma(cl, yb, fma(sl, yb2, zi))));
 }
 
 }  // namespace vs

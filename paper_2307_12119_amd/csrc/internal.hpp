@@ -23,8 +23,9 @@ hipError_t launch_det_coef(const TableSpec& sp, const double* lam64T, double c, 
 inline size_t coef_entries(int nx, int ny) { return (size_t)nx * (ny / 2 + 1) * 4; }
 size_t green_table_scratch_doubles(int nx, int ny);
 
+// tw32lo / qw32lo: the low parts (exact value - FP32 value, rounded) of tw32 / qw32
 hipError_t launch_twiddles(int n, Cx<double>* tw64, Cx<float>* tw32, Cx<double>* qw64, Cx<float>* qw32,
-                           hipStream_t stream);
+                           Cx<float>* tw32lo, Cx<float>* qw32lo, hipStream_t stream);
 
 // Row-pass variants.
 enum RowMode : int {
@@ -45,6 +46,8 @@ struct Twiddles {
   const Cx<float>* tw32;
   const Cx<double>* qw64;
   const Cx<float>* qw32;
+  const Cx<float>* tw32lo;  // low parts of tw32 and qw32 (compensated twiddles)
+  const Cx<float>* qw32lo;
 };
 
 struct PassArgs {
@@ -56,6 +59,7 @@ struct PassArgs {
   PointParams pp;
   Twiddles tw;   // twiddles of length nx (row passes)
   Twiddles twc;  // twiddles of length ny (column passes)
+  int ct;        // FP32 transforms with compensated twiddles (row modes HEAD / MERGED / LAST, column pass)
   int iter;        // 1-based iteration index of the pass
   int zero_start;  // iteration 1 starts from dT = 0 (no warm start)
   int use_s64;     // operate on MapPtrs::S64 instead of S
@@ -63,11 +67,13 @@ struct PassArgs {
 };
 
 // io: element type of the maps (VARSIM_F32 / VARSIM_F64); compute: type of the transforms.
+// With a.ct, FP32 modes HEAD / MERGED / LAST use compensated twiddles (launch_row_pass_ct).
 hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hipStream_t stream);
+hipError_t launch_row_pass_ct(int mode, const PassArgs& a, hipStream_t stream);
 // coef: the column-pass coefficient table of the compute type; variant: launch-shape candidate
 // 0 (default strip width), 1 (default width, two column pairs per transform group), 2 (half
 // width); col_pass_columns / col_pass_pairs give a candidate's strip width and pairs per group
-constexpr int kColVariants = 3;
+constexpr int kColVariants = 5;
 constexpr int kMaxGraphIterations = 16;  // fixed-point iterations one captured graph may hold
 hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream, int variant = 0);
 int col_pass_columns(int compute, int n, int variant);

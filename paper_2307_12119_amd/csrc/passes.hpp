@@ -41,7 +41,10 @@ __device__ __forceinline__ void xcd_tile(int& strip, int& map) {
 // COLS_ = 0: the default strip width (col_count); otherwise an explicit even width.  Each
 // transform group (one wavefront at N >= 512) handles PAIRS column pairs one after the other,
 // so a strip can be wider (longer contiguous row segments) without more threads.
-template <typename Tc, int N, int COLS_ = 0, int PAIRS_ = 1>
+// INPL_: each pair's transform scratch is its own two tile columns (element i of the padded
+// scratch at tile row lds_at(i)), so the tile needs no separate scratch and a wider strip fits
+// two workgroups per CU.
+template <typename Tc, int N, int COLS_ = 0, int PAIRS_ = 1, bool INPL_ = false>
 struct ColCfg {
   static constexpr int TPF = Shape<N>::TPF;
   static constexpr int COLS = COLS_ ? (COLS_ < N ? COLS_ : N) : col_count(N, (int)sizeof(Tc), TPF);
@@ -53,13 +56,16 @@ struct ColCfg {
   // at slot perm(y)), so the column reads of a half-wavefront walk consecutive tile rows; with
   // pitch COLS + 1 that costs 1.5x the conflict-free LDS time against 2x in natural order.
   static constexpr bool SLOT = N >= 256;
-  static constexpr int PITCH = SLOT ? COLS + 1 : (sizeof(Tc) == 4 ? COLS + 3 : COLS + 1);
-  static constexpr int TILE = N * PITCH;
-  static constexpr int SCRATCH = FFTS * 2 * Shape<N>::STRIDE;
+  static constexpr bool INPL = INPL_;
+  static constexpr int PITCH = (SLOT || INPL) ? COLS + 1 : (sizeof(Tc) == 4 ? COLS + 3 : COLS + 1);
+  // tile rows: N, or the padded transform length when the scratch lives in the tile
+  static constexpr int ROWS = INPL ? Shape<N>::STRIDE : N;
+  static constexpr int TILE = ROWS * PITCH;
+  static constexpr int SCRATCH = INPL ? 0 : FFTS * 2 * Shape<N>::STRIDE;
   // several column pairs per transform group: the transform scratch follows the tile, so each
   // pair is read from the tile only when its turn comes (one pair's values in registers)
-  static constexpr bool LAZY = PAIRS > 1;
-  static constexpr int LDS = LAZY ? TILE + SCRATCH : (TILE > SCRATCH ? TILE : SCRATCH);
+  static constexpr bool LAZY = !INPL && PAIRS > 1;
+  static constexpr int LDS = INPL ? TILE : (LAZY ? TILE + SCRATCH : (TILE > SCRATCH ? TILE : SCRATCH));
   // row-segment vectors each thread moves per tile
   static constexpr int LOADS = N * (COLS / VEC) / THREADS;
 };

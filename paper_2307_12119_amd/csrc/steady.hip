@@ -18,144 +18,11 @@
 #include "internal.hpp"
 #include "passes.hpp"
 #include "rowops.hpp"
+#include "rowpass.hpp"
 
 namespace vs {
 
 namespace {
-
-template <typename Tio, typename Tc, int N, int MODE>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS)
-    row_pass_kernel(PassArgs a, const Cx<Tc>* __restrict__ tw, const Cx<Tc>* __restrict__ qw) {
-  using Cfg = RowCfg<N>;
-  constexpr int TPF = Cfg::TPF;
-  constexpr int E = Shape<N>::E;
-  constexpr int ST = Shape<N>::STRIDE;
-  constexpr bool OS = MODE == ROW_OS_MID || MODE == ROW_OS_TAIL;
-  constexpr bool INV = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_CONV_TAIL || OS;
-  constexpr bool FWD = MODE == ROW_HEAD || MODE == ROW_MERGED || MODE == ROW_CONV_HEAD || MODE == ROW_OS_MID;
-  constexpr bool STATS = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_OS_TAIL;
-  __shared__ Tc s_re[Cfg::FFTS * ST];
-  __shared__ Tc s_im[Cfg::FFTS * ST];
-  __shared__ double s_red[3][Cfg::WAVES];
-
-  const int map = blockIdx.y;
-  unsigned flags = 0u;
-  if (MODE != ROW_CONV_HEAD && MODE != ROW_CONV_TAIL) {
-    flags = a.st.flags[map];
-    if (flags & kFlagSkip) return;
-    if ((MODE == ROW_MERGED || MODE == ROW_LAST) && finished_before(a.st, map, a.iter, a.pp.tol)) return;
-  }
-  const MapPtrs mp = a.maps[map];
-  int f = threadIdx.x / TPF;
-  if constexpr (TPF == 64) f = __builtin_amdgcn_readfirstlane(f);
-  const int t = threadIdx.x % TPF;
-  const int mirror = (__lane_id() & ~(TPF - 1)) + (TPF - 1 - t);
-  const int row = (blockIdx.x * Cfg::FFTS + f) * 2;
-  Tc* re = s_re + f * ST;
-  Tc* im = s_im + f * ST;
-  Tc* const Sa = (Tc*)(a.use_s64 ? mp.S64 : mp.S) + (long)row * N;
-  Tc* const Sb = Sa + N;
-  const long oa = (long)row * N, ob = oa + N;
-  const PointParams& pp = a.pp;
-
-  // slot m of this lane holds spectrum index / reordered sample t + TPF m
-  Tc zr[E], zi[E];
-
-  // ---- inverse half: spectrum rows -> theta (row DCT-III of the packed pair)
-  if constexpr (INV) {
-    Tc xa[E], xb[E], xa2[E], xb2[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      xa[m] = Sa[t + TPF * m];
-      xb[m] = Sb[t + TPF * m];
-    }
-    partner<Tc, N, false>(xa, xa2, t);
-    partner<Tc, N, false>(xb, xb2, t);
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const Cx<Tc> q = qw[t + TPF * m];
-      merge_pair<Tc>(xa[m], xb[m], xa2[m], xb2[m], q.r, q.i, zr[m], zi[m]);
-    }
-    fft_reg<Tc, N, +1>(zr, zi, re, im, tw, t);
-  }
-
-  // ---- pointwise: conductivity factor, Kirchhoff inverse, increment, stats, new power
-  LaneStats<Tc> ls;
-  const bool zero_old = (a.iter == 1) && (a.zero_start || (flags & kFlagWarmRejected));
-  if constexpr (MODE == ROW_CONV_TAIL) {
-    store_slots<Tio, Tc, N>((Tio*)mp.dT + oa, zr, t, mirror);
-    store_slots<Tio, Tc, N>((Tio*)mp.dT + ob, zi, t, mirror);
-  } else if constexpr (MODE == ROW_CONV_HEAD) {
-    load_slots<Tio, Tc, N, true>((const Tio*)mp.qd + oa, zr, t, mirror);
-    load_slots<Tio, Tc, N, true>((const Tio*)mp.qd + ob, zi, t, mirror);
-  } else if constexpr (OS) {
-    row_oneshot<Tio, Tc, N, MODE>(zr, mp, oa, t, mirror, pp, ls);
-    row_oneshot<Tio, Tc, N, MODE>(zi, mp, ob, t, mirror, pp, ls);
-  } else {
-    row_pointwise<Tio, Tc, N, MODE, true>(zr, mp, oa, t, mirror, zero_old, pp, ls);
-    row_pointwise<Tio, Tc, N, MODE, true>(zi, mp, ob, t, mirror, zero_old, pp, ls);
-  }
-
-  if constexpr (STATS) {
-    constexpr int W = Cfg::WAVE;
-    const int wave = threadIdx.x / W;
-    const bool bad = !(ls.xmax <= (Tc)pp.cap) || !isfinite(ls.sum);
-    double inc = wave_max<W>((double)ls.inc);
-    const unsigned bad_any = __any(bad);
-    double sum = 0.0;
-    unsigned long long best = 0ull;
-    if (MODE != ROW_RESID) {
-      sum = wave_sum<W>((double)ls.sum);
-      best = ls.imax == 0x7fffffff ? 0ull : pack_max((float)ls.xmax, ls.imax);
-      best = wave_max_u64<W>(best);
-    }
-    if ((threadIdx.x % W) == 0) {
-      s_red[0][wave] = bad_any ? (double)NAN : inc;
-      s_red[1][wave] = sum;
-      s_red[2][wave] = __longlong_as_double((long long)best);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double i0 = s_red[0][0], s0 = s_red[1][0];
-      unsigned long long b0 = (unsigned long long)__double_as_longlong(s_red[2][0]);
-      bool any_bad = isnan(i0);
-      for (int w = 1; w < Cfg::WAVES; ++w) {
-        any_bad = any_bad || isnan(s_red[0][w]);
-        i0 = fmax(i0, s_red[0][w]);
-        s0 += s_red[1][w];
-        const unsigned long long bw = (unsigned long long)__double_as_longlong(s_red[2][w]);
-        b0 = bw > b0 ? bw : b0;
-      }
-      if (MODE == ROW_RESID) {
-        atomicMax(&a.st.resid64[map], (unsigned long long)__double_as_longlong(any_bad ? (double)INFINITY : i0));
-      } else {
-        const long slot = (long)map * a.st.stride + a.iter;
-        atomicMax(&a.st.resid[slot], (unsigned long long)__double_as_longlong(any_bad ? (double)INFINITY : i0));
-        a.st.part[(long)map * kRowGroupsMax + blockIdx.x] = s0;
-        atomicMax(&a.st.maxpack[slot], b0);
-        if (any_bad) atomicOr(&a.st.flags[map], kFlagRunaway);
-      }
-    }
-  }
-
-  // ---- forward half: P rows -> row DCT-II spectrum
-  if constexpr (FWD) {
-    wave_sync();
-    fft_reg<Tc, N, -1>(zr, zi, re, im, tw, t);
-    Tc pr[E], pim[E];
-    partner<Tc, N, true>(zr, pr, t);
-    partner<Tc, N, true>(zi, pim, t);
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int p = t + TPF * m;
-      const Cx<Tc> q = qw[p];
-      Tc xa, xb, xa2, xb2;
-      split_pair<Tc>(zr[m], zi[m], pr[m], pim[m], q.r, q.i, xa, xb, xa2, xb2);
-      Sa[p] = xa;
-      Sb[p] = xb;
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------------------
 template <typename T>
@@ -351,6 +218,7 @@ hipError_t row_dispatch_n(int mode, const PassArgs& a, const Cx<Tc>* tw, const C
 hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hipStream_t stream) {
   if (compute == VARSIM_F32) {
     if (io != VARSIM_F32) return hipErrorInvalidValue;
+    if (a.ct && (mode == ROW_HEAD || mode == ROW_MERGED || mode == ROW_LAST)) return launch_row_pass_ct(mode, a, stream);
     return row_dispatch_n<float, float>(mode, a, a.tw.tw32, a.tw.qw32, stream);
   }
   if (io == VARSIM_F32) return row_dispatch_n<float, double>(mode, a, a.tw.tw64, a.tw.qw64, stream);

@@ -300,17 +300,22 @@ __global__ void __launch_bounds__(256) coef_kernel(const double* __restrict__ la
   c32[o + 3] = 0.0f;
 }
 
-// DFT twiddles exp(-2 pi i k / n) and quarter-wave pairs (cos, sin)(pi p / 2n)
-__global__ void twiddle_kernel(Cx<double>* tw64, Cx<float>* tw32, Cx<double>* qw64, Cx<float>* qw32, int n) {
+// DFT twiddles exp(-2 pi i k / n) and quarter-wave pairs (cos, sin)(pi p / 2n), FP64 and FP32,
+// and the FP32 low parts (FP64 value - FP32 value, rounded) for compensated twiddles
+__global__ void twiddle_kernel(Cx<double>* tw64, Cx<float>* tw32, Cx<double>* qw64, Cx<float>* qw32,
+                               Cx<float>* tw32lo, Cx<float>* qw32lo, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
+  auto lo = [](double v) { return (float)(v - (double)(float)v); };
   double s, c;
   sincospi(2.0 * k / n, &s, &c);
   tw64[k] = {c, -s};
   tw32[k] = {(float)c, (float)-s};
+  tw32lo[k] = {lo(c), lo(-s)};
   sincospi(0.5 * k / n, &s, &c);
   qw64[k] = {c, s};
   qw32[k] = {(float)c, (float)s};
+  qw32lo[k] = {lo(c), lo(s)};
 }
 
 }  // namespace
@@ -365,8 +370,9 @@ size_t green_table_scratch_doubles(int nx, int ny) {
 }
 
 hipError_t launch_twiddles(int n, Cx<double>* tw64, Cx<float>* tw32, Cx<double>* qw64, Cx<float>* qw32,
-                           hipStream_t stream) {
-  hipLaunchKernelGGL(twiddle_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, tw64, tw32, qw64, qw32, n);
+                           Cx<float>* tw32lo, Cx<float>* qw32lo, hipStream_t stream) {
+  hipLaunchKernelGGL(twiddle_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, tw64, tw32, qw64, qw32, tw32lo,
+                     qw32lo, n);
   return hipGetLastError();
 }
 

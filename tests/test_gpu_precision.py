@@ -1,0 +1,84 @@
+"""FP32 precision of the steady solve: compensated twiddles (every FP32 twiddle and butterfly
+constant held as hi + lo) against plain FP32-rounded ones, measured against FP64.
+
+Iterates are compared at a fixed iteration count (tolerance below reach), so the difference is
+the arithmetic's rounding alone; the FP64 reference is the oracle at 256^2 and, at 512^2 and
+1024^2, the GPU's FP64 path (itself within 1e-9 relative of the oracle in the steady tests)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests._util import gpu_item, leak_code, oracle_solve
+
+pytestmark = pytest.mark.gpu
+
+FP32_GATE_K = 0.05
+FP32_ACHIEVED_K = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    from paper_2307_12119_amd import varsim as V
+
+    c = V.Context(0, gpu_lib)
+    yield c
+    c.close()
+
+
+def _opts(prec, inp, max_iter, tol, ct=False):
+    from paper_2307_12119_amd import varsim as V
+
+    return V.make_options(prec, leak_code(inp), inp.beta, max_iter, tol, compensated_twiddles=ct)
+
+
+def test_compensated_fp32_solve_matches_oracle(ctx):
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    inp = W.config2(sample=7, n=256)
+    (ref, rst), _ = oracle_solve(inp, 1e-3, 50)
+    item = gpu_item(inp, torch.float32)
+    st = ctx.solve_steady(item, _opts(V.F32, inp, 50, 1e-3, ct=True))
+    err = float(np.max(np.abs(item["dT_out"].cpu().numpy().astype(np.float64) - ref)))
+    print(f"compensated FP32 256^2: iterations {st['iterations']} (oracle {rst.iterations}), max err {err:.2e} K",
+          flush=True)
+    assert st["status"] == V.OK and st["iterations"] == rst.iterations
+    assert err <= FP32_GATE_K and err <= FP32_ACHIEVED_K
+
+
+@pytest.mark.parametrize("n", [128, 512, 1024])
+def test_compensated_twiddles_reduce_fp32_error(ctx, n):
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    inps = [W.config2(sample=s, n=n) for s in range(2)]
+    iters = 5
+    errs = {}
+    for ct in (False, True):
+        items = [gpu_item(i, torch.float32) for i in inps]
+        ctx.solve_batch(items, _opts(V.F32, inps[0], iters, 1e-30, ct=ct), raise_on=())
+        refs = [gpu_item(i, torch.float64) for i in inps]
+        ctx.solve_batch(refs, _opts(V.F64, inps[0], iters, 1e-30), raise_on=())
+        errs[ct] = max(float((a["dT_out"].double() - b["dT_out"]).abs().max()) for a, b in zip(items, refs))
+    print(f"FP32 iterate {iters} at {n}^2 vs FP64: rounded twiddles {errs[False]:.3e} K, "
+          f"compensated {errs[True]:.3e} K", flush=True)
+    assert errs[True] <= FP32_ACHIEVED_K and errs[False] <= FP32_ACHIEVED_K
+    assert errs[True] < errs[False]
+
+
+def test_compensated_batch_equals_single(ctx):
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    inps = [W.config2(sample=s, n=n) for s, n in ((0, 64), (1, 256), (2, 64))]
+    opts = _opts(V.F32, inps[0], 50, 1e-3, ct=True)
+    batch = [gpu_item(i, torch.float32) for i in inps]
+    bst = ctx.solve_batch(batch, opts)
+    for inp, b, s in zip(inps, batch, bst):
+        one = gpu_item(inp, torch.float32)
+        st = ctx.solve_steady(one, opts)
+        assert s["status"] == st["status"] == V.OK
+        assert torch.equal(b["dT_out"], one["dT_out"])
