@@ -19,8 +19,12 @@ cosine modes; ``solve_lateral_k`` then solves the same finite-volume system (har
 conductances) by conjugate gradients preconditioned with the exact constant-conductivity
 solve, and ``solve_sparse`` takes the same map for a direct check on tiny grids.
 
+A layered box (``solve_modes_stack``: the package stack of Table param, constant conductivity per
+layer, isothermal or convective bottom face) keeps the cosine-mode split, with the vertical
+conductance between cell centres the series resistance of their half cells.
+
 Parity: pinned (``solve_modes`` and ``solve_lateral_k`` against ``solve_sparse`` to rounding;
-convergence order checked).
+``solve_modes_stack`` of one layer against ``solve_modes``; convergence order checked).
 """
 from __future__ import annotations
 
@@ -80,6 +84,79 @@ def solve_modes(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float, 
         x_top = dp[z] - cp[z] * x_top
     t_top = sfft.idctn(x_top, type=2, norm="ortho")
     return _coarse_centres(_surface_from_top_cells(t_top, q_fine, dz, k), r)
+
+
+def solve_modes_stack(q_coarse: np.ndarray, lx: float, ly: float, layers, h_bottom: float | None, r: int,
+                      nz_per_layer) -> np.ndarray:
+    """Top-surface rise at the coarse cell centres [K] of a layered box (layers = [(t, k), ...]
+    top first, each split into nz_per_layer[i] cells in depth), bottom face isothermal
+    (h_bottom None) or convective with coefficient h_bottom: the same cosine-mode split and one
+    tridiagonal system in depth per mode, the vertical conductance between two cell centres the
+    series resistance of their half cells."""
+    if r % 2 == 0:
+        raise ValueError("refinement must be odd")
+    ny, nx = q_coarse.shape
+    mfx, mfy = nx * r, ny * r
+    hx, hy = lx / mfx, ly / mfy
+    q_fine = _fine_flux(q_coarse, r)
+    lam_x = (2.0 - 2.0 * np.cos(np.pi * np.arange(mfx) / mfx)) / (hx * hx)
+    lam_y = (2.0 - 2.0 * np.cos(np.pi * np.arange(mfy) / mfy)) / (hy * hy)
+    lam = lam_y[:, None] + lam_x[None, :]
+    dz, kz = [], []
+    for (t, k), nz in zip(layers, nz_per_layer):
+        dz += [t / nz] * nz
+        kz += [k] * nz
+    nzt = len(dz)
+    # conductance per unit area between centres z and z + 1, and from the last centre to the
+    # bottom boundary (through the half cell, plus 1 / h for a convective face)
+    g = [1.0 / (0.5 * dz[z] / kz[z] + 0.5 * dz[z + 1] / kz[z + 1]) for z in range(nzt - 1)]
+    rb = 0.5 * dz[-1] / kz[-1] + (0.0 if h_bottom is None else 1.0 / h_bottom)
+    gb = 1.0 / rb
+    qh = sfft.dctn(q_fine, type=2, norm="ortho")
+    diag, sub, sup = [], [], []
+    for z in range(nzt):
+        d = kz[z] * lam * dz[z]
+        if z > 0:
+            d = d + g[z - 1]
+        if z < nzt - 1:
+            d = d + g[z]
+        else:
+            d = d + gb
+        diag.append(d)
+        sub.append(-g[z - 1] if z > 0 else 0.0)
+        sup.append(-g[z] if z < nzt - 1 else 0.0)
+    rhs = [np.zeros(lam.shape) for _ in range(nzt)]
+    rhs[0] = qh
+    cp, dp = [None] * nzt, [None] * nzt
+    cp[0] = sup[0] / diag[0]
+    dp[0] = rhs[0] / diag[0]
+    for z in range(1, nzt):
+        den = diag[z] - sub[z] * cp[z - 1]
+        cp[z] = sup[z] / den
+        dp[z] = (rhs[z] - sub[z] * dp[z - 1]) / den
+    x_top = dp[-1]
+    for z in range(nzt - 2, -1, -1):
+        x_top = dp[z] - cp[z] * x_top
+    t_top = sfft.idctn(x_top, type=2, norm="ortho")
+    return _coarse_centres(t_top + q_fine * 0.5 * dz[0] / kz[0], r)
+
+
+def richardson_stack(q_coarse: np.ndarray, lx: float, ly: float, layers, h_bottom: float | None, r0: int = 3,
+                     nz0=(4, 2, 4), levels: int = 2) -> np.ndarray:
+    """``richardson`` for a layered box: refine laterally and in depth by 3 per level."""
+    sols = []
+    r, nz = r0, list(nz0)
+    for _ in range(levels + 1):
+        sols.append(solve_modes_stack(q_coarse, lx, ly, layers, h_bottom, r, nz))
+        r *= 3
+        nz = [3 * v for v in nz]
+    cur = sols
+    order = 2
+    for _ in range(levels):
+        f = 3.0 ** order
+        cur = [(f * cur[i + 1] - cur[i]) / (f - 1.0) for i in range(len(cur) - 1)]
+        order += 2
+    return cur[-1]
 
 
 def solve_sparse(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float, r: int, nz: int,
