@@ -155,6 +155,7 @@ def main() -> int:
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-warm-started solve")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the compensated-twiddle leg (FP32 error at fixed iterations, time cost)")
+    ap.add_argument("--no-anderson", action="store_true", help="skip the Anderson(1)-accelerated leg")
     ap.add_argument("--no-oneshot", action="store_true",
                     help="skip the one-shot modified-Green's-function leg (solver, warm start, ablation)")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes (no timing of candidates)")
@@ -396,6 +397,8 @@ def main() -> int:
     if not args.no_surrogate:
         result["surrogate"], out_w = surrogate_bench(ctx, items, qd, lv, cm, out, opts, ws, args, maps_per_s,
                                                      float(it.mean()))
+    if not args.no_anderson:
+        result["anderson"] = anderson_bench(ctx, items, out, ws, args, maps_per_s, float(it.mean()))
     if not args.no_precision:
         result["precision"] = precision_bench(ctx, items, out, opts, ws, args, maps_per_s)
     if not args.no_oneshot:
@@ -546,6 +549,35 @@ def mixed_bench(ctx, samples, args) -> dict:
             "maps_per_s": round(len(items) / el, 1), "ms_per_step": round(el * 1e3, 3),
             "statuses": sorted({int(x) for x in st["status"]}), "classes": per, "graph_launched": graph,
             "_first_maps": first}
+
+
+def anderson_bench(ctx, items, out_plain, ws, args, plain_maps_per_s, plain_iters) -> dict:
+    """The same batch with Anderson(1) mixing (a classical acceleration, same stop rule and
+    accuracy): maps/s, iterations and the speedup over the plain Picard solve."""
+    import numpy as np
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    opts = V.make_options(V.F32, V.LEAK_EXP, 0.017, 50, args.tol, f64_residual=True, anderson=True)
+    out_a = torch.zeros_like(out_plain)
+    items_a = ctx.prepare([dict(it, dT_out=out_a[i]) for i, it in enumerate(items)])
+    ws_a = torch.empty(ctx.workspace_bytes(items_a, opts), dtype=torch.uint8, device=out_plain.device)
+    for _ in range(args.warmup):
+        ctx.solve_batch(items_a, opts, ws_a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = ctx.solve_batch(items_a, opts, ws_a)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    return {"maps_per_s": round(args.batch / el, 2), "ms_per_step": round(el * 1e3, 4),
+            "speedup_vs_plain": round(args.batch / el / plain_maps_per_s, 4),
+            "iterations_mean": float(np.mean(st["iterations"])), "plain_iterations_mean": plain_iters,
+            "residual_f64_max_K": float(np.max(st["residual_f64_K"])),
+            "max_diff_vs_plain_K": float((out_a - out_plain).abs().max()),
+            "statuses": sorted({int(x) for x in st["status"]}),
+            "note": "two row passes per iteration (evaluation with the residual dot products, then mixing)"}
 
 
 def precision_bench(ctx, items, out_plain, opts, ws, args, plain_maps_per_s) -> dict:

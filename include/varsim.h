@@ -104,6 +104,15 @@ typedef struct varsim_options {
                                    the product with lo, removing the constants' own rounding from
                                    the result (maps of any size then take the two-pass path).
                                    Ignored by FP64 solves, the one-shot and transient solves. */
+  int32_t anderson;             /* 0: plain Picard iteration.  1: Anderson mixing with one stored
+                                   difference (a classical acceleration, not from the paper):
+                                   x_{k+1} = g_k - gamma_k (g_k - g_{k-1}), g_k = G(x_k),
+                                   f_k = g_k - x_k, gamma_k = <f_k - f_{k-1}, f_k> /
+                                   |f_k - f_{k-1}|^2 (sums over the map, FP64, fixed order), with
+                                   the same stopping rule (max |G(x) - x| <= tol_K, result G(x)).
+                                   Two row passes per iteration and three more maps of workspace
+                                   per problem; maps of any size take the two-pass path.  Used by
+                                   varsim_solve_steady / _batch / _batch_noalloc. */
 } varsim_options;
 
 /* One steady problem (all maps device pointers [ny][nx]; see conventions above). */

@@ -80,6 +80,7 @@ varsim_status check_options(varsim_ctx* ctx, const varsim_options* o) {
     return fail(ctx, VARSIM_ERR_INVALID, "bad cond_model");
   if (o->compensated_twiddles != 0 && o->compensated_twiddles != 1)
     return fail(ctx, VARSIM_ERR_INVALID, "compensated_twiddles must be 0 or 1");
+  if (o->anderson != 0 && o->anderson != 1) return fail(ctx, VARSIM_ERR_INVALID, "anderson must be 0 or 1");
   return VARSIM_OK;
 }
 
@@ -191,9 +192,9 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 // Workspace layout of a batch (problems in group-sorted order).
 struct Layout {
   int stride = 0;
-  size_t resid = 0, sum = 0, maxpack = 0, flags = 0, resid64 = 0, part = 0, state_end = 0;
+  size_t resid = 0, sum = 0, maxpack = 0, flags = 0, resid64 = 0, part = 0, aa = 0, state_end = 0;
   size_t stats = 0, maps = 0, prep = 0, order = 0;
-  std::vector<size_t> S, QL, MINV, S64;
+  std::vector<size_t> S, QL, MINV, S64, AX, AG, AF;
   size_t total = 0;
 };
 
@@ -227,6 +228,8 @@ Layout make_layout(const std::vector<const varsim_problem*>& probs, const varsim
   L.state_end = off;  // the words above are zeroed at the start of a call; the partial sums need not be
   L.part = off;
   off = align_up(off + n * kRowGroupsMax * 8);
+  L.aa = off;  // Anderson mixing: per-workgroup dot products (written before being read)
+  if (o->anderson) off = align_up(off + n * kRowGroupsMax * 2 * 8);
   L.stats = off;
   off = align_up(off + n * sizeof(varsim_stats));
   L.maps = off;
@@ -257,6 +260,14 @@ Layout make_layout(const std::vector<const varsim_problem*>& probs, const varsim
       off = align_up(off + cells * 8);
     } else {
       L.S64.push_back((size_t)-1);
+    }
+    for (auto* v : {&L.AX, &L.AG, &L.AF}) {  // Anderson mixing: x_k, G(x_{k-1}), f_{k-1}
+      if (o->anderson) {
+        v->push_back(off);
+        off = align_up(off + cells * es);
+      } else {
+        v->push_back((size_t)-1);
+      }
     }
   }
   L.total = off;
@@ -680,6 +691,7 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
   base.resid64 = (unsigned long long*)(ws + L.resid64);
   base.stride = L.stride;
   base.part = (double*)(ws + L.part);
+  base.aa = (double*)(ws + L.aa);
   MapPtrs* d_maps = (MapPtrs*)(ws + L.maps);
   PrepArgs* d_prep = (PrepArgs*)(ws + L.prep);
   int* d_order = (int*)(ws + L.order);
@@ -687,6 +699,7 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
   varsim_stats* d_stats = (varsim_stats*)(ws + L.stats);
   const int io = opts->precision;
   const bool want_res = opts->final_f64_residual != 0;
+  const bool anderson = opts->anderson != 0;
 
   wait_descriptors(ctx);
   ctx->h_maps.assign(n, MapPtrs{});
@@ -704,6 +717,9 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
     const bool leak = p->q_leak0 && opts->leak != VARSIM_LEAK_NONE;
     m.ql = leak ? (L.QL[i] != (size_t)-1 ? (const void*)(ws + L.QL[i]) : p->q_leak0) : nullptr;
     m.minv = L.MINV[i] != (size_t)-1 ? ws + L.MINV[i] : nullptr;
+    m.ax = L.AX[i] != (size_t)-1 ? ws + L.AX[i] : nullptr;
+    m.ag = L.AG[i] != (size_t)-1 ? ws + L.AG[i] : nullptr;
+    m.af = L.AF[i] != (size_t)-1 ? ws + L.AF[i] : nullptr;
     q.q_leak0 = p->q_leak0;
     q.leak_var = p->leak_var;
     q.cond_map = p->cond_map;
@@ -737,6 +753,7 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
     a.st.flags += g.first;
     a.st.resid64 += g.first;
     a.st.part += (size_t)g.first * kRowGroupsMax;
+    a.st.aa += (size_t)g.first * kRowGroupsMax * 2;
     a.pp = point_params(g.geom, opts);
     a.tw = twiddles_of(g.tw);
     a.twc = twiddles_of(g.twc);
@@ -752,9 +769,11 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
     const Group& g = groups[gi];
     PassArgs a = group_args(g, 1);
     const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
-    // the LDS-resident solver has no compensated-twiddle variant: such solves take the two passes
-    const int lim = opts->compensated_twiddles && io == VARSIM_F32 ? 0
-                    : ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
+    // the LDS-resident solver has no compensated-twiddle or Anderson variant: such solves take
+    // the two-pass path
+    const int lim = (opts->compensated_twiddles && io == VARSIM_F32) || opts->anderson
+                        ? 0
+                        : ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
     if (!(g.geom->nx == g.geom->ny && g.geom->nx <= lim) &&
         (st = col_variant_for(ctx, a, io, lam, s, &col_var[gi], !no_alloc)) != VARSIM_OK)
       return st;
@@ -786,9 +805,11 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
         if (!sorted[i]->dT_init)
           HIP_TRY(launch_zero_words(sorted[i]->dT_out, (size_t)g.geom->nx * g.geom->ny * esize(io), s));
     }
-    // the LDS-resident solver has no compensated-twiddle variant: such solves take the two passes
-    const int lim = opts->compensated_twiddles && io == VARSIM_F32 ? 0
-                    : ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
+    // the LDS-resident solver has no compensated-twiddle or Anderson variant: such solves take
+    // the two-pass path
+    const int lim = (opts->compensated_twiddles && io == VARSIM_F32) || opts->anderson
+                        ? 0
+                        : ctx->small_limit < 0 ? small_max_n(io) : std::min(ctx->small_limit, small_max_n(io));
     own[gi] = g.geom->nx == g.geom->ny && g.geom->nx <= lim;  // the LDS-resident solver takes square maps
     if (own[gi]) {
       const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
@@ -812,6 +833,13 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
       const void* lam = io == VARSIM_F32 ? (const void*)g.table.coef32 : (const void*)g.table.coef64;
       hipError_t e = timed(ctx, "col", q, [&] { return launch_col_pass(io, a, lam, q, col_var[gi]); });
       if (e != hipSuccess) return e;
+      if (anderson) {  // evaluate G and the residual dot products, then mix the next iterate
+        e = timed(ctx, "aa_eval", q, [&] { return launch_row_pass(ROW_AA_EVAL, io, io, a, q); });
+        if (e == hipSuccess && k < opts->max_iter)
+          e = timed(ctx, "aa_mix", q, [&] { return launch_row_pass(ROW_AA_MIX, io, io, a, q); });
+        if (e != hipSuccess) return e;
+        continue;
+      }
       const int mode = k < opts->max_iter ? ROW_MERGED : ROW_LAST;
       e = timed(ctx, mode == ROW_MERGED ? "row_merged" : "row_last", q,
                 [&] { return launch_row_pass(mode, io, io, a, q); });

@@ -36,6 +36,11 @@ struct MapPtrs {
   void* S64;         // FP64 work array for the residual pass, or null
   const void* init;  // warm start (io type), or null
   void* aux;         // spare per-map pointer (transient state)
+  // Anderson mixing (io type, or null): the current iterate x_k, the previous G(x), the
+  // previous residual G(x) - x
+  void* ax;
+  void* ag;
+  void* af;
 };
 
 // Pointwise physics constants of one geometry.
@@ -78,6 +83,9 @@ struct IterState {
   // two-pass row passes: [maps][kRowGroupsMax] sum of dT over each workgroup's rows in the last
   // iteration that ran (overwritten each iteration, no atomics); added in a fixed order at the end
   double* part;
+  // Anderson mixing: [maps][kRowGroupsMax][2] each row-pass workgroup's sums of df f and df df
+  // (df = f_k - f_{k-1}) in the last evaluation, added in a fixed order by the mixing pass
+  double* aa;
 };
 constexpr int kRowGroupsMax = 128;  // row-pass workgroups of one map, at most
 

@@ -39,6 +39,9 @@ enum RowMode : int {
   // deterministic operator's coefficients:
   ROW_OS_MID = 6,   // S -> theta_det (stored in dT) -> beta hx hy (QL / m - mu) theta_det -> row DCT-II -> S
   ROW_OS_TAIL = 7,  // S -> theta_rand (+ theta_det from dT) -> Phi^-1 -> dT, statistics
+  // Anderson(1) mixing, two row passes per iteration:
+  ROW_AA_EVAL = 8,  // S -> g = G(x_k) (to dT), f = g - x_k (to af), statistics, dot products
+  ROW_AA_MIX = 9,   // x_{k+1} = g - gamma (g - g_prev) (to ax; g to ag) -> P -> row DCT-II -> S
 };
 
 struct Twiddles {

@@ -24,19 +24,30 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
   constexpr int E = Shape<N>::E;
   constexpr int ST = Shape<N>::STRIDE;
   constexpr bool OS = MODE == ROW_OS_MID || MODE == ROW_OS_TAIL;
-  constexpr bool INV = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_CONV_TAIL || OS;
-  constexpr bool FWD = MODE == ROW_HEAD || MODE == ROW_MERGED || MODE == ROW_CONV_HEAD || MODE == ROW_OS_MID;
-  constexpr bool STATS = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_OS_TAIL;
+  constexpr bool AA = MODE == ROW_AA_EVAL || MODE == ROW_AA_MIX;
+  constexpr bool INV = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_CONV_TAIL || OS ||
+                       MODE == ROW_AA_EVAL;
+  constexpr bool FWD = MODE == ROW_HEAD || MODE == ROW_MERGED || MODE == ROW_CONV_HEAD || MODE == ROW_OS_MID ||
+                       MODE == ROW_AA_MIX;
+  constexpr bool STATS = MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_RESID || MODE == ROW_OS_TAIL ||
+                         MODE == ROW_AA_EVAL;
   __shared__ Tc s_re[Cfg::FFTS * ST];
   __shared__ Tc s_im[Cfg::FFTS * ST];
-  __shared__ double s_red[3][Cfg::WAVES];
+  __shared__ double s_red[AA ? 5 : 3][Cfg::WAVES];
+  __shared__ double s_gamma;
 
   const int map = blockIdx.y;
   unsigned flags = 0u;
   if (MODE != ROW_CONV_HEAD && MODE != ROW_CONV_TAIL) {
     flags = a.st.flags[map];
     if (flags & kFlagSkip) return;
-    if ((MODE == ROW_MERGED || MODE == ROW_LAST) && finished_before(a.st, map, a.iter, a.pp.tol)) return;
+    if ((MODE == ROW_MERGED || MODE == ROW_LAST || MODE == ROW_AA_EVAL) &&
+        finished_before(a.st, map, a.iter, a.pp.tol))
+      return;
+    // the mixing pass follows this iteration's evaluation: a map that has just converged (or
+    // converged before, its later increments staying 0) keeps G(x) in dT
+    if (MODE == ROW_AA_MIX && __longlong_as_double((long long)a.st.resid[(long)map * a.st.stride + a.iter]) <= a.pp.tol)
+      return;
   }
   const MapPtrs mp = a.maps[map];
   int f = threadIdx.x / TPF;
@@ -80,6 +91,23 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
   // ---- pointwise: conductivity factor, Kirchhoff inverse, increment, stats, new power
   LaneStats<Tc> ls;
   const bool zero_old = (a.iter == 1) && (a.zero_start || (flags & kFlagWarmRejected));
+  double d1 = 0.0, d2 = 0.0;  // Anderson dot products of this lane
+  if constexpr (MODE == ROW_AA_MIX) {
+    // gamma = <df, f> / <df, df> from the evaluation's per-workgroup sums, added in index order
+    // (every workgroup of the map gets the same bits)
+    if (threadIdx.x == 0) {
+      double s1 = 0.0, s2 = 0.0;
+      if (a.iter >= 2) {
+        const double* pa = a.st.aa + (long)map * kRowGroupsMax * 2;
+        for (int g = 0; g < (int)gridDim.x; ++g) {
+          s1 += pa[2 * g];
+          s2 += pa[2 * g + 1];
+        }
+      }
+      s_gamma = s2 > 0.0 ? s1 / s2 : 0.0;
+    }
+    __syncthreads();
+  }
   if constexpr (MODE == ROW_CONV_TAIL) {
     store_slots<Tio, Tc, N>((Tio*)mp.dT + oa, zr, t, mirror);
     store_slots<Tio, Tc, N>((Tio*)mp.dT + ob, zi, t, mirror);
@@ -89,6 +117,10 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
   } else if constexpr (OS) {
     row_oneshot<Tio, Tc, N, MODE>(zr, mp, oa, t, mirror, pp, ls);
     row_oneshot<Tio, Tc, N, MODE>(zi, mp, ob, t, mirror, pp, ls);
+  } else if constexpr (AA) {
+    const double gamma = MODE == ROW_AA_MIX ? s_gamma : 0.0;
+    row_anderson<Tio, Tc, N, MODE, true>(zr, mp, oa, t, mirror, zero_old, a.iter, gamma, pp, ls, d1, d2);
+    row_anderson<Tio, Tc, N, MODE, true>(zi, mp, ob, t, mirror, zero_old, a.iter, gamma, pp, ls, d1, d2);
   } else {
     row_pointwise<Tio, Tc, N, MODE, true>(zr, mp, oa, t, mirror, zero_old, pp, ls);
     row_pointwise<Tio, Tc, N, MODE, true>(zi, mp, ob, t, mirror, zero_old, pp, ls);
@@ -107,10 +139,18 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
       best = ls.imax == 0x7fffffff ? 0ull : pack_max((float)ls.xmax, ls.imax);
       best = wave_max_u64<W>(best);
     }
+    if constexpr (AA) {
+      d1 = wave_sum<W>(d1);
+      d2 = wave_sum<W>(d2);
+    }
     if ((threadIdx.x % W) == 0) {
       s_red[0][wave] = bad_any ? (double)NAN : inc;
       s_red[1][wave] = sum;
       s_red[2][wave] = __longlong_as_double((long long)best);
+      if constexpr (AA) {
+        s_red[3][wave] = d1;
+        s_red[4][wave] = d2;
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -132,6 +172,16 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
         a.st.part[(long)map * kRowGroupsMax + blockIdx.x] = s0;
         atomicMax(&a.st.maxpack[slot], b0);
         if (any_bad) atomicOr(&a.st.flags[map], kFlagRunaway);
+        if constexpr (AA) {
+          double e1 = s_red[3][0], e2 = s_red[4][0];
+          for (int w = 1; w < Cfg::WAVES; ++w) {
+            e1 += s_red[3][w];
+            e2 += s_red[4][w];
+          }
+          double* pa = a.st.aa + ((long)map * kRowGroupsMax + blockIdx.x) * 2;
+          pa[0] = e1;
+          pa[1] = e2;
+        }
       }
     }
   }

@@ -194,6 +194,18 @@ hipError_t row_dispatch_mode(int mode, const PassArgs& a, const Cx<Tc>* tw, cons
       else
         return hipErrorInvalidValue;
       break;
+    case ROW_AA_EVAL:
+      if constexpr (std::is_same<Tio, Tc>::value)
+        hipLaunchKernelGGL((row_pass_kernel<Tio, Tc, N, ROW_AA_EVAL>), grid, block, 0, s, a, tw, qw);
+      else
+        return hipErrorInvalidValue;
+      break;
+    case ROW_AA_MIX:
+      if constexpr (std::is_same<Tio, Tc>::value)
+        hipLaunchKernelGGL((row_pass_kernel<Tio, Tc, N, ROW_AA_MIX>), grid, block, 0, s, a, tw, qw);
+      else
+        return hipErrorInvalidValue;
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -41,7 +41,7 @@ class Geometry(Structure):
 class Options(Structure):
     _fields_ = [("leak", c_int32), ("beta_per_K", c_double), ("sv_radius", c_int32), ("precision", c_int32),
                 ("max_iter", c_int32), ("tol_K", c_double), ("dT_cap_K", c_double), ("final_f64_residual", c_int32),
-                ("cond_model", c_int32), ("compensated_twiddles", c_int32)]
+                ("cond_model", c_int32), ("compensated_twiddles", c_int32), ("anderson", c_int32)]
 
 
 class Problem(Structure):
@@ -186,9 +186,9 @@ def make_geometry(die: Die, n: int, ny: int | None = None) -> tuple[Geometry, La
 
 def make_options(precision: int = F32, leak: int = LEAK_EXP, beta: float = 0.017, max_iter: int = 50,
                  tol: float = 1e-3, cap: float = 1000.0, f64_residual: bool = False,
-                 cond: int = COND_SOURCE, compensated_twiddles: bool = False) -> Options:
+                 cond: int = COND_SOURCE, compensated_twiddles: bool = False, anderson: bool = False) -> Options:
     return Options(leak, beta, 0, precision, max_iter, tol, cap, 1 if f64_residual else 0, cond,
-                   1 if compensated_twiddles else 0)
+                   1 if compensated_twiddles else 0, 1 if anderson else 0)
 
 
 class Context:
