@@ -23,7 +23,11 @@ A layered box (``solve_modes_stack``: the package stack of Table param, constant
 layer, isothermal or convective bottom face) keeps the cosine-mode split, with the vertical
 conductance between cell centres the series resistance of their half cells.
 
+``transient_modes`` adds the heat capacity (the transient form of Eq. fourier) to the same box
+and solves each lateral mode's depth system exactly in time through its eigenvectors.
+
 Parity: pinned (``solve_modes`` and ``solve_lateral_k`` against ``solve_sparse`` to rounding;
+``transient_modes`` at long times against ``solve_modes``;
 ``solve_modes_stack`` of one layer against ``solve_modes``; convergence order checked).
 """
 from __future__ import annotations
@@ -157,6 +161,44 @@ def richardson_stack(q_coarse: np.ndarray, lx: float, ly: float, layers, h_botto
         cur = [(f * cur[i + 1] - cur[i]) / (f - 1.0) for i in range(len(cur) - 1)]
         order += 2
     return cur[-1]
+
+
+def transient_modes(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float, rho_c: float, r: int, nz: int,
+                    times) -> np.ndarray:
+    """Top-surface rise at the coarse cell centres [K] at each of ``times`` after the flux q is
+    switched on at t = 0 (Eq. fourier with its heat-capacity term), for the same finite-volume
+    box as ``solve_modes``: per lateral cosine mode the depth system rho_c dz dT/dt = -A T + b
+    is solved exactly in time through the eigenvectors of the symmetric tridiagonal A."""
+    from scipy.linalg import eigh_tridiagonal
+
+    if r % 2 == 0:
+        raise ValueError("refinement must be odd")
+    ny, nx = q_coarse.shape
+    mfx, mfy = nx * r, ny * r
+    hx, hy, dz = lx / mfx, ly / mfy, t / nz
+    q_fine = _fine_flux(q_coarse, r)
+    lam_x = (2.0 - 2.0 * np.cos(np.pi * np.arange(mfx) / mfx)) / (hx * hx)
+    lam_y = (2.0 - 2.0 * np.cos(np.pi * np.arange(mfy) / mfy)) / (hy * hy)
+    lam = (lam_y[:, None] + lam_x[None, :]).ravel()
+    qh = sfft.dctn(q_fine, type=2, norm="ortho").ravel()
+    g = k / dz  # conductance per unit area between neighbouring centres
+    cap = rho_c * dz
+    times = np.atleast_1d(np.asarray(times, dtype=np.float64))
+    top = np.empty((len(times), lam.size))
+    off = np.full(nz - 1, -g / cap)
+    for i, lm in enumerate(lam):
+        d = np.full(nz, 2.0 * g + k * lm * dz)
+        d[0] -= g  # adiabatic top face (the flux enters as a source)
+        d[-1] += g  # isothermal bottom face half a cell below (conductance 2 k / dz in total)
+        mu, v = eigh_tridiagonal(d / cap, off)
+        proj = v[0, :] * (qh[i] / cap)  # b has the flux in the top cell only
+        # T_top(t) = sum_j v[0, j] proj_j (1 - exp(-mu_j t)) / mu_j
+        top[:, i] = (-np.expm1(-np.outer(times, mu)) / mu) @ (v[0, :] * proj)
+    out = []
+    for it in range(len(times)):
+        t_top = sfft.idctn(top[it].reshape(mfy, mfx), type=2, norm="ortho")
+        out.append(_coarse_centres(t_top + q_fine * 0.5 * dz / k, r))
+    return np.array(out)
 
 
 def solve_sparse(q_coarse: np.ndarray, lx: float, ly: float, t: float, k: float, r: int, nz: int,

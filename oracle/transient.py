@@ -24,6 +24,10 @@ Definition followed:
     source side (P_n / m enters the superposition, the default) or on the target side
     (theta_n / m).
 
+Multi-pole ("modal") option: each cosine mode responds with the slab's slowest depth modes
+exactly and the rest lumped into one pole that keeps the first moment (``slab_poles``); one pole
+is the moment model.
+
 The step kernels come from lambda (an (N+1)-point cosine transform of the periodised steady
 kernel) by the inverse transform; the superposition itself is a plain direct sum.
 
@@ -43,6 +47,34 @@ import scipy.fft as sfft
 from . import steady as S
 
 
+def slab_poles(s: np.ndarray, t: float, alpha: float, n_poles: int):
+    """Weights w_j and time constants tau_j of the multi-pole ("modal") transient model.
+
+    The slab's surface response to a flux step at lateral wavenumber s is exactly the sum over
+    its depth modes cos(beta_m z), beta_m = (m + 1/2) pi / t (adiabatic top, isothermal bottom),
+    of c_m (1 - exp(-t / tau_m)) with tau_m = 1 / (alpha (s^2 + beta_m^2)) and
+    c_m = 2 / (k t (s^2 + beta_m^2)); the c_m sum to the steady symbol tanh(s t) / (k s).  The
+    model keeps the slowest n_poles - 1 depth modes as they are (normalised weights
+    w_m = c_m k s / tanh(s t)) and lumps the rest into one pole with the remaining weight and
+    the time constant that keeps the total first moment equal to tau_moment(s): the steady
+    value and the first moment are exact, and n_poles = 1 is the moment model.
+    Returns (w, tau), arrays of shape (n_poles,) + s.shape."""
+    s = np.asarray(s, dtype=np.float64)
+    x = s * t
+    with np.errstate(invalid="ignore", divide="ignore"):
+        x_over_tanh = np.where(x < 1e-8, 1.0, x / np.tanh(np.where(x < 1e-8, 1.0, x)))
+    w, tau = [], []
+    for m in range(n_poles - 1):
+        bt = (m + 0.5) * math.pi  # beta_m t
+        w.append(2.0 * x_over_tanh / (x * x + bt * bt))
+        tau.append(t * t / (alpha * (x * x + bt * bt)))
+    w_rest = 1.0 - sum(w) if w else np.ones_like(s)
+    first = tau_moment(s, t, alpha) - sum(wi * ti for wi, ti in zip(w, tau)) if w else tau_moment(s, t, alpha)
+    w.append(w_rest)
+    tau.append(first / w_rest)
+    return np.array(w), np.array(tau)
+
+
 def tau_moment(s: np.ndarray, t: float, alpha: float) -> np.ndarray:
     """First moment of the slab's step response at lateral wavenumber s (closed form)."""
     s = np.asarray(s, dtype=np.float64)
@@ -59,10 +91,12 @@ def tau_moment(s: np.ndarray, t: float, alpha: float) -> np.ndarray:
 
 
 class TransientModel:
-    """Single-pole-per-mode transient model of one die (Eqs. Ttran, tranGreen)."""
+    """Transient model of one die: one pole per cosine mode (Eqs. Ttran, tranGreen; "moment" or
+    "lumped" time constants), or the slab's slowest depth modes plus one lumped pole per cosine
+    mode ("modal", n_poles poles; see ``slab_poles``)."""
 
     def __init__(self, geom: S.Geometry, rho_c: float, tau_model: str = "moment",
-                 operator: S.DirectSum | None = None):
+                 operator: S.DirectSum | None = None, n_poles: int = 1):
         self.geom = geom
         self.op = operator or S.DirectSum(geom)
         g = geom
@@ -76,13 +110,21 @@ class TransientModel:
             self.tau = tau_moment(s, g.t, self.alpha)
         elif tau_model == "lumped":
             self.tau = rho_c * g.t / 3.0 * g.hx * g.hy * self.lam_full
+        elif tau_model == "modal":
+            self.tau = tau_moment(s, g.t, self.alpha)  # the first moment of every mode's response
         else:
             raise ValueError(tau_model)
+        # poles of every mode: weights [n_poles][N+1][N+1] and time constants
+        if tau_model == "modal":
+            self.weights, self.taus = slab_poles(s, g.t, self.alpha, n_poles)
+        else:
+            self.weights, self.taus = np.ones((1,) + s.shape), self.tau[None]
         self.rho_c = rho_c
 
     def step_kernel(self, time: float) -> np.ndarray:
-        """Real-space periodised kernel whose cosine eigenvalues are lambda (1 - exp(-time/tau))."""
-        shat = self.lam_full * (-np.expm1(-time / self.tau))
+        """Real-space periodised kernel whose cosine eigenvalues are
+        lambda sum_j w_j (1 - exp(-time / tau_j))."""
+        shat = self.lam_full * np.sum(self.weights * -np.expm1(-time / self.taus), axis=0)
         return sfft.idct(sfft.idct(shat, type=1, axis=0), type=1, axis=1)
 
 
