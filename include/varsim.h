@@ -23,8 +23,11 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Work is
  *     stream-ordered; calls that return statistics synchronise that stream before returning.
  *   - A context is not thread-safe: use one context per host thread.
- *   - Supported grids: nx == ny, a power of two in [16, 1024]; one silicon layer with an
- *     isothermal bottom at the ambient temperature.  Anything else is VARSIM_ERR_UNSUPPORTED.
+ *   - Supported grids: nx and ny powers of two in [16, 1024], ny a multiple of the row pass's
+ *     rows per workgroup (which excludes 32 x 16, 64 x 16, 64 x 32 and 128 x 16); the die is
+ *     the first layer, optionally above a package stack of up to 8 layers with an isothermal or
+ *     convective bottom (steady solves; transients take one square layer over an isothermal
+ *     bottom).  Anything else is VARSIM_ERR_UNSUPPORTED.
  *
  * Errors: every entry point returns a varsim_status; on failure varsim_last_error() holds a
  * message.  Device failures (launch or runtime errors) return VARSIM_ERR_DEVICE.
@@ -68,7 +71,7 @@ enum { VARSIM_COND_SOURCE = 0, VARSIM_COND_TARGET = 1 };
 
 typedef struct varsim_ctx varsim_ctx;
 
-/* One material layer (Table param gives the paper's stack; one silicon layer is supported). */
+/* One material layer (Table param gives the paper's stack: silicon, TIM, heat spreader). */
 typedef struct varsim_layer {
   double thickness_m;   /* t, > 0 */
   double k0_W_mK;       /* conductivity at 300 K, > 0 (Eq. condsi) */
@@ -76,14 +79,21 @@ typedef struct varsim_layer {
   double rho_c_J_m3K;   /* volumetric heat capacity, > 0 (transient only) */
 } varsim_layer;
 
-/* Die geometry and boundary (Sec. V-A: a die of lx x ly discretised on an nx x ny grid). */
+/* Die geometry and boundary (Sec. V-A: a die of lx x ly discretised on an nx x ny grid).
+ * Power enters the top face of layer 0 (the silicon); the layers below it (the package of
+ * Table param, Sec. II-B's f_sp = f_silic + const) share the die's lateral extent and
+ * adiabatic side walls, each with the constant conductivity k0 (T_amb / 300)^-eta.  The stack
+ * enters the solve through the exact surface impedance of the layers (Eq. fourier layer by
+ * layer) added to the silicon slab's cosine eigenvalues; k(T) (the Kirchhoff inverse) uses
+ * layer 0's law, which is exact for one layer over an isothermal bottom and an approximation
+ * otherwise. */
 typedef struct varsim_geometry {
   double lx_m, ly_m;            /* die size, > 0 */
-  int32_t nx, ny;               /* grid; nx == ny, power of two in [16, 1024] */
-  int32_t n_layers;             /* must be 1 */
-  const varsim_layer* layers;   /* host pointer, n_layers entries */
-  int32_t bottom_bc;            /* 0 = bottom face isothermal at t_amb_K (only value supported) */
-  double h_bottom_W_m2K;        /* reserved for a convective bottom; ignored */
+  int32_t nx, ny;               /* grid (see the supported grids above) */
+  int32_t n_layers;             /* 1..8 */
+  const varsim_layer* layers;   /* host pointer, n_layers entries, top first */
+  int32_t bottom_bc;            /* 0 = bottom face isothermal at t_amb_K; 1 = convective to t_amb_K */
+  double h_bottom_W_m2K;        /* heat-transfer coefficient of the convective bottom, > 0 */
   double t_amb_K;               /* ambient temperature, > 0 */
 } varsim_geometry;
 
@@ -170,8 +180,9 @@ VARSIM_API const char* varsim_last_error(const varsim_ctx* ctx);
  * the mirror images of the side walls), a in [0, nx], b in [0, ny], and its cosine transform
  *     lambda[p][q] = sum_{a, b in (-n, n]} K_per(a, b) cos(pi p b / ny) cos(pi q a / nx)
  * which diagonalises the mirrored convolution.  The conductivity used is k(T_amb).
- *   kernel_out : DEVICE double [ny + 1][nx + 1], or NULL
- *   lambda_out : DEVICE double [ny][nx], or NULL
+ *   kernel_out : DEVICE double [ny + 1][nx + 1], or NULL (must be NULL for a package stack,
+ *                whose eigenvalues alone are tabulated: UNSUPPORTED otherwise)
+ *   lambda_out : DEVICE double [ny][nx], or NULL (a stack's eigenvalues include its layers)
  * The table is also cached in the context for the solves.  Synchronises `stream`.
  * Errors: INVALID, UNSUPPORTED, DEVICE, NO_MEMORY.
  */

@@ -57,13 +57,17 @@ varsim_status check_geometry(varsim_ctx* ctx, const varsim_geometry* g) {
   if (row_pass_groups(g->nx, g->ny) < 1)
     return fail(ctx, VARSIM_ERR_UNSUPPORTED, "grid %dx%d: rows of %d cells need ny >= %d", g->nx, g->ny, g->nx,
                 row_pass_rows(g->nx));
-  if (g->n_layers != 1 || !g->layers)
-    return fail(ctx, g->n_layers < 1 || !g->layers ? VARSIM_ERR_INVALID : VARSIM_ERR_UNSUPPORTED,
-                "exactly one layer is supported");
-  if (g->bottom_bc != 0) return fail(ctx, VARSIM_ERR_UNSUPPORTED, "only an isothermal bottom is supported");
-  const varsim_layer& L = g->layers[0];
-  if (!(L.thickness_m > 0) || !(L.k0_W_mK > 0) || !(L.eta >= 0))
-    return fail(ctx, VARSIM_ERR_INVALID, "layer thickness, k0 must be positive and eta >= 0");
+  if (g->n_layers < 1 || !g->layers) return fail(ctx, VARSIM_ERR_INVALID, "at least one layer is required");
+  if (g->n_layers > kMaxLayers) return fail(ctx, VARSIM_ERR_UNSUPPORTED, "at most %d layers", kMaxLayers);
+  for (int i = 0; i < g->n_layers; ++i) {
+    const varsim_layer& L = g->layers[i];
+    if (!(L.thickness_m > 0) || !(L.k0_W_mK > 0) || !(L.eta >= 0) || !std::isfinite(L.thickness_m) ||
+        !std::isfinite(L.k0_W_mK) || !std::isfinite(L.eta))
+      return fail(ctx, VARSIM_ERR_INVALID, "layer %d: thickness, k0 must be positive and eta >= 0", i);
+  }
+  if (g->bottom_bc != 0 && g->bottom_bc != 1) return fail(ctx, VARSIM_ERR_INVALID, "bottom_bc must be 0 or 1");
+  if (g->bottom_bc == 1 && (!(g->h_bottom_W_m2K > 0) || !std::isfinite(g->h_bottom_W_m2K)))
+    return fail(ctx, VARSIM_ERR_INVALID, "a convective bottom needs h_bottom_W_m2K > 0");
   return VARSIM_OK;
 }
 
@@ -84,13 +88,50 @@ varsim_status check_options(varsim_ctx* ctx, const varsim_options* o) {
   return VARSIM_OK;
 }
 
-double k_ref_of(const varsim_geometry* g) {
-  const varsim_layer& L = g->layers[0];
+double k_ref_of(const varsim_geometry* g, int layer = 0) {
+  const varsim_layer& L = g->layers[layer];
   return L.k0_W_mK * std::pow(g->t_amb_K / 300.0, -L.eta);
 }
 
+bool is_stack(const varsim_geometry* g) { return g->n_layers > 1 || g->bottom_bc != 0; }
+
+// One-dimensional thermal resistance of the die and package per unit area, sum t_i / k_i (+ 1/h):
+// the response of the uniform mode, the largest eigenvalue of the operator times hx hy.
+double series_resistance(const varsim_geometry* g) {
+  double r = g->bottom_bc ? 1.0 / g->h_bottom_W_m2K : 0.0;
+  for (int i = 0; i < g->n_layers; ++i) r += g->layers[i].thickness_m / k_ref_of(g, i);
+  return r;
+}
+
 TableKey key_of(const varsim_geometry* g) {
-  return TableKey(g->nx, g->ny, g->lx_m, g->ly_m, g->layers[0].thickness_m, k_ref_of(g));
+  std::vector<double> extra;
+  if (is_stack(g)) {
+    extra.push_back(g->bottom_bc);
+    extra.push_back(g->bottom_bc ? g->h_bottom_W_m2K : 0.0);
+    for (int i = 1; i < g->n_layers; ++i) {
+      extra.push_back(g->layers[i].thickness_m);
+      extra.push_back(k_ref_of(g, i));
+    }
+  }
+  return TableKey(g->nx, g->ny, g->lx_m, g->ly_m, g->layers[0].thickness_m, k_ref_of(g), extra);
+}
+
+// The table description of a geometry: grid, first layer, and the package stack if any.
+TableSpec spec_of(const varsim_geometry* g) {
+  TableSpec sp{g->nx, g->ny, g->lx_m, g->ly_m, g->layers[0].thickness_m, k_ref_of(g), StackSpec{}};
+  if (is_stack(g)) {
+    StackSpec& st = sp.stack;
+    st.n = g->n_layers;
+    st.bottom_h = g->bottom_bc ? g->h_bottom_W_m2K : 0.0;
+    for (int i = 0; i < g->n_layers; ++i) {
+      st.t[i] = g->layers[i].thickness_m;
+      st.k[i] = k_ref_of(g, i);
+    }
+    // aliases until exp(-2 |kappa| t1) < 1e-21: |kappa| >= 2 pi j / h_max
+    const double hmax = std::max(g->lx_m / g->nx, g->ly_m / g->ny);
+    st.aliases = 1 + (int)std::ceil(25.0 * hmax / (2.0 * M_PI * st.t[0]));
+  }
+  return sp;
 }
 
 varsim_status get_twiddles(varsim_ctx* ctx, int n, hipStream_t s, TwEntry* out) {
@@ -119,7 +160,7 @@ varsim_status get_table(varsim_ctx* ctx, const varsim_geometry* g, hipStream_t s
     *out = it->second;
     return VARSIM_OK;
   }
-  TableSpec sp{g->nx, g->ny, g->lx_m, g->ly_m, g->layers[0].thickness_m, k_ref_of(g)};
+  TableSpec sp = spec_of(g);
   TableEntry e = it != ctx->tables.end() ? it->second : TableEntry{};
   const bool fresh = it == ctx->tables.end();
   if (fresh) {
@@ -180,7 +221,7 @@ varsim_status get_det_coef(varsim_ctx* ctx, const varsim_geometry* g, const Tabl
     (void)hipFree(e.coef64);
     return fail(ctx, VARSIM_ERR_NO_MEMORY, "deterministic-operator table allocation failed");
   }
-  const TableSpec sp{g->nx, g->ny, g->lx_m, g->ly_m, g->layers[0].thickness_m, k_ref_of(g)};
+  const TableSpec sp = spec_of(g);
   HIP_TRY(timed(ctx, "det_table", s, [&] { return launch_det_coef(sp, tab.lam64T, c, e.coef64, e.coef32, s); }));
   ctx->det_coefs[key] = e;
   *out = e;
@@ -361,6 +402,8 @@ varsim_status check_transient(varsim_ctx* ctx, const varsim_problem* p, const va
   if (s != VARSIM_OK) return s;
   if (p->geom->nx != p->geom->ny)
     return fail(ctx, VARSIM_ERR_UNSUPPORTED, "transient solves take square grids (nx == ny)");
+  if (is_stack(p->geom))
+    return fail(ctx, VARSIM_ERR_UNSUPPORTED, "transient solves take one layer over an isothermal bottom");
   if ((s = check_options(ctx, o)) != VARSIM_OK) return s;
   if (!p->dT_out) return fail(ctx, VARSIM_ERR_INVALID, "dT_out is required");
   if (!(p->geom->layers[0].rho_c_J_m3K > 0) || !std::isfinite(p->geom->layers[0].rho_c_J_m3K))
@@ -566,6 +609,8 @@ varsim_status varsim_green_table(varsim_ctx* ctx, const varsim_geometry* geom, v
   TwEntry tw;
   if ((st = get_twiddles(ctx, geom->nx, s, &tw)) != VARSIM_OK) return st;
   if ((st = get_twiddles(ctx, geom->ny, s, &tw)) != VARSIM_OK) return st;
+  if (kernel_out && is_stack(geom))
+    return fail(ctx, VARSIM_ERR_UNSUPPORTED, "K_per is tabulated for a single slab only (lambda_out covers stacks)");
   if (kernel_out)
     HIP_TRY(hipMemcpyAsync(kernel_out, e.kper, (size_t)(geom->nx + 1) * (geom->ny + 1) * sizeof(double),
                            hipMemcpyDeviceToDevice, s));
@@ -1023,11 +1068,11 @@ varsim_status varsim_solve_oneshot(varsim_ctx* ctx, const varsim_problem* proble
   std::vector<DetEntry> det(groups.size());
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     Group& g = groups[gi];
-    // the deterministic operator (I - c K) is invertible while c lambda_max = beta mu t / k_ref < 1
-    // (lambda_max = sum of the kernel = t / (k_ref hx hy))
+    // the deterministic operator (I - c K) is invertible while c lambda_max = beta mu R < 1
+    // (lambda_max = sum of the kernel = R / (hx hy), R the series resistance)
     const double c = beta * (g.geom->lx_m / g.geom->nx) * (g.geom->ly_m / g.geom->ny) * os->mu_W_m2;
-    if (beta * os->mu_W_m2 * g.geom->layers[0].thickness_m / k_ref_of(g.geom) >= 1.0)
-      return fail(ctx, VARSIM_ERR_RUNAWAY, "beta mu t / k >= 1: the linearised leakage has no fixed point");
+    if (beta * os->mu_W_m2 * series_resistance(g.geom) >= 1.0)
+      return fail(ctx, VARSIM_ERR_RUNAWAY, "beta mu R >= 1: the linearised leakage has no fixed point");
     if ((st = get_table(ctx, g.geom, s, &g.table)) != VARSIM_OK) return st;
     if ((st = get_twiddles(ctx, g.geom->nx, s, &g.tw)) != VARSIM_OK) return st;
     if ((st = get_twiddles(ctx, g.geom->ny, s, &g.twc)) != VARSIM_OK) return st;
@@ -1219,7 +1264,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   q.flags = d_flags;
 
   // static inputs: flags, spectral state, QL, 1/m, block ids, per-mode (a, b)
-  const TableSpec sp{g->nx, g->ny, g->lx_m, g->ly_m, g->layers[0].thickness_m, k_ref_of(g)};
+  const TableSpec sp = spec_of(g);
   const double alpha = sp.k_ref / g->layers[0].rho_c_J_m3K;
   HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(ws, L.state_end, s); }));
   HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(a.state, (size_t)cells * esize(io), s); }));

@@ -34,7 +34,8 @@ struct TwEntry {
 
 inline Twiddles twiddles_of(const TwEntry& e) { return Twiddles{e.tw64, e.tw32, e.qw64, e.qw32, e.tw32lo, e.qw32lo}; }
 
-using TableKey = std::tuple<int, int, double, double, double, double>;
+// (nx, ny, lx, ly, t1, k1_ref, {bottom_bc, h, t2, k2_ref, t3, k3_ref, ...} for a stack)
+using TableKey = std::tuple<int, int, double, double, double, double, std::vector<double>>;
 
 // Column coefficients of the one-shot solve's deterministic operator, per (geometry, c).
 struct DetEntry {

@@ -5,9 +5,19 @@
 
 namespace vs {
 
+// Package layers below the first (silicon) layer and the bottom face (Table param).
+constexpr int kMaxLayers = 8;
+struct StackSpec {
+  int n;            // layers including the first (1: a single slab)
+  int aliases;      // image aliases per side summed for the eigenvalue correction
+  double bottom_h;  // convective bottom coefficient W/m^2K (0: isothermal bottom)
+  double t[kMaxLayers], k[kMaxLayers];  // thickness and conductivity (at T_amb) of each layer
+};
+
 struct TableSpec {
   int nx, ny;
-  double lx, ly, t, k_ref;
+  double lx, ly, t, k_ref;  // grid, die size, first layer's thickness and conductivity at T_amb
+  StackSpec stack;          // zero: a single slab over an isothermal bottom
 };
 
 // Green's-function table: K_per [ny+1][nx+1], lambda transposed and scaled (FP64, FP32), the

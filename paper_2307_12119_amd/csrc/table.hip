@@ -318,6 +318,56 @@ __global__ void twiddle_kernel(Cx<double>* tw64, Cx<float>* tw32, Cx<double>* qw
   qw32lo[k] = {lo(c), lo(s)};
 }
 
+// Package stack below the first layer (Table param; Sec. II-B's f_sp = f_silic + const): the
+// first layer's cosine eigenvalues get the stack's extra impedance.  With Z the impedance
+// T / q seen from the bottom face of layer 1 looking down (Z = 0 isothermal, 1/h convective,
+// then up through each lower layer: Z <- (Z + tanh(s t) / (k s)) / (1 + k s tanh(s t) Z)), the
+// stack's surface symbol minus layer 1's alone is, without cancellation,
+//     dF(s) = Z sech^2(s t1) / (1 + k1 s tanh(s t1) Z),
+// and the mirrored, cell-averaged operator's eigenvalue gains
+//     dlambda[p][q] = (1 / (hx hy)) sum_{i, j} dF(|kappa|) S(kappa),
+//     kappa = (pi (q + 2 nx j) / lx, pi (p + 2 ny i) / ly),  S = sinc(kx hx / 2) sinc(ky hy / 2)
+// (the images' Poisson sum; |i|, |j| <= aliases, beyond which exp(-2 |kappa| t1) < 1e-21).
+__global__ void __launch_bounds__(256) stack_lambda_kernel(double* __restrict__ lam64T, float* __restrict__ lam32T,
+                                                           double* __restrict__ lam_rowmajor, StackSpec st, int nx,
+                                                           int ny, double lx, double ly, double scale) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (p >= ny) return;
+  const double hx = lx / nx, hy = ly / ny;
+  double acc = 0.0;
+  for (int j = -st.aliases; j <= st.aliases; ++j) {
+    const double kx = M_PI * (q + 2.0 * nx * j) / lx;
+    const double ux = 0.5 * kx * hx;
+    const double sx = ux == 0.0 ? 1.0 : sin(ux) / ux;
+    for (int i = -st.aliases; i <= st.aliases; ++i) {
+      const double ky = M_PI * (p + 2.0 * ny * i) / ly;
+      const double uy = 0.5 * ky * hy;
+      const double sy = uy == 0.0 ? 1.0 : sin(uy) / uy;
+      const double s = hypot(kx, ky);
+      double z = st.bottom_h > 0.0 ? 1.0 / st.bottom_h : 0.0;
+      double dF;
+      if (s == 0.0) {
+        for (int l = st.n - 1; l >= 1; --l) z += st.t[l] / st.k[l];
+        dF = z;
+      } else {
+        for (int l = st.n - 1; l >= 1; --l) {
+          const double th = tanh(s * st.t[l]);
+          z = (z + th / (st.k[l] * s)) / (1.0 + st.k[l] * s * th * z);
+        }
+        const double th1 = tanh(s * st.t[0]), ch = cosh(s * st.t[0]);
+        dF = s * st.t[0] > 350.0 ? 0.0 : z / (ch * ch) / (1.0 + st.k[0] * s * th1 * z);
+      }
+      acc += dF * sx * sy;
+    }
+  }
+  const double d = acc / (hx * hy);
+  const size_t o = (size_t)q * ny + p;
+  lam64T[o] += d * scale;
+  lam32T[o] = (float)lam64T[o];
+  if (lam_rowmajor) lam_rowmajor[(size_t)p * nx + q] += d;
+}
+
 }  // namespace
 
 // number of 2L periods per side beyond which the kernel is below 1e-30 of its peak
@@ -351,6 +401,9 @@ hipError_t launch_green_table(const TableSpec& sp, double* kper, double* lam64T,
                      sp.ny);
   hipLaunchKernelGGL(dct1_y_kernel, dim3((sp.ny + 255) / 256, sp.nx), dim3(256), 0, stream, A, lam64T, lam32T,
                      lam_rowmajor, cosy, sp.nx, sp.ny, 1.0 / ((double)sp.nx * sp.ny));
+  if (sp.stack.n > 1 || sp.stack.bottom_h > 0.0)
+    hipLaunchKernelGGL(stack_lambda_kernel, dim3((sp.ny + 255) / 256, sp.nx), dim3(256), 0, stream, lam64T, lam32T,
+                       lam_rowmajor, sp.stack, sp.nx, sp.ny, sp.lx, sp.ly, 1.0 / ((double)sp.nx * sp.ny));
   hipLaunchKernelGGL(coef_kernel, dim3((sp.ny / 2 + 1 + 255) / 256, sp.nx), dim3(256), 0, stream, lam64T, coef64, coef32,
                      sp.nx, sp.ny, 0.0);
   return hipGetLastError();

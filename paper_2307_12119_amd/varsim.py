@@ -166,7 +166,9 @@ def _stream() -> int:
 
 @dataclass
 class Die:
-    """Geometry and material of a single-layer die (SI units)."""
+    """Geometry and material of a die (SI units): the silicon layer, optionally the package
+    layers below it (``stack``: (thickness, k0, eta) per layer, top first) and a convective
+    bottom (``h_bottom`` in W/m^2K; None: isothermal at t_amb)."""
 
     lx_m: float
     ly_m: float
@@ -175,13 +177,19 @@ class Die:
     eta: float
     t_amb: float
     rho_c: float = 1.66e6
+    stack: tuple = ()
+    h_bottom: float | None = None
 
 
-def make_geometry(die: Die, n: int, ny: int | None = None) -> tuple[Geometry, Layer]:
-    """Geometry of an n x n grid (n columns by ny rows when ny is given)."""
-    layer = Layer(die.t_m, die.k0, die.eta, die.rho_c)
-    geom = Geometry(die.lx_m, die.ly_m, n, ny or n, 1, None, 0, 0.0, die.t_amb)
-    return geom, layer
+def make_geometry(die: Die, n: int, ny: int | None = None):
+    """Geometry of an n x n grid (n columns by ny rows when ny is given) and its layer array
+    (keep both alive while the geometry is used); geom.layers already points at the array."""
+    layers = [Layer(die.t_m, die.k0, die.eta, die.rho_c)] + [Layer(t, k, e, die.rho_c) for t, k, e in die.stack]
+    arr = (Layer * len(layers))(*layers)
+    bc = 0 if die.h_bottom is None else 1
+    geom = Geometry(die.lx_m, die.ly_m, n, ny or n, len(layers), ctypes.cast(arr, POINTER(Layer)), bc,
+                    0.0 if die.h_bottom is None else float(die.h_bottom), die.t_amb)
+    return geom, arr
 
 
 def make_options(precision: int = F32, leak: int = LEAK_EXP, beta: float = 0.017, max_iter: int = 50,
@@ -222,14 +230,15 @@ class Context:
 
     # -------------------------------------------------------------------------------- table
     def green_table(self, die: Die, n: int, ny: int | None = None):
-        """(K_per [ny+1][n+1], lambda [ny][n]) as FP64 device tensors (ny = n by default)."""
+        """(K_per [ny+1][n+1], lambda [ny][n]) as FP64 device tensors (ny = n by default); K_per is
+        None for a package stack (only its eigenvalues are tabulated)."""
         import torch
 
         ny = ny or n
         geom, layer = make_geometry(die, n, ny)
-        geom.layers = ctypes.pointer(layer)
         dev = torch.device("cuda", self.device)
-        kper = torch.empty((ny + 1, n + 1), dtype=torch.float64, device=dev)
+        slab = not die.stack and die.h_bottom is None
+        kper = torch.empty((ny + 1, n + 1), dtype=torch.float64, device=dev) if slab else None
         lam = torch.empty((ny, n), dtype=torch.float64, device=dev)
         self._check(self.lib.varsim_green_table(self.handle, ctypes.byref(geom), _ptr(kper), _ptr(lam), _stream()))
         return kper, lam
@@ -240,7 +249,6 @@ class Context:
 
         ny, n = power.shape[-2], power.shape[-1]
         geom, layer = make_geometry(die, n, ny)
-        geom.layers = ctypes.pointer(layer)
         prec = F64 if power.dtype == torch.float64 else F32
         out = torch.empty_like(power) if out is None else out
         n_maps = power.numel() // (n * ny)
@@ -255,7 +263,6 @@ class Context:
             geom, layer = make_geometry(it["die"], it["dT_out"].shape[-1], it["dT_out"].shape[-2])
             layers.append(layer)
             geoms.append(geom)
-            geom.layers = ctypes.pointer(layer)
             probs[i] = Problem(ctypes.pointer(geom), _ptr(it.get("q_dyn")), _ptr(it.get("q_leak0")),
                                _ptr(it.get("leak_var")), _ptr(it.get("cond_map")), _ptr(it.get("dT_init")),
                                _ptr(it["dT_out"]))
