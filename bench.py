@@ -897,6 +897,21 @@ def transient_bench(ctx, runs: int) -> dict:
     torch.cuda.synchronize()
     wall_untimed = time.perf_counter() - t0
     got = snaps.cpu().numpy().astype(np.float64)
+    # the multi-pole model (the slab's 3 slowest depth modes + 1 lumped pole per cosine mode)
+    ws4 = torch.empty(ctx.transient_workspace_bytes(item, rects, trace, inp.dt_s, opts, every, V.TAU_MODAL, 4),
+                      dtype=torch.uint8, device=dev)
+    snaps4 = torch.zeros_like(snaps)
+    ctx.solve_transient(item, rects, trace, inp.dt_s, opts, snaps4, every, tau_model=V.TAU_MODAL, workspace=ws4,
+                        n_poles=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.solve_transient(item, rects, trace, inp.dt_s, opts, snaps4, every, tau_model=V.TAU_MODAL, workspace=ws4,
+                        n_poles=4)
+    torch.cuda.synchronize()
+    wall4 = time.perf_counter() - t0
+    modal = {"poles": 4, "ms_per_run": round(wall4 * 1e3, 3),
+             "max_diff_vs_single_pole_K": float((snaps4 - snaps).abs().max())}
+    del ws4, snaps4
     item64, rects64, trace64, snaps64 = setup(torch.float64)
     opts64 = V.make_options(V.F64, V.LEAK_EXP, inp.beta, 1, 1e-3)
     ctx.solve_transient(item64, rects64, trace64, inp.dt_s, opts64, snaps64, every)
@@ -915,7 +930,7 @@ def transient_bench(ctx, runs: int) -> dict:
             "ms_per_run": round(wall_untimed * 1e3, 3), "ms_per_run_with_kernel_events": round(wall * 1e3, 3),
             "steps_per_s": round(steps / wall_untimed, 1), "status": st["status"],
             "dT_max_K": st["dT_max_K"], "fp64_shadow_max_diff_K": float(np.max(np.abs(got - ref))),
-            "kernels": kernels,
+            "kernels": kernels, "modal": modal,
             "autotune": [l for l in ctx.autotune_report().strip().split("\n") if l.startswith("transient")]}
 
 

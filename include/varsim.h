@@ -61,7 +61,11 @@ typedef enum varsim_status {
 
 enum { VARSIM_LEAK_NONE = 0, VARSIM_LEAK_EXP = 1, VARSIM_LEAK_LINEAR = 2 };
 enum { VARSIM_F32 = 0, VARSIM_F64 = 1 };
-enum { VARSIM_TAU_MOMENT = 0, VARSIM_TAU_LUMPED = 1 };
+/* Transient time constants per cosine mode: MOMENT -- one pole with the exact first moment of
+ * the slab's response; LUMPED -- one pole with the paper's tau = C F(f_sp0), C = rho c t / 3;
+ * MODAL -- the slab's slowest depth modes as separate poles (n_poles - 1 of them) plus one
+ * lumped pole keeping the first moment (n_poles = 1 is MOMENT). */
+enum { VARSIM_TAU_MOMENT = 0, VARSIM_TAU_LUMPED = 1, VARSIM_TAU_MODAL = 2 };
 /* Where the conductivity-variation factor 1/m acts (Eq. fspvsk read as a Hadamard factor):
  *   SOURCE: theta = K (*) (P / m) -- each source's heat spreads with its own cell's conductivity;
  *   TARGET: theta = (K (*) P) / m -- the target cell's conductivity scales its rise.
@@ -160,7 +164,11 @@ typedef struct varsim_transient {
                                    overwrite earlier ones where they overlap */
   const void* trace;            /* DEVICE [n_steps][n_blocks] dynamic power density of each block
                                    held over step n, W/m^2, element type = precision */
-  int32_t tau_model;            /* VARSIM_TAU_MOMENT or VARSIM_TAU_LUMPED */
+  int32_t tau_model;            /* VARSIM_TAU_MOMENT, VARSIM_TAU_LUMPED or VARSIM_TAU_MODAL */
+  int32_t n_poles;              /* poles per mode of VARSIM_TAU_MODAL, in [1, 8] (ignored otherwise);
+                                   each pole keeps its own spectral state (n_poles maps of
+                                   workspace) and moves two more maps of state and coefficients
+                                   per step */
 } varsim_transient;
 
 /* ----------------------------------------------------------------------------------------

@@ -412,8 +412,10 @@ varsim_status check_transient(varsim_ctx* ctx, const varsim_problem* p, const va
   if (tr->n_steps < 1 || tr->out_every < 1 || tr->n_blocks < 1)
     return fail(ctx, VARSIM_ERR_INVALID, "n_steps, out_every and n_blocks must be >= 1");
   if (!tr->block_rects || !tr->trace) return fail(ctx, VARSIM_ERR_INVALID, "block_rects and trace are required");
-  if (tr->tau_model != VARSIM_TAU_MOMENT && tr->tau_model != VARSIM_TAU_LUMPED)
+  if (tr->tau_model != VARSIM_TAU_MOMENT && tr->tau_model != VARSIM_TAU_LUMPED && tr->tau_model != VARSIM_TAU_MODAL)
     return fail(ctx, VARSIM_ERR_INVALID, "bad tau_model");
+  if (tr->tau_model == VARSIM_TAU_MODAL && (tr->n_poles < 1 || tr->n_poles > kMaxPoles))
+    return fail(ctx, VARSIM_ERR_INVALID, "n_poles must be in [1, %d]", kMaxPoles);
   return VARSIM_OK;
 }
 
@@ -423,9 +425,12 @@ struct TransLayout {
   size_t QL = (size_t)-1, MINV = (size_t)-1, IDZ = 0, QLZ = (size_t)-1, MINVZ = (size_t)-1, total = 0;
 };
 
-TransLayout make_transient_layout(const varsim_problem* p, const varsim_options* o) {
+int poles_of(const varsim_transient* tr) { return tr->tau_model == VARSIM_TAU_MODAL ? tr->n_poles : 1; }
+
+TransLayout make_transient_layout(const varsim_problem* p, const varsim_transient* tr, const varsim_options* o) {
   TransLayout L;
   const size_t cells = (size_t)p->geom->nx * p->geom->ny, es = esize(o->precision);
+  const size_t poles = (size_t)poles_of(tr);
   size_t off = 0;
   L.flags = off;
   off = align_up(off + 4);
@@ -436,10 +441,10 @@ TransLayout make_transient_layout(const varsim_problem* p, const varsim_options*
   off = align_up(off + sizeof(PrepArgs));
   L.S = off;
   off = align_up(off + cells * es);
-  L.state = off;
-  off = align_up(off + cells * es);
+  L.state = off;  // one plane per pole
+  off = align_up(off + poles * cells * es);
   L.ab = off;
-  off = align_up(off + 2 * cells * es);
+  off = align_up(off + poles * 2 * cells * es);
   L.ids = off;
   off = align_up(off + cells * 4);
   if (p->q_leak0 && o->leak != VARSIM_LEAK_NONE && p->leak_var) {
@@ -1202,7 +1207,7 @@ varsim_status varsim_transient_workspace_size(varsim_ctx* ctx, const varsim_prob
   if (!bytes) return fail(ctx, VARSIM_ERR_INVALID, "bytes is NULL");
   varsim_status st = check_transient(ctx, problem, tr, opts);
   if (st != VARSIM_OK) return st;
-  *bytes = make_transient_layout(problem, opts).total;
+  *bytes = make_transient_layout(problem, tr, opts).total;
   return VARSIM_OK;
 }
 
@@ -1213,7 +1218,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   if (!stats || !workspace) return fail(ctx, VARSIM_ERR_INVALID, "NULL stats or workspace");
   varsim_status st = check_transient(ctx, problem, tr, opts);
   if (st != VARSIM_OK) return st;
-  const TransLayout L = make_transient_layout(problem, opts);
+  const TransLayout L = make_transient_layout(problem, tr, opts);
   if (ws_bytes < L.total)
     return fail(ctx, VARSIM_ERR_NO_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
   hipStream_t s = (hipStream_t)stream;
@@ -1236,6 +1241,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   a.n = g->nx;
   a.S = ws + L.S;
   a.state = ws + L.state;
+  a.poles = poles_of(tr);
   a.ab = ws + L.ab;
   a.ids = (const int*)(ws + L.ids);
   a.trace = tr->trace;
@@ -1267,7 +1273,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   const TableSpec sp = spec_of(g);
   const double alpha = sp.k_ref / g->layers[0].rho_c_J_m3K;
   HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(ws, L.state_end, s); }));
-  HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(a.state, (size_t)cells * esize(io), s); }));
+  HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(a.state, (size_t)a.poles * cells * esize(io), s); }));
   HIP_TRY(hipMemcpyAsync(d_prep, ctx->h_prep.data(), sizeof(PrepArgs), hipMemcpyHostToDevice, s));
   HIP_TRY(timed(ctx, "prep", s, [&] { return launch_prep(io, d_prep, 1, cells, s); }));
   HIP_TRY(timed(ctx, "setup", s, [&] {
@@ -1275,7 +1281,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   }));
   HIP_TRY(timed(ctx, "setup", s, [&] {
     return launch_transient_coef(sp, tab.lam64T, io, (void*)a.ab, alpha, tr->dt_s, tr->tau_model,
-                                 g->layers[0].rho_c_J_m3K, s);
+                                 g->layers[0].rho_c_J_m3K, a.poles, s);
   }));
   if (transient_single_ok(g->nx)) {
     HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zorder(4, a.ids, (void*)a.idz, g->nx, s); }));
@@ -1349,7 +1355,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
     cv = (int)(std::min_element(ms.begin() + nv, ms.end()) - (ms.begin() + nv));
     ctx->tr_choice[key] = {rv, cv};
     ctx->tr_ms[key] = ms;
-    HIP_TRY(launch_zero_words(a.state, (size_t)cells * esize(io), s));
+    HIP_TRY(launch_zero_words(a.state, (size_t)a.poles * cells * esize(io), s));
     HIP_TRY(launch_zero_words(d_flags, sizeof(unsigned), s));
   }
   if (ctx->force_tr_row >= 0) rv = ctx->force_tr_row < nv ? ctx->force_tr_row : 0;

@@ -131,11 +131,13 @@ int row_pass_rows(int nx);
 int row_pass_groups(int nx, int ny);
 
 // Transient solve of one map (element type T = io = compute type).
+constexpr int kMaxPoles = 8;  // poles per cosine mode of the multi-pole transient model
 struct TransArgs {
   int n;
   void* S;            // [n][n] transform work array
-  void* state;        // [n][n] spectral state theta_hat, layout [q][p] (q: row-transform index)
-  const void* ab;     // [n][n][2] per-mode (a, b), layout [q][p]
+  void* state;        // [poles][n][n] spectral state theta_hat, layout [q][p] (q: row-transform index)
+  const void* ab;     // [poles][n][n][2] per-mode (a, b), layout [q][p]
+  int poles;          // poles per mode (1 but for the multi-pole model)
   const int* ids;     // [n][n] block id of each cell, -1 where no block
   const void* trace;  // [n_steps][n_blocks] block power densities
   int n_blocks;
@@ -157,7 +159,7 @@ enum TransMode : int { TR_HEAD = 0, TR_MERGED = 1, TR_LAST = 2 };
 
 // (a, b) per mode from lambda (lam64T, scaled as the column pass uses it), dt and tau_model
 hipError_t launch_transient_coef(const TableSpec& sp, const double* lam64T, int io, void* ab, double alpha, double dt,
-                                 int tau_model, double rho_c, hipStream_t stream);
+                                 int tau_model, double rho_c, int poles, hipStream_t stream);
 hipError_t launch_block_ids(const int* rects, int n_blocks, int* ids, int nx, int ny, hipStream_t stream);
 // TR_HEAD: P_1 -> row spectrum; TR_MERGED (step n): row synthesis -> dT_n -> P_{n+1} -> row
 // spectrum; TR_LAST: row synthesis -> dT_n (final)

@@ -44,27 +44,48 @@ __device__ double tau_moment(double s, double t, double alpha) {
   return (1.0 - x / sinh(x)) / (2.0 * alpha * s * s);
 }
 
-// ab[q][p] = (exp(-dt/tau), -expm1(-dt/tau) lambda'), lambda' = lamT[q][p] (scaled by 1/(nx ny))
+// ab[j][q][p] = (exp(-dt/tau_j), -expm1(-dt/tau_j) w_j lambda'), lambda' = lamT[q][p] (scaled by
+// 1/(nx ny)), for the poles j < poles of mode (p, q).  One pole: tau = the lumped (rho c t / 3)
+// hx hy lambda or the moment tau(s), w = 1.  Modal (poles >= 1): the slab's depth modes
+// m < poles - 1, tau_m = t^2 / (alpha ((s t)^2 + ((m + 1/2) pi)^2)), w_m = 2 (s t / tanh(s t)) /
+// ((s t)^2 + ((m + 1/2) pi)^2), and one last pole with the remaining weight whose time constant
+// keeps the first moment sum_j w_j tau_j = tau(s).
 template <typename T>
 __global__ void __launch_bounds__(256) transient_coef_kernel(const double* __restrict__ lamT, T* __restrict__ ab,
                                                              int nx, int ny, double lx, double ly, double t,
-                                                             double alpha, double dt, int tau_model, double lumped_c) {
+                                                             double alpha, double dt, int tau_model, double lumped_c,
+                                                             int poles) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (p >= ny) return;
   const double lam = lamT[(size_t)q * ny + p];
-  double tau;
+  const double s = M_PI * sqrt(((double)p / ly) * ((double)p / ly) + ((double)q / lx) * ((double)q / lx));
+  const size_t plane = (size_t)nx * ny * 2;
+  auto put = [&](int j, double tau, double w) {
+    const size_t o = j * plane + ((size_t)q * ny + p) * 2;
+    ab[o] = (T)exp(-dt / tau);
+    ab[o + 1] = (T)(-expm1(-dt / tau) * w * lam);
+  };
   if (tau_model == VARSIM_TAU_LUMPED) {
-    tau = lumped_c * lam;  // (rho c t / 3) hx hy lambda = (rho c t / 3) (lx ly) lambda'
-  } else {
-    const double s = M_PI * sqrt(((double)p / ly) * ((double)p / ly) + ((double)q / lx) * ((double)q / lx));
-    tau = tau_moment(s, t, alpha);
+    put(0, lumped_c * lam, 1.0);  // (rho c t / 3) hx hy lambda = (rho c t / 3) (lx ly) lambda'
+    return;
   }
-  const double a = exp(-dt / tau);
-  const double b = -expm1(-dt / tau) * lam;
-  const size_t o = ((size_t)q * ny + p) * 2;
-  ab[o] = (T)a;
-  ab[o + 1] = (T)b;
+  const double tm = tau_moment(s, t, alpha);
+  if (tau_model != VARSIM_TAU_MODAL || poles <= 1) {
+    put(0, tm, 1.0);
+    return;
+  }
+  const double x = s * t, xt = x < 1e-8 ? 1.0 : x / tanh(x);
+  double wsum = 0.0, first = 0.0;
+  for (int m = 0; m < poles - 1; ++m) {
+    const double bt = (m + 0.5) * M_PI, d = x * x + bt * bt;
+    const double w = 2.0 * xt / d, tau = t * t / (alpha * d);
+    put(m, tau, w);
+    wsum += w;
+    first += w * tau;
+  }
+  const double wr = 1.0 - wsum;
+  put(poles - 1, (tm - first) / wr, wr);
 }
 
 // block id of each cell: the last block (painter's order) whose rectangle covers it, else -1
@@ -268,6 +289,19 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
     nb[m] = dot2(kb.v[0], stb[p], kb.v[1], xb);
     sta[p] = na[m];
     stb[p] = nb[m];
+    // further poles of the multi-pole model: their states follow in planes of N^2, and the
+    // mode's rise is the sum over poles (pole 0 first)
+    for (int j = 1; j < a.poles; ++j) {
+      Tc* sja = sta + (long)j * N * N;
+      Tc* sjb = sja + N;
+      const Vec<Tc, 2> ja = aba[(long)j * N * N + p], jb = abb[(long)j * N * N + p];
+      const Tc ua = dot2(ja.v[0], sja[p], ja.v[1], xa);
+      const Tc ub = dot2(jb.v[0], sjb[p], jb.v[1], xb);
+      sja[p] = ua;
+      sjb[p] = ub;
+      na[m] += ua;
+      nb[m] += ub;
+    }
   }
   Tc na2[E], nb2[E];
   partner<Tc, N, false>(na, na2, t);
@@ -425,16 +459,16 @@ hipError_t tr_dispatch(int which, int mode, int v, int n, const TransArgs& a, in
 }  // namespace
 
 hipError_t launch_transient_coef(const TableSpec& sp, const double* lam64T, int io, void* ab, double alpha, double dt,
-                                 int tau_model, double rho_c, hipStream_t stream) {
+                                 int tau_model, double rho_c, int poles, hipStream_t stream) {
   // lumped: tau = (rho c t / 3) hx hy lambda = (rho c t / 3) lx ly lambda'
   const double lumped_c = rho_c * sp.t / 3.0 * sp.lx * sp.ly;
   const dim3 grid((sp.ny + 255) / 256, sp.nx);
   if (io == VARSIM_F32)
     hipLaunchKernelGGL(transient_coef_kernel<float>, grid, dim3(256), 0, stream, lam64T, (float*)ab, sp.nx, sp.ny, sp.lx,
-                       sp.ly, sp.t, alpha, dt, tau_model, lumped_c);
+                       sp.ly, sp.t, alpha, dt, tau_model, lumped_c, poles);
   else
     hipLaunchKernelGGL(transient_coef_kernel<double>, grid, dim3(256), 0, stream, lam64T, (double*)ab, sp.nx, sp.ny,
-                       sp.lx, sp.ly, sp.t, alpha, dt, tau_model, lumped_c);
+                       sp.lx, sp.ly, sp.t, alpha, dt, tau_model, lumped_c, poles);
   return hipGetLastError();
 }
 

@@ -269,14 +269,26 @@ __global__ void __launch_bounds__((TrCol1Cfg<Tc, N, COLS>::THREADS))
       s1[m] = st[h];
     }
   }
-  // per-mode update theta_hat = a theta_hat + b P_hat at modes p and hi(p)
+  // per-mode update theta_hat = a theta_hat + b P_hat at modes p and hi(p); further poles of the
+  // multi-pole model keep their states in planes of N^2 and add to the mode's rise (pole 0 first)
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int p = t + TPF * m, h = spec_hi<N>(p);
-    const Tc n0 = dot2(k0[m].v[0], s0[m], k0[m].v[1], zr[m]);
-    const Tc n1 = dot2(k1[m].v[0], s1[m], k1[m].v[1], zi[m]);
+    const Tc P0 = zr[m], P1 = zi[m];
+    Tc n0 = dot2(k0[m].v[0], s0[m], k0[m].v[1], P0);
+    Tc n1 = dot2(k1[m].v[0], s1[m], k1[m].v[1], P1);
     st[p] = n0;
     st[h] = n1;
+    for (int j = 1; j < a.poles; ++j) {
+      Tc* sj = st + (long)j * N * N;
+      const Vec<Tc, 2> kj0 = ab[(long)j * N * N + p], kj1 = ab[(long)j * N * N + h];
+      const Tc u0 = dot2(kj0.v[0], sj[p], kj0.v[1], P0);
+      const Tc u1 = dot2(kj1.v[0], sj[h], kj1.v[1], P1);
+      sj[p] = u0;
+      sj[h] = u1;
+      n0 += u0;
+      n1 += u1;
+    }
     zr[m] = n0;
     zi[m] = n1;
   }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libvarsim.so")
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_NOT_CONVERGED, ERR_RUNAWAY, ERR_DEVICE, ERR_NO_MEMORY = range(7)
 LEAK_NONE, LEAK_EXP, LEAK_LINEAR = 0, 1, 2
 F32, F64 = 0, 1
-TAU_MOMENT, TAU_LUMPED = 0, 1
+TAU_MOMENT, TAU_LUMPED, TAU_MODAL = 0, 1, 2
 COND_SOURCE, COND_TARGET = 0, 1
 
 
@@ -60,7 +60,7 @@ class Stats(Structure):
 
 class Transient(Structure):
     _fields_ = [("dt_s", c_double), ("n_steps", c_int32), ("out_every", c_int32), ("n_blocks", c_int32),
-                ("block_rects", c_void_p), ("trace", c_void_p), ("tau_model", c_int32)]
+                ("block_rects", c_void_p), ("trace", c_void_p), ("tau_model", c_int32), ("n_poles", c_int32)]
 
 
 class OneShot(Structure):
@@ -383,13 +383,15 @@ class Context:
         return self.solve_batch([item], opts, workspace)[0]
 
     # ----------------------------------------------------------------------------- transient
-    def _transient(self, block_rects, trace, dt_s: float, out_every: int, tau_model: int) -> Transient:
-        return Transient(dt_s, trace.shape[0], out_every, trace.shape[1], _ptr(block_rects), _ptr(trace), tau_model)
+    def _transient(self, block_rects, trace, dt_s: float, out_every: int, tau_model: int,
+                   n_poles: int = 1) -> Transient:
+        return Transient(dt_s, trace.shape[0], out_every, trace.shape[1], _ptr(block_rects), _ptr(trace), tau_model,
+                         n_poles)
 
     def transient_workspace_bytes(self, item: dict, block_rects, trace, dt_s: float, opts: Options,
-                                  out_every: int = 1, tau_model: int = TAU_MOMENT) -> int:
+                                  out_every: int = 1, tau_model: int = TAU_MOMENT, n_poles: int = 1) -> int:
         probs, keep = self._problems([item])
-        tr = self._transient(block_rects, trace, dt_s, out_every, tau_model)
+        tr = self._transient(block_rects, trace, dt_s, out_every, tau_model, n_poles)
         n = ctypes.c_size_t(0)
         self._check(self.lib.varsim_transient_workspace_size(self.handle, probs, ctypes.byref(tr),
                                                              ctypes.byref(opts), ctypes.byref(n)))
@@ -397,15 +399,15 @@ class Context:
 
     def solve_transient(self, item: dict, block_rects, trace, dt_s: float, opts: Options, snapshots=None,
                         out_every: int = 1, tau_model: int = TAU_MOMENT, workspace=None,
-                        raise_on=(ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY)) -> dict:
+                        raise_on=(ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY), n_poles: int = 1) -> dict:
         """Transient solve from dT = 0 (item: die, dT_out, optional q_leak0, leak_var, cond_map as
         device tensors).  block_rects: int32 [n_blocks][4] device tensor; trace: [n_steps][n_blocks]
         device tensor of the map dtype; snapshots: optional [n_steps // out_every][n][n] output."""
         import torch
 
         probs, keep = self._problems([item])
-        tr = self._transient(block_rects, trace, dt_s, out_every, tau_model)
-        need = self.transient_workspace_bytes(item, block_rects, trace, dt_s, opts, out_every, tau_model)
+        tr = self._transient(block_rects, trace, dt_s, out_every, tau_model, n_poles)
+        need = self.transient_workspace_bytes(item, block_rects, trace, dt_s, opts, out_every, tau_model, n_poles)
         if workspace is None or workspace.numel() < need:
             workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=torch.device("cuda", self.device))
         stats = Stats()

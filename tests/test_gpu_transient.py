@@ -340,3 +340,51 @@ def test_transient_launch_shapes_give_identical_results(ctx, n):
     for last in f64[1:]:
         assert np.max(np.abs(last - f64[0])) <= 1e-12 * scale
     assert np.max(np.abs(one[0][1] - pair[0][1])) <= 1e-4 * scale
+
+
+# ----------------------------------------------------------------------------- multi-pole model
+@pytest.mark.parametrize("n,poles,rv_cv", [(32, 3, None), (64, 4, (3, 3)), (64, 4, (0, 0)), (64, 2, (4, 5))])
+def test_transient_modal_fp64_matches_oracle(ctx, n, poles, rv_cv):
+    """The multi-pole ("modal") model: each cosine mode's slowest depth modes as separate poles
+    with their own spectral states, through both pass families, against the oracle's
+    full-history superposition of the same model."""
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    inp = W.transient_problem(n=n, n_steps=12, dt_s=50e-6, n_blocks=8, hold_s=200e-6, seed=n + poles)
+    g = S.geometry_from_die(inp.die, inp.n)
+    model = T.TransientModel(g, inp.die.rho_c, "modal", n_poles=poles)
+    steps = np.stack([W.raster_trace_step(inp.block_rects, inp.trace[k], inp.n) for k in range(inp.n_steps)])
+    rec, _ = T.solve_transient(model, steps, inp.dt_s, q_leak=inp.q_leak0 * inp.leak_var, cond_map=inp.cond_map,
+                               leak="exp", beta=inp.beta, record_every=2)
+    item = {"die": die_of(inp), "q_leak0": to_dev(inp.q_leak0, torch.float64),
+            "leak_var": to_dev(inp.leak_var, torch.float64), "cond_map": to_dev(inp.cond_map, torch.float64),
+            "dT_out": torch.zeros((n, n), dtype=torch.float64, device="cuda")}
+    snaps = torch.zeros((inp.n_steps // 2, n, n), dtype=torch.float64, device="cuda")
+    opts = V.make_options(V.F64, V.LEAK_EXP, inp.beta, 1, 1e-3)
+    with _variants(ctx, rv_cv):
+        st = ctx.solve_transient(item, to_dev(inp.block_rects, torch.int32), to_dev(inp.trace, torch.float64),
+                                 inp.dt_s, opts, snapshots=snaps, out_every=2, tau_model=V.TAU_MODAL, n_poles=poles)
+    got = snaps.cpu().numpy()
+    print(f"modal transient {n}^2, {poles} poles, variants {rv_cv}: max rel err "
+          f"{np.max(np.abs(got - rec)) / np.max(rec):.2e}", flush=True)
+    assert st["status"] == V.OK
+    assert np.max(np.abs(got - rec)) <= FP64_GATE_REL * np.max(rec)
+
+
+def test_transient_modal_one_pole_is_the_moment_model(ctx):
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    inp = W.transient_problem(n=64, n_steps=10, dt_s=50e-6, n_blocks=8, hold_s=200e-6, seed=3)
+    outs = []
+    for tau, poles in ((V.TAU_MOMENT, 1), (V.TAU_MODAL, 1)):
+        item = {"die": die_of(inp), "q_leak0": to_dev(inp.q_leak0, torch.float32),
+                "leak_var": to_dev(inp.leak_var, torch.float32), "cond_map": to_dev(inp.cond_map, torch.float32),
+                "dT_out": torch.zeros((64, 64), dtype=torch.float32, device="cuda")}
+        ctx.solve_transient(item, to_dev(inp.block_rects, torch.int32), to_dev(inp.trace, torch.float32), inp.dt_s,
+                            V.make_options(V.F32, V.LEAK_EXP, inp.beta, 1, 1e-3), tau_model=tau, n_poles=poles)
+        outs.append(item["dT_out"].cpu())
+    assert torch.equal(outs[0], outs[1])
