@@ -16,8 +16,14 @@ Definition followed:
   * Eq. tranapprox: a power map held over (t_{n-1}, t_n] enters through the step kernels,
         theta_n = sum_{j=1..n} S_j (*) (P_{n-j+1} - P_{n-j}),   P_0 = 0,
     with S_j the real-space kernel whose cosine eigenvalues are S_hat(j dt) and (*) the same
-    mirror-image direct sum as the steady oracle.  Here the whole history is kept (the paper
-    truncates it after 5 ms).
+    mirror-image direct sum as the steady oracle.  By default the whole history is kept.
+  * Truncated history (Sec. IV-E, the paper's 5 ms horizon): with horizon h the step kernels
+    are taken as saturated from the h-th on (S_j = S_inf, the steady kernel, for j >= h), so the
+    differences older than h - 1 steps telescope into one term,
+        theta_n = sum_{j=1..min(n, h-1)} S_j (*) (P_{n-j+1} - P_{n-j}) + [n >= h] S_inf (*) P_{n-h+1}.
+    The paper's printed collapse pairs S_inf with P(t_{n-5}) for its five kernels; the pattern of
+    the sum (S_j multiplies the difference that ends at t_{n-j+1}) puts the saturated kernel on
+    P_{n-h+1}, which is the reading taken here.
   * Leakage and k(T) (Sec. IV-E: "substitute the leakage-aware Green's function"): step n uses
     the previous step's rise, P_n = hx hy [q_dyn(t_n) + q_leak0 v L(dT_{n-1})], and
     dT_n = Phi^-1(theta_n) pointwise; the conductivity map enters as in the steady oracle, on the
@@ -130,15 +136,20 @@ class TransientModel:
 
 def solve_transient(model: TransientModel, q_dyn_steps: np.ndarray, dt: float, q_leak: np.ndarray | None = None,
                     cond_map: np.ndarray | None = None, leak: str = "exp", beta: float = 0.017,
-                    record_every: int = 1, cond: str = "source"):
-    """Full-history superposition (Eq. tranapprox) with the one-step-lagged leakage loop.
+                    record_every: int = 1, cond: str = "source", horizon: int | None = None):
+    """Superposition of step responses (Eq. tranapprox) with the one-step-lagged leakage loop.
 
-    q_dyn_steps: [n_steps][ny][nx] dynamic power density held over each step.  Returns the rises
-    dT_n for n = record_every, 2 record_every, ... (array [n_rec][ny][nx]) and the final rise.
+    q_dyn_steps: [n_steps][ny][nx] dynamic power density held over each step.  horizon None keeps
+    the whole history; horizon h >= 2 saturates the step kernels from the h-th on (the paper's
+    truncated history).  Returns the rises dT_n for n = record_every, 2 record_every, ... (array
+    [n_rec][ny][nx]) and the final rise.
     """
     g = model.geom
     n_steps = q_dyn_steps.shape[0]
-    kernels = [S.DirectSum(g, table=model.step_kernel((j + 1) * dt)) for j in range(n_steps)]
+    if horizon is not None and horizon < 2:
+        raise ValueError("horizon must be at least 2")
+    n_kern = n_steps if horizon is None else min(n_steps, horizon - 1)
+    kernels = [S.DirectSum(g, table=model.step_kernel((j + 1) * dt)) for j in range(n_kern)]
     dT = np.zeros((g.ny, g.nx))
     p_hist = []  # P_1 .. P_n in W per cell
     out = []
@@ -154,10 +165,13 @@ def solve_transient(model: TransientModel, q_dyn_steps: np.ndarray, dt: float, q
             p_new = p_new / cond_map
         p_hist.append(p_new)
         theta = np.zeros((g.ny, g.nx))
-        for j in range(1, n + 1):  # S_j applied to P_{n-j+1} - P_{n-j}
+        last = n if horizon is None else min(n, horizon - 1)
+        for j in range(1, last + 1):  # S_j applied to P_{n-j+1} - P_{n-j}
             newer = p_hist[n - j]
             older = p_hist[n - j - 1] if n - j - 1 >= 0 else 0.0
             theta += kernels[j - 1].apply(newer - older)
+        if horizon is not None and n >= horizon:  # the saturated kernel on P_{n-h+1}
+            theta += model.op.apply(p_hist[n - horizon])
         if cond_map is not None and cond == "target":
             theta = theta / cond_map
         dT, ok = S.kirchhoff_inverse(theta, g.t_amb, g.eta)

@@ -160,3 +160,71 @@ def test_pole_models_against_finite_volume_transient():
         err[name] = float(np.max(np.abs(out - ref)) / np.max(ref[-1]))
     assert 0.10 < err["moment"] < 0.20, err
     assert err["modal4"] < 0.025, err
+
+
+# ----------------------------------------------------------------------------- truncated history
+def test_truncated_history_longer_than_the_run_is_the_full_history():
+    n, steps, dt = 8, 9, 30e-6
+    g = _geom(n)
+    model = T.TransientModel(g, RHOC)
+    q = np.random.default_rng(5).uniform(0.0, 2e6, (steps, n, n))
+    full, _ = T.solve_transient(model, q, dt, leak="none")
+    trunc, _ = T.solve_transient(model, q, dt, leak="none", horizon=steps + 1)
+    assert np.array_equal(full, trunc)
+    with pytest.raises(ValueError):
+        T.solve_transient(model, q, dt, leak="none", horizon=1)
+
+
+@pytest.mark.parametrize("horizon", [2, 3, 6])
+def test_truncated_history_uniform_pulse_closed_form(horizon):
+    """Uniform power on for m steps, then off: only the uniform mode responds, with step response
+    R (1 - exp(-t / tau0)), saturated to R from the horizon on.  The rise at step n is
+    q R (s(n) - s(n - m)) with s(j) = 1 - exp(-j dt / tau0) for 0 < j < h, 1 for j >= h, 0 for
+    j <= 0 -- exactly zero once the switch-off is h steps old."""
+    n, dt, on, steps = 8, 40e-6, 4, 14
+    g = _geom(n)
+    model = T.TransientModel(g, RHOC)
+    q = 1.5e6
+    trace = np.zeros((steps, n, n))
+    trace[:on] = q
+    rec, _ = T.solve_transient(model, trace, dt, leak="none", horizon=horizon)
+    tau0 = TD * TD * RHOC / (3.0 * KC)
+
+    def s(j):
+        return 0.0 if j <= 0 else (1.0 if j >= horizon else 1.0 - math.exp(-j * dt / tau0))
+
+    for i in range(steps):
+        step = i + 1
+        expect = q * TD / KC * (s(step) - s(step - on))
+        assert np.allclose(rec[i], expect, rtol=1e-11, atol=1e-12 * q * TD / KC)
+    assert np.all(rec[on + horizon - 1:] == pytest.approx(0.0, abs=1e-12 * q * TD / KC))
+
+
+@pytest.mark.parametrize("n_poles,tau_model", [(1, "moment"), (3, "modal")])
+def test_truncated_history_equals_its_recursive_form(n_poles, tau_model):
+    """The truncated superposition (real-space step kernels, direct sums) against an independent
+    per-mode recursion: with pole weights c_j = lambda w_j and a_j = exp(-dt / tau_j), the history
+    cut at h obeys y_j,n = a_j y_j,n-1 + c_j (1 - a_j) (P_n - a_j^(h-1) P_(n-h+1)) and
+    theta_n = sum_j (y_j,n + c_j a_j^(h-1) P_(n-h+1)) (the transform of P is zero before step 1),
+    with the lagged leakage and a conductivity map."""
+    n, steps, dt, h = 16, 20, 20e-6, 7
+    g = _geom(n, eta=1.3)
+    model = T.TransientModel(g, RHOC, tau_model, n_poles=n_poles)
+    tr = W.transient_problem(n=n, n_steps=steps, dt_s=dt, n_blocks=6, hold_s=3 * dt)
+    qd = np.stack([W.raster_trace_step(tr.block_rects, tr.trace[i], n) for i in range(steps)])
+    ql = tr.q_leak0 * tr.leak_var
+    rec, _ = T.solve_transient(model, qd, dt, q_leak=ql, cond_map=tr.cond_map, horizon=h)
+    c = model.lam_full[None, :n, :n] * model.weights[:, :n, :n]
+    a = np.exp(-dt / model.taus[:, :n, :n])
+    ah = a ** (h - 1)
+    y = np.zeros((n_poles, n, n))
+    hist = []
+    dT = np.zeros((n, n))
+    for i in range(steps):
+        p = g.hx * g.hy * (qd[i] + ql * np.exp(0.017 * dT)) / tr.cond_map
+        hist.append(sfft.dctn(p, type=2))
+        old = hist[i - h + 1] if i - h + 1 >= 0 else 0.0
+        y = a * y + c * (1.0 - a) * (hist[i] - ah * old)
+        theta = sfft.idctn(np.sum(y + c * ah * old, axis=0), type=2)
+        dT, ok = S.kirchhoff_inverse(theta, g.t_amb, g.eta)
+        assert np.allclose(rec[i], dT, rtol=1e-10, atol=1e-11 * np.max(np.abs(dT)))
