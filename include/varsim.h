@@ -169,6 +169,15 @@ typedef struct varsim_transient {
                                    each pole keeps its own spectral state (n_poles maps of
                                    workspace) and moves two more maps of state and coefficients
                                    per step */
+  int32_t history_steps;        /* 0: the whole power history enters (exact per-mode recursion).
+                                   h in [2, 2^20]: the truncated history of Sec. IV-E (the paper's
+                                   5 ms horizon is h = 5 ms / dt_s): the step responses are taken as
+                                   saturated from the h-th step on, so the rise at step n is
+                                   sum_{j<h} S_j (*) (P_{n-j+1} - P_{n-j}) + S_inf (*) P_{n-h+1} and
+                                   a power change is forgotten h steps after it.  Costs h - 1 maps
+                                   of workspace (the spectra of the last h - 1 steps) plus
+                                   n_poles + 1 coefficient maps, and moves 3 + n_poles more maps
+                                   per step (n_poles = 1 but for VARSIM_TAU_MODAL) */
 } varsim_transient;
 
 /* ----------------------------------------------------------------------------------------

@@ -416,12 +416,14 @@ varsim_status check_transient(varsim_ctx* ctx, const varsim_problem* p, const va
     return fail(ctx, VARSIM_ERR_INVALID, "bad tau_model");
   if (tr->tau_model == VARSIM_TAU_MODAL && (tr->n_poles < 1 || tr->n_poles > kMaxPoles))
     return fail(ctx, VARSIM_ERR_INVALID, "n_poles must be in [1, %d]", kMaxPoles);
+  if (tr->history_steps != 0 && (tr->history_steps < 2 || tr->history_steps > kMaxHistory))
+    return fail(ctx, VARSIM_ERR_INVALID, "history_steps must be 0 or in [2, %d]", kMaxHistory);
   return VARSIM_OK;
 }
 
 // Workspace of one transient solve.
 struct TransLayout {
-  size_t flags = 0, state_end = 0, stats = 0, prep = 0, S = 0, state = 0, ab = 0, ids = 0;
+  size_t flags = 0, state_end = 0, stats = 0, prep = 0, S = 0, state = 0, ab = 0, ring = 0, fir = 0, ids = 0;
   size_t QL = (size_t)-1, MINV = (size_t)-1, IDZ = 0, QLZ = (size_t)-1, MINVZ = (size_t)-1, total = 0;
 };
 
@@ -445,6 +447,12 @@ TransLayout make_transient_layout(const varsim_problem* p, const varsim_transien
   off = align_up(off + poles * cells * es);
   L.ab = off;
   off = align_up(off + poles * 2 * cells * es);
+  if (tr->history_steps >= 2) {  // truncated history: ring of past spectra, coefficient planes
+    L.ring = off;
+    off = align_up(off + (size_t)(tr->history_steps - 1) * cells * es);
+    L.fir = off;
+    off = align_up(off + (poles + 1) * cells * es);
+  }
   L.ids = off;
   off = align_up(off + cells * 4);
   if (p->q_leak0 && o->leak != VARSIM_LEAK_NONE && p->leak_var) {
@@ -1257,6 +1265,11 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   a.idz = (const int*)(ws + L.IDZ);
   a.qlz = a.ql ? ws + L.QLZ : nullptr;
   a.minvz = a.minv ? ws + L.MINVZ : nullptr;
+  a.hist = tr->history_steps;
+  a.ring = a.hist >= 2 ? ws + L.ring : nullptr;
+  a.fir = a.hist >= 2 ? ws + L.fir : nullptr;
+  a.slot = 0;
+  const size_t ring_bytes = a.ring ? (size_t)(a.hist - 1) * cells * esize(io) : 0;
 
   wait_descriptors(ctx);
   ctx->h_prep.assign(1, PrepArgs{});
@@ -1274,14 +1287,15 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   const double alpha = sp.k_ref / g->layers[0].rho_c_J_m3K;
   HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(ws, L.state_end, s); }));
   HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(a.state, (size_t)a.poles * cells * esize(io), s); }));
+  if (a.ring) HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(a.ring, ring_bytes, s); }));
   HIP_TRY(hipMemcpyAsync(d_prep, ctx->h_prep.data(), sizeof(PrepArgs), hipMemcpyHostToDevice, s));
   HIP_TRY(timed(ctx, "prep", s, [&] { return launch_prep(io, d_prep, 1, cells, s); }));
   HIP_TRY(timed(ctx, "setup", s, [&] {
     return launch_block_ids(tr->block_rects, tr->n_blocks, (int*)a.ids, g->nx, g->ny, s);
   }));
   HIP_TRY(timed(ctx, "setup", s, [&] {
-    return launch_transient_coef(sp, tab.lam64T, io, (void*)a.ab, alpha, tr->dt_s, tr->tau_model,
-                                 g->layers[0].rho_c_J_m3K, a.poles, s);
+    return launch_transient_coef(sp, tab.lam64T, io, (void*)a.ab, (void*)a.fir, a.hist, alpha, tr->dt_s,
+                                 tr->tau_model, g->layers[0].rho_c_J_m3K, a.poles, s);
   }));
   if (transient_single_ok(g->nx)) {
     HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zorder(4, a.ids, (void*)a.idz, g->nx, s); }));
@@ -1356,6 +1370,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
     ctx->tr_choice[key] = {rv, cv};
     ctx->tr_ms[key] = ms;
     HIP_TRY(launch_zero_words(a.state, (size_t)a.poles * cells * esize(io), s));
+    if (a.ring) HIP_TRY(launch_zero_words(a.ring, ring_bytes, s));
     HIP_TRY(launch_zero_words(d_flags, sizeof(unsigned), s));
   }
   if (ctx->force_tr_row >= 0) rv = ctx->force_tr_row < nv ? ctx->force_tr_row : 0;
@@ -1364,6 +1379,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   // step n: column pass (mode update with P_n) then row pass (dT_n, and P_{n+1} unless last)
   HIP_TRY(timed(ctx, "tr_row_head", s, [&] { return launch_transient_row(TR_HEAD, io, a, 0, s, rv); }));
   for (int n = 1; n <= tr->n_steps; ++n) {
+    if (a.ring) a.slot = n % (a.hist - 1);  // holds P_hat of step n - (hist - 1) until this step's enters
     HIP_TRY(timed(ctx, "tr_col", s, [&] { return launch_transient_col(io, a, s, cv); }));
     const bool last = n == tr->n_steps;
     HIP_TRY(timed(ctx, last ? "tr_row_last" : "tr_row", s,

@@ -132,6 +132,7 @@ int row_pass_groups(int nx, int ny);
 
 // Transient solve of one map (element type T = io = compute type).
 constexpr int kMaxPoles = 8;  // poles per cosine mode of the multi-pole transient model
+constexpr int kMaxHistory = 1 << 20;  // longest truncated transient history, steps
 struct TransArgs {
   int n;
   void* S;            // [n][n] transform work array
@@ -146,6 +147,14 @@ struct TransArgs {
   void* dT;           // final rise
   void* snaps;        // [n_steps / out_every][n][n], or null
   int out_every;
+  // truncated history of hist steps (Eq. tranapprox with saturated step kernels), or ring null:
+  // ring [hist - 1][n][n] holds the spectra of the last hist - 1 steps (slot = step mod (hist - 1),
+  // layout [q][p]); fir [poles + 1][n][n] the per-pole coefficients -b_j r_j and then the
+  // saturated part sum_j c_j r_j, r_j = exp(-(hist - 1) dt / tau_j)
+  void* ring;
+  const void* fir;
+  int hist;
+  int slot;
   unsigned* flags;    // runaway flag word
   PointParams pp;
   Twiddles tw;
@@ -158,8 +167,9 @@ struct TransArgs {
 enum TransMode : int { TR_HEAD = 0, TR_MERGED = 1, TR_LAST = 2 };
 
 // (a, b) per mode from lambda (lam64T, scaled as the column pass uses it), dt and tau_model
-hipError_t launch_transient_coef(const TableSpec& sp, const double* lam64T, int io, void* ab, double alpha, double dt,
-                                 int tau_model, double rho_c, int poles, hipStream_t stream);
+// (and, fir non-null, the truncated-history coefficients of hist steps)
+hipError_t launch_transient_coef(const TableSpec& sp, const double* lam64T, int io, void* ab, void* fir, int hist,
+                                 double alpha, double dt, int tau_model, double rho_c, int poles, hipStream_t stream);
 hipError_t launch_block_ids(const int* rects, int n_blocks, int* ids, int nx, int ny, hipStream_t stream);
 // TR_HEAD: P_1 -> row spectrum; TR_MERGED (step n): row synthesis -> dT_n -> P_{n+1} -> row
 // spectrum; TR_LAST: row synthesis -> dT_n (final)

@@ -50,29 +50,43 @@ __device__ double tau_moment(double s, double t, double alpha) {
 // m < poles - 1, tau_m = t^2 / (alpha ((s t)^2 + ((m + 1/2) pi)^2)), w_m = 2 (s t / tanh(s t)) /
 // ((s t)^2 + ((m + 1/2) pi)^2), and one last pole with the remaining weight whose time constant
 // keeps the first moment sum_j w_j tau_j = tau(s).
+// Truncated history of h steps (fir non-null): with c_j = w_j lambda' and r_j = exp(-(h - 1) dt /
+// tau_j), fir[j][q][p] = -b_j r_j for each pole and fir[poles][q][p] = sum_j c_j r_j.
 template <typename T>
 __global__ void __launch_bounds__(256) transient_coef_kernel(const double* __restrict__ lamT, T* __restrict__ ab,
-                                                             int nx, int ny, double lx, double ly, double t,
-                                                             double alpha, double dt, int tau_model, double lumped_c,
-                                                             int poles) {
+                                                             T* __restrict__ fir, int nx, int ny, double lx, double ly,
+                                                             double t, double alpha, double dt, int tau_model,
+                                                             double lumped_c, int poles, int hist) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (p >= ny) return;
   const double lam = lamT[(size_t)q * ny + p];
   const double s = M_PI * sqrt(((double)p / ly) * ((double)p / ly) + ((double)q / lx) * ((double)q / lx));
-  const size_t plane = (size_t)nx * ny * 2;
+  const size_t plane = (size_t)nx * ny * 2, cell = (size_t)q * ny + p;
+  double tail = 0.0;  // sum_j c_j r_j of the truncated history
   auto put = [&](int j, double tau, double w) {
-    const size_t o = j * plane + ((size_t)q * ny + p) * 2;
+    const size_t o = j * plane + cell * 2;
+    const double b = -expm1(-dt / tau) * w * lam;
     ab[o] = (T)exp(-dt / tau);
-    ab[o + 1] = (T)(-expm1(-dt / tau) * w * lam);
+    ab[o + 1] = (T)b;
+    if (fir) {
+      const double r = exp(-(double)(hist - 1) * dt / tau);
+      fir[j * (plane / 2) + cell] = (T)(-b * r);
+      tail += w * lam * r;
+    }
+  };
+  auto finish = [&]() {
+    if (fir) fir[poles * (plane / 2) + cell] = (T)tail;
   };
   if (tau_model == VARSIM_TAU_LUMPED) {
     put(0, lumped_c * lam, 1.0);  // (rho c t / 3) hx hy lambda = (rho c t / 3) (lx ly) lambda'
+    finish();
     return;
   }
   const double tm = tau_moment(s, t, alpha);
   if (tau_model != VARSIM_TAU_MODAL || poles <= 1) {
     put(0, tm, 1.0);
+    finish();
     return;
   }
   const double x = s * t, xt = x < 1e-8 ? 1.0 : x / tanh(x);
@@ -86,6 +100,7 @@ __global__ void __launch_bounds__(256) transient_coef_kernel(const double* __res
   }
   const double wr = 1.0 - wsum;
   put(poles - 1, (tm - first) / wr, wr);
+  finish();
 }
 
 // block id of each cell: the last block (painter's order) whose rectangle covers it, else -1
@@ -228,7 +243,8 @@ __global__ void __launch_bounds__((TrRowCfg<N, FFTS_>::THREADS))
   }
 }
 
-template <typename Tc, int N, int COLS>
+// FIR: the truncated history of a.hist steps (the ring of past spectra and the fir planes)
+template <typename Tc, int N, int COLS, bool FIR>
 __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
     transient_col_kernel(TransArgs a, const Cx<Tc>* __restrict__ tw, const Cx<Tc>* __restrict__ qw) {
   using Cfg = ColCfg<Tc, N, COLS>;
@@ -277,6 +293,9 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
   Tc* stb = sta + N;
   const Vec<Tc, 2>* aba = reinterpret_cast<const Vec<Tc, 2>*>(a.ab) + (long)qa * N;
   const Vec<Tc, 2>* abb = aba + N;
+  // truncated history: the spectrum of h - 1 steps ago leaves the ring slot this step's enters
+  Tc* ra = FIR ? (Tc*)a.ring + (long)a.slot * N * N + (long)qa * N : nullptr;
+  const Tc* fa = FIR ? (const Tc*)a.fir + (long)qa * N : nullptr;
   Tc na[E], nb[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -284,9 +303,20 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
     const Cx<Tc> q = qw[p];
     Tc xa, xb, xa2, xb2;
     split_pair<Tc>(zr[m], zi[m], pr[m], pim[m], q.r, q.i, xa, xb, xa2, xb2);
+    Tc oa = 0, ob = 0;
+    if constexpr (FIR) {
+      oa = ra[p];
+      ob = ra[N + p];
+      ra[p] = xa;
+      ra[N + p] = xb;
+    }
     const Vec<Tc, 2> ka = aba[p], kb = abb[p];
     na[m] = dot2(ka.v[0], sta[p], ka.v[1], xa);
     nb[m] = dot2(kb.v[0], stb[p], kb.v[1], xb);
+    if constexpr (FIR) {
+      na[m] = fma(fa[p], oa, na[m]);
+      nb[m] = fma(fa[N + p], ob, nb[m]);
+    }
     sta[p] = na[m];
     stb[p] = nb[m];
     // further poles of the multi-pole model: their states follow in planes of N^2, and the
@@ -295,12 +325,20 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS>::THREADS))
       Tc* sja = sta + (long)j * N * N;
       Tc* sjb = sja + N;
       const Vec<Tc, 2> ja = aba[(long)j * N * N + p], jb = abb[(long)j * N * N + p];
-      const Tc ua = dot2(ja.v[0], sja[p], ja.v[1], xa);
-      const Tc ub = dot2(jb.v[0], sjb[p], jb.v[1], xb);
+      Tc ua = dot2(ja.v[0], sja[p], ja.v[1], xa);
+      Tc ub = dot2(jb.v[0], sjb[p], jb.v[1], xb);
+      if constexpr (FIR) {
+        ua = fma(fa[(long)j * N * N + p], oa, ua);
+        ub = fma(fa[(long)j * N * N + N + p], ob, ub);
+      }
       sja[p] = ua;
       sjb[p] = ub;
       na[m] += ua;
       nb[m] += ub;
+    }
+    if constexpr (FIR) {  // the saturated step response on the leaving spectrum
+      na[m] = fma(fa[(long)a.poles * N * N + p], oa, na[m]);
+      nb[m] = fma(fa[(long)a.poles * N * N + N + p], ob, nb[m]);
     }
   }
   Tc na2[E], nb2[E];
@@ -421,7 +459,11 @@ constexpr int tr_col_cols() {
 template <typename Tc, int N, int COLS>
 hipError_t tr_col_shape(const TransArgs& a, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   using Cfg = ColCfg<Tc, N, COLS>;
-  hipLaunchKernelGGL((transient_col_kernel<Tc, N, COLS>), dim3(N / Cfg::COLS, 1), dim3(Cfg::THREADS), 0, s, a, tw, qw);
+  const dim3 grid(N / Cfg::COLS, 1), block(Cfg::THREADS);
+  if (a.ring)
+    hipLaunchKernelGGL((transient_col_kernel<Tc, N, COLS, true>), grid, block, 0, s, a, tw, qw);
+  else
+    hipLaunchKernelGGL((transient_col_kernel<Tc, N, COLS, false>), grid, block, 0, s, a, tw, qw);
   return hipGetLastError();
 }
 
@@ -458,17 +500,17 @@ hipError_t tr_dispatch(int which, int mode, int v, int n, const TransArgs& a, in
 
 }  // namespace
 
-hipError_t launch_transient_coef(const TableSpec& sp, const double* lam64T, int io, void* ab, double alpha, double dt,
-                                 int tau_model, double rho_c, int poles, hipStream_t stream) {
+hipError_t launch_transient_coef(const TableSpec& sp, const double* lam64T, int io, void* ab, void* fir, int hist,
+                                 double alpha, double dt, int tau_model, double rho_c, int poles, hipStream_t stream) {
   // lumped: tau = (rho c t / 3) hx hy lambda = (rho c t / 3) lx ly lambda'
   const double lumped_c = rho_c * sp.t / 3.0 * sp.lx * sp.ly;
   const dim3 grid((sp.ny + 255) / 256, sp.nx);
   if (io == VARSIM_F32)
-    hipLaunchKernelGGL(transient_coef_kernel<float>, grid, dim3(256), 0, stream, lam64T, (float*)ab, sp.nx, sp.ny, sp.lx,
-                       sp.ly, sp.t, alpha, dt, tau_model, lumped_c, poles);
+    hipLaunchKernelGGL(transient_coef_kernel<float>, grid, dim3(256), 0, stream, lam64T, (float*)ab, (float*)fir, sp.nx,
+                       sp.ny, sp.lx, sp.ly, sp.t, alpha, dt, tau_model, lumped_c, poles, hist);
   else
-    hipLaunchKernelGGL(transient_coef_kernel<double>, grid, dim3(256), 0, stream, lam64T, (double*)ab, sp.nx, sp.ny,
-                       sp.lx, sp.ly, sp.t, alpha, dt, tau_model, lumped_c, poles);
+    hipLaunchKernelGGL(transient_coef_kernel<double>, grid, dim3(256), 0, stream, lam64T, (double*)ab, (double*)fir,
+                       sp.nx, sp.ny, sp.lx, sp.ly, sp.t, alpha, dt, tau_model, lumped_c, poles, hist);
   return hipGetLastError();
 }
 

@@ -203,7 +203,8 @@ struct TrCol1Cfg {
   static constexpr int LDS = TILE > SCRATCH ? TILE : SCRATCH;
 };
 
-template <typename Tc, int N, int COLS>
+// FIR: the truncated history of a.hist steps (the ring of past spectra and the fir planes)
+template <typename Tc, int N, int COLS, bool FIR>
 __global__ void __launch_bounds__((TrCol1Cfg<Tc, N, COLS>::THREADS))
     transient_col1_kernel(TransArgs a, const Cx<Tc>* __restrict__ tw, const Cx<Tc>* __restrict__ qw) {
   using Cfg = TrCol1Cfg<Tc, N, COLS>;
@@ -270,24 +271,46 @@ __global__ void __launch_bounds__((TrCol1Cfg<Tc, N, COLS>::THREADS))
     }
   }
   // per-mode update theta_hat = a theta_hat + b P_hat at modes p and hi(p); further poles of the
-  // multi-pole model keep their states in planes of N^2 and add to the mode's rise (pole 0 first)
+  // multi-pole model keep their states in planes of N^2 and add to the mode's rise (pole 0 first).
+  // Truncated history: the spectrum of h - 1 steps ago leaves the ring slot this step's enters.
+  Tc* rg = FIR ? (Tc*)a.ring + (long)a.slot * N * N + (long)q * N : nullptr;
+  const Tc* fc = FIR ? (const Tc*)a.fir + (long)q * N : nullptr;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int p = t + TPF * m, h = spec_hi<N>(p);
     const Tc P0 = zr[m], P1 = zi[m];
+    Tc o0 = 0, o1 = 0;
+    if constexpr (FIR) {
+      o0 = rg[p];
+      o1 = rg[h];
+      rg[p] = P0;
+      rg[h] = P1;
+    }
     Tc n0 = dot2(k0[m].v[0], s0[m], k0[m].v[1], P0);
     Tc n1 = dot2(k1[m].v[0], s1[m], k1[m].v[1], P1);
+    if constexpr (FIR) {
+      n0 = fma(fc[p], o0, n0);
+      n1 = fma(fc[h], o1, n1);
+    }
     st[p] = n0;
     st[h] = n1;
     for (int j = 1; j < a.poles; ++j) {
       Tc* sj = st + (long)j * N * N;
       const Vec<Tc, 2> kj0 = ab[(long)j * N * N + p], kj1 = ab[(long)j * N * N + h];
-      const Tc u0 = dot2(kj0.v[0], sj[p], kj0.v[1], P0);
-      const Tc u1 = dot2(kj1.v[0], sj[h], kj1.v[1], P1);
+      Tc u0 = dot2(kj0.v[0], sj[p], kj0.v[1], P0);
+      Tc u1 = dot2(kj1.v[0], sj[h], kj1.v[1], P1);
+      if constexpr (FIR) {
+        u0 = fma(fc[(long)j * N * N + p], o0, u0);
+        u1 = fma(fc[(long)j * N * N + h], o1, u1);
+      }
       sj[p] = u0;
       sj[h] = u1;
       n0 += u0;
       n1 += u1;
+    }
+    if constexpr (FIR) {  // the saturated step response on the leaving spectrum
+      n0 = fma(fc[(long)a.poles * N * N + p], o0, n0);
+      n1 = fma(fc[(long)a.poles * N * N + h], o1, n1);
     }
     zr[m] = n0;
     zi[m] = n1;
@@ -348,7 +371,12 @@ constexpr int col1_cols() {
 template <typename Tc, int N, int COLS>
 hipError_t col1_shape(const TransArgs& a, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   using Cfg = TrCol1Cfg<Tc, N, COLS>;
-  hipLaunchKernelGGL((transient_col1_kernel<Tc, N, COLS>), dim3(N / COLS, 1), dim3(Cfg::THREADS), 0, s, a, tw, qw);
+  if (a.ring)
+    hipLaunchKernelGGL((transient_col1_kernel<Tc, N, COLS, true>), dim3(N / COLS, 1), dim3(Cfg::THREADS), 0, s, a, tw,
+                       qw);
+  else
+    hipLaunchKernelGGL((transient_col1_kernel<Tc, N, COLS, false>), dim3(N / COLS, 1), dim3(Cfg::THREADS), 0, s, a, tw,
+                       qw);
   return hipGetLastError();
 }
 

@@ -60,7 +60,8 @@ class Stats(Structure):
 
 class Transient(Structure):
     _fields_ = [("dt_s", c_double), ("n_steps", c_int32), ("out_every", c_int32), ("n_blocks", c_int32),
-                ("block_rects", c_void_p), ("trace", c_void_p), ("tau_model", c_int32), ("n_poles", c_int32)]
+                ("block_rects", c_void_p), ("trace", c_void_p), ("tau_model", c_int32), ("n_poles", c_int32),
+                ("history_steps", c_int32)]
 
 
 class OneShot(Structure):
@@ -384,14 +385,15 @@ class Context:
 
     # ----------------------------------------------------------------------------- transient
     def _transient(self, block_rects, trace, dt_s: float, out_every: int, tau_model: int,
-                   n_poles: int = 1) -> Transient:
+                   n_poles: int = 1, history_steps: int = 0) -> Transient:
         return Transient(dt_s, trace.shape[0], out_every, trace.shape[1], _ptr(block_rects), _ptr(trace), tau_model,
-                         n_poles)
+                         n_poles, history_steps)
 
     def transient_workspace_bytes(self, item: dict, block_rects, trace, dt_s: float, opts: Options,
-                                  out_every: int = 1, tau_model: int = TAU_MOMENT, n_poles: int = 1) -> int:
+                                  out_every: int = 1, tau_model: int = TAU_MOMENT, n_poles: int = 1,
+                                  history_steps: int = 0) -> int:
         probs, keep = self._problems([item])
-        tr = self._transient(block_rects, trace, dt_s, out_every, tau_model, n_poles)
+        tr = self._transient(block_rects, trace, dt_s, out_every, tau_model, n_poles, history_steps)
         n = ctypes.c_size_t(0)
         self._check(self.lib.varsim_transient_workspace_size(self.handle, probs, ctypes.byref(tr),
                                                              ctypes.byref(opts), ctypes.byref(n)))
@@ -399,15 +401,18 @@ class Context:
 
     def solve_transient(self, item: dict, block_rects, trace, dt_s: float, opts: Options, snapshots=None,
                         out_every: int = 1, tau_model: int = TAU_MOMENT, workspace=None,
-                        raise_on=(ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY), n_poles: int = 1) -> dict:
+                        raise_on=(ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_NO_MEMORY), n_poles: int = 1,
+                        history_steps: int = 0) -> dict:
         """Transient solve from dT = 0 (item: die, dT_out, optional q_leak0, leak_var, cond_map as
         device tensors).  block_rects: int32 [n_blocks][4] device tensor; trace: [n_steps][n_blocks]
-        device tensor of the map dtype; snapshots: optional [n_steps // out_every][n][n] output."""
+        device tensor of the map dtype; snapshots: optional [n_steps // out_every][n][n] output;
+        history_steps: 0 for the whole history, h >= 2 for the history truncated after h steps."""
         import torch
 
         probs, keep = self._problems([item])
-        tr = self._transient(block_rects, trace, dt_s, out_every, tau_model, n_poles)
-        need = self.transient_workspace_bytes(item, block_rects, trace, dt_s, opts, out_every, tau_model, n_poles)
+        tr = self._transient(block_rects, trace, dt_s, out_every, tau_model, n_poles, history_steps)
+        need = self.transient_workspace_bytes(item, block_rects, trace, dt_s, opts, out_every, tau_model, n_poles,
+                                              history_steps)
         if workspace is None or workspace.numel() < need:
             workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=torch.device("cuda", self.device))
         stats = Stats()

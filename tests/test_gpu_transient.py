@@ -42,7 +42,8 @@ def _leak_code(name):
     return {"exp": V.LEAK_EXP, "linear": V.LEAK_LINEAR, "none": V.LEAK_NONE}[name]
 
 
-def _run_gpu(ctx, inp, dtype, out_every=1, tau="moment", leak="exp", cap=1000.0, snapshots=True, cond="source"):
+def _run_gpu(ctx, inp, dtype, out_every=1, tau="moment", leak="exp", cap=1000.0, snapshots=True, cond="source",
+             history_steps=0):
     import torch
     from paper_2307_12119_amd import varsim as V
 
@@ -64,7 +65,7 @@ def _run_gpu(ctx, inp, dtype, out_every=1, tau="moment", leak="exp", cap=1000.0,
                           cond={"source": V.COND_SOURCE, "target": V.COND_TARGET}[cond])
     st = ctx.solve_transient(item, rects, trace, inp.dt_s, opts, snapshots=snaps, out_every=out_every,
                              tau_model=_tau_code(tau), raise_on=(V.ERR_INVALID, V.ERR_UNSUPPORTED, V.ERR_DEVICE,
-                                                                  V.ERR_NO_MEMORY))
+                                                                  V.ERR_NO_MEMORY), history_steps=history_steps)
     torch.cuda.synchronize()
     rec = None if snaps is None else snaps.cpu().numpy().astype(np.float64)
     return st, rec, item["dT_out"].cpu().numpy().astype(np.float64)
@@ -388,3 +389,90 @@ def test_transient_modal_one_pole_is_the_moment_model(ctx):
                             V.make_options(V.F32, V.LEAK_EXP, inp.beta, 1, 1e-3), tau_model=tau, n_poles=poles)
         outs.append(item["dT_out"].cpu())
     assert torch.equal(outs[0], outs[1])
+
+
+# ----------------------------------------------------------------------------- truncated history
+@pytest.mark.parametrize("n,h,tau,poles,rv_cv", [(32, 4, "moment", 1, None), (64, 5, "moment", 1, (3, 3)),
+                                                 (64, 3, "modal", 3, (0, 0)), (64, 7, "lumped", 1, (4, 5)),
+                                                 (16, 2, "moment", 1, None)])
+def test_transient_truncated_history_fp64_matches_oracle(ctx, n, h, tau, poles, rv_cv):
+    """The paper's truncated history (step responses saturated from the h-th step on), kept on the
+    GPU as a ring of the last h - 1 spectra, against the oracle's direct superposition."""
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    inp = W.transient_problem(n=n, n_steps=14, dt_s=50e-6, n_blocks=8, hold_s=150e-6, seed=n + h)
+    g = S.geometry_from_die(inp.die, inp.n)
+    model = T.TransientModel(g, inp.die.rho_c, tau, n_poles=poles)
+    steps = np.stack([W.raster_trace_step(inp.block_rects, inp.trace[k], inp.n) for k in range(inp.n_steps)])
+    rec, _ = T.solve_transient(model, steps, inp.dt_s, q_leak=inp.q_leak0 * inp.leak_var, cond_map=inp.cond_map,
+                               leak="exp", beta=inp.beta, horizon=h)
+    item = {"die": die_of(inp), "q_leak0": to_dev(inp.q_leak0, torch.float64),
+            "leak_var": to_dev(inp.leak_var, torch.float64), "cond_map": to_dev(inp.cond_map, torch.float64),
+            "dT_out": torch.zeros((n, n), dtype=torch.float64, device="cuda")}
+    snaps = torch.zeros((inp.n_steps, n, n), dtype=torch.float64, device="cuda")
+    opts = V.make_options(V.F64, V.LEAK_EXP, inp.beta, 1, 1e-3)
+    code = {"moment": V.TAU_MOMENT, "lumped": V.TAU_LUMPED, "modal": V.TAU_MODAL}[tau]
+    with _variants(ctx, rv_cv):
+        st = ctx.solve_transient(item, to_dev(inp.block_rects, torch.int32), to_dev(inp.trace, torch.float64),
+                                 inp.dt_s, opts, snapshots=snaps, tau_model=code, n_poles=poles, history_steps=h)
+    got = snaps.cpu().numpy()
+    print(f"truncated history {n}^2, h {h}, {tau} ({poles} poles), variants {rv_cv}: max rel err "
+          f"{np.max(np.abs(got - rec)) / np.max(rec):.2e}", flush=True)
+    assert st["status"] == V.OK
+    assert np.max(np.abs(got - rec)) <= FP64_GATE_REL * np.max(rec)
+
+
+@pytest.mark.parametrize("rv_cv", [(0, 0), (3, 3)], ids=["pair", "one-row"])
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+def test_transient_truncated_history_uniform_pulse_1024(ctx, dtype_name, rv_cv):
+    """Uniform power on for 6 steps, then off, history cut at h = 9: the rise at step n is
+    q R (s(n) - s(n - 6)), s(j) = 1 - exp(-j dt / tau(0)) below h, 1 from h on (0 for j <= 0), so
+    it is exactly zero from step 6 + h on (eta = 0: dT = theta)."""
+    import torch
+
+    dtype = getattr(torch, dtype_name)
+    n, steps, dt, q, on, h = 1024, 20, 100e-6, 2.0e6, 6, 9
+    die = W.Die(eta=0.0)
+    trace = np.zeros((steps, 1))
+    trace[:on] = q
+    inp = W.TransientInputs(die, n, dt, steps, np.array([[0, 0, n, n]], np.int32), trace, None, None, None)
+    with _variants(ctx, rv_cv):
+        st, rec, _ = _run_gpu(ctx, inp, dtype, out_every=1, leak="none", history_steps=h)
+    assert st["status"] == 0
+    tau0 = die.t_m ** 2 * die.rho_c / (3.0 * die.k0)
+    R = die.t_m / die.k0
+
+    def sat(j):
+        return 0.0 if j <= 0 else (1.0 if j >= h else -math.expm1(-j * dt / tau0))
+
+    expect = np.array([q * R * (sat(k + 1) - sat(k + 1 - on)) for k in range(steps)])
+    tol = 1e-9 * q * R if dtype == torch.float64 else 2e-3
+    assert np.max(np.abs(rec - expect[:, None, None])) <= tol
+    assert np.max(np.abs(rec[on + h - 1:])) <= tol and np.max(np.abs(rec[on + h - 2])) > 0.01
+
+
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+def test_transient_history_longer_than_the_run_is_the_full_history(ctx, dtype_name):
+    """A history longer than the run never drops a term: the ring path returns the bits of the
+    full-history recursion (every leaving spectrum is zero)."""
+    import torch
+
+    dtype = getattr(torch, dtype_name)
+    inp = _case_input(64, 8, 50e-6, True, seed=4)
+    _, full, _ = _run_gpu(ctx, inp, dtype)
+    _, cut, _ = _run_gpu(ctx, inp, dtype, history_steps=9)
+    assert np.array_equal(full, cut)
+
+
+def test_transient_history_argument_errors(ctx):
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    inp = _case_input(16, 3, 50e-6, False)
+    for h in (1, -2, (1 << 20) + 1):
+        with pytest.raises(V.VarsimError) as e:
+            _run_gpu(ctx, inp, torch.float64, history_steps=h)
+        assert e.value.status == V.ERR_INVALID
