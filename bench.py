@@ -164,6 +164,9 @@ def main() -> int:
     ap.add_argument("--small-batch", type=int, default=4096)
     ap.add_argument("--mixed-batch", type=int, default=256, help="samples per size class")
     ap.add_argument("--transient-runs", type=int, default=3)
+    ap.add_argument("--no-transient-models", action="store_true",
+                    help="transient leg: the single-pole full-history run and its FP64 shadow only (no "
+                         "multi-pole or truncated-history runs)")
     ap.add_argument("--tol", type=float, default=1e-3, help="fixed-point tolerance (max increment, K)")
     ap.add_argument("--side-tol", type=float, default=1e-2,
                     help="tolerance of the side leg timed without kernel events (0: skip it)")
@@ -408,7 +411,7 @@ def main() -> int:
         result["oneshot"] = oneshot_bench(ctx, items, out, opts, ws, args, mu, maps_per_s, float(it.mean()))
     if not args.no_transient:
         del ws
-        result["transient"] = transient_bench(ctx, args.transient_runs)
+        result["transient"] = transient_bench(ctx, args.transient_runs, not args.no_transient_models)
     if small_in is not None:
         result["small"] = small_bench(ctx, small_in, args)
     if mixed_in is not None:
@@ -852,7 +855,7 @@ def surrogate_training(ctx, spec, qd, lv, cm, target, args, batch: int = 64, ste
 TRANSIENT_BYTES_PER_CELL = {"tr_row": 20, "tr_col": 24}  # FP32: see transient_bench
 
 
-def transient_bench(ctx, runs: int) -> dict:
+def transient_bench(ctx, runs: int, models: bool = True) -> dict:
     """One 1000-step transient of a 64-block, 1024 x 1024 die (10 us steps, block powers redrawn
     every 1 ms, leakage + variation, k(T) with eta = 1.3), FP32, snapshots every 100 steps; the
     same run in FP64 (untimed) gives the FP32 error at every snapshot."""
@@ -897,7 +900,40 @@ def transient_bench(ctx, runs: int) -> dict:
     torch.cuda.synchronize()
     wall_untimed = time.perf_counter() - t0
     got = snaps.cpu().numpy().astype(np.float64)
-    # the multi-pole model (the slab's 3 slowest depth modes + 1 lumped pole per cosine mode)
+    modal = truncated = None
+    if models:
+        modal, truncated = transient_models(ctx, item, rects, trace, inp, opts, every, snaps, dev)
+    item64, rects64, trace64, snaps64 = setup(torch.float64)
+    opts64 = V.make_options(V.F64, V.LEAK_EXP, inp.beta, 1, 1e-3)
+    ctx.solve_transient(item64, rects64, trace64, inp.dt_s, opts64, snaps64, every)
+    torch.cuda.synchronize()
+    ref = snaps64.cpu().numpy()
+    kernels = {}
+    for name in ("tr_row", "tr_col"):
+        v = kt.get(name)
+        if not v:
+            continue
+        avg = v["total_ms"] / v["count"]
+        kernels[name] = {"launches": v["count"], "avg_ms": avg,
+                         "GB/s": TRANSIENT_BYTES_PER_CELL[name] * n * n / (avg * 1e-3) / 1e9}
+    return {"workload": "transient 1024x1024 FP32, 1000 steps of 10 us, 64 blocks redrawn every 1 ms, "
+                        "leakage + variation, eta 1.3, snapshots every 100 steps",
+            "ms_per_run": round(wall_untimed * 1e3, 3), "ms_per_run_with_kernel_events": round(wall * 1e3, 3),
+            "steps_per_s": round(steps / wall_untimed, 1), "status": st["status"],
+            "dT_max_K": st["dT_max_K"], "fp64_shadow_max_diff_K": float(np.max(np.abs(got - ref))),
+            "kernels": kernels, "modal": modal, "truncated_history": truncated,
+            "autotune": [l for l in ctx.autotune_report().strip().split("\n") if l.startswith("transient")]}
+
+
+def transient_models(ctx, item, rects, trace, inp, opts, every, snaps, dev):
+    """The transient of transient_bench with the multi-pole model (the slab's 3 slowest depth modes
+    + 1 lumped pole per cosine mode) and with the paper's truncated history (step responses
+    saturated after 5 ms), each timed once after a warm-up, against the single-pole full-history
+    snapshots."""
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
     ws4 = torch.empty(ctx.transient_workspace_bytes(item, rects, trace, inp.dt_s, opts, every, V.TAU_MODAL, 4),
                       dtype=torch.uint8, device=dev)
     snaps4 = torch.zeros_like(snaps)
@@ -927,26 +963,7 @@ def transient_bench(ctx, runs: int) -> dict:
                  "workspace_MiB": round(wsh.numel() / 2 ** 20, 1),
                  "max_diff_vs_full_history_K": float((snapsh - snaps).abs().max())}
     del wsh, snapsh
-    item64, rects64, trace64, snaps64 = setup(torch.float64)
-    opts64 = V.make_options(V.F64, V.LEAK_EXP, inp.beta, 1, 1e-3)
-    ctx.solve_transient(item64, rects64, trace64, inp.dt_s, opts64, snaps64, every)
-    torch.cuda.synchronize()
-    ref = snaps64.cpu().numpy()
-    kernels = {}
-    for name in ("tr_row", "tr_col"):
-        v = kt.get(name)
-        if not v:
-            continue
-        avg = v["total_ms"] / v["count"]
-        kernels[name] = {"launches": v["count"], "avg_ms": avg,
-                         "GB/s": TRANSIENT_BYTES_PER_CELL[name] * n * n / (avg * 1e-3) / 1e9}
-    return {"workload": "transient 1024x1024 FP32, 1000 steps of 10 us, 64 blocks redrawn every 1 ms, "
-                        "leakage + variation, eta 1.3, snapshots every 100 steps",
-            "ms_per_run": round(wall_untimed * 1e3, 3), "ms_per_run_with_kernel_events": round(wall * 1e3, 3),
-            "steps_per_s": round(steps / wall_untimed, 1), "status": st["status"],
-            "dT_max_K": st["dT_max_K"], "fp64_shadow_max_diff_K": float(np.max(np.abs(got - ref))),
-            "kernels": kernels, "modal": modal, "truncated_history": truncated,
-            "autotune": [l for l in ctx.autotune_report().strip().split("\n") if l.startswith("transient")]}
+    return modal, truncated
 
 
 def host_info() -> dict:

@@ -418,6 +418,17 @@ VARSIM_API varsim_status varsim_nn_conv(varsim_ctx* ctx, int32_t op, int32_t k, 
  */
 VARSIM_API varsim_status varsim_set_autotune(varsim_ctx* ctx, int32_t enable);
 VARSIM_API varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len);
+/* Persisted tuning: varsim_autotune_export writes the context's kept choices as text (a header
+ * line "varsim-tuning 1", then one line per choice: "col nx ny precision log2_group variant" and
+ * "tr n precision row_variant col_variant"); *needed (if not NULL) receives the size including the
+ * terminating NUL, and buf NULL only queries it (VARSIM_ERR_NO_MEMORY if len is smaller).
+ * varsim_autotune_import adds the choices of such text to the context, replacing kept choices of
+ * the same kinds, so that a later process can skip the timing runs; the text is checked whole
+ * first (VARSIM_ERR_INVALID on any malformed or out-of-range line, the context unchanged).  The
+ * choices only select among tilings of the same arithmetic, so an imported choice can cost
+ * speed, never accuracy; they are specific to the GPU model they were timed on. */
+VARSIM_API varsim_status varsim_autotune_export(varsim_ctx* ctx, char* buf, size_t len, size_t* needed);
+VARSIM_API varsim_status varsim_autotune_import(varsim_ctx* ctx, const char* text);
 /* Small grids: a map with N <= max_n is solved start to finish by one workgroup that keeps its
  * spectrum in LDS (one launch for the whole fixed point, convergence decided on the device);
  * larger maps use two HBM passes per iteration.  The limit is capped at 128 (FP32) / 64 (FP64),
@@ -452,8 +463,8 @@ VARSIM_API varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t varia
  * workgroup; column: widest strip / half / quarter), available for N >= 64 (an N below that
  * falls back to candidate 0).  Results agree to rounding.  -1 returns to the tuned, forced
  * (varsim_force_col_variant) or default choice (candidate 3 for both passes where N >= 64, else
- * 0; with autotuning on, the candidates are timed over whole steps on the first solve of each
- * (N, precision)).  VARSIM_ERR_INVALID outside [-1, 6). */
+ * 0; with autotuning on, every (row, column) pair is timed over whole steps on the first solve
+ * of each (N, precision) and the fastest pair kept).  VARSIM_ERR_INVALID outside [-1, 6). */
 VARSIM_API varsim_status varsim_force_transient_variant(varsim_ctx* ctx, int32_t row_variant,
                                                         int32_t col_variant);
 

@@ -1334,10 +1334,11 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    // Candidates are timed inside whole steps (column pass + row pass, as the solve runs them):
-    // first the row candidates with column candidate 0, then the column candidates with the
-    // chosen row candidate; each over 10 steps, two rounds, the faster round kept.  A short
-    // untimed burst first brings an idle GPU up to speed.
+    // Candidates are timed inside whole steps (column pass + row pass, as the solve runs them),
+    // every (row, column) pair, since the best row pass depends on the column pass before it
+    // (the two families leave the spectrum in different cache states); each pair over 40 steps,
+    // two rounds, the faster round kept.  A short untimed burst first brings an idle GPU up to
+    // speed.
     auto steps = [&](int r, int c, int count) -> hipError_t {
       for (int q = 0; q < count; ++q) {
         hipError_t e = launch_transient_col(io, t, s, c);
@@ -1346,27 +1347,31 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
       }
       return hipSuccess;
     };
+    // a burst of 10 untimed steps first: the launches that follow an idle gap (the previous
+    // candidate's synchronisation) run slower than those of a long solve and would skew the
+    // comparison
     auto time_steps = [&](int r, int c, float* out) -> hipError_t {
-      hipError_t e = steps(r, c, 1);
+      constexpr int kTimed = 40;
+      hipError_t e = steps(r, c, 10);
       if (e == hipSuccess) e = hipEventRecord(e0, s);
-      if (e == hipSuccess) e = steps(r, c, 10);
+      if (e == hipSuccess) e = steps(r, c, kTimed);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float el = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
-      *out = std::min(*out, el / 10.f);
+      *out = std::min(*out, el / kTimed);
       return e;
     };
     HIP_TRY(steps(0, 0, 40));
-    std::vector<float> ms(2 * nv, 1e30f);
+    std::vector<float> ms(nv * nv, 1e30f);  // ms[row * nv + column]
     for (int round = 0; round < 2; ++round)
-      for (int v = 0; v < nv; ++v) HIP_TRY(time_steps(v, 0, &ms[v]));
-    rv = (int)(std::min_element(ms.begin(), ms.begin() + nv) - ms.begin());
-    for (int round = 0; round < 2; ++round)
-      for (int v = 0; v < nv; ++v) HIP_TRY(time_steps(rv, v, &ms[nv + v]));
+      for (int r = 0; r < nv; ++r)
+        for (int c = 0; c < nv; ++c) HIP_TRY(time_steps(r, c, &ms[r * nv + c]));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    cv = (int)(std::min_element(ms.begin() + nv, ms.end()) - (ms.begin() + nv));
+    const int best = (int)(std::min_element(ms.begin(), ms.end()) - ms.begin());
+    rv = best / nv;
+    cv = best % nv;
     ctx->tr_choice[key] = {rv, cv};
     ctx->tr_ms[key] = ms;
     HIP_TRY(launch_zero_words(a.state, (size_t)a.poles * cells * esize(io), s));
@@ -1400,6 +1405,8 @@ varsim_status varsim_set_autotune(varsim_ctx* ctx, int32_t enable) {
   if (enable < 0) {
     ctx->col_choice.clear();
     ctx->col_ms.clear();
+    ctx->tr_choice.clear();
+    ctx->tr_ms.clear();
   }
   return VARSIM_OK;
 }
@@ -1441,6 +1448,76 @@ varsim_status varsim_force_transient_variant(varsim_ctx* ctx, int32_t row_varian
   return VARSIM_OK;
 }
 
+varsim_status varsim_autotune_export(varsim_ctx* ctx, char* buf, size_t len, size_t* needed) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  std::string out = "varsim-tuning 1\n";
+  char line[128];
+  for (const auto& kv : ctx->col_choice) {
+    snprintf(line, sizeof line, "col %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
+             std::get<2>(kv.first), std::get<3>(kv.first), kv.second);
+    out += line;
+  }
+  for (const auto& kv : ctx->tr_choice) {
+    snprintf(line, sizeof line, "tr %d %d %d %d\n", kv.first.first, kv.first.second, kv.second.first,
+             kv.second.second);
+    out += line;
+  }
+  if (needed) *needed = out.size() + 1;
+  if (!buf) return VARSIM_OK;
+  if (len < out.size() + 1) return fail(ctx, VARSIM_ERR_NO_MEMORY, "buffer of %zu bytes < %zu", len, out.size() + 1);
+  memcpy(buf, out.c_str(), out.size() + 1);
+  return VARSIM_OK;
+}
+
+varsim_status varsim_autotune_import(varsim_ctx* ctx, const char* text) {
+  if (!ctx) return VARSIM_ERR_INVALID;
+  if (!text) return fail(ctx, VARSIM_ERR_INVALID, "text is NULL");
+  // parse everything first; the context changes only if every line is valid
+  std::vector<std::pair<std::tuple<int, int, int, int>, int>> cols;
+  std::vector<std::pair<std::pair<int, int>, std::pair<int, int>>> trs;
+  auto pow2_in = [](int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; };
+  auto prec_ok = [](int p) { return p == VARSIM_F32 || p == VARSIM_F64; };
+  const char* p = text;
+  int lineno = 0;
+  bool header = false;
+  while (*p) {
+    const char* e = strchr(p, '\n');
+    const size_t n = e ? (size_t)(e - p) : strlen(p);
+    std::string ln(p, n);
+    p += n + (e ? 1 : 0);
+    ++lineno;
+    if (ln.find_first_not_of(" \t\r") == std::string::npos) continue;
+    int a0, a1, a2, a3, a4, used = 0;
+    if (!header) {
+      if (sscanf(ln.c_str(), "varsim-tuning %d %n", &a0, &used) != 1 || a0 != 1 || ln.c_str()[used])
+        return fail(ctx, VARSIM_ERR_INVALID, "line %d: expected the header 'varsim-tuning 1'", lineno);
+      header = true;
+    } else if (sscanf(ln.c_str(), "col %d %d %d %d %d %n", &a0, &a1, &a2, &a3, &a4, &used) == 5 && !ln.c_str()[used]) {
+      if (!pow2_in(a0, 16, 1024) || !pow2_in(a1, 16, 1024) || !prec_ok(a2) || a3 < 0 || a3 > 30 || a4 < 0 ||
+          a4 >= kColVariants)
+        return fail(ctx, VARSIM_ERR_INVALID, "line %d: column choice out of range", lineno);
+      cols.push_back({std::make_tuple(a0, a1, a2, a3), a4});
+    } else if (sscanf(ln.c_str(), "tr %d %d %d %d %n", &a0, &a1, &a2, &a3, &used) == 4 && !ln.c_str()[used]) {
+      if (!pow2_in(a0, 16, 1024) || !prec_ok(a1) || a2 < 0 || a2 >= transient_variants(a0) || a3 < 0 ||
+          a3 >= transient_variants(a0))
+        return fail(ctx, VARSIM_ERR_INVALID, "line %d: transient choice out of range", lineno);
+      trs.push_back({{a0, a1}, {a2, a3}});
+    } else {
+      return fail(ctx, VARSIM_ERR_INVALID, "line %d: not a tuning record", lineno);
+    }
+  }
+  if (!header) return fail(ctx, VARSIM_ERR_INVALID, "no 'varsim-tuning 1' header");
+  for (const auto& c : cols) {
+    ctx->col_choice[c.first] = c.second;
+    ctx->col_ms.erase(c.first);
+  }
+  for (const auto& t : trs) {
+    ctx->tr_choice[t.first] = t.second;
+    ctx->tr_ms.erase(t.first);
+  }
+  return VARSIM_OK;
+}
+
 varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
   if (!ctx || !buf || !len) return VARSIM_ERR_INVALID;
   std::string out;
@@ -1453,7 +1530,14 @@ varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
     else
       snprintf(line, sizeof line, "col nx=%d ny=%d %s maps>=%d:", nx, n, c == VARSIM_F32 ? "f32" : "f64", 1 << b);
     out += line;
-    const auto& ms = ctx->col_ms[kv.first];
+    const auto found = ctx->col_ms.find(kv.first);
+    if (found == ctx->col_ms.end()) {
+      snprintf(line, sizeof line, " %d cols x%d (imported)\n", col_pass_columns(c, n, kv.second),
+               col_pass_pairs(c, n, kv.second));
+      out += line;
+      continue;
+    }
+    const auto& ms = found->second;
     for (int v = 0; v < (int)ms.size(); ++v) {
       snprintf(line, sizeof line, " %d cols x%d %.4f ms%s", col_pass_columns(c, n, v), col_pass_pairs(c, n, v), ms[v],
                v == kv.second ? "*" : "");
@@ -1462,19 +1546,27 @@ varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
     out += "\n";
   }
   for (const auto& kv : ctx->tr_choice) {
-    const auto& ms = ctx->tr_ms[kv.first];
-    const int nv = (int)ms.size() / 2;
-    snprintf(line, sizeof line, "transient n=%d %s ms per step: row candidates", kv.first.first,
+    const auto found = ctx->tr_ms.find(kv.first);
+    if (found == ctx->tr_ms.end()) {
+      snprintf(line, sizeof line, "transient n=%d %s row candidate %d column candidate %d (imported)\n", kv.first.first,
+               kv.first.second == VARSIM_F32 ? "f32" : "f64", kv.second.first, kv.second.second);
+      out += line;
+      continue;
+    }
+    const auto& ms = found->second;
+    int nv = 0;
+    while (nv * nv < (int)ms.size()) ++nv;
+    snprintf(line, sizeof line, "transient n=%d %s ms per step, row candidate: column candidates", kv.first.first,
              kv.first.second == VARSIM_F32 ? "f32" : "f64");
     out += line;
-    for (int v = 0; v < nv; ++v) {
-      snprintf(line, sizeof line, " %.4f%s", ms[v], v == kv.second.first ? "*" : "");
+    for (int r = 0; r < nv; ++r) {
+      snprintf(line, sizeof line, "%s r%d:", r ? ";" : "", r);
       out += line;
-    }
-    out += "; column candidates";
-    for (int v = 0; v < nv; ++v) {
-      snprintf(line, sizeof line, " %.4f%s", ms[nv + v], v == kv.second.second ? "*" : "");
-      out += line;
+      for (int c = 0; c < nv; ++c) {
+        const bool chosen = r == kv.second.first && c == kv.second.second;
+        snprintf(line, sizeof line, " %.4f%s", ms[r * nv + c], chosen ? "*" : "");
+        out += line;
+      }
     }
     out += "\n";
   }

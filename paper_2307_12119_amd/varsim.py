@@ -114,6 +114,8 @@ EXPORTS = {
                                c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "varsim_set_autotune": (c_int, [c_void_p, c_int32]),
     "varsim_autotune_report": (c_int, [c_void_p, c_char_p, c_size_t]),
+    "varsim_autotune_export": (c_int, [c_void_p, c_char_p, c_size_t, POINTER(c_size_t)]),
+    "varsim_autotune_import": (c_int, [c_void_p, c_char_p]),
     "varsim_force_col_variant": (c_int, [c_void_p, c_int32]),
     "varsim_force_transient_variant": (c_int, [c_void_p, c_int32, c_int32]),
     "varsim_set_small_path": (c_int, [c_void_p, c_int32]),
@@ -449,6 +451,18 @@ class Context:
         buf = ctypes.create_string_buffer(8192)
         self._check(self.lib.varsim_autotune_report(self.handle, buf, len(buf)))
         return buf.value.decode()
+
+    def autotune_export(self) -> str:
+        """The kept launch-shape choices as text (varsim_autotune_export)."""
+        need = ctypes.c_size_t(0)
+        self._check(self.lib.varsim_autotune_export(self.handle, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        self._check(self.lib.varsim_autotune_export(self.handle, buf, len(buf), None))
+        return buf.value.decode()
+
+    def autotune_import(self, text: str):
+        """Add the choices of autotune_export text to this context (varsim_autotune_import)."""
+        self._check(self.lib.varsim_autotune_import(self.handle, text.encode()))
 
     # -------------------------------------------------------------------------------- timing
     def set_timing(self, enable: bool):

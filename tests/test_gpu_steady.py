@@ -537,3 +537,41 @@ def test_lds_resident_path_equals_two_pass_path(ctx, prec, n):
     assert t0[0]["status"] == t1[0]["status"] == V.ERR_NOT_CONVERGED
     assert t0[0]["iterations"] == t1[0]["iterations"] == 2
     assert t0[0]["last_increment_K"] == t1[0]["last_increment_K"]
+
+
+def test_tuning_export_import_roundtrip(gpu_lib):
+    """Choices timed in one context, exported as text and imported into a fresh one, apply there
+    without timing: the same solves give the same bits, and the report marks them imported.
+    Malformed text is rejected whole."""
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    inps = [W.config2(sample=s, n=n) for s, n in ((0, 256), (1, 256), (2, 512))]
+    opts = _opts(V.F32, inps[0], 50, 1e-3)
+    a = V.Context(0, gpu_lib)
+    b = V.Context(0, gpu_lib)
+    try:
+        a.set_autotune(1)
+        first = [gpu_item(i, torch.float32) for i in inps]
+        a.solve_batch(first, opts)
+        text = a.autotune_export()
+        lines = text.strip().splitlines()
+        assert lines[0] == "varsim-tuning 1" and any(l.startswith("col 256 256 ") for l in lines)
+        before = b.autotune_export()
+        for bad in ("col 256 256 0 1 2\n", "varsim-tuning 1\ncol 256 256 0 1 9\n",
+                    "varsim-tuning 1\ntr 48 0 1 1\n", "varsim-tuning 1\ncol 256 256 0 1\n"):
+            with pytest.raises(V.VarsimError) as e:
+                b.autotune_import(bad)
+            assert e.value.status == V.ERR_INVALID
+        assert b.autotune_export() == before
+        b.autotune_import(text)
+        assert b.autotune_export() == text
+        assert "(imported)" in b.autotune_report()
+        second = [gpu_item(i, torch.float32) for i in inps]
+        b.solve_batch(second, opts)
+        for x, y in zip(first, second):
+            assert torch.equal(x["dT_out"], y["dT_out"])
+    finally:
+        a.close()
+        b.close()

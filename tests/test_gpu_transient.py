@@ -476,3 +476,25 @@ def test_transient_history_argument_errors(ctx):
         with pytest.raises(V.VarsimError) as e:
             _run_gpu(ctx, inp, torch.float64, history_steps=h)
         assert e.value.status == V.ERR_INVALID
+
+
+def test_transient_autotune_picks_a_pair_and_matches_it(ctx):
+    """With autotuning on, the first transient solve of a size times every (row, column) pass pair
+    and keeps the fastest; the solve then equals the same pair forced, bit for bit."""
+    import torch
+
+    inp = _case_input(128, 6, 50e-6, True, seed=6)
+    ctx.set_autotune(1)
+    try:
+        st, tuned, _ = _run_gpu(ctx, inp, torch.float32)
+        line = [l for l in ctx.autotune_report().splitlines() if l.startswith("transient n=128 f32")]
+    finally:
+        ctx.set_autotune(-1)
+    assert st["status"] == 0 and len(line) == 1
+    rows = line[0].split(":", 1)[1].split(";")
+    assert len(rows) == 6 and all(len(r.split(":")[1].split()) == 6 for r in rows)
+    pick = [(i, j) for i, r in enumerate(rows) for j, v in enumerate(r.split(":")[1].split()) if v.endswith("*")]
+    assert len(pick) == 1
+    with _variants(ctx, pick[0]):
+        _, forced, _ = _run_gpu(ctx, inp, torch.float32)
+    assert np.array_equal(tuned, forced)
