@@ -14,9 +14,18 @@
 namespace vs {
 namespace {  // each translation unit keeps its own instantiations
 
+// Waves per SIMD the register allocation must leave room for: the FP32 merged pass of the
+// two-pass sizes is HBM-bound and needs four to hide its load latency (it fits 128 VGPRs without
+// spilling); other instantiations are left to the compiler.
+template <typename Tio, typename Tc, int N, int MODE>
+constexpr int row_min_waves() {
+  return (sizeof(Tio) == 4 && sizeof(Tc) == 4 && MODE == ROW_MERGED && N >= 128 && N <= 512) ? 4 : 1;
+}
+
 // CT: compensated twiddles (twl, qwl: low parts of tw, qw; FP32 only)
 template <typename Tio, typename Tc, int N, int MODE, bool CT = false>
 __global__ void __launch_bounds__(RowCfg<N>::THREADS)
+    __attribute__((amdgpu_waves_per_eu(row_min_waves<Tio, Tc, N, MODE>())))
     row_pass_kernel(PassArgs a, const Cx<Tc>* __restrict__ tw, const Cx<Tc>* __restrict__ qw,
                     const Cx<Tc>* __restrict__ twl = nullptr, const Cx<Tc>* __restrict__ qwl = nullptr) {
   using Cfg = RowCfg<N>;
