@@ -105,17 +105,19 @@ def generate(batch: int, n: int, workers: int):
 
 
 def algorithmic_bytes(n: int) -> dict:
-    """Bytes each kernel class must move per map it processes (FP32 maps, FP64 residual pass)."""
+    """Bytes each kernel class must move per map it processes (FP32 maps, FP64 residual pass), with
+    the conductivity factor on the source side (the default): the FP32 passes read q_dyn / m and
+    QL / m, which the prep pass writes once per solve."""
     c = n * n
     return {
-        "prep": 20 * c,         # read q_leak0, v, m; write QL, 1/m
-        "row_head": 12 * c,     # read q_dyn, QL; write spectrum
+        "prep": 32 * c,         # read q_leak0, v, m, q_dyn; write QL, 1/m, q_dyn / m, QL / m
+        "row_head": 12 * c,     # read q_dyn / m, QL / m; write spectrum
         "col": 8 * c,           # read + write spectrum
-        "row_merged": 28 * c,   # read spectrum, dT, q_dyn, QL, 1/m; write dT, spectrum
-        "row_last": 20 * c,     # read spectrum, dT, 1/m; write dT
-        "resid_head": 20 * c,   # read dT, q_dyn, QL; write FP64 spectrum
+        "row_merged": 24 * c,   # read spectrum, dT, q_dyn / m, QL / m; write dT, spectrum
+        "row_last": 12 * c,     # read spectrum, dT; write dT
+        "resid_head": 24 * c,   # read dT, q_dyn, QL, 1/m; write FP64 spectrum
         "resid_col": 16 * c,    # read + write FP64 spectrum
-        "resid_tail": 16 * c,   # read FP64 spectrum, 1/m, dT
+        "resid_tail": 12 * c,   # read FP64 spectrum, dT
     }
 
 

@@ -235,11 +235,21 @@ struct Layout {
   int stride = 0;
   size_t resid = 0, sum = 0, maxpack = 0, flags = 0, resid64 = 0, part = 0, aa = 0, state_end = 0;
   size_t stats = 0, maps = 0, prep = 0, order = 0;
-  std::vector<size_t> S, QL, MINV, S64, AX, AG, AF;
+  std::vector<size_t> S, QL, MINV, S64, AX, AG, AF, QS, QLS;
   size_t total = 0;
 };
 
 size_t esize(int precision) { return precision == VARSIM_F64 ? 8 : 4; }
+
+// The FP32 passes' source-side inputs of map i (MapPtrs::qs, qls: the prep kernel's q_dyn / m and
+// QL / m, else q_dyn and QL themselves) and the prep outputs that fill them; m.ql must be set.
+void set_source_inputs(MapPtrs& m, PrepArgs& q, const varsim_problem* p, const Layout& L, int i, char* ws) {
+  m.qs = L.QS[i] != (size_t)-1 ? (const void*)(ws + L.QS[i]) : p->q_dyn;
+  m.qls = L.QLS[i] != (size_t)-1 ? (const void*)(ws + L.QLS[i]) : m.ql;
+  q.q_dyn = p->q_dyn;
+  q.qs_out = L.QS[i] != (size_t)-1 ? ws + L.QS[i] : nullptr;
+  q.qls_out = L.QLS[i] != (size_t)-1 ? ws + L.QLS[i] : nullptr;
+}
 
 // true for memory the device owns (hipMalloc / torch tensors), false for host memory
 bool is_device_ptr(const void* p) {
@@ -296,6 +306,13 @@ Layout make_layout(const std::vector<const varsim_problem*>& probs, const varsim
     } else {
       L.MINV.push_back((size_t)-1);
     }
+    // FP32 with the conductivity factor on the source side: q_dyn / m and QL / m
+    const bool pre = p->cond_map && o->precision == VARSIM_F32 && o->cond_model == VARSIM_COND_SOURCE;
+    L.QS.push_back(pre ? off : (size_t)-1);
+    if (pre) off = align_up(off + cells * es);
+    const bool pre_leak = pre && p->q_leak0 && o->leak != VARSIM_LEAK_NONE;
+    L.QLS.push_back(pre_leak ? off : (size_t)-1);
+    if (pre_leak) off = align_up(off + cells * es);
     if (o->final_f64_residual && o->precision == VARSIM_F32) {
       L.S64.push_back(off);
       off = align_up(off + cells * 8);
@@ -786,6 +803,7 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
     q.minv_out = (void*)m.minv;
     q.dT = p->dT_out;
     q.flags = base.flags + i;
+    set_source_inputs(m, q, p, L, i, ws);
     any_init = any_init || p->dT_init;
   }
 
@@ -1130,6 +1148,7 @@ varsim_status varsim_solve_oneshot(varsim_ctx* ctx, const varsim_problem* proble
     q.minv_out = (void*)m.minv;
     q.dT = p->dT_out;
     q.flags = base.flags + i;  // dT_init is not used
+    set_source_inputs(m, q, p, L, i, ws);
   }
   HIP_TRY(timed(ctx, "setup", s, [&] { return launch_zero_words(ws, L.state_end, s); }));
   HIP_TRY(hipMemcpyAsync(d_maps, ctx->h_maps.data(), n * sizeof(MapPtrs), hipMemcpyHostToDevice, s));

@@ -41,6 +41,11 @@ struct MapPtrs {
   void* ax;
   void* ag;
   void* af;
+  // FP32 passes with the conductivity factor on the source side read the power inputs already
+  // divided by m (io type): q_dyn / m and QL / m, written once per solve by the prep kernel (qd
+  // and ql themselves where no conductivity map is given), so that no 1/m map is read per iteration
+  const void* qs;
+  const void* qls;
 };
 
 // Pointwise physics constants of one geometry.

@@ -102,6 +102,11 @@ struct PrepArgs {
   void* minv_out;  // or null
   void* dT;
   unsigned* flags;  // this map's flag word
+  // source-side inputs of the FP32 passes (MapPtrs::qs, qls), or null: q_dyn / m and
+  // q_leak0 v / m (need cond_map; minv_out is then set too)
+  const void* q_dyn;
+  void* qs_out;
+  void* qls_out;
 };
 // args: device array of n_maps entries; count = cells per map
 hipError_t launch_prep(int io, const PrepArgs* args, int n_maps, long count, hipStream_t stream);

@@ -75,21 +75,26 @@ __device__ __forceinline__ void row_pointwise(Tc* z, const MapPtrs& mp, long off
     }
   }
   if constexpr (MODE == ROW_HEAD || MODE == ROW_MERGED) {
+    // FP32 transforms with the factor on the source side: the inputs come divided by m already
+    constexpr bool kPre = sizeof(Tc) == 4;
+    const bool pre = kPre && pp.cond_src;
     Tc q[E];
-    load_slots<Tio, Tc, N, NT>((const Tio*)mp.qd + off, q, t, mirror);
+    load_slots<Tio, Tc, N, NT>((const Tio*)(pre ? mp.qs : mp.qd) + off, q, t, mirror);
     if (mp.ql) {
       Tc ql[E];
-      load_slots<Tio, Tc, N, NT>((const Tio*)mp.ql + off, ql, t, mirror);
+      load_slots<Tio, Tc, N, NT>((const Tio*)(pre ? mp.qls : mp.ql) + off, ql, t, mirror);
 #pragma unroll
       for (int m = 0; m < E; ++m) q[m] += ql[m] * leak_factor<Tc>(x[m], pp);
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) z[m] = (Tc)pp.hxhy * q[m];
-    if (mp.minv && pp.cond_src) {  // source side: the power is scaled
-      Tc mv[E];
-      load_slots<Tio, Tc, N, NT>((const Tio*)mp.minv + off, mv, t, mirror);
+    if constexpr (!kPre) {
+      if (mp.minv && pp.cond_src) {  // source side: the power is scaled
+        Tc mv[E];
+        load_slots<Tio, Tc, N, NT>((const Tio*)mp.minv + off, mv, t, mirror);
 #pragma unroll
-      for (int m = 0; m < E; ++m) z[m] *= mv[m];
+        for (int m = 0; m < E; ++m) z[m] *= mv[m];
+      }
     }
   }
 }

@@ -35,11 +35,12 @@ __global__ void __launch_bounds__(256) prep_kernel(const PrepArgs* __restrict__ 
   bool invalid = false, warm_bad = false;
   const long nv = count / V;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (long)gridDim.x * blockDim.x) {
-    if (pa.ql_out) {
-      vec_t v = __builtin_nontemporal_load((const vec_t*)pa.q_leak0 + i);
+    vec_t v = (T)0;
+    if (pa.ql_out || pa.qls_out) {
+      v = __builtin_nontemporal_load((const vec_t*)pa.q_leak0 + i);
       if (pa.leak_var) v *= __builtin_nontemporal_load((const vec_t*)pa.leak_var + i);
-      ((vec_t*)pa.ql_out)[i] = v;
     }
+    if (pa.ql_out) ((vec_t*)pa.ql_out)[i] = v;
     if (pa.minv_out) {
       const vec_t m = __builtin_nontemporal_load((const vec_t*)pa.cond_map + i);
       vec_t r;
@@ -49,6 +50,8 @@ __global__ void __launch_bounds__(256) prep_kernel(const PrepArgs* __restrict__ 
         r[e] = (T)1 / m[e];
       }
       ((vec_t*)pa.minv_out)[i] = r;
+      if (pa.qs_out) ((vec_t*)pa.qs_out)[i] = __builtin_nontemporal_load((const vec_t*)pa.q_dyn + i) * r;
+      if (pa.qls_out) ((vec_t*)pa.qls_out)[i] = v * r;
     }
     if (pa.init) {
       const vec_t w = ((const vec_t*)pa.init)[i];

@@ -55,17 +55,22 @@ def test_compensated_twiddles_reduce_fp32_error(ctx, n):
 
     inps = [W.config2(sample=s, n=n) for s in range(2)]
     iters = 5
-    errs = {}
+    errs, mean = {}, {}
     for ct in (False, True):
         items = [gpu_item(i, torch.float32) for i in inps]
         ctx.solve_batch(items, _opts(V.F32, inps[0], iters, 1e-30, ct=ct), raise_on=())
         refs = [gpu_item(i, torch.float64) for i in inps]
         ctx.solve_batch(refs, _opts(V.F64, inps[0], iters, 1e-30), raise_on=())
-        errs[ct] = max(float((a["dT_out"].double() - b["dT_out"]).abs().max()) for a, b in zip(items, refs))
-    print(f"FP32 iterate {iters} at {n}^2 vs FP64: rounded twiddles {errs[False]:.3e} K, "
-          f"compensated {errs[True]:.3e} K", flush=True)
+        d = [(a["dT_out"].double() - b["dT_out"]).abs() for a, b in zip(items, refs)]
+        errs[ct] = max(float(x.max()) for x in d)
+        mean[ct] = sum(float(x.mean()) for x in d) / len(d)
+    print(f"FP32 iterate {iters} at {n}^2 vs FP64: rounded twiddles max {errs[False]:.3e} K mean "
+          f"{mean[False]:.3e} K, compensated max {errs[True]:.3e} K mean {mean[True]:.3e} K", flush=True)
     assert errs[True] <= FP32_ACHIEVED_K and errs[False] <= FP32_ACHIEVED_K
-    assert errs[True] < errs[False]
+    # the largest error sits at the FP32 resolution of the stored rise (about one ulp of the peak,
+    # for either set of twiddles, which of the two is larger is chance); the transforms' own
+    # rounding, which the compensation removes, shows in the mean error
+    assert mean[True] < mean[False]
 
 
 def test_compensated_batch_equals_single(ctx):

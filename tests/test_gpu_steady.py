@@ -184,9 +184,11 @@ def test_fp64_conductivity_exponent_one(ctx, n):
     assert st["status"] == V.OK and st["iterations"] == rs.iterations
     got = item["dT_out"].cpu().numpy()
     assert np.max(np.abs(got - ref)) <= FP64_GATE_REL * np.max(ref)
-    # FP32 on the same problem (the FP32 series / exp2 fallback of the eta = 1 branch)
+    # FP32 on the same problem (the FP32 series / exp2 fallback of the eta = 1 branch); the
+    # tolerance stays above FP32's resolution at the peak rise (an increment of 1e-6 K is below
+    # one ulp of a 16 K rise, where the FP32 iteration may end on a two-value cycle)
     item32 = gpu_item(inp, torch.float32)
-    st32 = ctx.solve_steady(item32, _opts(V.F32, inp, 40, 1e-6))
+    st32 = ctx.solve_steady(item32, _opts(V.F32, inp, 40, 1e-5))
     assert st32["status"] == V.OK
     assert np.max(np.abs(item32["dT_out"].cpu().numpy().astype(np.float64) - ref)) <= FP32_ACHIEVED_K
 
@@ -245,7 +247,8 @@ def test_anisotropic_cells(ctx, prec):
     (ref, rs), _ = oracle_solve(inp, 1e-9, 40)
     dt = torch.float64 if prec == "f64" else torch.float32
     item = gpu_item(inp, dt)
-    st = ctx.solve_steady(item, _opts(V.F64 if prec == "f64" else V.F32, inp, 40, 1e-9 if prec == "f64" else 1e-6))
+    # FP32: a tolerance above the resolution at the peak rise (see test_fp64_conductivity_exponent_one)
+    st = ctx.solve_steady(item, _opts(V.F64 if prec == "f64" else V.F32, inp, 40, 1e-9 if prec == "f64" else 1e-5))
     assert st["status"] == V.OK
     got = item["dT_out"].cpu().numpy().astype(np.float64)
     if prec == "f64":

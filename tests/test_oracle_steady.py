@@ -252,6 +252,14 @@ def test_conductivity_map_placement_against_finite_volume():
     assert errs["source"] < 0.006
     assert errs["target"] > 3.0 * errs["source"]
     assert err_ignore > 5.0 * errs["source"]  # the map matters: ignoring it is far worse
+    # a smoothed map (a (2R + 1)^2 box average of m, mirrored at the edges) on the source side does
+    # worse than the pointwise one: the stencil radius stays 0
+    for radius in (1, 2):
+        pad = np.pad(m, radius, mode="symmetric")
+        sm = sum(pad[radius + dy:radius + dy + m.shape[0], radius + dx:radius + dx + m.shape[1]]
+                 for dy in range(-radius, radius + 1) for dx in range(-radius, radius + 1)) / (2 * radius + 1) ** 2
+        dT, _ = S.solve_steady(S.SteadyProblem(g, qd, cond_map=sm), S.Options(leak="none", cond="source"))
+        assert float(np.max(np.abs(dT - ref))) / mx > 1.2 * errs["source"], radius
 
 
 def test_lateral_conductivity_solvers_agree():
