@@ -463,8 +463,9 @@ VARSIM_API varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t varia
  * workgroup; column: widest strip / half / quarter), available for N >= 64 (an N below that
  * falls back to candidate 0).  Results agree to rounding.  -1 returns to the tuned, forced
  * (varsim_force_col_variant) or default choice (candidate 3 for both passes where N >= 64, else
- * 0; with autotuning on, every (row, column) pair is timed over whole steps on the first solve
- * of each (N, precision) and the fastest pair kept).  VARSIM_ERR_INVALID outside [-1, 6). */
+ * 0; with autotuning on, the (row, column) pairs of the one-sequence family (of the
+ * two-sequence family where N < 64) are timed over whole steps on the first solve of each
+ * (N, precision) and the fastest pair kept).  VARSIM_ERR_INVALID outside [-1, 6). */
 VARSIM_API varsim_status varsim_force_transient_variant(varsim_ctx* ctx, int32_t row_variant,
                                                         int32_t col_variant);
 

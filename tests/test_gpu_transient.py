@@ -493,8 +493,11 @@ def test_transient_autotune_picks_a_pair_and_matches_it(ctx):
     assert st["status"] == 0 and len(line) == 1
     rows = line[0].split(":", 1)[1].split(";")
     assert len(rows) == 6 and all(len(r.split(":")[1].split()) == 6 for r in rows)
-    pick = [(i, j) for i, r in enumerate(rows) for j, v in enumerate(r.split(":")[1].split()) if v.endswith("*")]
-    assert len(pick) == 1
+    cells = [[v for v in r.split(":")[1].split()] for r in rows]
+    # at n >= 64 the one-sequence pairs (candidates 3..5) are the ones timed
+    assert all((v != "-") == (i >= 3 and j >= 3) for i, r in enumerate(cells) for j, v in enumerate(r))
+    pick = [(i, j) for i, r in enumerate(cells) for j, v in enumerate(r) if v.endswith("*")]
+    assert len(pick) == 1 and pick[0][0] >= 3 and pick[0][1] >= 3
     with _variants(ctx, pick[0]):
         _, forced, _ = _run_gpu(ctx, inp, torch.float32)
     assert np.array_equal(tuned, forced)
