@@ -10,8 +10,12 @@
  *     conductivity-variation map scales the Green's function as 1/k (Eq. fspvsk);
  *   - leakage and conductivity are iterated against temperature until convergence, the
  *     ground truth of Sec. V-C;
- *   - transients use the single-pole transient Green's function (Eq. tranGreen) superposed
- *     over a piecewise-constant power history (Eq. tranapprox).
+ *   - transients use the single-pole transient Green's function (Eq. tranGreen), or the slab's
+ *     multi-pole response, superposed over a piecewise-constant power history (Eq. tranapprox),
+ *     whole or truncated after a horizon as in Sec. IV-E;
+ *   - optionally: a package stack below the die (Table param), the one-shot leakage-aware
+ *     Green's functions (Sec. IV-C, Eqs. detsol, randsol, detrandsol), Anderson(1) mixing of
+ *     the fixed point, FP32 transforms with compensated twiddles.
  *
  * Conventions shared by every entry point
  *   - SI units throughout: metres, watts, kelvin, seconds; power maps are densities in W/m^2.
