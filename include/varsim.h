@@ -455,10 +455,13 @@ VARSIM_API varsim_status varsim_set_graph_iterations(varsim_ctx* ctx, int32_t it
 /* Testing / manual tuning: every later column pass (solves and varsim_conv) uses strip-width
  * candidate `variant` (0 = default strip width, 1 = default width with two column pairs per
  * transform group, 2 = half width, 3 / 4 = the wide strip of 128-byte row segments whose
- * transforms use the strip's own tile columns as scratch, one / two pairs per group; square
- * maps only, rectangular ones keep 0), and transient solves use row-pass candidate `variant`
- * and column candidate `variant` (see varsim_force_transient_variant); -1 returns to the
- * default or tuned choices.  VARSIM_ERR_INVALID outside [-1, 4]. */
+ * transforms use the strip's own tile columns as scratch, one / two pairs per group, 5 / 6 =
+ * the pipelined pass on the same 128-byte strips (a few workgroups per CU walk the strips,
+ * loading the next strip while transforming the current one), two / four pairs per group,
+ * where the strips split evenly over the 8 XCDs (else candidate 0); square maps only,
+ * rectangular ones keep 0), and transient solves use row-pass candidate `variant` and column
+ * candidate `variant` (see varsim_force_transient_variant; variant 6 leaves them at their
+ * default); -1 returns to the default or tuned choices.  VARSIM_ERR_INVALID outside [-1, 6]. */
 VARSIM_API varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t variant);
 /* Testing / manual tuning of transient solves: row-pass candidate `row_variant` and column-pass
  * candidate `col_variant`, each in [0, 6): 0..2 transform two rows (columns) per DFT (row: rows

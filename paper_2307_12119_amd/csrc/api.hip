@@ -519,7 +519,8 @@ varsim_status col_variant_for(varsim_ctx* ctx, const PassArgs& group, int comput
     int dup = -1;
     for (int u = 0; u < v; ++u)
       if (col_pass_columns(compute, a.ny, u) == col_pass_columns(compute, a.ny, v) &&
-          col_pass_pairs(compute, a.ny, u) == col_pass_pairs(compute, a.ny, v))
+          col_pass_pairs(compute, a.ny, u) == col_pass_pairs(compute, a.ny, v) &&
+          col_pass_pipelined(compute, a.ny, u) == col_pass_pipelined(compute, a.ny, v))
         dup = u;
     if (dup >= 0) {
       ms[v] = ms[dup];
@@ -1342,7 +1343,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   int rv = nv > 3 ? 3 : 0, cv = rv;  // untuned default: one-sequence passes where available
   const auto key = std::make_pair(g->nx, io);
   auto it = ctx->tr_choice.find(key);
-  if (ctx->force_col >= 0) {
+  if (ctx->force_col >= 0 && ctx->force_col < kTrVariants) {
     rv = cv = ctx->force_col;
   } else if (it != ctx->tr_choice.end()) {
     rv = it->second.first;
@@ -1560,15 +1561,15 @@ varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
     out += line;
     const auto found = ctx->col_ms.find(kv.first);
     if (found == ctx->col_ms.end()) {
-      snprintf(line, sizeof line, " %d cols x%d (imported)\n", col_pass_columns(c, n, kv.second),
-               col_pass_pairs(c, n, kv.second));
+      snprintf(line, sizeof line, " %d cols x%d%s (imported)\n", col_pass_columns(c, n, kv.second),
+               col_pass_pairs(c, n, kv.second), col_pass_pipelined(c, n, kv.second) ? " pipelined" : "");
       out += line;
       continue;
     }
     const auto& ms = found->second;
     for (int v = 0; v < (int)ms.size(); ++v) {
-      snprintf(line, sizeof line, " %d cols x%d %.4f ms%s", col_pass_columns(c, n, v), col_pass_pairs(c, n, v), ms[v],
-               v == kv.second ? "*" : "");
+      snprintf(line, sizeof line, " %d cols x%d%s %.4f ms%s", col_pass_columns(c, n, v), col_pass_pairs(c, n, v),
+               col_pass_pipelined(c, n, v) ? " pipelined" : "", ms[v], v == kv.second ? "*" : "");
       out += line;
     }
     out += "\n";

@@ -186,10 +186,190 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS, INPL>::THREADS))
   }
 }
 
+// Pipelined column pass: a grid of a few workgroups per CU, each walking a list of strips and
+// loading the next strip's rows into registers while the current strip is transformed in place
+// in LDS, so the HBM reads of one strip overlap the transforms of the previous one (a one-shot
+// workgroup sits idle on its loads and its CU's memory pipe idles while all its workgroups
+// transform).  Strips are COLS columns wide (128-byte row segments); the tile and its in-place
+// transform scratch are those of the in-place strip.  Strips split over the XCDs as in
+// xcd_strip_tile: XCD x walks strips [x S/8, (x+1) S/8) of every map.
+template <typename Tc, int N>
+constexpr int pipe_cols() {
+  int c = 128 / (int)sizeof(Tc);
+  if (c > N / 8) c = N / 8;
+  while (c > 2 && (long)Shape<N>::STRIDE * (c + 1) * (long)sizeof(Tc) > 150 * 1024) c /= 2;
+  return c;
+}
+// register budget: the waves per SIMD that the workgroups fitting one CU's 160 KB of LDS bring
+template <typename Tc, int N, int COLS, int PAIRS>
+constexpr int pipe_waves_per_eu() {
+  using Cfg = ColCfg<Tc, N, COLS, PAIRS, true>;
+  const long bytes = (long)Cfg::LDS * (long)sizeof(Tc);
+  const int wgs = (int)(160 * 1024 / bytes);
+  const int w = wgs * (Cfg::THREADS / 64) / 4;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+template <typename Tc, int N, int COLS, int PAIRS, bool CT = false>
+__global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS, true>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(pipe_waves_per_eu<Tc, N, COLS, PAIRS>())))
+    col_pipe_kernel(PassArgs a, const Tc* __restrict__ coef, const Cx<Tc>* __restrict__ tw,
+                    const Cx<Tc>* __restrict__ twl) {
+  using Cfg = ColCfg<Tc, N, COLS, PAIRS, true>;
+  constexpr int TPF = Cfg::TPF;
+  constexpr int E = Shape<N>::E;
+  constexpr int VEC = Cfg::VEC;
+  constexpr int VPR = Cfg::COLS / VEC;
+  constexpr int P = Cfg::PITCH;
+  constexpr int NP = Cfg::PAIRS;
+  constexpr int SP = N / Cfg::COLS / 8;  // strips per XCD
+  static_assert(SP >= 1 && (N / Cfg::COLS) % 8 == 0, "strips must split over the 8 XCDs");
+  __shared__ Tc lds[Cfg::LDS];
+
+  const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+  const long count = (long)SP * a.n_maps;  // strips of this XCD
+  auto map_of = [&](long j) { return (int)(j / SP); };
+  auto strip_of = [&](long j) { return xcd * SP + (int)(j % SP); };
+  auto active = [&](int map) {
+    if (a.iter < 0) return true;  // plain convolution: no solver state
+    if (a.st.flags[map] & kFlagSkip) return false;
+    return a.resid_pass || !finished_before(a.st, map, a.iter, a.pp.tol);
+  };
+  auto next_active = [&](long j) {
+    while (j < count && !active(map_of(j))) j += per;
+    return j;
+  };
+  auto strip_base = [&](long j) {
+    const MapPtrs mp = a.maps[map_of(j)];
+    return (Tc*)(a.use_s64 ? mp.S64 : mp.S) + strip_of(j) * Cfg::COLS;
+  };
+
+  long j = next_active(blockIdx.x >> 3);
+  if (j >= count) return;
+  Vec<Tc, VEC> pre[Cfg::LOADS];
+  {
+    const Tc* S = strip_base(j);
+#pragma unroll
+    for (int k = 0; k < Cfg::LOADS; ++k) {
+      const int it = threadIdx.x + k * Cfg::THREADS;
+      pre[k] = *reinterpret_cast<const Vec<Tc, VEC>*>(S + (long)(it / VPR) * N + (it % VPR) * VEC);
+    }
+  }
+
+  int f = threadIdx.x / TPF;
+  if constexpr (TPF == 64) f = __builtin_amdgcn_readfirstlane(f);
+  const int t = threadIdx.x % TPF;
+#pragma unroll 1
+  while (true) {
+#pragma unroll
+    for (int k = 0; k < Cfg::LOADS; ++k) {
+      const int it = threadIdx.x + k * Cfg::THREADS;
+      const int y = it / VPR, jj = it % VPR;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) lds[tile_row<Cfg, N>(y) * P + jj * VEC + e] = pre[k].v[e];
+    }
+    __syncthreads();
+    const long jn = next_active(j + per);
+    if (jn < count) {
+      const Tc* Sn = strip_base(jn);
+#pragma unroll
+      for (int k = 0; k < Cfg::LOADS; ++k) {
+        const int it = threadIdx.x + k * Cfg::THREADS;
+        pre[k] = *reinterpret_cast<const Vec<Tc, VEC>*>(Sn + (long)(it / VPR) * N + (it % VPR) * VEC);
+      }
+    }
+
+    const int c0 = strip_of(j) * Cfg::COLS;
+#pragma unroll 1
+    for (int q = 0; q < NP; ++q) {
+      const int c = 2 * (f + Cfg::FFTS * q);
+      Tc zr[E], zi[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int y = tile_slot<Cfg, N>(t + TPF * m);
+        zr[m] = lds[y * P + c];
+        zi[m] = lds[y * P + c + 1];
+      }
+      fft_reg<Tc, N, -1, 1, CT, P>(zr, zi, lds + c, lds + c + 1, tw, t, twl);
+      Tc pr[E], pim[E];
+      partner<Tc, N, true>(zr, pr, t);
+      partner<Tc, N, true>(zi, pim, t);
+      const Vec<Tc, 4>* ca = reinterpret_cast<const Vec<Tc, 4>*>(coef) + (long)(c0 + c) * (N / 2 + 1);
+      const Vec<Tc, 4>* cb = ca + (N / 2 + 1);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int p = t + TPF * m;
+        const bool hi = m >= E / 2;
+        const int pi = hi ? N - p : p;
+        lambda_pair<Tc>(ca[pi], cb[pi], hi, zr[m], zi[m], pr[m], pim[m]);
+      }
+      wave_sync();
+      fft_reg<Tc, N, +1, 1, CT, P>(zr, zi, lds + c, lds + c + 1, tw, t, twl);
+      wave_sync();
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int y = tile_slot<Cfg, N>(t + TPF * m);
+        lds[y * P + c] = zr[m];
+        lds[y * P + c + 1] = zi[m];
+      }
+    }
+    __syncthreads();
+
+    Tc* S = strip_base(j);
+#pragma unroll
+    for (int k = 0; k < Cfg::LOADS; ++k) {
+      const int it = threadIdx.x + k * Cfg::THREADS;
+      const int y = it / VPR, jj = it % VPR;
+      Vec<Tc, VEC> v;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) v.v[e] = lds[tile_row<Cfg, N>(y) * P + jj * VEC + e];
+      *reinterpret_cast<Vec<Tc, VEC>*>(S + (long)y * N + jj * VEC) = v;
+    }
+    if (jn >= count) break;
+    __syncthreads();  // the stores' LDS reads are done before the next strip is written there
+    j = jn;
+  }
+}
+
+// Workgroups per CU of a pipelined instantiation (from its LDS and register use) and the CU
+// count, taken once per instantiation.
+template <typename K>
+int pipe_grid(K kernel, int threads) {
+  static int grid = 0;
+  if (!grid) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1)
+      return 0;
+    grid = (cus * per + 7) / 8 * 8;
+  }
+  return grid;
+}
+
+template <typename Tc, int N, int COLS, int PAIRS, bool CT>
+hipError_t col_pipe_launch(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, hipStream_t s) {
+  using Cfg = ColCfg<Tc, N, COLS, PAIRS, true>;
+  if (a.n != N || a.ny != N) return hipErrorInvalidValue;  // square maps only
+  const Cx<Tc>* twl = nullptr;
+  if constexpr (CT) {
+    twl = (const Cx<Tc>*)a.twc.tw32lo;
+    if (!twl) return hipErrorInvalidValue;
+  }
+  auto k = col_pipe_kernel<Tc, N, COLS, PAIRS, CT>;
+  int grid = pipe_grid(k, Cfg::THREADS);
+  if (grid <= 0) return hipErrorInvalidConfiguration;
+  const long tiles = (long)(N / Cfg::COLS) * a.n_maps;
+  if (tiles < grid) grid = (int)((tiles + 7) / 8 * 8);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(Cfg::THREADS), 0, s, a, coef, tw, twl);
+  return hipGetLastError();
+}
+
 // Strip-width candidates: 0 = the default width, 1 = the default width with two column pairs
 // per transform group (half the wavefronts, each taking its pairs from the tile in turn), 2 =
 // half the default width, 3 / 4 = the wide in-place strip (128-byte row segments where two
-// workgroups' tiles fit one CU's LDS) with one / two pairs per transform group.
+// workgroups' tiles fit one CU's LDS) with one / two pairs per transform group, 5 / 6 = the
+// pipelined pass on 128-byte strips with two / four pairs per transform group (where the strips
+// split over the 8 XCDs; otherwise candidate 0).
 template <typename Tc, int N>
 constexpr int col_wide() {
   int c = 128 / (int)sizeof(Tc);
@@ -232,9 +412,26 @@ template <typename Tc, int N, int V, bool CT>
 hipError_t col_launch_v(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   return col_launch<Tc, N, col_candidate<Tc, N, V>(), col_pairs<V>(), true, CT, col_inplace<V>()>(a, coef, tw, qw, s);
 }
+template <int V>
+constexpr int pipe_pairs() {
+  return V == 5 ? 2 : 4;
+}
+template <typename Tc, int N, int V>
+constexpr bool pipe_ok() {
+  return V >= 5 && (N / pipe_cols<Tc, N>()) % 8 == 0 && N / pipe_cols<Tc, N>() >= 8;
+}
+template <typename Tc, int N, int V, bool CT>
+hipError_t col_pipe_v(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+  if constexpr (pipe_ok<Tc, N, V>())
+    return col_pipe_launch<Tc, N, pipe_cols<Tc, N>(), pipe_pairs<V>(), CT>(a, coef, tw, s);
+  else
+    return col_launch_v<Tc, N, 0, CT>(a, coef, tw, qw, s);
+}
 template <typename Tc, int N, bool CT>
 hipError_t col_variant_ct(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   switch (v) {
+    case 5: return col_pipe_v<Tc, N, 5, CT>(a, coef, tw, qw, s);
+    case 6: return col_pipe_v<Tc, N, 6, CT>(a, coef, tw, qw, s);
     case 0: return col_launch_v<Tc, N, 0, CT>(a, coef, tw, qw, s);
     case 1: return col_launch_v<Tc, N, 1, CT>(a, coef, tw, qw, s);
     case 2: return col_launch_v<Tc, N, 2, CT>(a, coef, tw, qw, s);
@@ -270,6 +467,8 @@ hipError_t col_dispatch_n(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>
 template <typename Tc, int N>
 int col_cols_of(int v) {
   switch (v) {
+    case 5: return pipe_ok<Tc, N, 5>() ? pipe_cols<Tc, N>() : col_candidate<Tc, N, 0>();
+    case 6: return pipe_ok<Tc, N, 6>() ? pipe_cols<Tc, N>() : col_candidate<Tc, N, 0>();
     case 0: return col_candidate<Tc, N, 0>();
     case 1: return col_candidate<Tc, N, 1>();
     case 2: return col_candidate<Tc, N, 2>();
@@ -282,9 +481,18 @@ template <typename Tc, int N, int V>
 constexpr int col_pairs_eff() {
   return ColCfg<Tc, N, col_candidate<Tc, N, V>(), col_pairs<V>(), col_inplace<V>()>::PAIRS;
 }
+template <typename Tc, int N, int V>
+constexpr int pipe_pairs_eff() {
+  if constexpr (pipe_ok<Tc, N, V>())
+    return ColCfg<Tc, N, pipe_cols<Tc, N>(), pipe_pairs<V>(), true>::PAIRS;
+  else
+    return col_pairs_eff<Tc, N, 0>();
+}
 template <typename Tc, int N>
 int col_pairs_of(int v) {
   switch (v) {
+    case 5: return pipe_pairs_eff<Tc, N, 5>();
+    case 6: return pipe_pairs_eff<Tc, N, 6>();
     case 0: return col_pairs_eff<Tc, N, 0>();
     case 1: return col_pairs_eff<Tc, N, 1>();
     case 2: return col_pairs_eff<Tc, N, 2>();
@@ -311,6 +519,19 @@ int col_pass_pairs(int compute, int n, int variant) {
     case 256: return f ? col_pairs_of<float, 256>(variant) : col_pairs_of<double, 256>(variant);
     case 512: return f ? col_pairs_of<float, 512>(variant) : col_pairs_of<double, 512>(variant);
     case 1024: return f ? col_pairs_of<float, 1024>(variant) : col_pairs_of<double, 1024>(variant);
+    default: return 0;
+  }
+}
+
+int col_pass_pipelined(int compute, int n, int variant) {
+  const bool f = compute == VARSIM_F32;
+  if (variant != 5 && variant != 6) return 0;
+  const bool six = variant == 6;
+  switch (n) {
+#define VS_PIPE_OK(NN) \
+  case NN: return f ? (six ? pipe_ok<float, NN, 6>() : pipe_ok<float, NN, 5>()) : (six ? pipe_ok<double, NN, 6>() : pipe_ok<double, NN, 5>());
+    VS_PIPE_OK(16) VS_PIPE_OK(32) VS_PIPE_OK(64) VS_PIPE_OK(128) VS_PIPE_OK(256) VS_PIPE_OK(512) VS_PIPE_OK(1024)
+#undef VS_PIPE_OK
     default: return 0;
   }
 }

@@ -85,12 +85,15 @@ hipError_t launch_row_pass(int mode, int io, int compute, const PassArgs& a, hip
 hipError_t launch_row_pass_ct(int mode, const PassArgs& a, hipStream_t stream);
 // coef: the column-pass coefficient table of the compute type; variant: launch-shape candidate
 // 0 (default strip width), 1 (default width, two column pairs per transform group), 2 (half
-// width); col_pass_columns / col_pass_pairs give a candidate's strip width and pairs per group
-constexpr int kColVariants = 5;
+// width), 3 / 4 (wide in-place strip, one / two pairs), 5 / 6 (pipelined 128-byte strips, two /
+// four pairs); col_pass_columns / col_pass_pairs give a candidate's strip width and pairs per
+// group, col_pass_pipelined whether it runs as the pipelined pass
+constexpr int kColVariants = 7;
 constexpr int kMaxGraphIterations = 16;  // fixed-point iterations one captured graph may hold
 hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream, int variant = 0);
 int col_pass_columns(int compute, int n, int variant);
 int col_pass_pairs(int compute, int n, int variant);
+int col_pass_pipelined(int compute, int n, int variant);
 
 // Static inputs: QL = q_leak0 * v, MINV = 1 / m (per map), warm-start screening and copy.
 struct PrepArgs {

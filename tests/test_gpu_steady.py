@@ -484,7 +484,7 @@ def test_column_strip_widths_give_identical_results(ctx, n):
     opts = _opts(V.F32, inp, 50, 1e-3, res=True)
     convs, maps = [], []
     try:
-        for v in range(5):
+        for v in range(7):
             ctx.force_col_variant(v)
             convs.append(ctx.conv(die, p).cpu())
             item = gpu_item(inp, torch.float32)
