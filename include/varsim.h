@@ -460,19 +460,23 @@ VARSIM_API varsim_status varsim_set_graph_iterations(varsim_ctx* ctx, int32_t it
  * loading the next strip while transforming the current one), two / four pairs per group,
  * where the strips split evenly over the 8 XCDs (else candidate 0); square maps only,
  * rectangular ones keep 0), and transient solves use row-pass candidate `variant` and column
- * candidate `variant` (see varsim_force_transient_variant; variant 6 leaves them at their
- * default); -1 returns to the default or tuned choices.  VARSIM_ERR_INVALID outside [-1, 6]. */
+ * candidate `variant` where N has that candidate (see varsim_force_transient_variant; else
+ * their default); -1 returns to the default or tuned choices.  VARSIM_ERR_INVALID outside
+ * [-1, 6]. */
 VARSIM_API varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t variant);
 /* Testing / manual tuning of transient solves: row-pass candidate `row_variant` and column-pass
- * candidate `col_variant`, each in [0, 6): 0..2 transform two rows (columns) per DFT (row: rows
+ * candidate `col_variant`, each in [0, 8): 0..2 transform two rows (columns) per DFT (row: rows
  * per workgroup default / half / one pair; column: strip width default / half / quarter); 3..5
  * transform one row (column) per DFT of half the length (row: 1 / 2 / 4 wavefronts per
- * workgroup; column: widest strip / half / quarter), available for N >= 64 (an N below that
- * falls back to candidate 0).  Results agree to rounding.  -1 returns to the tuned, forced
- * (varsim_force_col_variant) or default choice (candidate 3 for both passes where N >= 64, else
- * 0; with autotuning on, the (row, column) pairs of the one-sequence family (of the
- * two-sequence family where N < 64) are timed over whole steps on the first solve of each
- * (N, precision) and the fastest pair kept).  VARSIM_ERR_INVALID outside [-1, 6). */
+ * workgroup; column: widest strip / half / quarter), available for N >= 64; 6..7 spread each
+ * row (column) over two wavefronts, the half-length DFT split into two quarter-length DFTs of
+ * the even and the odd coefficients (row: 1 / 2 rows per workgroup; column: 4 / 2 columns per
+ * strip), available for N = 1024.  A candidate N does not have falls back to candidate 0.
+ * Results agree to rounding.  -1 returns to the tuned, forced (varsim_force_col_variant) or
+ * default choice (candidate 3 for both passes where N >= 64, else 0; with autotuning on, the
+ * (row, column) pairs of the one-sequence families (of the two-sequence family where N < 64)
+ * are timed over whole steps on the first solve of each (N, precision) and the fastest pair
+ * kept).  VARSIM_ERR_INVALID outside [-1, 8). */
 VARSIM_API varsim_status varsim_force_transient_variant(varsim_ctx* ctx, int32_t row_variant,
                                                         int32_t col_variant);
 

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libvarsim.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["table.hip", "steady.hip", "steady_ct.hip", "small.hip", "colpass.hip", "transient.hip", "transient1.hip", "nn.hip", "api.hip", "net.hip"]
+SOURCES = ["table.hip", "steady.hip", "steady_ct.hip", "small.hip", "colpass.hip", "transient.hip", "transient1.hip", "transient2.hip", "nn.hip", "api.hip", "net.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-function",

@@ -1343,7 +1343,7 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
   int rv = nv > 3 ? 3 : 0, cv = rv;  // untuned default: one-sequence passes where available
   const auto key = std::make_pair(g->nx, io);
   auto it = ctx->tr_choice.find(key);
-  if (ctx->force_col >= 0 && ctx->force_col < kTrVariants) {
+  if (ctx->force_col >= 0 && ctx->force_col < nv) {
     rv = cv = ctx->force_col;
   } else if (it != ctx->tr_choice.end()) {
     rv = it->second.first;
@@ -1357,7 +1357,8 @@ varsim_status varsim_solve_transient(varsim_ctx* ctx, const varsim_problem* prob
     // Candidates are timed inside whole steps (column pass + row pass, as the solve runs them),
     // every (row, column) pair of one pass family, since the best row pass depends on the column
     // pass before it; each pair over 60 steps, two rounds, the faster round kept, after a long
-    // untimed burst.  Where the one-sequence passes exist (n >= 64) only their pairs are timed:
+    // untimed burst.  Where the one-sequence passes exist (n >= 64) only their pairs are timed
+    // (with the split one-sequence passes where those exist, n = 1024):
     // they were the faster family in every long solve measured, while short timed bursts that
     // follow other GPU work (steady solves in the same process) can rank the two families the
     // other way round (the two-sequence rows measured faster in the bursts and ran 1.18x slower

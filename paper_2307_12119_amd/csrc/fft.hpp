@@ -74,9 +74,11 @@ __device__ __forceinline__ double lane_get(double v, int src) {
 
 // out[m] = element N - (t + TPF m) of the group's sequence held in own[] (lane-reversed).
 // PERIODIC: index N means 0 (a DFT); otherwise element N is taken as 0 (a cosine spectrum).
-template <typename T, int N, bool PERIODIC>
+// EL: elements per lane (default: the transform's own shape; a smaller EL spreads the sequence
+// over TPF = N / EL <= 64 lanes)
+template <typename T, int N, bool PERIODIC, int EL = Shape<N>::E>
 __device__ __forceinline__ void partner(const T* own, T* out, int t) {
-  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
+  constexpr int E = EL, TPF = N / EL;
   const int lane = __lane_id();
   const int src = (lane & ~(TPF - 1)) + ((TPF - t) & (TPF - 1));
   const bool head = t == 0;
@@ -265,11 +267,12 @@ __device__ __forceinline__ void dft_r(T* r, T* i) {
 // tw[TS k] = exp(-2 pi i k / N): TS = 1 with the table of N, TS = 2 with the table of 2N.
 // CT: twl holds the low parts of the same twiddles (compensated twiddles).  LS: element stride
 // of the LDS buffer (1: re / im contiguous; > 1: a column of a row-major tile of pitch LS).
-template <typename T, int N, int NS, int DIR, int TS = 1, bool CT = false, int LS = 1>
+template <typename T, int N, int NS, int DIR, int TS = 1, bool CT = false, int LS = 1, int EL = Shape<N>::E>
 __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx<T>* __restrict__ tw, int t,
                                             const Cx<T>* __restrict__ twl = nullptr) {
-  constexpr int E = Shape<N>::E, TPF = Shape<N>::TPF;
-  constexpr int R = (N / NS >= 8) ? 8 : (N / NS);
+  constexpr int E = EL, TPF = N / EL;
+  constexpr int R0 = (N / NS >= 8) ? 8 : (N / NS);
+  constexpr int R = R0 < E ? R0 : E;  // the radix never exceeds the elements a lane holds
   constexpr int NB = N / R, PER = E / R;
   constexpr bool LAST = NS * R == N;
   T yr[E], yi[E];
@@ -321,17 +324,17 @@ __device__ __forceinline__ void stages_from(T* xr, T* xi, T* re, T* im, const Cx
   }
   if constexpr (!LAST) {
     wave_sync();
-    stages_from<T, N, NS * R, DIR, TS, CT, LS>(xr, xi, re, im, tw, t, twl);
+    stages_from<T, N, NS * R, DIR, TS, CT, LS, EL>(xr, xi, re, im, tw, t, twl);
   }
 }
 
 // Unnormalised DFT (DIR = -1) or inverse DFT (DIR = +1) of the group's sequence, slot m of lane
 // t holding element t + TPF m on entry and on exit.  (re, im): this group's LDS buffer; the
 // caller must have finished its own reads of that buffer (wave_sync) before the call.
-template <typename T, int N, int DIR, int TS = 1, bool CT = false, int LS = 1>
+template <typename T, int N, int DIR, int TS = 1, bool CT = false, int LS = 1, int EL = Shape<N>::E>
 __device__ __forceinline__ void fft_reg(T* xr, T* xi, T* re, T* im, const Cx<T>* __restrict__ tw, int t,
                                         const Cx<T>* __restrict__ twl = nullptr) {
-  constexpr int E = Shape<N>::E;
+  constexpr int E = EL;
   dft_r<T, E, DIR, CT>(xr, xi);
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -340,7 +343,7 @@ __device__ __forceinline__ void fft_reg(T* xr, T* xi, T* re, T* im, const Cx<T>*
     im[s * LS] = xi[r];
   }
   wave_sync();
-  stages_from<T, N, E, DIR, TS, CT, LS>(xr, xi, re, im, tw, t, twl);
+  stages_from<T, N, E, DIR, TS, CT, LS, EL>(xr, xi, re, im, tw, t, twl);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -184,14 +184,18 @@ hipError_t launch_block_ids(const int* rects, int n_blocks, int* ids, int nx, in
 // variant: launch-shape candidate.  0..2: two sequences per transform (row: rows per workgroup
 // default / half / one pair; column: strip width default / half / quarter); 3..5: one sequence
 // per transform (row: 1 / 2 / 4 wavefronts per workgroup; column: widest strip / half /
-// quarter), available where transient_single_ok(n).
-constexpr int kTrVariants = 6;
+// quarter), available where transient_single_ok(n); 6..7: one sequence over two wavefronts
+// (row: 1 / 2 rows per workgroup; column: 4 / 2 columns per strip), where transient_split_ok(n).
+constexpr int kTrVariants = 8;
 bool transient_single_ok(int n);
+bool transient_split_ok(int n);
 int transient_variants(int n);
 hipError_t launch_transient_row(int mode, int io, const TransArgs& a, int step, hipStream_t stream, int variant = 0);
 hipError_t launch_transient_col(int io, const TransArgs& a, hipStream_t stream, int variant = 0);
 hipError_t launch_transient_row1(int mode, int io, const TransArgs& a, int step, hipStream_t stream, int variant);
 hipError_t launch_transient_col1(int io, const TransArgs& a, hipStream_t stream, int variant);
+hipError_t launch_transient_row2(int mode, int io, const TransArgs& a, int step, hipStream_t stream, int variant);
+hipError_t launch_transient_col2(int io, const TransArgs& a, hipStream_t stream, int variant);
 // dst[row][2j + k] = src[row][z_sample(j, k)] for an n x n array of esz-byte elements
 hipError_t launch_zorder(int esz, const void* src, void* dst, int n, hipStream_t stream);
 hipError_t launch_map_stats(int io, const void* dT, long cells, const unsigned* flags, int steps, varsim_stats* out,

@@ -111,4 +111,131 @@ __device__ __forceinline__ void dct3_single(T* zr, T* zi, T* re, T* im, const Cx
   fft_reg<T, M, +1, 2>(zr, zi, re, im, tw, t);
 }
 
+// ---------------------------------------------------------------------------------------
+// The same transforms with the DFT of length M split over two wavefronts (radix 2 in
+// frequency): with H = M / 2,
+//     Z[2k]     = DFT_H(z[j] + z[j + H])[k]
+//     Z[2k + 1] = DFT_H((z[j] - z[j + H]) W_M^j)[k],
+// so wavefront h = 0 transforms a[j] = z[j] + z[j + H] into the even-indexed spectrum and h = 1
+// transforms b[j] = (z[j] - z[j + H]) W_M^j into the odd one, each lane holding EL = H / 64
+// elements (j = t + 64 m).  The split into cosine coefficients pairs Z[p] with Z[M - p], which
+// lies in the same half (even p: element (H - k) mod H of wavefront 0; odd p: element H - 1 - k
+// of wavefront 1), so each wavefront finishes its half of the coefficients on its own:
+// wavefront h ends with (X[p], X[hi(p)]) for p = 2 (t + 64 m) + h.  The inverse runs the same
+// steps backwards: wavefront 0 returns A[j] = IDFT_H of the even half, wavefront 1
+// B[j] = W_M^-j IDFT_H of the odd half, and z[j] = A[j] + B[j], z[j + H] = A[j] - B[j]
+// (combined by the caller through LDS).  One sequence then occupies two wavefronts, which
+// halves each wavefront's serial chain where a single map cannot fill the chip.
+template <int N>
+struct SplitShape {
+  static constexpr int M = N / 2, H = N / 4, EL = H / 64, TS = N / H;
+  static_assert(EL >= 2 && EL * 64 == H, "one sequence half per wavefront of 64 lanes");
+};
+
+// element E-1-m of lane 63-t: H - 1 - (t + 64 m) of the wavefront's sequence
+template <typename T, int EL>
+__device__ __forceinline__ void reversed(const T* own, T* out, int t) {
+#pragma unroll
+  for (int m = 0; m < EL; ++m) out[m] = lane_get(own[EL - 1 - m], 63 - t);
+}
+
+// (zr, zi): a[j] (h = 0) or b[j] (h = 1) at j = t + 64 m -> (X[p], X[hi(p)]), p = 2 (t + 64 m) + h
+template <typename T, int N>
+__device__ __forceinline__ void dct2_split(T* zr, T* zi, T* re, T* im, const Cx<T>* __restrict__ tw,
+                                           const Cx<T>* __restrict__ qw, int t, int h) {
+  using Sh = SplitShape<N>;
+  constexpr int H = Sh::H, EL = Sh::EL;
+  wave_sync();
+  fft_reg<T, H, -1, Sh::TS, false, 1, EL>(zr, zi, re, im, tw, t);
+  T cr[EL], ci[EL];
+  if (h == 0) {
+    partner<T, H, true, EL>(zr, cr, t);
+    partner<T, H, true, EL>(zi, ci, t);
+  } else {
+    reversed<T, EL>(zr, cr, t);
+    reversed<T, EL>(zi, ci, t);
+  }
+  const bool head = h == 0 && t == 0;
+#pragma unroll
+  for (int m = 0; m < EL; ++m) {
+    const int p = 2 * (t + 64 * m) + h;
+    const T evr = (T)0.5 * (zr[m] + cr[m]), evi = (T)0.5 * (zi[m] - ci[m]);
+    const T odr = (T)0.5 * (zi[m] + ci[m]), odi = (T)0.5 * (cr[m] - zr[m]);
+    const Cx<T> w = tw[p];
+    const T vr = evr + dot2(w.r, odr, -w.i, odi);
+    const T vi = evi + dot2(w.r, odi, w.i, odr);
+    const Cx<T> q = qw[p];
+    zr[m] = dot2(q.r, vr, q.i, vi);
+    T hi = dot2(q.i, vr, -q.r, vi);
+    if (m == 0) hi = head ? (evr - odr) * (T)0.70710678118654752440 : hi;
+    zi[m] = hi;
+  }
+}
+
+// (X[p], X[hi(p)]), p = 2 (t + 64 m) + h -> A[j] (h = 0) or B[j] (h = 1) at j = t + 64 m
+template <typename T, int N>
+__device__ __forceinline__ void dct3_split(T* zr, T* zi, T* re, T* im, const Cx<T>* __restrict__ tw,
+                                           const Cx<T>* __restrict__ qw, int t, int h) {
+  using Sh = SplitShape<N>;
+  constexpr int H = Sh::H, EL = Sh::EL;
+  const bool head = h == 0 && t == 0;
+  T vr[EL], vi[EL];
+  const T vm = (T)1.41421356237309504880 * zi[0];
+#pragma unroll
+  for (int m = 0; m < EL; ++m) {
+    const Cx<T> q = qw[2 * (t + 64 * m) + h];
+    vr[m] = dot2(q.r, zr[m], q.i, zi[m]);
+    vi[m] = dot2(q.i, zr[m], -q.r, zi[m]);
+  }
+  vi[0] = head ? (T)0 : vi[0];
+  T cr[EL], ci[EL];
+  if (h == 0) {
+    partner<T, H, true, EL>(vr, cr, t);
+    partner<T, H, true, EL>(vi, ci, t);
+  } else {
+    reversed<T, EL>(vr, cr, t);
+    reversed<T, EL>(vi, ci, t);
+  }
+#pragma unroll
+  for (int m = 0; m < EL; ++m) {
+    const int p = 2 * (t + 64 * m) + h;
+    T gr = cr[m], gi = -ci[m];
+    if (m == 0) {
+      gr = head ? vm : gr;
+      gi = head ? (T)0 : gi;
+    }
+    const T sr = vr[m] + gr, si = vi[m] + gi;
+    const T dr = vr[m] - gr, di = vi[m] - gi;
+    const Cx<T> w = tw[p];
+    zr[m] = sr - dot2(w.r, di, -w.i, dr);
+    zi[m] = si + dot2(w.r, dr, w.i, di);
+  }
+  wave_sync();
+  fft_reg<T, H, +1, Sh::TS, false, 1, EL>(zr, zi, re, im, tw, t);
+  if (h == 1) {
+#pragma unroll
+    for (int m = 0; m < EL; ++m) {
+      const Cx<T> w = tw[2 * (t + 64 * m)];  // W_M^j; multiplied by its conjugate
+      const T r = zr[m], i = zi[m];
+      zr[m] = dot2(w.r, r, w.i, i);
+      zi[m] = dot2(w.r, i, -w.i, r);
+    }
+  }
+}
+
+// a[j] (h = 0) or b[j] (h = 1) from z[j] = (ar, ai) and z[j + H] = (br, bi) at j = t + 64 m
+template <typename T, int N>
+__device__ __forceinline__ void split_inputs(T& zr, T& zi, T ar, T ai, T br, T bi, int j, int h,
+                                             const Cx<T>* __restrict__ tw) {
+  if (h == 0) {
+    zr = ar + br;
+    zi = ai + bi;
+  } else {
+    const Cx<T> w = tw[2 * j];  // W_M^j
+    const T dr = ar - br, di = ai - bi;
+    zr = dot2(dr, w.r, -di, w.i);
+    zi = dot2(dr, w.i, di, w.r);
+  }
+}
+
 }  // namespace vs

@@ -521,15 +521,17 @@ hipError_t launch_block_ids(const int* rects, int n_blocks, int* ids, int nx, in
   return hipGetLastError();
 }
 
-int transient_variants(int n) { return transient_single_ok(n) ? kTrVariants : 3; }
+int transient_variants(int n) { return transient_split_ok(n) ? kTrVariants : transient_single_ok(n) ? 6 : 3; }
 
 hipError_t launch_transient_row(int mode, int io, const TransArgs& a, int step, hipStream_t stream, int variant) {
+  if (variant >= 6) return launch_transient_row2(mode, io, a, step, stream, variant - 6);
   if (variant >= 3) return launch_transient_row1(mode, io, a, step, stream, variant - 3);
   return io == VARSIM_F32 ? tr_dispatch<float>(0, mode, variant, a.n, a, step, stream)
                           : tr_dispatch<double>(0, mode, variant, a.n, a, step, stream);
 }
 
 hipError_t launch_transient_col(int io, const TransArgs& a, hipStream_t stream, int variant) {
+  if (variant >= 6) return launch_transient_col2(io, a, stream, variant - 6);
   if (variant >= 3) return launch_transient_col1(io, a, stream, variant - 3);
   return io == VARSIM_F32 ? tr_dispatch<float>(1, 0, variant, a.n, a, 0, stream)
                           : tr_dispatch<double>(1, 0, variant, a.n, a, 0, stream);

@@ -270,50 +270,14 @@ __global__ void __launch_bounds__((TrCol1Cfg<Tc, N, COLS>::THREADS))
       s1[m] = st[h];
     }
   }
-  // per-mode update theta_hat = a theta_hat + b P_hat at modes p and hi(p); further poles of the
-  // multi-pole model keep their states in planes of N^2 and add to the mode's rise (pole 0 first).
-  // Truncated history: the spectrum of h - 1 steps ago leaves the ring slot this step's enters.
+  // per-mode update at modes p and hi(p) (mode_step: further poles, truncated history)
   Tc* rg = FIR ? (Tc*)a.ring + (long)a.slot * N * N + (long)q * N : nullptr;
   const Tc* fc = FIR ? (const Tc*)a.fir + (long)q * N : nullptr;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int p = t + TPF * m, h = spec_hi<N>(p);
-    const Tc P0 = zr[m], P1 = zi[m];
-    Tc o0 = 0, o1 = 0;
-    if constexpr (FIR) {
-      o0 = rg[p];
-      o1 = rg[h];
-      rg[p] = P0;
-      rg[h] = P1;
-    }
-    Tc n0 = dot2(k0[m].v[0], s0[m], k0[m].v[1], P0);
-    Tc n1 = dot2(k1[m].v[0], s1[m], k1[m].v[1], P1);
-    if constexpr (FIR) {
-      n0 = fma(fc[p], o0, n0);
-      n1 = fma(fc[h], o1, n1);
-    }
-    st[p] = n0;
-    st[h] = n1;
-    for (int j = 1; j < a.poles; ++j) {
-      Tc* sj = st + (long)j * N * N;
-      const Vec<Tc, 2> kj0 = ab[(long)j * N * N + p], kj1 = ab[(long)j * N * N + h];
-      Tc u0 = dot2(kj0.v[0], sj[p], kj0.v[1], P0);
-      Tc u1 = dot2(kj1.v[0], sj[h], kj1.v[1], P1);
-      if constexpr (FIR) {
-        u0 = fma(fc[(long)j * N * N + p], o0, u0);
-        u1 = fma(fc[(long)j * N * N + h], o1, u1);
-      }
-      sj[p] = u0;
-      sj[h] = u1;
-      n0 += u0;
-      n1 += u1;
-    }
-    if constexpr (FIR) {  // the saturated step response on the leaving spectrum
-      n0 = fma(fc[(long)a.poles * N * N + p], o0, n0);
-      n1 = fma(fc[(long)a.poles * N * N + h], o1, n1);
-    }
-    zr[m] = n0;
-    zi[m] = n1;
+    zr[m] = mode_step<Tc, FIR>(zr[m], k0[m], s0[m], st, ab, rg, fc, (long)N * N, a.poles, p);
+    zi[m] = mode_step<Tc, FIR>(zi[m], k1[m], s1[m], st, ab, rg, fc, (long)N * N, a.poles, h);
   }
   dct3_single<Tc, N>(zr, zi, re, im, tw, qw, t);
   __syncthreads();

@@ -77,4 +77,33 @@ __device__ __forceinline__ void add_leakage_n(Tc* q, const Tc* ql, const Tc* dT,
   }
 }
 
+// One mode's state update in the column pass (Eqs. tranGreen, tranapprox): theta_hat = a theta_hat
+// + b P_hat for the first pole ((a, b) in k and its state s already loaded); further poles of the
+// multi-pole model keep their states and (a, b) in planes of `plane` values (pole j at st, ab
+// + j plane) and add to the mode's rise; with a truncated history (FIR) the spectrum of h - 1
+// steps ago leaves ring slot rg[p] as this step's P_hat enters, weighted by the per-pole FIR
+// coefficients and finally the saturated part (fc planes 0..poles).  Returns the mode's rise.
+template <typename Tc, bool FIR>
+__device__ __forceinline__ Tc mode_step(Tc P, Vec<Tc, 2> k, Tc s, Tc* st, const Vec<Tc, 2>* ab, Tc* rg,
+                                        const Tc* fc, long plane, int poles, int p) {
+  Tc o = 0;
+  if constexpr (FIR) {
+    o = rg[p];
+    rg[p] = P;
+  }
+  Tc n = dot2(k.v[0], s, k.v[1], P);
+  if constexpr (FIR) n = fma(fc[p], o, n);
+  st[p] = n;
+  for (int j = 1; j < poles; ++j) {
+    Tc* sj = st + (long)j * plane;
+    const Vec<Tc, 2> kj = ab[(long)j * plane + p];
+    Tc u = dot2(kj.v[0], sj[p], kj.v[1], P);
+    if constexpr (FIR) u = fma(fc[(long)j * plane + p], o, u);
+    sj[p] = u;
+    n += u;
+  }
+  if constexpr (FIR) n = fma(fc[(long)poles * plane + p], o, n);  // the saturated step response
+  return n;
+}
+
 }  // namespace vs

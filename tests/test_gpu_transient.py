@@ -197,7 +197,7 @@ def test_transient_one_row_passes_fp32_match_oracle(ctx):
     assert np.max(np.abs(last - ref_last)) <= FP32_GATE_K
 
 
-@pytest.mark.parametrize("rv_cv", [(0, 0), (3, 3)], ids=["pair", "one-row"])
+@pytest.mark.parametrize("rv_cv", [(0, 0), (3, 3), (6, 6), (7, 7)], ids=["pair", "one-row", "split", "split-2"])
 @pytest.mark.parametrize("dtype_name", ["float64", "float32"])
 @pytest.mark.parametrize("eta", [0.0, 1.3])
 def test_transient_uniform_power_closed_form_1024(ctx, dtype_name, eta, rv_cv):
@@ -241,7 +241,8 @@ def test_transient_long_time_reaches_steady_fixed_point(ctx):
     assert np.max(np.abs(last - ref)) <= 1e-9 * np.max(ref)
 
 
-@pytest.mark.parametrize("rv_cv", [(0, 0), (3, 3), (4, 5)], ids=["pair", "one-row", "one-row-narrow"])
+@pytest.mark.parametrize("rv_cv", [(0, 0), (3, 3), (4, 5), (6, 6), (7, 7), (6, 4)],
+                         ids=["pair", "one-row", "one-row-narrow", "split", "split-2", "split-row-one-row-col"])
 def test_transient_full_size_sampled(ctx, rv_cv):
     """1024 x 1024, FP32, leakage + variation: at sampled cells the recorded rise of the last step
     equals the oracle's superposition of the power history rebuilt from the recorded rises."""
@@ -274,6 +275,71 @@ def test_transient_full_size_sampled(ctx, rv_cv):
     assert np.all(ok)
     assert np.max(np.abs(last[rows, cols] - expect)) <= FP32_GATE_K
     assert np.max(expect) > 1.0
+
+
+def test_transient_split_passes_fp64_1024(ctx):
+    """1024 x 1024, FP64, leakage + variation: the passes that spread each row (column) over two
+    wavefronts (candidates 6, 7, alone and mixed with the one-wavefront passes) agree with the
+    one-wavefront passes to rounding, also with two poles per mode and with a truncated history,
+    and the last step equals the oracle's superposition at sampled cells to 1e-9 of the max rise."""
+    import torch
+    from paper_2307_12119_amd import varsim as V
+
+    n, steps, dt = 1024, 8, 50e-6
+    inp = W.transient_problem(n=n, n_steps=steps, dt_s=dt, n_blocks=64, hold_s=2 * dt, seed=5)
+
+    def run(rv_cv, **kw):
+        with _variants(ctx, rv_cv):
+            st, rec, last = _run_gpu(ctx, inp, torch.float64, out_every=1, **kw)
+        assert st["status"] == 0
+        return rec, last
+
+    base_rec, base = run((3, 3))
+    scale = np.max(np.abs(base))
+    for rv_cv in ((6, 6), (7, 7), (6, 3), (3, 7)):
+        rec, last = run(rv_cv)
+        assert np.max(np.abs(rec - base_rec)) <= 1e-12 * scale, rv_cv
+    for kw in ({"history_steps": 4}, {"tau": "lumped"}):
+        ref_rec, _ = run((3, 3), **kw)
+        rec, _ = run((6, 6), **kw)
+        assert np.max(np.abs(rec - ref_rec)) <= 1e-12 * np.max(np.abs(ref_rec)), kw
+    # two poles per mode (the multi-pole model) through the binding's modal option
+    item_kw = dict(n_poles=2)
+    outs = []
+    for rv_cv in ((3, 3), (6, 6)):
+        dtype = torch.float64
+        item = {"die": die_of(inp), "q_leak0": to_dev(inp.q_leak0, dtype), "leak_var": to_dev(inp.leak_var, dtype),
+                "cond_map": to_dev(inp.cond_map, dtype), "dT_out": torch.zeros((n, n), dtype=dtype, device="cuda")}
+        snaps = torch.zeros((steps, n, n), dtype=dtype, device="cuda")
+        opts = V.make_options(V.F64, V.LEAK_EXP, inp.beta, 1, 1e-3)
+        with _variants(ctx, rv_cv):
+            st = ctx.solve_transient(item, to_dev(inp.block_rects, torch.int32), to_dev(inp.trace, dtype), dt, opts,
+                                     snaps, 1, tau_model=V.TAU_MODAL, **item_kw)
+        assert st["status"] == 0
+        outs.append(snaps.cpu().numpy())
+    assert np.max(np.abs(outs[1] - outs[0])) <= 1e-12 * np.max(np.abs(outs[0]))
+    # the oracle's superposition at sampled cells, power history rebuilt from the split run
+    rec, last = run((6, 6))
+    g = S.geometry_from_die(inp.die, n)
+    model = T.TransientModel(g, inp.die.rho_c)
+    ql = inp.q_leak0 * inp.leak_var
+    hist = [np.zeros((n, n))]
+    prev = np.zeros((n, n))
+    for k in range(steps):
+        q = W.raster_trace_step(inp.block_rects, inp.trace[k], n) + ql * np.exp(inp.beta * prev)
+        hist.append(g.hx * g.hy * q / inp.cond_map)
+        prev = rec[k]
+    rng = np.random.default_rng(12)
+    hot = np.unravel_index(int(np.argmax(last)), last.shape)
+    rows = np.concatenate([[0, n - 1, hot[0], 511, 512], rng.integers(0, n, 10)])
+    cols = np.concatenate([[0, n - 1, hot[1], 512, 511], rng.integers(0, n, 10)])
+    theta = np.zeros(len(rows))
+    for j in range(1, steps + 1):
+        op = S.DirectSum(g, table=model.step_kernel(j * dt))
+        theta += op.apply_at(hist[steps - j + 1] - hist[steps - j], rows, cols)
+    expect, ok = S.kirchhoff_inverse(theta, g.t_amb, g.eta)
+    assert np.all(ok)
+    assert np.max(np.abs(last[rows, cols] - expect)) <= FP64_GATE_REL * np.max(last)
 
 
 def test_transient_statuses_and_edges(ctx):
@@ -424,7 +490,7 @@ def test_transient_truncated_history_fp64_matches_oracle(ctx, n, h, tau, poles, 
     assert np.max(np.abs(got - rec)) <= FP64_GATE_REL * np.max(rec)
 
 
-@pytest.mark.parametrize("rv_cv", [(0, 0), (3, 3)], ids=["pair", "one-row"])
+@pytest.mark.parametrize("rv_cv", [(0, 0), (3, 3), (6, 6)], ids=["pair", "one-row", "split"])
 @pytest.mark.parametrize("dtype_name", ["float64", "float32"])
 def test_transient_truncated_history_uniform_pulse_1024(ctx, dtype_name, rv_cv):
     """Uniform power on for 6 steps, then off, history cut at h = 9: the rise at step n is
