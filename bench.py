@@ -28,13 +28,13 @@ METRIC = "converged 512² thermal maps/s at ≤0.05 K max err; surrogate vs plai
 HBM_PEAK_GBS = 8000.0
 
 
-def _sample(i: int, n: int, fft_workers: int = 1):
+def _sample(i: int, n: int, fft_workers: int = 1, floorplan: int = 0):
     import numpy as np
 
     import workloads.gen as W
 
     W.FFT_WORKERS = fft_workers
-    inp = W.config2(sample=i, n=n)
+    inp = W.config2(sample=i, n=n, floorplan=floorplan)
     f = lambda a: a.astype(np.float32)
     return f(inp.q_dyn), f(inp.q_leak0), f(inp.leak_var), f(inp.cond_map)
 
@@ -63,14 +63,16 @@ def generate_extra(args):
     """Inputs of the small-grid and mixed-size legs, made before the GPU is touched."""
     import multiprocessing as mp
 
-    small = mixed = None
+    small = mixed = unseen = None
     jobs = []
     if not args.no_small:
         jobs.append("small")
     if not args.no_mixed:
         jobs.append("mixed")
+    if not args.no_surrogate and args.unseen_batch > 0:
+        jobs.append("unseen")
     if not jobs:
-        return None, None
+        return None, None, None
     pool = mp.get_context("fork").Pool(max(1, args.workers))
     try:
         if "small" in jobs:
@@ -78,10 +80,12 @@ def generate_extra(args):
         if "mixed" in jobs:
             # size classes interleaved in the problem array
             mixed = pool.starmap(_sample_mixed, [(c, i) for i in range(args.mixed_batch) for c in range(4)])
+        if "unseen" in jobs:
+            unseen = pool.starmap(_sample, [(i, args.n, 1, UNSEEN_FLOORPLAN) for i in range(args.unseen_batch)])
     finally:
         pool.close()
         pool.join()
-    return small, mixed
+    return small, mixed, unseen
 
 
 def generate(batch: int, n: int, workers: int):
@@ -102,6 +106,38 @@ def generate(batch: int, n: int, workers: int):
         pool.close()  # workers exit on their own (no signal)
         pool.join()
     return out
+
+
+def stream_ceiling(n: int, batch: int, buffers: int = 6, reps: int = 24) -> dict:
+    """What plain streaming reaches on this GPU at the batch's footprint, as context for the
+    roofline fraction (the fraction itself is taken against the published 8 TB/s): an in-place
+    scale (read + write, the access pattern of the solver's passes) and a copy, over `buffers`
+    rotating arrays of one batch-sized plane each, so that the 256 MB last-level cache holds
+    none of the next launch's data."""
+    import torch
+
+    dev = torch.device("cuda", 0)
+    planes = [torch.ones((batch, n, n), dtype=torch.float32, device=dev) for _ in range(buffers)]
+    nbytes = 2 * planes[0].numel() * 4
+
+    def timed(fn):
+        for k in range(buffers):
+            fn(k)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(reps):
+            fn(k)
+        e1.record()
+        e1.synchronize()
+        return nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    inplace = timed(lambda k: planes[k % buffers].mul_(1.0001))
+    copy = timed(lambda k: planes[(k + 1) % buffers].copy_(planes[k % buffers]))
+    del planes
+    torch.cuda.empty_cache()
+    return {"inplace_GBps": round(inplace, 1), "copy_GBps": round(copy, 1),
+            "method": f"torch in-place mul_ / copy_ over {buffers} rotating {batch}x{n}x{n} FP32 planes"}
 
 
 def algorithmic_bytes(n: int) -> dict:
@@ -155,6 +191,8 @@ def main() -> int:
                     help="run one plain device-to-device copy of this size first (counter calibration)")
     ap.add_argument("--no-transient", action="store_true", help="skip the 1024^2 x 1000-step transient run")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-warm-started solve")
+    ap.add_argument("--unseen-batch", type=int, default=64,
+                    help="maps of a floorplan outside the training set for the surrogate's generalisation check")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the compensated-twiddle leg (FP32 error at fixed iterations, time cost)")
     ap.add_argument("--no-anderson", action="store_true", help="skip the Anderson(1)-accelerated leg")
@@ -194,7 +232,7 @@ def main() -> int:
             import numpy as np
 
             np.save(args.inputs_cache, np.stack([np.stack(s) for s in samples]))
-    small_in, mixed_in = generate_extra(args)
+    small_in, mixed_in, unseen_in = generate_extra(args)
     t_gen = time.perf_counter() - t_gen
     print(f"[bench] generated {args.batch} samples of {args.n}^2 (+ extra legs) in {t_gen:.1f} s", file=sys.stderr,
           flush=True)
@@ -385,7 +423,8 @@ def main() -> int:
                    "n": args.n, "batch": args.batch, "tol_K": args.tol, "precision": "f32"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "bytes_per_launch": int(dom_bytes_per_launch), "avg_launch_ms": kernels[dom]["avg_ms"]},
+                     "bytes_per_launch": int(dom_bytes_per_launch), "avg_launch_ms": kernels[dom]["avg_ms"],
+                     "stream_ceiling": stream_ceiling(args.n, args.batch)},
         "solve": {"iterations_mean": float(it.mean()), "iterations_max": int(it.max()), "statuses": statuses,
                   "residual_f64_max_K": float(np.max(resid)),
                   "effective_GBps_all_kernels": round(total_alg / elapsed / 1e9, 1),
@@ -402,6 +441,8 @@ def main() -> int:
     if not args.no_surrogate:
         result["surrogate"], out_w = surrogate_bench(ctx, items, qd, lv, cm, out, opts, ws, args, maps_per_s,
                                                      float(it.mean()))
+        if unseen_in is not None and out_w is not None:
+            result["surrogate"]["unseen_floorplan"] = surrogate_unseen(ctx, unseen_in, die, opts, args)
     if not args.no_anderson:
         result["anderson"] = anderson_bench(ctx, items, out, ws, args, maps_per_s, float(it.mean()))
     if not args.no_precision:
@@ -795,6 +836,41 @@ def surrogate_bench(ctx, items, qd, lv, cm, out_plain, opts, ws, args, plain_map
                           "frac": None if achieved is None else round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
                           "flops_per_launch_batch": flops, "conv_ms_per_batch": conv_ms},
              "weights": os.path.relpath(SURROGATE_WEIGHTS, ROOT), "training": training}, out_w)
+
+
+UNSEEN_FLOORPLAN = 8  # the network was trained on floorplans 0..7
+
+
+def surrogate_unseen(ctx, samples, die, opts, args) -> dict:
+    """Maps of a floorplan the network never saw in training: its prediction error against the
+    plain solve's converged maps, and the iterations the warm start needs against the cold one."""
+    import numpy as np
+    import torch
+
+    from paper_2307_12119_amd import varsim as V
+
+    dev = torch.device("cuda", 0)
+    stack = lambda k: torch.from_numpy(np.stack([s_[k] for s_ in samples])).to(dev)
+    qd, ql, lv, cm = stack(0), stack(1), stack(2), stack(3)
+    b = len(samples)
+    out_p, out_w, init = torch.zeros_like(qd), torch.zeros_like(qd), torch.empty_like(qd)
+    items = [{"die": die, "q_dyn": qd[i], "q_leak0": ql[i], "leak_var": lv[i], "cond_map": cm[i], "dT_out": out_p[i]}
+             for i in range(b)]
+    plain = ctx.prepare(items)
+    warm = ctx.prepare([dict(it, dT_init=init[i], dT_out=out_w[i]) for i, it in enumerate(items)])
+    ws = torch.empty(ctx.workspace_bytes(plain, opts), dtype=torch.uint8, device=dev)
+    st_p = ctx.solve_batch(plain, opts, ws)
+    net = V.Net(ctx, V.NetSpec(n=args.n))
+    net.set_params(torch.from_numpy(np.load(SURROGATE_WEIGHTS)).to(dev))
+    net.forward(qd, lv, cm, init, workspace=torch.empty(net.workspace_bytes(b, False), dtype=torch.uint8, device=dev))
+    st_w = ctx.solve_batch(warm, opts, ws)
+    torch.cuda.synchronize()
+    err = (init - out_p).abs()
+    return {"floorplan": UNSEEN_FLOORPLAN, "maps": b, "trained_floorplans": "0..7",
+            "prediction_mae_K": float(err.mean()), "prediction_max_err_K": float(err.max()),
+            "iterations_mean": float(np.mean(st_w["iterations"])), "plain_iterations_mean": float(np.mean(st_p["iterations"])),
+            "statuses": sorted({int(x) for x in st_w["status"]} | {int(x) for x in st_p["status"]}),
+            "max_diff_vs_plain_K": float((out_w - out_p).abs().max())}
 
 
 def surrogate_training(ctx, spec, qd, lv, cm, target, args, batch: int = 64, steps: int = 10) -> dict:

@@ -156,12 +156,25 @@ def test_net_forward_matches_oracle(ctx, n):
     got = out.cpu().numpy().astype(np.float64)
     ref, _ = NN.forward(spec, _bf16_weights(spec, p), q.astype(np.float64), v.astype(np.float64),
                         m.astype(np.float64))
-    assert np.max(np.abs(got - ref)) <= 0.03 * np.max(np.abs(ref))
+    # every element within 2^-6 of the prediction's largest magnitude (measured: 6.9e-3 at n = 64,
+    # 6.5e-3 at n = 256).  The kernels store each layer's activations in BF16; the FP32
+    # accumulation of the matrix cores differs from FP64 by enough to flip the BF16 rounding of
+    # activations wherever a pre-activation cancels, so even an oracle that rounds its own
+    # activations to BF16 agrees no better (5.0e-3 and 7.1e-3) and agreement to FP32 is out of reach.
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"network forward n={n}: max |gpu - oracle| {err:.2e} of the largest magnitude")
+    assert err <= 2.0 ** -6
     assert np.corrcoef(got.ravel(), ref.ravel())[0, 1] > 0.999
 
 
 @pytest.mark.parametrize("n", [64, 256])
 def test_net_gradient_matches_oracle(ctx, n):
+    """Per parameter tensor: relative L2 distance <= 5 % and cosine >= 0.998 against the FP64
+    oracle.  The bound is on whole tensors: with BF16 activations and output-side gradients, an
+    element of a deep layer's weight gradient sums over few pixels (2 x 2 at level 3 of a 64 x 64
+    map) whose ReLU masks and BF16 roundings can differ from FP64's, so single elements move by up
+    to 15 % of their tensor's largest (measured; an oracle rounding its own activations and
+    gradients to BF16 agrees no better elementwise)."""
     import torch
 
     net, spec, p = _net(ctx, {"n": n}, seed=1)
