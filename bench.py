@@ -470,6 +470,9 @@ def main() -> int:
             result["surrogate"]["max_err_vs_oracle_K"] = max(errs_w.values())
         if not args.no_oracle_timings:
             result["oracle_timings"] = oracle_timings(ctx, per_iter_s, args)
+    check_rec = result["transient"].pop("_check_record", None) if result.get("transient") else None
+    if check_rec is not None and not args.no_cpu_baseline:
+        result["transient"]["oracle_check"] = transient_oracle_check(check_rec)
     if result.get("mixed") and not args.no_cpu_baseline:
         result["mixed"]["oracle_check"] = mixed_oracle_check(result["mixed"].pop("_first_maps"), args.tol)
     elif result.get("mixed"):
@@ -978,6 +981,13 @@ def transient_bench(ctx, runs: int, models: bool = True) -> dict:
     torch.cuda.synchronize()
     wall_untimed = time.perf_counter() - t0
     got = snaps.cpu().numpy().astype(np.float64)
+    # the first TRANSIENT_CHECK_STEPS steps again, every step recorded, for the oracle check at
+    # sampled cells (cpu_baseline leg)
+    rec = torch.zeros((TRANSIENT_CHECK_STEPS, n, n), dtype=torch.float32, device=dev)
+    ctx.solve_transient(item, rects, trace[:TRANSIENT_CHECK_STEPS], inp.dt_s, opts, rec, 1)
+    torch.cuda.synchronize()
+    check_rec = rec.cpu().numpy().astype(np.float64)
+    del rec
     modal = truncated = None
     if models:
         modal, truncated = transient_models(ctx, item, rects, trace, inp, opts, every, snaps, dev)
@@ -1000,7 +1010,51 @@ def transient_bench(ctx, runs: int, models: bool = True) -> dict:
             "steps_per_s": round(steps / wall_untimed, 1), "status": st["status"],
             "dT_max_K": st["dT_max_K"], "fp64_shadow_max_diff_K": float(np.max(np.abs(got - ref))),
             "kernels": kernels, "modal": modal, "truncated_history": truncated,
-            "autotune": [l for l in ctx.autotune_report().strip().split("\n") if l.startswith("transient")]}
+            "autotune": [l for l in ctx.autotune_report().strip().split("\n") if l.startswith("transient")],
+            "_check_record": check_rec}
+
+
+TRANSIENT_CHECK_STEPS = 20
+
+
+def transient_oracle_check(rec) -> dict:
+    """The oracle's superposition (Eq. tranapprox over the whole history, FP64 direct sums) of the
+    transient leg's first steps at sampled cells -- the hottest cell, the corners, the die centre
+    and random cells -- with the power history rebuilt from the recorded rises, against the
+    GPU's FP32 rise of the last of those steps."""
+    import numpy as np
+
+    import workloads.gen as W
+    from oracle import steady as S
+    from oracle import transient as T
+
+    t0 = time.perf_counter()
+    steps, n = rec.shape[0], rec.shape[1]
+    inp = W.transient_problem(n=n, n_steps=1000, dt_s=10e-6, n_blocks=64, hold_s=1e-3, seed=0)
+    g = S.geometry_from_die(inp.die, n)
+    model = T.TransientModel(g, inp.die.rho_c)
+    ql = inp.q_leak0 * inp.leak_var
+    hist = [np.zeros((n, n))]
+    prev = np.zeros((n, n))
+    for k in range(steps):
+        q = W.raster_trace_step(inp.block_rects, inp.trace[k], n) + ql * np.exp(inp.beta * prev)
+        hist.append(g.hx * g.hy * q / inp.cond_map)  # conductivity factor on the source side
+        prev = rec[k]
+    last = rec[-1]
+    hot = np.unravel_index(int(np.argmax(last)), last.shape)
+    rng = np.random.default_rng(17)
+    rows = np.concatenate([[hot[0], 0, 0, n - 1, n - 1, n // 2], rng.integers(0, n, 10)])
+    cols = np.concatenate([[hot[1], 0, n - 1, 0, n - 1, n // 2], rng.integers(0, n, 10)])
+    theta = np.zeros(len(rows))
+    for j in range(1, steps + 1):
+        op = S.DirectSum(g, table=model.step_kernel(j * inp.dt_s))
+        theta += op.apply_at(hist[steps - j + 1] - hist[steps - j], rows, cols)
+    expect, ok = S.kirchhoff_inverse(theta, g.t_amb, g.eta)
+    err = np.abs(last[rows, cols] - expect)
+    return {"steps": steps, "cells": len(rows), "max_err_K": float(np.max(err)) if np.all(ok) else None,
+            "rise_at_hottest_K": float(expect[0]), "seconds": round(time.perf_counter() - t0, 1),
+            "note": "FP32 rise of the leg's first steps (same problem, same tuned passes) against the "
+                    "oracle's superposition at sampled cells"}
 
 
 def transient_models(ctx, item, rects, trace, inp, opts, every, snaps, dev):
