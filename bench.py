@@ -174,7 +174,72 @@ def measured_traffic(kernel: str, n: int, batch: int):
     return rec["traffic_bytes_per_map_pass"]
 
 
+TRAFFIC_SOURCES = {
+    "row_merged": ["paper_2307_12119_amd/csrc/common.hpp", "paper_2307_12119_amd/csrc/fft.hpp",
+                   "paper_2307_12119_amd/csrc/passes.hpp", "paper_2307_12119_amd/csrc/rowops.hpp",
+                   "paper_2307_12119_amd/csrc/rowpass.hpp", "paper_2307_12119_amd/csrc/steady.hip"],
+    "col": ["paper_2307_12119_amd/csrc/common.hpp", "paper_2307_12119_amd/csrc/fft.hpp",
+            "paper_2307_12119_amd/csrc/passes.hpp", "paper_2307_12119_amd/csrc/colpass.hip"],
+}
+
+
+def traffic_record(fetch_dir: str, write_dir: str, kernel: str, symbol: str, maps: float, probe_mb: int,
+                   fetch_cmd: str, write_cmd: str, workload: str) -> dict:
+    """profiles/*_traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of the
+    same bench command with a copy probe: the kernel's KiB per dispatch, scaled by what the same
+    counter reads for the plain copy of probe_mb MiB (which reads and writes exactly that many
+    bytes), per map-pass (every map active in every dispatch).  The record carries the hash of
+    the kernel's sources, so that the bench drops it once they change."""
+    import csv
+    import glob
+    import hashlib
+    import re
+
+    def per_dispatch(d, counter):
+        out = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    v = out.setdefault(r["Dispatch_Id"], [r["Kernel_Name"], 0.0])
+                    v[1] += float(r["Counter_Value"])  # summed in case a counter is split per XCD
+        return out
+
+    probe = probe_mb << 20
+    got = {}
+    for d, ctr in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        disp = per_dispatch(d, ctr)
+        copies = [v for v in disp.values() if "copyBuffer" in v[0] or ("elementwise_kernel" in v[0] and "copy" in v[0])]
+        if not copies:
+            raise SystemExit(f"no copy-probe dispatch in {d}")
+        hits = [v[1] for v in disp.values() if re.search(symbol, v[0])]
+        if not hits:
+            raise SystemExit(f"no dispatch of {symbol} in {d}")
+        got[ctr] = (sum(hits) / len(hits), max(copies, key=lambda v: v[1])[1], len(hits))
+    fetch_kib, fetch_probe, n_disp = got["FETCH_SIZE"]
+    write_kib, write_probe, _ = got["WRITE_SIZE"]
+    fscale, wscale = (probe / 1024) / fetch_probe, (probe / 1024) / write_probe
+    sources = TRAFFIC_SOURCES[kernel]
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    per_disp = (fetch_kib * fscale + write_kib * wscale) * 1024
+    return {"kernel": kernel, "kernel_symbol_regex": symbol, "workload": workload, "fetch_cmd": fetch_cmd,
+            "write_cmd": write_cmd, "dispatches": n_disp, "fetch_kib_per_dispatch": fetch_kib,
+            "write_kib_per_dispatch": write_kib, "copy_probe_bytes": probe, "copy_probe_fetch_kib": fetch_probe,
+            "copy_probe_write_kib": write_probe, "fetch_scale": fscale, "write_scale": wscale,
+            "map_passes_per_dispatch": maps, "source_sha256": h.hexdigest(), "source_files": sources,
+            "traffic_bytes_per_dispatch": per_disp, "traffic_bytes_per_map_pass": per_disp / maps}
+
+
 def main() -> int:
+    if len(sys.argv) > 1 and sys.argv[1] == "--traffic-record":
+        # bench.py --traffic-record FETCH_DIR WRITE_DIR KERNEL SYMBOL_REGEX MAPS PROBE_MB OUT_JSON WORKLOAD
+        #                           FETCH_CMD WRITE_CMD  (no GPU use)
+        fd, wd, kernel, sym, maps, probe_mb, out, workload, fcmd, wcmd = sys.argv[2:12]
+        rec = traffic_record(fd, wd, kernel, sym, float(maps), int(probe_mb), fcmd, wcmd, workload)
+        json.dump(rec, open(out, "w"), indent=1)
+        print(json.dumps(rec))
+        return 0
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
