@@ -32,11 +32,20 @@ __device__ __forceinline__ void xcd_strip_tile(int& strip, int& map) {
   map = i / per;
 }
 
+// Waves per SIMD the register allocation must leave room for: the FP64 1024-point transforms
+// with one pair per transform group need a few registers more than 256 and would otherwise run
+// one wave per SIMD; other instantiations are left to the compiler.
+template <typename Tc, int N, int PAIRS>
+constexpr int col_min_waves() {
+  return sizeof(Tc) == 8 && N == 1024 && PAIRS == 1 ? 2 : 1;
+}
+
 // SQ: square map, row stride N known at compile time (otherwise the run-time row length a.n;
 // a run-time stride costs the square maps about 15 % of the pass).  CT: compensated twiddles
 // (twl: low parts of tw; FP32 only).
 template <typename Tc, int N, int COLS, int PAIRS, bool SQ, bool CT = false, bool INPL = false>
 __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS, INPL>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(col_min_waves<Tc, N, ColCfg<Tc, N, COLS, PAIRS, INPL>::PAIRS>())))
     col_pass_kernel(PassArgs a, const Tc* __restrict__ coef, const Cx<Tc>* __restrict__ tw,
                     const Cx<Tc>* __restrict__ qw, const Cx<Tc>* __restrict__ twl) {
   using Cfg = ColCfg<Tc, N, COLS, PAIRS, INPL>;

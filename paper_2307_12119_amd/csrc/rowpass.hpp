@@ -16,10 +16,12 @@ namespace {  // each translation unit keeps its own instantiations
 
 // Waves per SIMD the register allocation must leave room for: the FP32 merged pass of the
 // two-pass sizes is HBM-bound and needs four to hide its load latency (it fits 128 VGPRs without
-// spilling); other instantiations are left to the compiler.
+// spilling at N <= 512; at N = 1024 two, for 72 bytes of spills, against one wave per SIMD
+// uncapped); other instantiations are left to the compiler.
 template <typename Tio, typename Tc, int N, int MODE>
 constexpr int row_min_waves() {
-  return (sizeof(Tio) == 4 && sizeof(Tc) == 4 && MODE == ROW_MERGED && N >= 128 && N <= 512) ? 4 : 1;
+  if (sizeof(Tio) != 4 || sizeof(Tc) != 4 || MODE != ROW_MERGED) return 1;
+  return N >= 128 && N <= 512 ? 4 : (N == 1024 ? 2 : 1);
 }
 
 // CT: compensated twiddles (twl, qwl: low parts of tw, qw; FP32 only)
