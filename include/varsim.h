@@ -458,11 +458,15 @@ VARSIM_API varsim_status varsim_set_graph_iterations(varsim_ctx* ctx, int32_t it
  * transforms use the strip's own tile columns as scratch, one / two pairs per group, 5 / 6 =
  * the pipelined pass on the same 128-byte strips (a few workgroups per CU walk the strips,
  * loading the next strip while transforming the current one), two / four pairs per group,
- * where the strips split evenly over the 8 XCDs (else candidate 0); square maps only,
- * rectangular ones keep 0), and transient solves use row-pass candidate `variant` and column
- * candidate `variant` where N has that candidate (see varsim_force_transient_variant; else
- * their default); -1 returns to the default or tuned choices.  VARSIM_ERR_INVALID outside
- * [-1, 6]. */
+ * where the strips split evenly over the 8 XCDs (else candidate 0), 7 / 8 = one column per DFT
+ * of half the length with lambda applied to its cosine coefficients, default / half strip
+ * width (N >= 256 inside solves; elsewhere candidate 0); square maps only, rectangular ones
+ * keep 0), and transient solves use row-pass candidate `variant` and column candidate
+ * `variant` where N has that candidate (see varsim_force_transient_variant; else their
+ * default); -1 returns to the default or tuned choices.  Candidates 0..6 give bitwise equal
+ * results, and so do 7 and 8; the two families agree to rounding.  Untuned and tuned choices
+ * stay in one family per (N, precision): one column per DFT for FP64 at N >= 512, two columns
+ * otherwise.  VARSIM_ERR_INVALID outside [-1, 8]. */
 VARSIM_API varsim_status varsim_force_col_variant(varsim_ctx* ctx, int32_t variant);
 /* Testing / manual tuning of transient solves: row-pass candidate `row_variant` and column-pass
  * candidate `col_variant`, each in [0, 8): 0..2 transform two rows (columns) per DFT (row: rows

@@ -497,9 +497,20 @@ TransLayout make_transient_layout(const varsim_problem* p, const varsim_transien
 
 // Column-pass strip width for a group: the tuned choice if the context has one (timing the
 // candidates on this group's own arrays first if autotuning is on), else the default.
+// The transform family a column pass of this size and precision takes: FP64 at N >= 512 transforms
+// one column per DFT of half the length (candidates 7 / 8; the 1024-point pair needs more
+// registers than one wavefront per SIMD leaves, and at N = 512 the one-column pass measured
+// equal or faster), everything else two columns per DFT (candidates 0..6).  The family is fixed
+// per (N, precision) rather than timed, so that the tuner's choice never changes the arithmetic.
+int col_family_for(const PassArgs& group, int compute) {
+  const bool lam = compute == VARSIM_F32 ? group.lam32 != nullptr : group.lam64 != nullptr;
+  return compute == VARSIM_F64 && lam && group.n == group.ny && group.ny >= 512 ? 1 : 0;
+}
+
 varsim_status col_variant_for(varsim_ctx* ctx, const PassArgs& group, int compute, const void* coef, hipStream_t s,
                               int* variant, bool may_tune = true) {
-  *variant = ctx->force_col >= 0 ? ctx->force_col : 0;
+  const int family = col_family_for(group, compute);
+  *variant = ctx->force_col >= 0 ? ctx->force_col : (family ? 7 : 0);
   if (ctx->force_col >= 0 || group.n != group.ny) return VARSIM_OK;  // rectangular maps: default strip
   const auto key = std::make_tuple(group.n, group.ny, compute, ilog2(group.n_maps));
   auto it = ctx->col_choice.find(key);
@@ -514,13 +525,18 @@ varsim_status col_variant_for(varsim_ctx* ctx, const PassArgs& group, int comput
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   std::vector<float> ms(kColVariants, 0.f);
-  int best = 0;
+  int best = *variant;
   for (int v = 0; v < kColVariants; ++v) {
+    if (col_pass_family(compute, a.ny, v) != family) {
+      ms[v] = -1.f;  // not timed: another transform family
+      continue;
+    }
     int dup = -1;
     for (int u = 0; u < v; ++u)
       if (col_pass_columns(compute, a.ny, u) == col_pass_columns(compute, a.ny, v) &&
           col_pass_pairs(compute, a.ny, u) == col_pass_pairs(compute, a.ny, v) &&
-          col_pass_pipelined(compute, a.ny, u) == col_pass_pipelined(compute, a.ny, v))
+          col_pass_pipelined(compute, a.ny, u) == col_pass_pipelined(compute, a.ny, v) &&
+          col_pass_family(compute, a.ny, u) == col_pass_family(compute, a.ny, v))
         dup = u;
     if (dup >= 0) {
       ms[v] = ms[dup];
@@ -837,6 +853,8 @@ static varsim_status solve_batch_impl(varsim_ctx* ctx, const varsim_problem* pro
     a.ct = opts->compensated_twiddles && io == VARSIM_F32 ? 1 : 0;
     a.iter = iter;
     a.zero_start = 0;
+    a.lam32 = g.table.lam32T;
+    a.lam64 = g.table.lam64T;
     return a;
   };
 
@@ -1563,14 +1581,17 @@ varsim_status varsim_autotune_report(varsim_ctx* ctx, char* buf, size_t len) {
     const auto found = ctx->col_ms.find(kv.first);
     if (found == ctx->col_ms.end()) {
       snprintf(line, sizeof line, " %d cols x%d%s (imported)\n", col_pass_columns(c, n, kv.second),
-               col_pass_pairs(c, n, kv.second), col_pass_pipelined(c, n, kv.second) ? " pipelined" : "");
+               col_pass_pairs(c, n, kv.second),
+               col_pass_family(c, n, kv.second) ? " one-column" : col_pass_pipelined(c, n, kv.second) ? " pipelined" : "");
       out += line;
       continue;
     }
     const auto& ms = found->second;
     for (int v = 0; v < (int)ms.size(); ++v) {
+      if (ms[v] < 0.f) continue;  // another transform family, not timed
       snprintf(line, sizeof line, " %d cols x%d%s %.4f ms%s", col_pass_columns(c, n, v), col_pass_pairs(c, n, v),
-               col_pass_pipelined(c, n, v) ? " pipelined" : "", ms[v], v == kv.second ? "*" : "");
+               col_pass_family(c, n, v) ? " one-column" : col_pass_pipelined(c, n, v) ? " pipelined" : "", ms[v],
+               v == kv.second ? "*" : "");
       out += line;
     }
     out += "\n";

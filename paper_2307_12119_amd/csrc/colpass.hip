@@ -10,6 +10,7 @@
 #include "fft.hpp"
 #include "internal.hpp"
 #include "passes.hpp"
+#include "single.hpp"
 
 namespace vs {
 
@@ -339,6 +340,121 @@ __global__ void __launch_bounds__((ColCfg<Tc, N, COLS, PAIRS, true>::THREADS))
   }
 }
 
+// One-sequence column pass: each column through a complex DFT of N/2 points (single.hpp),
+// COLS columns per workgroup, one per group of TPF lanes.  The DFT leaves the column's cosine
+// coefficients X[p] and X[hi(p)] in one lane, so lambda multiplies them directly (no split and
+// merge of two packed columns); a column needs half the registers of a packed pair, which is
+// what the 1024-point columns (16 elements per lane in the packed form) are short of.  The
+// strip is staged in LDS with its rows in z order; the transform scratch reuses the tile.
+template <typename Tc, int N, int COLS_>
+struct Col1Cfg {
+  static constexpr int M = N / 2;
+  static constexpr int E = Shape<M>::E, TPF = Shape<M>::TPF;
+  static constexpr int COLS = COLS_;
+  static constexpr int THREADS = COLS * TPF;
+  static constexpr int VEC = (int)(16 / sizeof(Tc)) < COLS ? (int)(16 / sizeof(Tc)) : COLS;
+  static constexpr int VPR = COLS / VEC;
+  static constexpr int PITCH = COLS + 1;
+  static constexpr int TILE = N * PITCH;
+  static constexpr int ST = Shape<M>::STRIDE;
+  static constexpr int SCRATCH = COLS * 2 * ST;
+  static constexpr int LDS = TILE > SCRATCH ? TILE : SCRATCH;
+};
+
+template <typename Tc, int N, int COLS>
+__global__ void __launch_bounds__((Col1Cfg<Tc, N, COLS>::THREADS))
+    col1_pass_kernel(PassArgs a, const Tc* __restrict__ lam, const Cx<Tc>* __restrict__ tw,
+                     const Cx<Tc>* __restrict__ qw) {
+  using Cfg = Col1Cfg<Tc, N, COLS>;
+  constexpr int M = Cfg::M, E = Cfg::E, TPF = Cfg::TPF, ST = Cfg::ST;
+  constexpr int VEC = Cfg::VEC, VPR = Cfg::VPR, P = Cfg::PITCH;
+  __shared__ Tc lds[Cfg::LDS];
+
+  int strip, map;
+  xcd_strip_tile(strip, map);
+  if (a.iter >= 0) {
+    if (a.st.flags[map] & kFlagSkip) return;
+    if (!a.resid_pass && finished_before(a.st, map, a.iter, a.pp.tol)) return;
+  }
+  const MapPtrs mp = a.maps[map];
+  Tc* S = (Tc*)(a.use_s64 ? mp.S64 : mp.S);
+  const int c0 = strip * COLS;
+  for (int it = threadIdx.x; it < N * VPR; it += Cfg::THREADS) {
+    const int y = it / VPR, j = it % VPR;
+    const Vec<Tc, VEC> v = *reinterpret_cast<const Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC);
+    Tc* d = lds + z_row<N>(y) * P + j * VEC;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) d[e] = v.v[e];
+  }
+  __syncthreads();
+
+  int f = threadIdx.x / TPF;
+  if constexpr (TPF == 64) f = __builtin_amdgcn_readfirstlane(f);
+  const int t = threadIdx.x % TPF;
+  Tc zr[E], zi[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    zr[m] = lds[(t + TPF * m) * P + f];
+    zi[m] = lds[(M + t + TPF * m) * P + f];
+  }
+  __syncthreads();
+  Tc* re = lds + f * ST;
+  Tc* im = lds + COLS * ST + f * ST;
+  dct2_single<Tc, N>(zr, zi, re, im, tw, qw, t);
+  const Tc* lq = lam + (long)(c0 + f) * N;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int p = t + TPF * m;
+    zr[m] *= lq[p];
+    zi[m] *= lq[spec_hi<N>(p)];
+  }
+  dct3_single<Tc, N>(zr, zi, re, im, tw, qw, t);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    lds[(t + TPF * m) * P + f] = zr[m];
+    lds[(M + t + TPF * m) * P + f] = zi[m];
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < N * VPR; it += Cfg::THREADS) {
+    const int y = it / VPR, j = it % VPR;
+    const Tc* src = lds + z_row<N>(y) * P + j * VEC;
+    Vec<Tc, VEC> v;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v.v[e] = src[e];
+    *reinterpret_cast<Vec<Tc, VEC>*>(S + (long)y * N + c0 + j * VEC) = v;
+  }
+}
+
+// strip width of the one-sequence pass: the widest (at most 16 columns) whose tile fits 64 KB,
+// halved for candidate 8
+template <typename Tc, int N, int V>
+constexpr int col1_cols() {
+  int c = 16;
+  while (c > 1 && ((long)N * (c + 1) * (long)sizeof(Tc) > 65536 || c * Shape<N / 2>::TPF > 1024)) c /= 2;
+  if (V == 8 && c > 1) c /= 2;
+  return c;
+}
+template <typename Tc, int N>
+constexpr bool col1_ok() {
+  return N >= 256;
+}
+
+template <typename Tc, int N, int V>
+hipError_t col1_launch(const PassArgs& a, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+  constexpr int COLS = col1_cols<Tc, N, V>();
+  using Cfg = Col1Cfg<Tc, N, COLS>;
+  const Tc* lam;
+  if constexpr (sizeof(Tc) == 4)
+    lam = a.lam32;
+  else
+    lam = a.lam64;
+  if (!lam || a.n != N || a.ny != N) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((col1_pass_kernel<Tc, N, COLS>), dim3(N / COLS, a.n_maps), dim3(Cfg::THREADS), 0, s, a, lam, tw,
+                     qw);
+  return hipGetLastError();
+}
+
 // Workgroups per CU of a pipelined instantiation (from its LDS and register use) and the CU
 // count, taken once per instantiation.
 template <typename K>
@@ -436,11 +552,21 @@ hipError_t col_pipe_v(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const
   else
     return col_launch_v<Tc, N, 0, CT>(a, coef, tw, qw, s);
 }
+// one-sequence candidates where available (and lambda is given), else candidate 0
+template <typename Tc, int N, int V, bool CT>
+hipError_t col1_v(const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
+  const bool have = sizeof(Tc) == 4 ? a.lam32 != nullptr : a.lam64 != nullptr;
+  if constexpr (col1_ok<Tc, N>() && !CT)
+    if (have) return col1_launch<Tc, N, V>(a, tw, qw, s);
+  return col_launch_v<Tc, N, 0, CT>(a, coef, tw, qw, s);
+}
 template <typename Tc, int N, bool CT>
 hipError_t col_variant_ct(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>* tw, const Cx<Tc>* qw, hipStream_t s) {
   switch (v) {
     case 5: return col_pipe_v<Tc, N, 5, CT>(a, coef, tw, qw, s);
     case 6: return col_pipe_v<Tc, N, 6, CT>(a, coef, tw, qw, s);
+    case 7: return col1_v<Tc, N, 7, CT>(a, coef, tw, qw, s);
+    case 8: return col1_v<Tc, N, 8, CT>(a, coef, tw, qw, s);
     case 0: return col_launch_v<Tc, N, 0, CT>(a, coef, tw, qw, s);
     case 1: return col_launch_v<Tc, N, 1, CT>(a, coef, tw, qw, s);
     case 2: return col_launch_v<Tc, N, 2, CT>(a, coef, tw, qw, s);
@@ -476,6 +602,8 @@ hipError_t col_dispatch_n(int v, const PassArgs& a, const Tc* coef, const Cx<Tc>
 template <typename Tc, int N>
 int col_cols_of(int v) {
   switch (v) {
+    case 7: return col1_ok<Tc, N>() ? col1_cols<Tc, N, 7>() : col_candidate<Tc, N, 0>();
+    case 8: return col1_ok<Tc, N>() ? col1_cols<Tc, N, 8>() : col_candidate<Tc, N, 0>();
     case 5: return pipe_ok<Tc, N, 5>() ? pipe_cols<Tc, N>() : col_candidate<Tc, N, 0>();
     case 6: return pipe_ok<Tc, N, 6>() ? pipe_cols<Tc, N>() : col_candidate<Tc, N, 0>();
     case 0: return col_candidate<Tc, N, 0>();
@@ -500,6 +628,8 @@ constexpr int pipe_pairs_eff() {
 template <typename Tc, int N>
 int col_pairs_of(int v) {
   switch (v) {
+    case 7:
+    case 8: return col1_ok<Tc, N>() ? 1 : col_pairs_eff<Tc, N, 0>();
     case 5: return pipe_pairs_eff<Tc, N, 5>();
     case 6: return pipe_pairs_eff<Tc, N, 6>();
     case 0: return col_pairs_eff<Tc, N, 0>();
@@ -543,6 +673,11 @@ int col_pass_pipelined(int compute, int n, int variant) {
 #undef VS_PIPE_OK
     default: return 0;
   }
+}
+
+int col_pass_family(int compute, int n, int variant) {
+  (void)compute;
+  return (variant == 7 || variant == 8) && n >= 256 ? 1 : 0;
 }
 
 int col_pass_columns(int compute, int n, int variant) {

@@ -77,6 +77,10 @@ struct PassArgs {
   int zero_start;  // iteration 1 starts from dT = 0 (no warm start)
   int use_s64;     // operate on MapPtrs::S64 instead of S
   int resid_pass;  // FP64 residual pass: skip only maps flagged invalid / runaway
+  // cosine eigenvalues lambda [q][p] of the column transforms (scaled as the column pass applies
+  // them) for the one-sequence column pass, or null where the pass applies other coefficients
+  const float* lam32 = nullptr;
+  const double* lam64 = nullptr;
 };
 
 // io: element type of the maps (VARSIM_F32 / VARSIM_F64); compute: type of the transforms.
@@ -86,14 +90,17 @@ hipError_t launch_row_pass_ct(int mode, const PassArgs& a, hipStream_t stream);
 // coef: the column-pass coefficient table of the compute type; variant: launch-shape candidate
 // 0 (default strip width), 1 (default width, two column pairs per transform group), 2 (half
 // width), 3 / 4 (wide in-place strip, one / two pairs), 5 / 6 (pipelined 128-byte strips, two /
-// four pairs); col_pass_columns / col_pass_pairs give a candidate's strip width and pairs per
-// group, col_pass_pipelined whether it runs as the pipelined pass
-constexpr int kColVariants = 7;
+// four pairs), 7 / 8 (one column per DFT of half the length, default / half strip width: N >= 256
+// and a.lam32 / a.lam64 set); col_pass_columns / col_pass_pairs give a candidate's strip width
+// and pairs per group, col_pass_pipelined whether it runs as the pipelined pass, col_pass_family
+// whether it transforms one column (1) or two columns (0) per DFT
+constexpr int kColVariants = 9;
 constexpr int kMaxGraphIterations = 16;  // fixed-point iterations one captured graph may hold
 hipError_t launch_col_pass(int compute, const PassArgs& a, const void* coef, hipStream_t stream, int variant = 0);
 int col_pass_columns(int compute, int n, int variant);
 int col_pass_pairs(int compute, int n, int variant);
 int col_pass_pipelined(int compute, int n, int variant);
+int col_pass_family(int compute, int n, int variant);
 
 // Static inputs: QL = q_leak0 * v, MINV = 1 / m (per map), warm-start screening and copy.
 struct PrepArgs {
