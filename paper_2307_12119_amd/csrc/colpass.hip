@@ -455,20 +455,23 @@ hipError_t col1_launch(const PassArgs& a, const Cx<Tc>* tw, const Cx<Tc>* qw, hi
   return hipGetLastError();
 }
 
-// Workgroups per CU of a pipelined instantiation (from its LDS and register use) and the CU
-// count, taken once per instantiation.
+// Workgroups per CU of a pipelined instantiation (from its LDS and register use) times the CU
+// count, a multiple of 8, taken once per instantiation and device (the grid size changes only
+// the speed: any grid walks every strip).
 template <typename K>
 int pipe_grid(K kernel, int threads) {
-  static int grid = 0;
-  if (!grid) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1)
-      return 0;
-    grid = (cus * per + 7) / 8 * 8;
-  }
-  return grid;
+  constexpr int kDevices = 64;
+  static int grid[kDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev < kDevices && grid[dev]) return grid[dev];
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1)
+    return 0;
+  const int g = (cus * per + 7) / 8 * 8;
+  if (dev < kDevices) grid[dev] = g;
+  return g;
 }
 
 template <typename Tc, int N, int COLS, int PAIRS, bool CT>
