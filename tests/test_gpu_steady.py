@@ -94,15 +94,20 @@ def test_conv_large_sampled_cells(ctx, n):
     assert np.max(np.abs(got32 - ref)) <= 2e-6 * np.max(np.abs(ref))
 
 
-def test_full_size_1024_fixed_point_sampled(ctx):
-    """1024 x 1024 FP32 solve: the oracle's fixed-point map, evaluated at sampled cells on the
-    GPU result, reproduces it (contraction: error to the fixed point <= residual / (1 - rho))."""
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_1024_fixed_point_sampled(ctx, prec):
+    """1024 x 1024 solve: the oracle's fixed-point map, evaluated at sampled cells on the GPU
+    result, reproduces it (contraction: error to the fixed point <= residual / (1 - rho)).  FP32
+    within 2e-3 K; FP64 (the one-column column passes of N >= 512, the capped 1024-point
+    transforms) iterated to 1e-10 K and within 1e-8 K."""
     import torch
     from paper_2307_12119_amd import varsim as V
 
     inp = W.config3(3, 0)
-    item = gpu_item(inp, torch.float32)
-    st = ctx.solve_steady(item, _opts(V.F32, inp, 50, 1e-4, res=True))
+    dtype, code, tol, gate = ((torch.float32, V.F32, 1e-4, 2e-3) if prec == "f32" else
+                              (torch.float64, V.F64, 1e-10, 1e-8))
+    item = gpu_item(inp, dtype)
+    st = ctx.solve_steady(item, _opts(code, inp, 60, tol, res=True))
     assert st["status"] == V.OK
     got = item["dT_out"].cpu().numpy().astype(np.float64)
     prob, opts = S.problem_from_inputs(inp)
@@ -113,8 +118,8 @@ def test_full_size_1024_fixed_point_sampled(ctx):
     theta = prob.op.apply_at(prob.power(got, opts) / prob.m, rows, cols)
     again, ok = S.kirchhoff_inverse(theta, prob.geom.t_amb, prob.geom.eta)
     assert np.all(ok)
-    assert np.max(np.abs(again - got[rows, cols])) <= 2e-3
-    assert st["residual_f64_K"] <= 2e-3
+    assert np.max(np.abs(again - got[rows, cols])) <= gate
+    assert st["residual_f64_K"] <= gate
 
 
 # ----------------------------------------------------------------------------- steady FP64
