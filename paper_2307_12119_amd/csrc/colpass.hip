@@ -3,6 +3,7 @@
 // mirrored Green's operator (folded into one step with the split of the two packed columns and
 // the merge for the inverse), and the column DCT-III, in place.  The strip width is a tuning
 // parameter: the library times the candidates on the actual batch and keeps the fastest.
+#include <atomic>
 #include <cmath>
 #include <type_traits>
 
@@ -461,16 +462,19 @@ hipError_t col1_launch(const PassArgs& a, const Cx<Tc>* tw, const Cx<Tc>* qw, hi
 template <typename K>
 int pipe_grid(K kernel, int threads) {
   constexpr int kDevices = 64;
-  static int grid[kDevices] = {};
+  static std::atomic<int> grid[kDevices];  // zero-initialised (static storage); host threads may race here
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
-  if (dev < kDevices && grid[dev]) return grid[dev];
+  if (dev < kDevices) {
+    const int g = grid[dev].load(std::memory_order_relaxed);
+    if (g) return g;
+  }
   int cus = 0, per = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1)
     return 0;
   const int g = (cus * per + 7) / 8 * 8;
-  if (dev < kDevices) grid[dev] = g;
+  if (dev < kDevices) grid[dev].store(g, std::memory_order_relaxed);
   return g;
 }
 
