@@ -414,9 +414,10 @@ VARSIM_API varsim_status varsim_nn_conv(varsim_ctx* ctx, int32_t op, int32_t k, 
 /* ----------------------------------------------------------------------------------------
  * Autotuning of launch shapes.  With autotuning on (enable = 1), the first solve of a group of
  * maps with a given (grid size, precision, power-of-two group size) times every column-pass
- * strip width on that group's own workspace arrays and keeps the fastest for later solves of
- * the same kind; results do not depend on the choice (the same arithmetic in a different
- * tiling).  enable = 0 stops tuning (kept choices still apply); enable = -1 also forgets them.
+ * strip width on that group's own workspace arrays (each timed launch right after a row pass
+ * over the group, as in the solve, which overwrites the group's spectrum workspace) and keeps
+ * the fastest for later solves of the same kind; results do not depend on the choice (the same
+ * arithmetic in a different tiling).  enable = 0 stops tuning (kept choices still apply); enable = -1 also forgets them.
  * varsim_autotune_report writes one line per tuned kind into buf (NUL-terminated; returns
  * VARSIM_ERR_NO_MEMORY if truncated).
  */

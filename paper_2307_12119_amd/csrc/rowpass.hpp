@@ -47,7 +47,10 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS)
   __shared__ double s_red[AA ? 5 : 3][Cfg::WAVES];
   __shared__ double s_gamma;
 
-  const int map = blockIdx.y;
+  // Maps in reverse launch order: the column pass walks them forward, so each pass starts on the
+  // maps the previous one wrote last, which a batch larger than the 256 MB MALL still has there
+  // (an LRU-like cache evicts first what a same-direction pass reads first).
+  const int map = gridDim.y - 1 - blockIdx.y;
   unsigned flags = 0u;
   if (MODE != ROW_CONV_HEAD && MODE != ROW_CONV_TAIL) {
     flags = a.st.flags[map];
