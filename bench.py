@@ -286,11 +286,15 @@ def main() -> int:
         return 2
 
     t_gen = time.perf_counter()
+    cached = None
     if args.inputs_cache and os.path.exists(args.inputs_cache):
         import numpy as np
 
-        arr = np.load(args.inputs_cache)
-        samples = [tuple(arr[i]) for i in range(arr.shape[0])]
+        cached = np.load(args.inputs_cache)
+        if cached.shape[0] != args.batch or cached.shape[-2:] != (args.n, args.n):
+            cached = None  # written for another workload: generate and overwrite
+    if cached is not None:
+        samples = [tuple(cached[i]) for i in range(cached.shape[0])]
     else:
         samples = generate(args.batch, args.n, args.workers)
         if args.inputs_cache:
